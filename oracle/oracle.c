@@ -1,0 +1,589 @@
+/*
+ * Plain, slow, single-threaded CPU oracle for the semi-Lagrangian dynamic
+ * programming scheme of "Dynamic Programming Techniques for Planar Orbital
+ * Transfer of LEO Satellites" (arXiv 2407.14675).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path calls, links or
+ * loads this file; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header, table or constant with
+ * the device library.
+ *
+ * Arithmetic is in `real`, which is double unless ORACLE_FLOAT is defined
+ * (the float build exists only to measure what single precision alone costs).
+ * Residuals and sums are always accumulated in double.
+ *
+ * What it computes (Section 3 of the paper):
+ *   - the fixed-point scheme eq:schema: for every grid node x_j
+ *       v_j = min_f { dt*l(x_j,f) + exp(-lambda*dt) * I[V](x_j + dt*Phi(x_j,f)) }
+ *     with I[V] the tensor-product (Q1) interpolation of the nodal values and
+ *     I[V](z) = M for z outside the domain (state-constraint penalty,
+ *     paragraph "Grid and polar coordinates");
+ *   - value iteration (paragraph "Policy Iteration", first display);
+ *   - policy iteration, eq:p_eval then eq:p_impr, with the evaluation done by
+ *     a fixed number of frozen-policy sweeps (modified policy iteration);
+ *   - the minimisation by tabulation and golden-section refinement
+ *     (paragraph "Efficient computation of the minimum");
+ *   - the approximate feedback eq:feed.
+ *
+ * Problem instance (nondimensional, mu = 1): state x = (r, v_r, v_t, m),
+ *   r'   = v_r
+ *   v_r' = v_t^2/r - mu/r^2 + thr*(a/m)*sin u
+ *   v_t' = -v_r*v_t/r       + thr*(a/m)*cos u
+ *   m'   = -c*thr
+ * (the polar system of Section 3 with the angle measured from the tangential
+ * direction, the cyclic angle theta dropped and mass added; the centrifugal
+ * term carries a plus sign, which is the physically correct one).  The foot
+ * point is one explicit Euler step.  A second model, a 2-D minimum-time
+ * eikonal x' = s*(sin u, cos u) in axes (v_r, v_t), exists to pin the scheme
+ * against a closed form.
+ *
+ * Grid: closed uniform tensor grid, node i_k at lo_k + i_k*h_k with
+ * h_k = (hi_k - lo_k)/(n_k - 1); storage is C order [m][v_t][v_r][r].
+ * The foot is expressed in grid coordinates, s_k = i_k + dt*b_k/h_k, which
+ * is the same point as (z_k - lo_k)/h_k but exact for a zero displacement.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef ORACLE_FLOAT
+typedef float real;
+#else
+typedef double real;
+#endif
+
+#define OR_PI 3.14159265358979323846
+
+typedef struct {
+  int32_t n[4];
+  double lo[4], hi[4];
+  int32_t model; /* 0 = planar orbit, 1 = 2-D eikonal in axes (v_r, v_t) */
+  double mu, accel, mdot, dt, lambda, w_time, w_fuel, M, speed;
+  double tgt_c[4], tgt_w[4];
+} or_problem;
+
+typedef struct {
+  int32_t mode; /* 0 = discrete table of n_angles thrust angles plus coast,
+                   1 = scan of n_scan angles, golden-section refinement */
+  int32_t n_angles, n_scan, n_golden;
+} or_search;
+
+enum { KIND_FREE = 0, KIND_TARGET = 1, KIND_INACTIVE = 2 };
+
+/* ------------------------------------------------------------------ grid */
+static double step(const or_problem *p, int k) {
+  return (p->hi[k] - p->lo[k]) / (double)(p->n[k] - 1);
+}
+
+static int64_t n_total(const or_problem *p) {
+  return (int64_t)p->n[0] * p->n[1] * p->n[2] * p->n[3];
+}
+
+static void node_index(const or_problem *p, int64_t j, int i[4]) {
+  for (int k = 0; k < 4; k++) {
+    i[k] = (int)(j % p->n[k]);
+    j /= p->n[k];
+  }
+}
+
+static int64_t flat_index(const or_problem *p, const int i[4]) {
+  return (((int64_t)i[3] * p->n[2] + i[2]) * p->n[1] + i[1]) * p->n[0] + i[0];
+}
+
+static void node_coords(const or_problem *p, const int i[4], real x[4]) {
+  for (int k = 0; k < 4; k++) x[k] = (real)(p->lo[k] + i[k] * step(p, k));
+}
+
+/* Fixed sets.  Target nodes: every node within the target box enlarged by
+ * half a cell on each constrained axis (nearest-node snapping of the box);
+ * V = 0 there.  Inactive nodes: mask[j] == 0; V = M there (nodes dropped
+ * from the reduced grid behave as outside the domain).  Target wins. */
+void or_classify(const or_problem *p, const uint8_t *mask, uint8_t *kind) {
+  int64_t N = n_total(p);
+  for (int64_t j = 0; j < N; j++) {
+    int i[4];
+    node_index(p, j, i);
+    int target = 1;
+    for (int k = 0; k < 4; k++) {
+      double x = p->lo[k] + i[k] * step(p, k);
+      if (!(fabs(x - p->tgt_c[k]) <= p->tgt_w[k] + 0.5 * step(p, k))) target = 0;
+    }
+    if (target) kind[j] = KIND_TARGET;
+    else if (mask && !mask[j]) kind[j] = KIND_INACTIVE;
+    else kind[j] = KIND_FREE;
+  }
+}
+
+void or_init_value(const or_problem *p, const uint8_t *kind, real *V) {
+  int64_t N = n_total(p);
+  for (int64_t j = 0; j < N; j++) V[j] = (kind[j] == KIND_TARGET) ? (real)0 : (real)p->M;
+}
+
+/* ------------------------------------------------------------- dynamics */
+/* Right-hand side b(x, f) for throttle thr in {0,1} and thrust angle u. */
+static void rhs(const or_problem *p, const real x[4], int thr, real u, real b[4]) {
+  if (p->model == 1) {
+    real s = thr ? (real)p->speed : (real)0;
+    b[0] = 0;
+    b[1] = s * (real)sin(u);
+    b[2] = s * (real)cos(u);
+    b[3] = 0;
+    return;
+  }
+  real r = x[0], vr = x[1], vt = x[2], m = x[3];
+  real acc = thr ? (real)p->accel / m : (real)0;
+  b[0] = vr;
+  b[1] = vt * vt / r - (real)p->mu / (r * r) + acc * (real)sin(u);
+  b[2] = -vr * vt / r + acc * (real)cos(u);
+  b[3] = -(real)p->mdot * (real)thr;
+}
+
+/* One explicit Euler step of length tau from an arbitrary state x. */
+void or_step(const or_problem *p, const real x[4], int thr, real u, real tau, real z[4]) {
+  real b[4];
+  rhs(p, x, thr, u, b);
+  for (int k = 0; k < 4; k++) z[k] = x[k] + tau * b[k];
+}
+
+/* Foot of node i in grid coordinates: s_k = i_k + tau*b_k/h_k. */
+static void foot_grid(const or_problem *p, const int i[4], int thr, real u, real tau, real s[4]) {
+  real x[4], b[4];
+  node_coords(p, i, x);
+  rhs(p, x, thr, u, b);
+  for (int k = 0; k < 4; k++) s[k] = (real)i[k] + tau * b[k] / (real)step(p, k);
+}
+
+/* --------------------------------------------------------- interpolation */
+/* Q1 interpolation at grid coordinates s (paper: multilinear I[V]).
+ * Outside the closed box [0, n_k - 1] in any axis the value is M.
+ * Inside, the cell is base_k = min(floor(s_k), n_k - 2), the local
+ * coordinate t_k = s_k - base_k, and I = sum over the 16 corners e of
+ * prod_k (e_k ? t_k : 1 - t_k) * V[base + e].
+ * If idx/w are given, the 16 corner indices and weights are returned. */
+static int cell(const or_problem *p, const real s[4], int base[4], real t[4]) {
+  for (int k = 0; k < 4; k++) {
+    if (!(s[k] >= 0 && s[k] <= (real)(p->n[k] - 1))) return 0;
+    int b = (int)floor(s[k]);
+    if (b > p->n[k] - 2) b = p->n[k] - 2;
+    base[k] = b;
+    t[k] = s[k] - (real)b;
+  }
+  return 1;
+}
+
+static real interp(const or_problem *p, const real *V, const real s[4]) {
+  int base[4];
+  real t[4];
+  if (!cell(p, s, base, t)) return (real)p->M;
+  real acc = 0;
+  for (int c = 0; c < 16; c++) {
+    real w = 1;
+    int corner[4];
+    for (int k = 0; k < 4; k++) {
+      int e = (c >> k) & 1;
+      w *= e ? t[k] : (real)1 - t[k];
+      corner[k] = base[k] + e;
+    }
+    acc += w * V[flat_index(p, corner)];
+  }
+  return acc;
+}
+
+/* Exported: value of I[V] at grid coordinates s. */
+real or_interp(const or_problem *p, const real *V, const real s[4]) { return interp(p, V, s); }
+
+/* Exported: corner indices and weights; returns 0 when s is outside. */
+int or_interp_weights(const or_problem *p, const real s[4], int64_t idx[16], real w[16]) {
+  int base[4];
+  real t[4];
+  if (!cell(p, s, base, t)) return 0;
+  for (int c = 0; c < 16; c++) {
+    real ww = 1;
+    int corner[4];
+    for (int k = 0; k < 4; k++) {
+      int e = (c >> k) & 1;
+      ww *= e ? t[k] : (real)1 - t[k];
+      corner[k] = base[k] + e;
+    }
+    idx[c] = flat_index(p, corner);
+    w[c] = ww;
+  }
+  return 1;
+}
+
+/* FP64 read-out of I[V] at a physical state x (float or double V). */
+/* Grid coordinate of a physical coordinate.  A state given in physical
+ * units that lies on a face of the box can round to just outside it; points
+ * within FACE_EPS cells of a face are put on the face. */
+#define FACE_EPS 1e-6
+static real to_grid(const or_problem *p, int k, double xk) {
+  double s = (xk - p->lo[k]) / step(p, k);
+  double top = (double)(p->n[k] - 1);
+  if (s < 0 && s > -FACE_EPS) s = 0;
+  if (s > top && s < top + FACE_EPS) s = top;
+  return (real)s;
+}
+
+double or_value_at(const or_problem *p, const real *V, const double x[4]) {
+  real s[4];
+  for (int k = 0; k < 4; k++) s[k] = to_grid(p, k, x[k]);
+  return (double)interp(p, V, s);
+}
+
+/* --------------------------------------------------- Bellman Q of a control */
+static real discount(const or_problem *p, real tau) { return (real)exp(-p->lambda * tau); }
+
+static real running_cost(const or_problem *p, int thr) {
+  return (real)p->w_time + (real)p->w_fuel * (real)thr;
+}
+
+/* Q(x_j, f) = dt*l + exp(-lambda*dt) * I[V](foot) at node i with step tau. */
+static real q_node(const or_problem *p, const real *V, const int i[4], int thr, real u, real tau) {
+  real s[4];
+  foot_grid(p, i, thr, u, tau, s);
+  return tau * running_cost(p, thr) + discount(p, tau) * interp(p, V, s);
+}
+
+real or_q(const or_problem *p, const real *V, int64_t j, int thr, real u) {
+  int i[4];
+  node_index(p, j, i);
+  return q_node(p, V, i, thr, u, (real)p->dt);
+}
+
+/* Q at an arbitrary state y (feedback, eq:feed): interpolation at y + tau*b. */
+static real q_state(const or_problem *p, const real *V, const real y[4], int thr, real u, real tau) {
+  real z[4], s[4];
+  or_step(p, y, thr, u, tau, z);
+  for (int k = 0; k < 4; k++) s[k] = to_grid(p, k, (double)z[k]);
+  return tau * running_cost(p, thr) + discount(p, tau) * interp(p, V, s);
+}
+
+/* ------------------------------------------------------------- search */
+typedef struct {
+  real q;      /* best Q over all controls */
+  real angle;  /* best thrust angle, wrapped into [-pi, pi) */
+  int thr;     /* 1 if thrust beats coast */
+  real margin; /* gap to the runner-up (tie indicator) */
+} choice;
+
+static real wrap_angle(real u) {
+  const real two_pi = (real)(2.0 * OR_PI);
+  while (u < (real)(-OR_PI)) u += two_pi;
+  while (u >= (real)OR_PI) u -= two_pi;
+  return u;
+}
+
+/* Q as a function of the control alone, at either a node or a free state. */
+typedef struct {
+  const or_problem *p;
+  const real *V;
+  const int *i;     /* node, or NULL */
+  const real *y;    /* state, when i == NULL */
+  real tau;
+} qfun;
+
+static real qeval(const qfun *f, int thr, real u) {
+  if (f->i) return q_node(f->p, f->V, f->i, thr, u, f->tau);
+  return q_state(f->p, f->V, f->y, thr, u, f->tau);
+}
+
+/* Discrete table: coast (index 0) and angles u_k = -pi + 2*pi*k/K (index k+1).
+ * The first minimum in index order wins (strict <), so coast wins exact ties. */
+static choice search_table(const qfun *f, int K) {
+  real q_coast = qeval(f, 0, 0);
+  real best = q_coast, second = INFINITY;
+  real best_thr_q = INFINITY, best_thr_u = 0;
+  int thr = 0;
+  for (int k = 0; k < K; k++) {
+    real u = (real)(-OR_PI + 2.0 * OR_PI * (double)k / (double)K);
+    real q = qeval(f, 1, u);
+    if (q < best_thr_q) { best_thr_q = q; best_thr_u = u; }
+    if (q < best) { second = best; best = q; thr = 1; }
+    else if (q < second) second = q;
+  }
+  choice c;
+  c.q = best;
+  c.angle = wrap_angle(best_thr_u);
+  c.thr = thr;
+  c.margin = second - best;
+  return c;
+}
+
+/* Scan of n_scan angles u_s = -pi + 2*pi*s/n_scan, then golden-section search
+ * (ratio (sqrt 5 - 1)/2) on [u_s* - 2*pi/n_scan, u_s* + 2*pi/n_scan]: two
+ * interior evaluations, then one per iteration.  The best evaluated point
+ * (scan sample included, strict < in evaluation order) is the thrust
+ * candidate; thrust is chosen iff its Q is strictly below the coast Q. */
+static choice search_scan_golden(const qfun *f, int n_scan, int n_golden) {
+  real *qs = (real *)calloc((size_t)(n_scan > 0 ? n_scan : 1), sizeof(real));
+  int s_best = 0;
+  for (int s = 0; s < n_scan; s++) {
+    real u = (real)(-OR_PI + 2.0 * OR_PI * (double)s / (double)n_scan);
+    qs[s] = qeval(f, 1, u);
+    if (qs[s] < qs[s_best]) s_best = s;
+  }
+  real best_q = qs[s_best];
+  real best_u = (real)(-OR_PI + 2.0 * OR_PI * (double)s_best / (double)n_scan);
+
+  /* runner-up basin: best other local minimum of the cyclic scan at distance >= 2 */
+  real basin_gap = INFINITY;
+  for (int s = 0; s < n_scan; s++) {
+    int d = abs(s - s_best);
+    if (n_scan - d < d) d = n_scan - d;
+    if (d < 2) continue;
+    real ql = qs[(s + n_scan - 1) % n_scan], qr = qs[(s + 1) % n_scan];
+    if (qs[s] <= ql && qs[s] <= qr && qs[s] - best_q < basin_gap) basin_gap = qs[s] - best_q;
+  }
+  free(qs);
+
+  if (n_golden > 0) {
+    const real rho = (real)((sqrt(5.0) - 1.0) / 2.0);
+    real half = (real)(2.0 * OR_PI / (double)n_scan);
+    real a = best_u - half, b = best_u + half;
+    real x1 = b - rho * (b - a), x2 = a + rho * (b - a);
+    real f1 = qeval(f, 1, x1);
+    if (f1 < best_q) { best_q = f1; best_u = x1; }
+    real f2 = qeval(f, 1, x2);
+    if (f2 < best_q) { best_q = f2; best_u = x2; }
+    for (int it = 0; it < n_golden; it++) {
+      if (f1 < f2) {
+        b = x2; x2 = x1; f2 = f1;
+        x1 = b - rho * (b - a);
+        f1 = qeval(f, 1, x1);
+        if (f1 < best_q) { best_q = f1; best_u = x1; }
+      } else {
+        a = x1; x1 = x2; f1 = f2;
+        x2 = a + rho * (b - a);
+        f2 = qeval(f, 1, x2);
+        if (f2 < best_q) { best_q = f2; best_u = x2; }
+      }
+    }
+  }
+
+  real q_coast = qeval(f, 0, 0);
+  choice c;
+  c.angle = wrap_angle(best_u);
+  c.thr = best_q < q_coast;
+  c.q = c.thr ? best_q : q_coast;
+  c.margin = fabs(best_q - q_coast);
+  if (basin_gap < c.margin) c.margin = basin_gap;
+  return c;
+}
+
+static choice search(const qfun *f, const or_search *sr) {
+  if (sr->mode == 0) return search_table(f, sr->n_angles);
+  return search_scan_golden(f, sr->n_scan, sr->n_golden);
+}
+
+/* ------------------------------------------------------------- sweeps */
+/* Relative residual used by the device stop rule:
+ * max_j |Vn_j - Vo_j| / max(1, |Vn_j|) and sum_j |Vn_j - Vo_j|, over free nodes. */
+void or_residual(int64_t N, const uint8_t *kind, const real *Vo, const real *Vn, double out[3]) {
+  double mx_rel = 0, sum = 0, mx_abs = 0;
+  for (int64_t j = 0; j < N; j++) {
+    if (kind[j] != KIND_FREE) continue;
+    double d = fabs((double)Vn[j] - (double)Vo[j]);
+    double den = fabs((double)Vn[j]);
+    if (den < 1.0) den = 1.0;
+    if (d / den > mx_rel) mx_rel = d / den;
+    if (d > mx_abs) mx_abs = d;
+    sum += d;
+  }
+  out[0] = mx_rel;
+  out[1] = sum;
+  out[2] = mx_abs;
+}
+
+/* One Jacobi Bellman sweep with full search.  Fixed nodes are copied.
+ * pol_ang / pol_thr / margin may be NULL. */
+void or_bellman_sweep(const or_problem *p, const uint8_t *kind, const or_search *sr,
+                      const real *Vin, real *Vout, real *pol_ang, uint8_t *pol_thr, real *margin) {
+  int64_t N = n_total(p);
+  for (int64_t j = 0; j < N; j++) {
+    if (kind[j] != KIND_FREE) {
+      Vout[j] = Vin[j];
+      if (pol_ang) pol_ang[j] = 0;
+      if (pol_thr) pol_thr[j] = 0;
+      if (margin) margin[j] = INFINITY;
+      continue;
+    }
+    int i[4];
+    node_index(p, j, i);
+    qfun f = {p, Vin, i, NULL, (real)p->dt};
+    choice c = search(&f, sr);
+    Vout[j] = c.q;
+    if (pol_ang) pol_ang[j] = c.angle;
+    if (pol_thr) pol_thr[j] = (uint8_t)c.thr;
+    if (margin) margin[j] = c.margin;
+  }
+}
+
+/* Bellman operator at a list of nodes only (sampled checks on large grids). */
+void or_bellman_nodes(const or_problem *p, const uint8_t *kind_at_nodes, const or_search *sr,
+                      const real *Vin, const int64_t *nodes, int64_t count,
+                      real *Vout, real *pol_ang, uint8_t *pol_thr, real *margin) {
+  for (int64_t c = 0; c < count; c++) {
+    int64_t j = nodes[c];
+    if (kind_at_nodes[c] != KIND_FREE) {
+      Vout[c] = Vin[j];
+      pol_ang[c] = 0;
+      pol_thr[c] = 0;
+      margin[c] = INFINITY;
+      continue;
+    }
+    int i[4];
+    node_index(p, j, i);
+    qfun f = {p, Vin, i, NULL, (real)p->dt};
+    choice ch = search(&f, sr);
+    Vout[c] = ch.q;
+    pol_ang[c] = ch.angle;
+    pol_thr[c] = (uint8_t)ch.thr;
+    margin[c] = ch.margin;
+  }
+}
+
+/* One frozen-policy sweep (eq:p_eval applied once). */
+void or_policy_eval_sweep(const or_problem *p, const uint8_t *kind, const real *Vin, real *Vout,
+                          const real *pol_ang, const uint8_t *pol_thr) {
+  int64_t N = n_total(p);
+  for (int64_t j = 0; j < N; j++) {
+    if (kind[j] != KIND_FREE) { Vout[j] = Vin[j]; continue; }
+    int i[4];
+    node_index(p, j, i);
+    Vout[j] = q_node(p, Vin, i, pol_thr[j], pol_ang[j], (real)p->dt);
+  }
+}
+
+/* ------------------------------------------------------------- solvers */
+/* Value iteration: V <- T V until max_j |dV_j| < tol_abs (FP64 rule) or, if
+ * tol_abs <= 0, until the relative residual is below tol_rel.
+ * Returns sweeps done (negative if max_sweeps was hit). */
+int64_t or_solve_vi(const or_problem *p, const uint8_t *kind, const or_search *sr, real *V,
+                    real *pol_ang, uint8_t *pol_thr, double tol_abs, double tol_rel,
+                    int64_t max_sweeps, double *last_resid) {
+  int64_t N = n_total(p);
+  real *W = (real *)malloc(sizeof(real) * (size_t)N);
+  int64_t k;
+  double res[3] = {0, 0, 0};
+  int done = 0;
+  for (k = 1; k <= max_sweeps; k++) {
+    or_bellman_sweep(p, kind, sr, V, W, pol_ang, pol_thr, NULL);
+    or_residual(N, kind, V, W, res);
+    memcpy(V, W, sizeof(real) * (size_t)N);
+    if (tol_abs > 0 ? res[2] < tol_abs : res[0] < tol_rel) { done = 1; break; }
+  }
+  free(W);
+  if (last_resid) { last_resid[0] = res[0]; last_resid[1] = res[1]; last_resid[2] = res[2]; }
+  return done ? k : -max_sweeps;
+}
+
+/* Modified policy iteration: greedy step (eq:p_impr together with T V);
+ * stop if its residual is below tolerance; otherwise eval_sweeps frozen-policy
+ * sweeps (eq:p_eval solved approximately); repeat.  eval_sweeps < 0 means
+ * "evaluate until the frozen-policy sweep changes V by less than tol/10". */
+int64_t or_solve_pi(const or_problem *p, const uint8_t *kind, const or_search *sr, real *V,
+                    real *pol_ang, uint8_t *pol_thr, double tol_abs, double tol_rel,
+                    int32_t eval_sweeps, int64_t max_outer, double *last_resid,
+                    int64_t *total_eval_sweeps) {
+  int64_t N = n_total(p);
+  real *W = (real *)malloc(sizeof(real) * (size_t)N);
+  double res[3] = {0, 0, 0};
+  int64_t it, evals = 0;
+  int done = 0;
+  for (it = 1; it <= max_outer; it++) {
+    or_bellman_sweep(p, kind, sr, V, W, pol_ang, pol_thr, NULL);
+    or_residual(N, kind, V, W, res);
+    memcpy(V, W, sizeof(real) * (size_t)N);
+    if (tol_abs > 0 ? res[2] < tol_abs : res[0] < tol_rel) { done = 1; break; }
+    if (eval_sweeps >= 0) {
+      for (int e = 0; e < eval_sweeps; e++) {
+        or_policy_eval_sweep(p, kind, V, W, pol_ang, pol_thr);
+        memcpy(V, W, sizeof(real) * (size_t)N);
+        evals++;
+      }
+    } else {
+      double inner_tol = (tol_abs > 0 ? tol_abs : tol_rel) * 0.1;
+      for (int64_t e = 0; e < 1000000; e++) {
+        double r2[3];
+        or_policy_eval_sweep(p, kind, V, W, pol_ang, pol_thr);
+        or_residual(N, kind, V, W, r2);
+        memcpy(V, W, sizeof(real) * (size_t)N);
+        evals++;
+        if ((tol_abs > 0 ? r2[2] : r2[0]) < inner_tol) break;
+      }
+    }
+  }
+  free(W);
+  if (last_resid) { last_resid[0] = res[0]; last_resid[1] = res[1]; last_resid[2] = res[2]; }
+  if (total_eval_sweeps) *total_eval_sweeps = evals;
+  return done ? it : -max_outer;
+}
+
+/* ------------------------------------------------------------- feedback */
+/* Approximate optimal feedback eq:feed at arbitrary states y (count x 4),
+ * with time step tau and the same search as the solver. */
+void or_feedback(const or_problem *p, const or_search *sr, const real *V, const double *states,
+                 int64_t count, double tau, real *angle_out, uint8_t *thr_out, real *q_out) {
+  for (int64_t c = 0; c < count; c++) {
+    real y[4];
+    for (int k = 0; k < 4; k++) y[k] = (real)states[4 * c + k];
+    qfun f = {p, V, NULL, y, (real)tau};
+    choice ch = search(&f, sr);
+    angle_out[c] = ch.angle;
+    thr_out[c] = (uint8_t)ch.thr;
+    if (q_out) q_out[c] = ch.q;
+  }
+}
+
+/* Brute force for tests: min over n angles u = -pi + 2*pi*k/n of the thrust Q. */
+real or_brute_thrust_min(const or_problem *p, const real *V, int64_t j, int64_t n, real *u_best) {
+  int i[4];
+  node_index(p, j, i);
+  real best = INFINITY, bu = 0;
+  for (int64_t k = 0; k < n; k++) {
+    real u = (real)(-OR_PI + 2.0 * OR_PI * (double)k / (double)n);
+    real q = q_node(p, V, i, 1, u, (real)p->dt);
+    if (q < best) { best = q; bu = u; }
+  }
+  if (u_best) *u_best = bu;
+  return best;
+}
+
+/* --------------------------------------------------------- reduced grid */
+/* Reachability mask of a fine grid from a coarse solution: a fine node is
+ * kept where the coarse value, interpolated at the node, is below `thresh`;
+ * the kept set is then dilated by dil[k] cells along each axis (box
+ * dilation).  Coarse and fine problems must share the domain box. */
+void or_mask_from_coarse(const or_problem *pc, const real *Vc, const or_problem *pf,
+                         double thresh, const int32_t dil[4], uint8_t *mask) {
+  int64_t N = n_total(pf);
+  uint8_t *seed = (uint8_t *)malloc((size_t)N);
+  for (int64_t j = 0; j < N; j++) {
+    int i[4];
+    node_index(pf, j, i);
+    double x[4];
+    for (int k = 0; k < 4; k++) x[k] = pf->lo[k] + i[k] * step(pf, k);
+    seed[j] = or_value_at(pc, Vc, x) < thresh;
+  }
+  for (int64_t j = 0; j < N; j++) {
+    int i[4];
+    node_index(pf, j, i);
+    int keep = 0;
+    int lo[4], hi[4];
+    for (int k = 0; k < 4; k++) {
+      lo[k] = i[k] - dil[k] < 0 ? 0 : i[k] - dil[k];
+      hi[k] = i[k] + dil[k] > pf->n[k] - 1 ? pf->n[k] - 1 : i[k] + dil[k];
+    }
+    int q[4];
+    for (q[3] = lo[3]; q[3] <= hi[3] && !keep; q[3]++)
+      for (q[2] = lo[2]; q[2] <= hi[2] && !keep; q[2]++)
+        for (q[1] = lo[1]; q[1] <= hi[1] && !keep; q[1]++)
+          for (q[0] = lo[0]; q[0] <= hi[0] && !keep; q[0]++)
+            if (seed[flat_index(pf, q)]) keep = 1;
+    mask[j] = (uint8_t)keep;
+  }
+  free(seed);
+}
+
+int32_t or_real_size(void) { return (int32_t)sizeof(real); }

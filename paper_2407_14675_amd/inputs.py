@@ -1,0 +1,190 @@
+"""Workload definitions and seeded input generators.
+
+This module is shared by the device path and by the CPU oracle, so it holds
+numbers and random draws only: grid extents, physical constants, search sizes
+and seeded fields.  It contains none of the method's arithmetic (no dynamics,
+no interpolation, no target snapping, no Bellman operator).
+
+Every workload is the nondimensional planar orbit-transfer problem
+(mu = 1, r0 = 1) in the state (r, v_r, v_t, m); the paper's own Example 1
+(Section 4) uses a different instance and is not one of these workloads.
+"""
+from __future__ import annotations
+
+import copy
+import math
+
+import numpy as np
+
+INF = float("inf")
+
+# Axis order of every state tuple and of every grid: (r, v_r, v_t, m).
+AXES = ("r", "v_r", "v_t", "m")
+
+# Domain of the orbit-transfer workloads.
+ORBIT_LO = (0.98, -0.05, 0.93, 0.90)
+ORBIT_HI = (1.08, 0.05, 1.02, 1.00)
+
+# Target box half-widths in (r, v_r, v_t); mass is unconstrained.
+TARGET_HALF_WIDTH = (0.005, 0.003, 0.003, INF)
+
+# Read-out point: circular orbit at r0 = 1 with full mass.
+X0 = (1.0, 0.0, 1.0, 1.0)
+
+
+def orbit_problem(n, *, target_radius=1.05, accel=1e-3, mdot=1e-3, dt=0.05,
+                  w_fuel=0.0, M=1e3, lam=0.0, search=None, name="orbit"):
+    """Planar orbit-transfer problem on a closed uniform grid with n[k] nodes per axis."""
+    if search is None:
+        search = dict(mode="table", n_angles=16)
+    return dict(
+        name=name,
+        model="orbit",
+        n=tuple(int(v) for v in n),
+        lo=ORBIT_LO,
+        hi=ORBIT_HI,
+        mu=1.0,
+        accel=float(accel),
+        mdot=float(mdot),
+        dt=float(dt),
+        lam=float(lam),
+        w_time=1.0,
+        w_fuel=float(w_fuel),
+        M=float(M),
+        speed=0.0,
+        tgt_c=(float(target_radius), 0.0, float(target_radius) ** -0.5, 0.0),
+        tgt_w=TARGET_HALF_WIDTH,
+        search=dict(search),
+    )
+
+
+def eikonal_problem(n_side=17, *, half=1.0, speed=1.0, n_angles=16, M=1e3, lam=0.0):
+    """2-D minimum-time problem x' = speed*(sin u, cos u) embedded in axes (v_r, v_t).
+
+    Axes r and m are dummy axes with two nodes and no motion.  With
+    dt*speed equal to the grid step, moves along the axes land on nodes.
+    """
+    h = 2.0 * half / (n_side - 1)
+    return dict(
+        name=f"eikonal_{n_side}",
+        model="eikonal",
+        n=(2, n_side, n_side, 2),
+        lo=(0.0, -half, -half, 0.0),
+        hi=(1.0, half, half, 1.0),
+        mu=0.0,
+        accel=0.0,
+        mdot=0.0,
+        dt=h / speed,
+        lam=float(lam),
+        w_time=1.0,
+        w_fuel=0.0,
+        M=float(M),
+        speed=float(speed),
+        tgt_c=(0.0, 0.0, 0.0, 0.0),
+        tgt_w=(INF, 0.0, 0.0, INF),
+        search=dict(mode="table", n_angles=n_angles),
+    )
+
+
+SCAN_GOLDEN = dict(mode="scan_golden", n_scan=64, n_golden=12)
+
+# Plain value iteration, discrete table of 16 angles plus coast, 12^4 grid.
+CONFIG0 = orbit_problem((12, 12, 12, 12), name="cfg0_vi_12^4")
+CONFIG0_TOL_ABS = 1e-8
+
+# Modified policy iteration on 48^4 with the reachability-masked active set.
+CONFIG1 = orbit_problem((48, 48, 48, 48), search=SCAN_GOLDEN, name="cfg1_pi_48^4_masked")
+CONFIG1_EVAL_SWEEPS = 20
+# Reduced grid of the 48^4 workload: a fine node is active where the 12^4
+# value, interpolated at the node, is below MASK_THRESHOLD_FRAC * M (the
+# target is reached with positive weight), dilated by MASK_DILATE cells.
+MASK_THRESHOLD_FRAC = 0.98
+MASK_DILATE = (1, 1, 1, 1)
+
+# Large single problem, 96 x 96 x 96 x 64, dt = 0.02, cost 1 + 0.1*throttle.
+def config2(accel=1e-3, n=(96, 96, 96, 64)):
+    return orbit_problem(n, accel=accel, dt=0.02, w_fuel=0.1, search=SCAN_GOLDEN,
+                         name=f"cfg2_{'x'.join(map(str, n))}_a{accel:g}")
+
+
+def config3_draws(n_prob=16, seed=3):
+    """Sixteen transfer problems: target radius, thrust level and grid side.
+
+    Problem 0 is forced to the smallest side (24) and the last to the largest (64).
+    """
+    rng = np.random.default_rng(seed)
+    radius = rng.uniform(1.02, 1.08, size=n_prob)
+    accel = rng.uniform(3e-4, 2e-3, size=n_prob)
+    side = rng.integers(24, 65, size=n_prob)
+    side[0] = 24
+    side[-1] = 64
+    return [dict(target_radius=float(radius[i]), accel=float(accel[i]), side=int(side[i]))
+            for i in range(n_prob)]
+
+
+def config3_problems(n_prob=16, seed=3, side_scale=1.0):
+    out = []
+    for i, d in enumerate(config3_draws(n_prob, seed)):
+        side = max(4, int(round(d["side"] * side_scale)))
+        out.append(orbit_problem((side,) * 4, target_radius=d["target_radius"],
+                                 accel=d["accel"], name=f"cfg3_p{i}_{side}^4"))
+    return out
+
+
+def with_grid(problem, n):
+    """Same physics on another grid."""
+    p = copy.deepcopy(problem)
+    p["n"] = tuple(int(v) for v in n)
+    p["name"] = problem["name"] + "@" + "x".join(map(str, n))
+    return p
+
+
+def n_nodes(problem):
+    n = problem["n"]
+    return int(n[0]) * int(n[1]) * int(n[2]) * int(n[3])
+
+
+# ---------------------------------------------------------------- random draws
+def random_value(problem, seed, low=0.0, high=50.0, frac_M=0.0):
+    """Random value field in C order [m][v_t][v_r][r] (float64)."""
+    rng = np.random.default_rng(seed)
+    n = problem["n"]
+    V = rng.uniform(low, high, size=(n[3], n[2], n[1], n[0]))
+    if frac_M > 0:
+        V[rng.random(V.shape) < frac_M] = problem["M"]
+    return V
+
+
+def random_states(problem, count, seed, margin=0.0):
+    """Uniform random states inside the domain box (count x 4, float64)."""
+    rng = np.random.default_rng(seed)
+    lo = np.asarray(problem["lo"], dtype=np.float64)
+    hi = np.asarray(problem["hi"], dtype=np.float64)
+    span = hi - lo
+    return lo + margin * span + rng.random((count, 4)) * span * (1.0 - 2.0 * margin)
+
+
+def random_multilinear_coeffs(seed=11):
+    """Sixteen coefficients, one per subset S of the four axes (bit k = axis k)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-1.0, 1.0, size=16)
+
+
+def random_nodes(problem, count, seed):
+    """Distinct random flat node indices."""
+    rng = np.random.default_rng(seed)
+    total = n_nodes(problem)
+    count = min(count, total)
+    return np.sort(rng.choice(total, size=count, replace=False)).astype(np.int64)
+
+
+def mlp_init(seed=4, widths=(4, 128, 128, 3)):
+    """Initial MLP parameters (uniform fan-in init), float64, as a list of (W, b)."""
+    rng = np.random.default_rng(seed)
+    params = []
+    for fan_in, fan_out in zip(widths[:-1], widths[1:]):
+        bound = 1.0 / math.sqrt(fan_in)
+        W = rng.uniform(-bound, bound, size=(fan_out, fan_in))
+        b = rng.uniform(-bound, bound, size=(fan_out,))
+        params.append((W, b))
+    return params

@@ -1,0 +1,320 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+None of these compares the oracle with itself: each checks a closed form, an
+invariant, a special case with a known answer, or brute force on a tiny input.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.core import KIND_FREE, KIND_TARGET, Oracle, mask_from_coarse
+from paper_2407_14675_amd import inputs
+
+
+def grid_coords(problem):
+    """Per-axis node coordinates of a closed uniform grid."""
+    return [np.linspace(problem["lo"][k], problem["hi"][k], problem["n"][k]) for k in range(4)]
+
+
+# --------------------------------------------------------------- T1 eikonal
+@pytest.fixture(scope="module")
+def eikonal_solution():
+    p = inputs.eikonal_problem(17)
+    o = Oracle(p)
+    res = o.solve_vi(tol_abs=1e-13, max_sweeps=2000)
+    assert res["converged"]
+    return p, o, res
+
+
+def test_eikonal_exact_on_axes(eikonal_solution):
+    """Minimum time to the origin at speed s is |x|/s.  With dt*s = h, moves
+    along an axis land exactly on nodes, so on axis nodes the discrete value
+    equals i*h/s (the Q1 interpolant of a convex function lies above it and the
+    operator is monotone, so nothing can do better)."""
+    p, o, res = eikonal_solution
+    V = res["V"]  # shape (2, 17, 17, 2): [m][v_t][v_r][r]
+    h = 2.0 / 16
+    c = 8
+    for i in range(-8, 9):
+        exact = abs(i) * h / p["speed"]
+        assert V[0, c + i, c, 0] == pytest.approx(exact, abs=1e-12)  # along axis v_t
+        assert V[0, c, c + i, 0] == pytest.approx(exact, abs=1e-12)  # along axis v_r
+        assert V[1, c, c + i, 1] == pytest.approx(exact, abs=1e-12)  # dummy axes do not matter
+
+
+def test_eikonal_lower_bound_and_accuracy(eikonal_solution):
+    """V >= |x|/s at every node; with 16 directions the discrete optimum is at
+    most |x|/(s*cos(pi/16)) plus an O(h) interpolation term."""
+    p, o, res = eikonal_solution
+    V = res["V"][0, :, :, 0]
+    x = np.linspace(-1, 1, 17)
+    dist = np.sqrt(x[:, None] ** 2 + x[None, :] ** 2)
+    assert np.all(V >= dist / p["speed"] - 1e-12)
+    inner = dist <= 0.75
+    bound = dist / (p["speed"] * math.cos(math.pi / 16)) + 2 * (2.0 / 16)
+    assert np.all(V[inner] <= bound[inner])
+
+
+def test_eikonal_feedback_points_home(eikonal_solution):
+    """On axis nodes the optimal direction is straight at the origin (eq:feed
+    with tau = dt): sin u, cos u = -sign of the coordinate."""
+    p, o, res = eikonal_solution
+    h = 2.0 / 16
+    states, want = [], []
+    for i in range(1, 8):
+        # axis v_t carries cos u, axis v_r carries sin u
+        states += [(0.0, 0.0, i * h, 0.0), (0.0, 0.0, -i * h, 0.0),
+                   (0.0, i * h, 0.0, 0.0), (0.0, -i * h, 0.0, 0.0)]
+        want += [(0.0, -1.0), (0.0, 1.0), (-1.0, 0.0), (1.0, 0.0)]
+    ang, thr, q = o.feedback(res["V"], np.array(states), tau=p["dt"])
+    assert np.all(thr == 1)
+    got = np.stack([np.sin(ang), np.cos(ang)], axis=1)
+    np.testing.assert_allclose(got, np.array(want), atol=1e-12)
+
+
+# --------------------------------------------------- T2 / T7 interpolation
+def _multilinear(coeffs, pts):
+    """sum over subsets S of the axes of c_S * prod_{k in S} x_k."""
+    out = np.zeros(len(pts))
+    for S in range(16):
+        term = np.full(len(pts), coeffs[S])
+        for k in range(4):
+            if (S >> k) & 1:
+                term = term * pts[:, k]
+        out += term
+    return out
+
+
+def test_interp_reproduces_multilinear_functions():
+    """Q1 interpolation is exact on span{prod_{k in S} x_k} (any subset S)."""
+    p = inputs.orbit_problem((5, 6, 7, 4))
+    o = Oracle(p)
+    coeffs = inputs.random_multilinear_coeffs(11)
+    ax = grid_coords(p)
+    mesh = np.stack(np.meshgrid(ax[0], ax[1], ax[2], ax[3], indexing="ij"), axis=-1).reshape(-1, 4)
+    vals = _multilinear(coeffs, mesh).reshape(5, 6, 7, 4).transpose(3, 2, 1, 0)  # to [m][vt][vr][r]
+    pts = inputs.random_states(p, 2000, seed=12)
+    lo = np.array(p["lo"])
+    h = (np.array(p["hi"]) - lo) / (np.array(p["n"]) - 1)
+    want = _multilinear(coeffs, pts)
+    got = np.array([o.interp(vals, (x - lo) / h) for x in pts])
+    np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-12)
+    got_phys = np.array([o.value_at(vals, x) for x in pts[:200]])
+    np.testing.assert_allclose(got_phys, want[:200], rtol=1e-12, atol=1e-12)
+    # nodes, faces and corners of the closed box are inside
+    corners = np.array([[lo[k] if (c >> k) & 1 == 0 else p["hi"][k] for k in range(4)]
+                        for c in range(16)])
+    got_c = np.array([o.value_at(vals, x) for x in corners])
+    np.testing.assert_allclose(got_c, _multilinear(coeffs, corners), rtol=1e-12, atol=1e-12)
+
+
+def test_interp_outside_is_penalty():
+    p = inputs.orbit_problem((5, 6, 7, 4))
+    o = Oracle(p)
+    V = np.zeros((4, 7, 6, 5))
+    for k in range(4):
+        s = np.array([1.0, 1.0, 1.0, 1.0])
+        s[k] = -1e-9
+        assert o.interp(V, s) == p["M"]
+        s[k] = p["n"][k] - 1 + 1e-9
+        assert o.interp(V, s) == p["M"]
+        s[k] = p["n"][k] - 1
+        assert o.interp(V, s) == 0.0
+
+
+def test_interp_weights_convex_and_local():
+    """Weights are >= 0, sum to 1 and sit on the 16 corners of the cell."""
+    p = inputs.orbit_problem((5, 6, 7, 4))
+    o = Oracle(p)
+    rng = np.random.default_rng(13)
+    n = np.array(p["n"])
+    for _ in range(500):
+        s = rng.random(4) * (n - 1)
+        ok, idx, w = o.interp_weights(s)
+        assert ok
+        assert np.all(w >= 0) and abs(w.sum() - 1) < 1e-14
+        base = np.minimum(np.floor(s).astype(int), n - 2)
+        strides = np.array([1, n[0], n[0] * n[1], n[0] * n[1] * n[2]])
+        expect = sorted(int(((base + np.array([(c >> k) & 1 for k in range(4)])) * strides).sum())
+                        for c in range(16))
+        assert sorted(idx.tolist()) == expect
+
+
+# --------------------------------------------------- T3 dynamics invariants
+def _energy(x):
+    return 0.5 * (x[1] ** 2 + x[2] ** 2) - 1.0 / x[0]
+
+
+def test_coast_step_conservation_defects():
+    """Angular momentum h = r v_t and energy E = (v_r^2 + v_t^2)/2 - 1/r are
+    conserved by the exact coast flow; one Euler step changes them by
+        dh = -dt^2 v_r^2 v_t / r
+        dE = dt^2 (A^2 + B^2)/2 - dt^2 v_r^2 / (r^2 (r + dt v_r)),
+    A = v_t^2/r - 1/r^2, B = -v_r v_t/r (mu = 1).  A wrong sign of the
+    centrifugal term leaves a first-order drift in E and fails this."""
+    p = inputs.CONFIG0
+    o = Oracle(p)
+    dt = p["dt"]
+    for x in inputs.random_states(p, 300, seed=21):
+        z = o.step(x, 0, 0.0)
+        r, vr, vt, m = x
+        A = vt * vt / r - 1.0 / (r * r)
+        B = -vr * vt / r
+        dh = z[0] * z[2] - r * vt
+        dE = _energy(z) - _energy(x)
+        assert dh == pytest.approx(-dt * dt * vr * vr * vt / r, rel=1e-6, abs=5e-15)
+        want = dt * dt * (A * A + B * B) / 2 - dt * dt * vr * vr / (r * r * (r + dt * vr))
+        assert dE == pytest.approx(want, rel=1e-6, abs=5e-15)
+        assert z[3] == m
+
+
+def test_thrust_step_torque_and_power():
+    """Thrust (radial share sin u, tangential share cos u, magnitude a/m)
+    adds to the coast step exactly: h gains (r + dt v_r) dt F_t (torque), E
+    gains dt F_r (v_r + dt A) + dt F_t (v_t + dt B) + dt^2 |F|^2/2 (work),
+    and mass drops by c dt."""
+    p = inputs.CONFIG0
+    o = Oracle(p)
+    dt, a, c = p["dt"], p["accel"], p["mdot"]
+    rng = np.random.default_rng(22)
+    for x in inputs.random_states(p, 300, seed=23):
+        u = rng.uniform(-math.pi, math.pi)
+        zc = o.step(x, 0, 0.0)
+        zt = o.step(x, 1, u)
+        r, vr, vt, m = x
+        Fr, Ft = a / m * math.sin(u), a / m * math.cos(u)
+        A = vt * vt / r - 1.0 / (r * r)
+        B = -vr * vt / r
+        dh = zt[0] * zt[2] - zc[0] * zc[2]
+        assert dh == pytest.approx((r + dt * vr) * dt * Ft, rel=1e-6, abs=5e-15)
+        dE = _energy(zt) - _energy(zc)
+        want = dt * Fr * (vr + dt * A) + dt * Ft * (vt + dt * B) + dt * dt * (Fr * Fr + Ft * Ft) / 2
+        assert dE == pytest.approx(want, rel=1e-6, abs=5e-15)
+        assert zt[3] == pytest.approx(m - c * dt, abs=1e-15)
+        assert zt[0] == zc[0]
+
+
+# ------------------------------------------------- fixed sets (target snapping)
+@pytest.mark.parametrize("n,count", [(12, 96), (48, 4800)])
+def test_target_node_counts(n, count):
+    """Target box snapped by half a cell: per axis the nodes within w + h/2 of
+    the centre.  By hand: at 12^4 two nodes in each of r, v_r, v_t (r: 1.04364,
+    1.05273; v_r: +-0.004545; v_t: 0.97091, 0.97909) times 12 mass planes = 96;
+    at 48^4, 5 x 4 x 5 x 48 = 4800."""
+    o = Oracle(inputs.with_grid(inputs.CONFIG0, (n,) * 4)) if n != 12 else Oracle(inputs.CONFIG0)
+    assert int((o.kind == KIND_TARGET).sum()) == count
+
+
+# ---------------------------------------------- T6 monotone and contraction
+def test_operator_monotone_and_contraction():
+    """V <= W implies T V <= T W (convex interpolation); with discount lambda > 0
+    the operator contracts by exp(-lambda dt) in the sup norm."""
+    p = inputs.orbit_problem((6, 6, 6, 6), lam=0.7)
+    o = Oracle(p)
+    rng = np.random.default_rng(31)
+    for trial in range(3):
+        V = inputs.random_value(p, seed=100 + trial)
+        W = V + rng.uniform(0, 3.0, size=V.shape)
+        TV = o.bellman_sweep(V)[0]
+        TW = o.bellman_sweep(W)[0]
+        free = o.kind == KIND_FREE
+        assert np.all(TV[free] <= TW[free] + 1e-12)
+        gap = np.max(np.abs(TV - TW)[free])
+        assert gap <= math.exp(-p["lam"] * p["dt"]) * np.max(np.abs(V - W)) + 1e-12
+
+
+# ---------------------------------------------------- T4 VI and PI agree
+def test_vi_and_pi_reach_the_same_fixed_point():
+    """Value iteration and policy iteration solve the same fixed-point problem
+    (the scheme is a contraction / monotone SSP), so they agree."""
+    p = inputs.with_grid(inputs.CONFIG0, (6, 6, 6, 6))
+    o = Oracle(p)
+    vi = o.solve_vi(tol_abs=1e-11, max_sweeps=200000)
+    pi20 = o.solve_pi(tol_abs=1e-11, eval_sweeps=20)
+    pix = o.solve_pi(tol_abs=1e-11, eval_sweeps=-1)
+    assert vi["converged"] and pi20["converged"] and pix["converged"]
+    scale = np.maximum(np.abs(vi["V"]), 1.0)
+    assert np.max(np.abs(vi["V"] - pi20["V"]) / scale) < 1e-9
+    assert np.max(np.abs(vi["V"] - pix["V"]) / scale) < 1e-9
+    # exact-evaluation PI needs far fewer greedy steps than VI needs sweeps
+    assert pix["outer"] < vi["sweeps"] / 5
+
+
+# ------------------------------------------------ T5 search vs brute force
+def test_golden_search_matches_brute_force():
+    """Scan of 64 + golden refinement reaches the minimum of Q over a
+    2^14-angle enumeration on a smooth value field."""
+    p = inputs.orbit_problem((6, 6, 6, 6), search=inputs.SCAN_GOLDEN, accel=2e-2)
+    o = Oracle(p)
+    ax = grid_coords(p)
+    R, VR, VT, MM = np.meshgrid(ax[0], ax[1], ax[2], ax[3], indexing="ij")
+    V = (200 * (R - 1.05) ** 2 + 300 * VR ** 2 + 500 * (VT - 0.976) ** 2 + 10 * (1 - MM))
+    V = V.transpose(3, 2, 1, 0).copy()
+    Vs, ang, thr, margin = o.bellman_sweep(V)
+    free = np.flatnonzero(o.kind.reshape(-1) == KIND_FREE)
+    bad = 0
+    for j in free:
+        qb, ub = o.brute_thrust_min(V, j, 1 << 14)
+        qg = o.q(V, j, 1, ang.reshape(-1)[j])
+        if qg - qb > 1e-6 * max(1.0, abs(qb)):
+            bad += 1
+    assert bad <= 0.01 * len(free)
+
+
+def test_table_search_is_exhaustive_first_minimum():
+    """Discrete table: the result is the first minimum over (coast, u_0..u_K-1),
+    coast winning exact ties."""
+    p = inputs.with_grid(inputs.CONFIG0, (5, 5, 5, 5))
+    o = Oracle(p)
+    V = inputs.random_value(p, seed=41)
+    Vs, ang, thr, margin = o.bellman_sweep(V)
+    K = p["search"]["n_angles"]
+    for j in np.flatnonzero(o.kind.reshape(-1) == KIND_FREE)[:200]:
+        qs = [o.q(V, j, 0, 0.0)] + [o.q(V, j, 1, -math.pi + 2 * math.pi * k / K) for k in range(K)]
+        best = int(np.argmin(qs))
+        assert Vs.reshape(-1)[j] == qs[best]
+        assert thr.reshape(-1)[j] == (1 if best > 0 else 0)
+
+
+# ------------------------------------------------------------- residual
+def test_residual_known_values():
+    p = inputs.with_grid(inputs.CONFIG0, (4, 4, 4, 4))
+    o = Oracle(p)
+    Vo = np.full(o.shape, 10.0)
+    Vn = Vo.copy()
+    free = np.argwhere(o.kind == KIND_FREE)
+    a, b = tuple(free[0]), tuple(free[1])
+    Vn[a] = 12.5          # |dV| = 2.5, relative to max(1, 12.5)
+    Vn[b] = 0.25          # |dV| = 9.75, relative to max(1, 0.25) = 1
+    r = o.residual(Vo, Vn)
+    assert r["max_rel"] == 9.75 and r["max_abs"] == 9.75 and r["sum_abs"] == 12.25
+
+
+# ---------------------------------------------------------------- mask
+def test_mask_dilation_box_counts():
+    """A single reachable coarse node on an identical fine grid dilates to a
+    (2d+1)^4 box clipped at the borders."""
+    p = inputs.with_grid(inputs.CONFIG0, (7, 7, 7, 7))
+    Vc = np.full((7, 7, 7, 7), p["M"])
+    Vc[3, 3, 3, 3] = 0.0
+    m = mask_from_coarse(p, Vc, p, (1, 1, 1, 1))
+    assert int(m.sum()) == 3 ** 4
+    Vc2 = np.full((7, 7, 7, 7), p["M"])
+    Vc2[0, 6, 0, 6] = 1.0
+    m2 = mask_from_coarse(p, Vc2, p, (2, 1, 2, 1))
+    assert int(m2.sum()) == 3 * 2 * 3 * 2  # (clipped 2+1) x (1+1) per axis
+    assert int(mask_from_coarse(p, Vc, p, (0, 0, 0, 0)).sum()) == 1
+
+
+# ------------------------------------------------------- T10 FP32 floor
+def test_float_build_precision_floor():
+    """The same scheme run in single precision stays within the 1e-4 relative
+    budget of the double result, so a float device path can meet it."""
+    p = inputs.with_grid(inputs.CONFIG0, (6, 6, 6, 6))
+    o64 = Oracle(p)
+    o32 = Oracle(p, precision="f32")
+    v64 = o64.solve_vi(tol_abs=1e-9, max_sweeps=50000)["V"]
+    r32 = o32.solve_vi(tol_abs=0.0, tol_rel=1e-7, max_sweeps=50000)
+    err = np.abs(r32["V"].astype(np.float64) - v64) / np.maximum(np.abs(v64), 1.0)
+    assert err.max() < 1e-4
