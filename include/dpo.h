@@ -1,0 +1,234 @@
+/*
+ * dpo.h — C ABI of libdpo.so, the MI355X (gfx950) semi-Lagrangian dynamic
+ * programming library for planar low-thrust orbit transfer.
+ *
+ * Method: "Dynamic Programming Techniques for Planar Orbital Transfer of LEO
+ * Satellites" (arXiv 2407.14675), Section 3.  The library computes the fixed
+ * point of the semi-Lagrangian scheme eq:schema
+ *
+ *     v_j = min_f { dt*l(x_j,f) + exp(-lambda*dt) * I[V](x_j + dt*Phi(x_j,f)) }
+ *
+ * on a closed uniform 4-D grid, with I[V] the Q1 (multilinear) interpolation
+ * and I[V](z) = M for feet outside the domain (state-constraint penalty,
+ * paragraph "Grid and polar coordinates"), by value iteration and by policy
+ * iteration (eq:p_eval, eq:p_impr), and evaluates the feedback eq:feed.
+ *
+ * Conventions (all entry points):
+ *  - Every function returns int: DPO_OK (0), DPO_ENOCONV (1, output valid but
+ *    the stop rule was not met), or a negative error.  Nothing aborts or
+ *    throws across the ABI.  dpo_last_error() gives the message.
+ *  - Array arguments are DEVICE pointers unless marked "host".  They are owned
+ *    by the caller, must be contiguous and must stay valid until the work
+ *    queued on `stream` has finished.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Sweeps are asynchronous on it; solvers synchronise it at residual checks.
+ *  - Node arrays have N = n[0]*n[1]*n[2]*n[3] entries in C order
+ *    [m][v_t][v_r][r]: axis 0 (r) fastest, axis 3 (m) slowest.
+ *  - Value functions are float32; residuals and read-outs are float64.
+ *  - One context must not be used from two threads at once.
+ */
+#ifndef DPO_H
+#define DPO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DPO_OK = 0,
+  DPO_ENOCONV = 1,   /* max sweeps / iterations reached; outputs hold the last iterate */
+  DPO_EINVAL = -1,   /* invalid argument (null pointer, bad size, bad grid or search) */
+  DPO_ENOMEM = -2,   /* device allocation failed */
+  DPO_EHIP = -3,     /* a HIP runtime call failed */
+  DPO_ENUMERIC = -4  /* a sweep produced a non-finite value */
+};
+
+enum { DPO_MODEL_ORBIT = 0, DPO_MODEL_EIKONAL = 1 };
+
+enum {
+  DPO_SEARCH_TABLE = 0,       /* coast + n_angles tabulated thrust angles (exhaustive) */
+  DPO_SEARCH_SCAN_GOLDEN = 1, /* scan of n_scan angles, n_golden golden-section steps */
+  DPO_SEARCH_SEEDED = 2       /* local golden search around a per-node seed angle */
+};
+
+/* Node kinds reported by dpo_get_kind(). */
+enum { DPO_KIND_FREE = 0, DPO_KIND_TARGET = 1, DPO_KIND_INACTIVE = 2 };
+
+/* Closed uniform grid (paper Section 3, "Grid and polar coordinates"):
+ * node i_k of axis k sits at lo[k] + i_k*(hi[k]-lo[k])/(n[k]-1).  Axis order
+ * (r, v_r, v_t, m).  Requires n[k] >= 2 and lo[k] < hi[k]. */
+typedef struct {
+  int32_t n[4];
+  double lo[4], hi[4];
+} dpo_grid;
+
+/* Problem (paper Section 2 and the polar system of Section 3):
+ *  model ORBIT:   r' = v_r, v_r' = v_t^2/r - mu/r^2 + thr*(accel/m)*sin u,
+ *                 v_t' = -v_r*v_t/r + thr*(accel/m)*cos u, m' = -mdot*thr;
+ *  model EIKONAL: v_r' = thr*speed*sin u, v_t' = thr*speed*cos u (r, m fixed).
+ *  Foot point: one explicit Euler step of length dt.
+ *  Running cost l = w_time + w_fuel*thr; discount exp(-lambda*dt) (eq:cost).
+ *  M: value of I[V] outside the domain and at inactive nodes.
+ *  Target: nodes with |x_k - tgt_c[k]| <= tgt_w[k] + h_k/2 on every axis get
+ *  V = 0 (use a huge tgt_w[k] for an unconstrained axis). */
+typedef struct {
+  int32_t model;
+  double mu, accel, mdot, dt, lambda, w_time, w_fuel, M, speed;
+  double tgt_c[4], tgt_w[4];
+} dpo_problem;
+
+/* Minimisation over the control set (paper Section 3, "Efficient computation
+ * of the minimum"): tabulation, then golden-section refinement.
+ *  TABLE:       controls = coast, u_k = -pi + 2*pi*k/n_angles (k < n_angles);
+ *               first minimum in that order wins, coast wins exact ties.
+ *  SCAN_GOLDEN: scan u_s = -pi + 2*pi*s/n_scan, then golden section with ratio
+ *               (sqrt5-1)/2 on [u_s* - 2*pi/n_scan, u_s* + 2*pi/n_scan]: two
+ *               interior evaluations then one per step (n_golden steps); the
+ *               best evaluated angle is the thrust candidate; thrust is chosen
+ *               iff its Q is strictly below the coast Q.
+ *  SEEDED:      golden section on [seed - local_half_width, seed + local_half_width]
+ *               with n_local evaluations in total, then coast; a node whose best
+ *               Q differs from its current value by more than
+ *               fallback_tol*max(1,|V|) repeats the SCAN_GOLDEN search.
+ *  Limits: 1 <= n_angles <= 1024; 8 <= n_scan <= 1024; 0 <= n_golden <= 64. */
+typedef struct {
+  int32_t mode, n_angles, n_scan, n_golden, n_local;
+  double local_half_width, fallback_tol;
+} dpo_search;
+
+/* Solver statistics (all counts since the call started). */
+typedef struct {
+  int64_t sweeps;         /* Bellman sweeps with full search (VI sweeps or PI greedy steps) */
+  int64_t eval_sweeps;    /* frozen-policy sweeps */
+  int64_t evals;          /* node-control Q evaluations */
+  int64_t fallback_nodes; /* SEEDED: nodes that repeated the full search */
+  double resid_max_rel;   /* last max |dV|/max(1,|V|) over free nodes (FP64) */
+  double resid_sum_abs;   /* last sum |dV| (FP64) */
+  double resid_max_abs;   /* last max |dV| (FP64) */
+  double seconds;         /* wall time from the first launch to the stop decision */
+  int32_t stalled;        /* 1 if stopped because the residual stopped decreasing */
+  int32_t converged;      /* 1 if the stop rule was met */
+} dpo_stats;
+
+typedef struct dpo_ctx dpo_ctx;
+
+/* ---------------------------------------------------------------- set-up */
+
+/* Create a context: copies *grid, *prob and *search; classifies every node
+ * (target / inactive / free) on the device in FP64 and compacts the free
+ * nodes into an index list (the reduced grid of Section 3).  active_mask is a
+ * DEVICE u8[N] (nonzero = active) or NULL for "all nodes active".  Runs on
+ * the null stream and synchronises.  *out is NULL on error. */
+int dpo_create(const dpo_grid* grid, const dpo_problem* prob, const dpo_search* search,
+               const uint8_t* active_mask, dpo_ctx** out);
+
+/* Destroy a context and free its device scratch.  NULL is ignored. */
+void dpo_destroy(dpo_ctx* ctx);
+
+/* Message of the last error on ctx, or of the calling thread when ctx is NULL. */
+const char* dpo_last_error(const dpo_ctx* ctx);
+
+/* Sizes: total nodes N and free (swept) nodes. */
+int dpo_sizes(const dpo_ctx* ctx, int64_t* n_nodes, int64_t* n_free);
+
+/* Copy the node kinds (DPO_KIND_*) into a device u8[N]. */
+int dpo_get_kind(dpo_ctx* ctx, uint8_t* kind, void* stream);
+
+/* Replace the search settings (same rules as in dpo_create). */
+int dpo_set_search(dpo_ctx* ctx, const dpo_search* search);
+
+/* V := 0 at target nodes, M elsewhere (the initial guess of value iteration
+ * and the fixed values every sweep relies on).  V is a device float[N]. */
+int dpo_init_value(dpo_ctx* ctx, float* V, void* stream);
+
+/* ---------------------------------------------------------------- sweeps */
+
+/* One Jacobi Bellman sweep with full search (eq:schema / eq:p_impr):
+ * for every free node writes V_out, the best thrust angle pol_angle (radians
+ * in [-pi, pi)) and pol_thr (1 = thrust).  Target and inactive nodes are not
+ * written: V_out must already hold their fixed values (dpo_init_value or a
+ * copy of V_in).  V_in and V_out must not overlap.  If resid is not NULL it
+ * receives (device double[5]) max|dV|/max(1,|V_out|), sum|dV|, max|dV|, the
+ * count of non-finite outputs and the count of seeded-search fallbacks,
+ * accumulated over the free nodes in FP64 in a fixed order.  pol_angle /
+ * pol_thr may be NULL.  SEEDED mode needs dpo_bellman_sweep_seeded instead. */
+int dpo_bellman_sweep(dpo_ctx* ctx, const float* V_in, float* V_out, float* pol_angle,
+                      uint8_t* pol_thr, double* resid, void* stream);
+
+/* SEEDED sweep: seed_angle is a device float[N] of proposed thrust angles.
+ * Nodes failing the fallback test repeat the SCAN_GOLDEN search; their count
+ * is resid[4]. */
+int dpo_bellman_sweep_seeded(dpo_ctx* ctx, const float* V_in, float* V_out, float* pol_angle,
+                             uint8_t* pol_thr, const float* seed_angle, double* resid,
+                             void* stream);
+
+/* One frozen-policy sweep (eq:p_eval applied once): Q of the stored control
+ * at every free node.  Same fixed-node and resid rules as dpo_bellman_sweep. */
+int dpo_policy_eval_sweep(dpo_ctx* ctx, const float* V_in, float* V_out, const float* pol_angle,
+                          const uint8_t* pol_thr, double* resid, void* stream);
+
+/* --------------------------------------------------------------- solvers */
+
+/* Value iteration (paper Section 3, "Policy Iteration", first display):
+ * V <- T V from the given V (initialise with dpo_init_value) until the
+ * relative residual max|dV|/max(1,|V|) < tol_rel, checked every check_every
+ * sweeps, or until it has not decreased for 64 checks (stalled).  Returns
+ * DPO_ENOCONV after max_sweeps.  V, pol_angle, pol_thr: device, N entries. */
+int dpo_solve_vi(dpo_ctx* ctx, float* V, float* pol_angle, uint8_t* pol_thr, double tol_rel,
+                 int64_t max_sweeps, int32_t check_every, dpo_stats* stats, void* stream);
+
+/* Modified policy iteration (eq:p_impr then eq:p_eval by eval_sweeps
+ * frozen-policy sweeps): stops when the residual of the greedy step is below
+ * tol_rel; V then holds T V and the policy its argmin.  seed_angle (device,
+ * nullable) enables the SEEDED greedy step for every outer iteration after the
+ * first.  Returns DPO_ENOCONV after max_outer greedy steps. */
+int dpo_solve_pi(dpo_ctx* ctx, float* V, float* pol_angle, uint8_t* pol_thr, double tol_rel,
+                 int32_t eval_sweeps, int64_t max_outer, const float* seed_angle,
+                 dpo_stats* stats, void* stream);
+
+/* ----------------------------------------------------- read-out, feedback */
+
+/* FP64 Q1 read-out of the float V at one physical state x (host double[4]);
+ * *out (host) = M outside the domain.  Synchronises stream. */
+int dpo_value_at(dpo_ctx* ctx, const float* V, const double* x, double* out, void* stream);
+
+/* Approximate optimal feedback eq:feed at n arbitrary states (device
+ * double[n*4]) with time step tau, using the context's search (TABLE or
+ * SCAN_GOLDEN): best thrust angle, throttle, and the minimal Q (q_out nullable). */
+int dpo_extract_feedback(dpo_ctx* ctx, const float* V, const double* states, int64_t n,
+                         double tau, float* angle_out, uint8_t* thr_out, float* q_out,
+                         void* stream);
+
+/* Reachability mask for a reduced grid: for every node of `fine` (same
+ * domain box as ctx), keep = (FP64 Q1 value of the coarse V at the node <
+ * thresh), then box-dilated by dilate[k] cells along axis k.  mask: device
+ * u8[N_fine].  Synchronises stream. */
+int dpo_mask_from_coarse(dpo_ctx* coarse, const float* V_coarse, const dpo_grid* fine,
+                         double thresh, const int32_t* dilate, uint8_t* mask, void* stream);
+
+/* ---------------------------------------------------------------- probes */
+
+/* Q1 interpolation (the sweep's device function) at n points given in grid
+ * coordinates (device float[n*4]); out: device float[n]; M outside. */
+int dpo_probe_interp(dpo_ctx* ctx, const float* V, const float* s, int64_t n, float* out,
+                     void* stream);
+
+/* Q(x_j, f) of eq:schema for n (node, control) pairs: nodes (device int32[n],
+ * flat indices), thr (device u8[n]), angle (device float[n]); q_out device
+ * float[n].  The node indices are copied to the host and range-checked first
+ * (blocking), so out-of-range indices give DPO_EINVAL. */
+int dpo_probe_q(dpo_ctx* ctx, const float* V, const int32_t* nodes, const uint8_t* thr,
+                const float* angle, int64_t n, float* q_out, void* stream);
+
+/* Foot displacement of n (node, control) pairs in cells per axis (device
+ * float[n*4]): s_k - i_k as used by the sweep. */
+int dpo_probe_foot(dpo_ctx* ctx, const int32_t* nodes, const uint8_t* thr, const float* angle,
+                   int64_t n, float* off_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPO_H */

@@ -91,6 +91,7 @@ def load(precision="f64"):
     lib.or_value_at.restype = C.c_double
     lib.or_q.argtypes = [P, vp, i64, C.c_int, real]
     lib.or_q.restype = real
+    lib.or_q_many.argtypes = [P, vp, vp, vp, vp, i64, vp]
     lib.or_residual.argtypes = [i64, vp, vp, vp, vp]
     lib.or_bellman_sweep.argtypes = [P, vp, S, vp, vp, vp, vp, vp]
     lib.or_bellman_nodes.argtypes = [P, vp, S, vp, vp, i64, vp, vp, vp, vp]
@@ -169,6 +170,16 @@ class Oracle:
     def q(self, V, j, thr, u):
         V = self._arr(V)
         return float(self.lib.or_q(C.byref(self.ps), _ptr(V), int(j), int(thr), u))
+
+    def q_many(self, V, nodes, thr, ang):
+        V = self._arr(V)
+        nodes = np.ascontiguousarray(np.asarray(nodes, dtype=np.int64).reshape(-1))
+        thr = np.ascontiguousarray(np.asarray(thr, dtype=np.uint8).reshape(-1))
+        ang = np.ascontiguousarray(np.asarray(ang, dtype=self.dtype).reshape(-1))
+        out = np.empty(nodes.size, dtype=self.dtype)
+        self.lib.or_q_many(C.byref(self.ps), _ptr(V), _ptr(nodes), _ptr(thr), _ptr(ang), nodes.size,
+                           _ptr(out))
+        return out
 
     def residual(self, Vold, Vnew):
         Vo, Vn = self._arr(Vold), self._arr(Vnew)

@@ -251,6 +251,12 @@ real or_q(const or_problem *p, const real *V, int64_t j, int thr, real u) {
   return q_node(p, V, i, thr, u, (real)p->dt);
 }
 
+/* Q for many (node, throttle, angle) triples. */
+void or_q_many(const or_problem *p, const real *V, const int64_t *nodes, const uint8_t *thr,
+               const real *ang, int64_t count, real *out) {
+  for (int64_t c = 0; c < count; c++) out[c] = or_q(p, V, nodes[c], thr[c], ang[c]);
+}
+
 /* Q at an arbitrary state y (feedback, eq:feed): interpolation at y + tau*b. */
 static real q_state(const or_problem *p, const real *V, const real y[4], int thr, real u, real tau) {
   real z[4], s[4];

@@ -1,0 +1,611 @@
+// Host side of libdpo: the C ABI declared in include/dpo.h.
+//
+// Owns the per-context device scratch (node kinds, compacted free-node list,
+// control tables, residual partials, a second value buffer for the solvers)
+// and runs the value- and policy-iteration loops of arXiv 2407.14675,
+// Section 3 ("Policy Iteration"): sweeps are queued asynchronously and the
+// host synchronises only to read the FP64 residual every few sweeps.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/dpo.h"
+#include "dpo_kernels.h"
+
+using namespace dpo;
+
+struct dpo_ctx {
+  dpo_grid grid;
+  dpo_problem prob;
+  dpo_search search;
+  Grid G;
+  Phys P;
+  TargetBox tb;
+  int64_t N = 0, n_free = 0;
+  uint8_t* kind = nullptr;
+  int* free_idx = nullptr;
+  float* tab = nullptr;  // [3][n_ang]: sin, cos, angle
+  int n_ang = 0;
+  int tab_cap = 0;
+  double* partial = nullptr;
+  int partial_blocks = 0;
+  double* resid = nullptr;  // kPartial doubles
+  float* work = nullptr;    // second value buffer of the solvers
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(dpo_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_err = msg;
+  return code;
+}
+
+int hip_fail(dpo_ctx* c, hipError_t e, const char* where) {
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  return fail(c, DPO_EHIP, m);
+}
+
+#define HIP_TRY(ctx, call)                                         \
+  do {                                                             \
+    hipError_t e_ = (call);                                        \
+    if (e_ != hipSuccess) return hip_fail((ctx), e_, #call);       \
+  } while (0)
+
+int validate_grid(dpo_ctx* c, const dpo_grid* g) {
+  if (!g) return fail(c, DPO_EINVAL, "grid is NULL");
+  long long N = 1;
+  for (int k = 0; k < 4; k++) {
+    if (g->n[k] < 2) return fail(c, DPO_EINVAL, "grid: n[k] must be >= 2");
+    if (!(g->lo[k] < g->hi[k]) || !std::isfinite(g->lo[k]) || !std::isfinite(g->hi[k]))
+      return fail(c, DPO_EINVAL, "grid: need finite lo[k] < hi[k]");
+    N *= g->n[k];
+  }
+  if (N > 0x7fffffffLL / 2) return fail(c, DPO_EINVAL, "grid: too many nodes (limit 2^30)");
+  return DPO_OK;
+}
+
+int validate_problem(dpo_ctx* c, const dpo_problem* p) {
+  if (!p) return fail(c, DPO_EINVAL, "problem is NULL");
+  if (p->model != DPO_MODEL_ORBIT && p->model != DPO_MODEL_EIKONAL)
+    return fail(c, DPO_EINVAL, "problem: unknown model");
+  if (!(p->dt > 0) || !std::isfinite(p->dt)) return fail(c, DPO_EINVAL, "problem: dt must be > 0");
+  if (!(p->lambda >= 0)) return fail(c, DPO_EINVAL, "problem: lambda must be >= 0");
+  if (!std::isfinite(p->M)) return fail(c, DPO_EINVAL, "problem: M must be finite");
+  if (p->model == DPO_MODEL_ORBIT && !(p->accel >= 0 && p->mdot >= 0))
+    return fail(c, DPO_EINVAL, "problem: accel and mdot must be >= 0");
+  return DPO_OK;
+}
+
+int validate_search(dpo_ctx* c, const dpo_search* s) {
+  if (!s) return fail(c, DPO_EINVAL, "search is NULL");
+  if (s->mode == DPO_SEARCH_TABLE) {
+    if (s->n_angles < 1 || s->n_angles > 1024) return fail(c, DPO_EINVAL, "search: n_angles in [1, 1024]");
+  } else if (s->mode == DPO_SEARCH_SCAN_GOLDEN || s->mode == DPO_SEARCH_SEEDED) {
+    if (s->n_scan < 8 || s->n_scan > 1024) return fail(c, DPO_EINVAL, "search: n_scan in [8, 1024]");
+    if (s->n_golden < 0 || s->n_golden > 64) return fail(c, DPO_EINVAL, "search: n_golden in [0, 64]");
+    if (s->mode == DPO_SEARCH_SEEDED) {
+      if (s->n_local < 3 || s->n_local > 64) return fail(c, DPO_EINVAL, "search: n_local in [3, 64]");
+      if (!(s->local_half_width > 0 && s->local_half_width <= 0.785398))
+        return fail(c, DPO_EINVAL, "search: local_half_width in (0, pi/4]");
+      if (!(s->fallback_tol >= 0)) return fail(c, DPO_EINVAL, "search: fallback_tol >= 0");
+    }
+  } else {
+    return fail(c, DPO_EINVAL, "search: unknown mode");
+  }
+  return DPO_OK;
+}
+
+hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Tabulated angles u_k = -pi + 2*pi*k/K (FP64, rounded to float).
+int upload_table(dpo_ctx* c) {
+  const int K = c->search.mode == DPO_SEARCH_TABLE ? c->search.n_angles : c->search.n_scan;
+  if (K > c->tab_cap) {
+    if (c->tab) hipFree(c->tab);
+    c->tab = nullptr;
+    if (hipMalloc(&c->tab, sizeof(float) * 3 * K) != hipSuccess) return fail(c, DPO_ENOMEM, "table alloc");
+    c->tab_cap = K;
+  }
+  std::vector<float> h(3 * K);
+  const double pi = 3.14159265358979323846;
+  for (int k = 0; k < K; k++) {
+    const double u = -pi + 2.0 * pi * (double)k / (double)K;
+    h[k] = (float)std::sin(u);
+    h[K + k] = (float)std::cos(u);
+    h[2 * K + k] = (float)u;
+  }
+  HIP_TRY(c, hipMemcpy(c->tab, h.data(), sizeof(float) * 3 * K, hipMemcpyHostToDevice));
+  c->n_ang = K;
+  return DPO_OK;
+}
+
+Grid make_grid(const dpo_grid& g) {
+  Grid G;
+  for (int k = 0; k < 4; k++) {
+    G.n[k] = g.n[k];
+    G.lo[k] = g.lo[k];
+    G.h[k] = (g.hi[k] - g.lo[k]) / (double)(g.n[k] - 1);
+    G.inv_h[k] = 1.0 / G.h[k];
+  }
+  G.st[0] = 1;
+  G.st[1] = g.n[0];
+  G.st[2] = g.n[0] * g.n[1];
+  G.st[3] = g.n[0] * g.n[1] * g.n[2];
+  return G;
+}
+
+SweepArgs base_args(const dpo_ctx* c) {
+  SweepArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.G = c->G;
+  a.P = c->P;
+  a.free_idx = c->free_idx;
+  a.n_free = (int)c->n_free;
+  a.tab_sin = c->tab;
+  a.tab_cos = c->tab + c->n_ang;
+  a.tab_ang = c->tab + 2 * c->n_ang;
+  a.n_ang = c->n_ang;
+  a.n_golden = c->search.n_golden;
+  a.half_width = (float)(2.0 * 3.14159265358979323846 / (double)(c->search.n_scan > 0 ? c->search.n_scan : 1));
+  a.n_local = c->search.n_local;
+  a.local_half_width = (float)c->search.local_half_width;
+  a.fallback_tol = (float)c->search.fallback_tol;
+  a.partial = c->partial;
+  a.mode = c->search.mode;
+  a.w_time = c->prob.w_time;
+  a.w_fuel = c->prob.w_fuel;
+  a.lambda = c->prob.lambda;
+  return a;
+}
+
+int sweep_blocks(const dpo_ctx* c) { return blocks_for(c->n_free); }
+
+// Final FP64 reduction of the last node kernel's partials into `out`.
+int finish_resid(dpo_ctx* c, double* out, hipStream_t s) {
+  if (!out) return DPO_OK;
+  const int nb = sweep_blocks(c);
+  if (nb == 0) {
+    HIP_TRY(c, hipMemsetAsync(out, 0, sizeof(double) * kPartial, s));
+    return DPO_OK;
+  }
+  HIP_TRY(c, launch_resid_final(c->partial, nb, out, s));
+  return DPO_OK;
+}
+
+int ensure_work(dpo_ctx* c) {
+  if (c->work) return DPO_OK;
+  if (hipMalloc(&c->work, sizeof(float) * (size_t)c->N) != hipSuccess)
+    return fail(c, DPO_ENOMEM, "solver work buffer alloc");
+  return DPO_OK;
+}
+
+int read_resid(dpo_ctx* c, double h[kPartial], hipStream_t s) {
+  HIP_TRY(c, hipMemcpyAsync(h, c->resid, sizeof(double) * kPartial, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  return DPO_OK;
+}
+
+int64_t evals_per_full_search(const dpo_ctx* c) {
+  if (c->search.mode == DPO_SEARCH_TABLE) return 1 + c->search.n_angles;
+  return 1 + c->search.n_scan + (c->search.n_golden > 0 ? 2 + c->search.n_golden : 0);
+}
+
+int sweep_full(dpo_ctx* c, const float* Vin, float* Vout, float* ang, uint8_t* thr, hipStream_t s) {
+  SweepArgs a = base_args(c);
+  a.V_in = Vin;
+  a.V_out = Vout;
+  a.pol_ang = ang;
+  a.pol_thr = thr;
+  if (a.n_free == 0) return DPO_OK;
+  hipError_t e = c->search.mode == DPO_SEARCH_TABLE ? launch_sweep_table(a, s) : launch_sweep_scan_golden(a, s);
+  if (e != hipSuccess) return hip_fail(c, e, "bellman sweep launch");
+  return DPO_OK;
+}
+
+int sweep_seeded(dpo_ctx* c, const float* Vin, float* Vout, float* ang, uint8_t* thr, const float* seed,
+                 hipStream_t s) {
+  SweepArgs a = base_args(c);
+  a.V_in = Vin;
+  a.V_out = Vout;
+  a.pol_ang = ang;
+  a.pol_thr = thr;
+  a.seed = seed;
+  if (a.n_free == 0) return DPO_OK;
+  hipError_t e = launch_sweep_seeded(a, s);
+  if (e != hipSuccess) return hip_fail(c, e, "seeded sweep launch");
+  return DPO_OK;
+}
+
+int sweep_eval(dpo_ctx* c, const float* Vin, float* Vout, const float* ang, const uint8_t* thr, hipStream_t s) {
+  SweepArgs a = base_args(c);
+  a.V_in = Vin;
+  a.V_out = Vout;
+  a.pol_ang_in = ang;
+  a.pol_thr_in = thr;
+  if (a.n_free == 0) return DPO_OK;
+  hipError_t e = launch_policy_eval(a, s);
+  if (e != hipSuccess) return hip_fail(c, e, "policy eval launch");
+  return DPO_OK;
+}
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+// ===================================================================== ABI
+extern "C" {
+
+const char* dpo_last_error(const dpo_ctx* ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+int dpo_create(const dpo_grid* grid, const dpo_problem* prob, const dpo_search* search,
+               const uint8_t* active_mask, dpo_ctx** out) {
+  if (!out) return fail(nullptr, DPO_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc;
+  if ((rc = validate_grid(nullptr, grid)) != DPO_OK) return rc;
+  if ((rc = validate_problem(nullptr, prob)) != DPO_OK) return rc;
+  if ((rc = validate_search(nullptr, search)) != DPO_OK) return rc;
+  dpo_ctx* c = new dpo_ctx();
+  c->grid = *grid;
+  c->prob = *prob;
+  c->search = *search;
+  c->G = make_grid(*grid);
+  c->P.model = prob->model;
+  c->P.mu = prob->mu;
+  c->P.accel = prob->accel;
+  c->P.mdot = prob->mdot;
+  c->P.dt = prob->dt;
+  c->P.speed = prob->speed;
+  c->P.q_coast = (float)(prob->dt * prob->w_time);
+  c->P.q_thr = (float)(prob->dt * (prob->w_time + prob->w_fuel));
+  c->P.gamma = (float)std::exp(-prob->lambda * prob->dt);
+  c->P.M = (float)prob->M;
+  for (int k = 0; k < 4; k++) {
+    c->tb.c[k] = prob->tgt_c[k];
+    c->tb.w[k] = prob->tgt_w[k];
+  }
+  c->N = (int64_t)grid->n[0] * grid->n[1] * grid->n[2] * grid->n[3];
+  const int N = (int)c->N;
+  int* counts = nullptr;
+  int* offsets = nullptr;
+  const int nch = compact_chunks(N);
+  auto cleanup = [&](int code) {
+    if (counts) hipFree(counts);
+    if (offsets) hipFree(offsets);
+    if (code != DPO_OK) {
+      g_err = c->err;
+      dpo_destroy(c);
+    }
+    return code;
+  };
+  if (hipMalloc(&c->kind, (size_t)N) != hipSuccess || hipMalloc(&c->free_idx, sizeof(int) * (size_t)N) != hipSuccess ||
+      hipMalloc(&counts, sizeof(int) * nch) != hipSuccess || hipMalloc(&offsets, sizeof(int) * (nch + 1)) != hipSuccess ||
+      hipMalloc(&c->resid, sizeof(double) * kPartial) != hipSuccess) {
+    c->err = "device allocation failed in dpo_create";
+    return cleanup(DPO_ENOMEM);
+  }
+  hipError_t e = launch_classify(c->G, c->tb, active_mask, c->kind, N, nullptr);
+  if (e == hipSuccess) e = launch_compact(c->kind, N, counts, offsets, c->free_idx, nullptr);
+  int total = 0;
+  if (e == hipSuccess) e = hipMemcpy(&total, offsets + nch, sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) {
+    c->err = std::string("dpo_create: ") + hipGetErrorString(e);
+    return cleanup(DPO_EHIP);
+  }
+  c->n_free = total;
+  c->partial_blocks = blocks_for(total > 0 ? total : 1);
+  if (hipMalloc(&c->partial, sizeof(double) * kPartial * c->partial_blocks) != hipSuccess) {
+    c->err = "device allocation failed in dpo_create";
+    return cleanup(DPO_ENOMEM);
+  }
+  if ((rc = upload_table(c)) != DPO_OK) return cleanup(rc);
+  *out = c;
+  return cleanup(DPO_OK);
+}
+
+void dpo_destroy(dpo_ctx* c) {
+  if (!c) return;
+  if (c->kind) hipFree(c->kind);
+  if (c->free_idx) hipFree(c->free_idx);
+  if (c->tab) hipFree(c->tab);
+  if (c->partial) hipFree(c->partial);
+  if (c->resid) hipFree(c->resid);
+  if (c->work) hipFree(c->work);
+  delete c;
+}
+
+int dpo_sizes(const dpo_ctx* c, int64_t* n_nodes, int64_t* n_free) {
+  if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
+  if (n_nodes) *n_nodes = c->N;
+  if (n_free) *n_free = c->n_free;
+  return DPO_OK;
+}
+
+int dpo_get_kind(dpo_ctx* c, uint8_t* kind, void* stream) {
+  if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
+  if (!kind) return fail(c, DPO_EINVAL, "kind is NULL");
+  HIP_TRY(c, hipMemcpyAsync(kind, c->kind, (size_t)c->N, hipMemcpyDeviceToDevice, S(stream)));
+  return DPO_OK;
+}
+
+int dpo_set_search(dpo_ctx* c, const dpo_search* search) {
+  if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
+  int rc = validate_search(c, search);
+  if (rc != DPO_OK) return rc;
+  c->search = *search;
+  return upload_table(c);
+}
+
+int dpo_init_value(dpo_ctx* c, float* V, void* stream) {
+  if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
+  if (!V) return fail(c, DPO_EINVAL, "V is NULL");
+  HIP_TRY(c, launch_init_value(c->kind, c->P.M, V, (int)c->N, S(stream)));
+  return DPO_OK;
+}
+
+int dpo_bellman_sweep(dpo_ctx* c, const float* V_in, float* V_out, float* pol_angle, uint8_t* pol_thr,
+                      double* resid, void* stream) {
+  if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
+  if (!V_in || !V_out) return fail(c, DPO_EINVAL, "V_in / V_out is NULL");
+  if (V_in == V_out) return fail(c, DPO_EINVAL, "V_in and V_out must differ (Jacobi sweep)");
+  if (c->search.mode == DPO_SEARCH_SEEDED) return fail(c, DPO_EINVAL, "SEEDED mode: use dpo_bellman_sweep_seeded");
+  int rc = sweep_full(c, V_in, V_out, pol_angle, pol_thr, S(stream));
+  if (rc != DPO_OK) return rc;
+  return finish_resid(c, resid, S(stream));
+}
+
+int dpo_bellman_sweep_seeded(dpo_ctx* c, const float* V_in, float* V_out, float* pol_angle, uint8_t* pol_thr,
+                             const float* seed_angle, double* resid, void* stream) {
+  if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
+  if (!V_in || !V_out || !seed_angle) return fail(c, DPO_EINVAL, "V_in / V_out / seed_angle is NULL");
+  if (V_in == V_out) return fail(c, DPO_EINVAL, "V_in and V_out must differ (Jacobi sweep)");
+  if (c->search.mode != DPO_SEARCH_SEEDED) return fail(c, DPO_EINVAL, "search mode is not SEEDED");
+  int rc = sweep_seeded(c, V_in, V_out, pol_angle, pol_thr, seed_angle, S(stream));
+  if (rc != DPO_OK) return rc;
+  return finish_resid(c, resid, S(stream));
+}
+
+int dpo_policy_eval_sweep(dpo_ctx* c, const float* V_in, float* V_out, const float* pol_angle,
+                          const uint8_t* pol_thr, double* resid, void* stream) {
+  if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
+  if (!V_in || !V_out || !pol_angle || !pol_thr) return fail(c, DPO_EINVAL, "null array argument");
+  if (V_in == V_out) return fail(c, DPO_EINVAL, "V_in and V_out must differ (Jacobi sweep)");
+  int rc = sweep_eval(c, V_in, V_out, pol_angle, pol_thr, S(stream));
+  if (rc != DPO_OK) return rc;
+  return finish_resid(c, resid, S(stream));
+}
+
+int dpo_solve_vi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, double tol_rel, int64_t max_sweeps,
+                 int32_t check_every, dpo_stats* st, void* stream) {
+  if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
+  if (!V || !pol_angle || !pol_thr) return fail(c, DPO_EINVAL, "null array argument");
+  if (max_sweeps < 1 || check_every < 1 || !(tol_rel >= 0)) return fail(c, DPO_EINVAL, "bad max_sweeps / check_every / tol");
+  if (c->search.mode == DPO_SEARCH_SEEDED) return fail(c, DPO_EINVAL, "value iteration needs TABLE or SCAN_GOLDEN");
+  int rc = ensure_work(c);
+  if (rc != DPO_OK) return rc;
+  hipStream_t s = S(stream);
+  dpo_stats local;
+  std::memset(&local, 0, sizeof(local));
+  const double t0 = now_s();
+  HIP_TRY(c, hipMemcpyAsync(c->work, V, sizeof(float) * (size_t)c->N, hipMemcpyDeviceToDevice, s));
+  float* cur = V;
+  float* nxt = c->work;
+  double best = INFINITY;
+  int since_best = 0;
+  int code = DPO_ENOCONV;
+  double h[kPartial] = {0, 0, 0, 0, 0};
+  int64_t k = 0;
+  while (k < max_sweeps) {
+    rc = sweep_full(c, cur, nxt, pol_angle, pol_thr, s);
+    if (rc != DPO_OK) return rc;
+    k++;
+    std::swap(cur, nxt);
+    if (k % check_every == 0 || k == max_sweeps) {
+      if ((rc = finish_resid(c, c->resid, s)) != DPO_OK) return rc;
+      if ((rc = read_resid(c, h, s)) != DPO_OK) return rc;
+      if (h[3] > 0) {
+        code = DPO_ENUMERIC;
+        fail(c, DPO_ENUMERIC, "value iteration produced non-finite values");
+        break;
+      }
+      if (h[0] < tol_rel) {
+        code = DPO_OK;
+        local.converged = 1;
+        break;
+      }
+      if (h[0] < best) {
+        best = h[0];
+        since_best = 0;
+      } else if (++since_best >= 64) {
+        local.stalled = 1;
+        break;
+      }
+    }
+  }
+  if (cur != V) HIP_TRY(c, hipMemcpyAsync(V, cur, sizeof(float) * (size_t)c->N, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  local.sweeps = k;
+  local.evals = k * c->n_free * evals_per_full_search(c);
+  local.resid_max_rel = h[0];
+  local.resid_sum_abs = h[1];
+  local.resid_max_abs = h[2];
+  local.seconds = now_s() - t0;
+  if (st) *st = local;
+  if (code == DPO_ENOCONV) fail(c, DPO_ENOCONV, local.stalled ? "value iteration stalled" : "max_sweeps reached");
+  return code;
+}
+
+int dpo_solve_pi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, double tol_rel, int32_t eval_sweeps,
+                 int64_t max_outer, const float* seed_angle, dpo_stats* st, void* stream) {
+  if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
+  if (!V || !pol_angle || !pol_thr) return fail(c, DPO_EINVAL, "null array argument");
+  if (max_outer < 1 || eval_sweeps < 0 || !(tol_rel >= 0)) return fail(c, DPO_EINVAL, "bad max_outer / eval_sweeps / tol");
+  const bool seeded = seed_angle != nullptr;
+  if (seeded && c->search.mode != DPO_SEARCH_SEEDED) return fail(c, DPO_EINVAL, "seed_angle given but search mode is not SEEDED");
+  if (!seeded && c->search.mode == DPO_SEARCH_SEEDED) return fail(c, DPO_EINVAL, "SEEDED mode needs seed_angle");
+  int rc = ensure_work(c);
+  if (rc != DPO_OK) return rc;
+  hipStream_t s = S(stream);
+  dpo_stats local;
+  std::memset(&local, 0, sizeof(local));
+  const double t0 = now_s();
+  HIP_TRY(c, hipMemcpyAsync(c->work, V, sizeof(float) * (size_t)c->N, hipMemcpyDeviceToDevice, s));
+  float* cur = V;
+  float* nxt = c->work;
+  int code = DPO_ENOCONV;
+  double h[kPartial] = {0, 0, 0, 0, 0};
+  int64_t it = 0, evals = 0, fallback = 0;
+  while (it < max_outer) {
+    // greedy step: policy improvement together with T V
+    if (seeded && it > 0) rc = sweep_seeded(c, cur, nxt, pol_angle, pol_thr, seed_angle, s);
+    else rc = sweep_full(c, cur, nxt, pol_angle, pol_thr, s);
+    if (rc != DPO_OK) return rc;
+    it++;
+    std::swap(cur, nxt);
+    if ((rc = finish_resid(c, c->resid, s)) != DPO_OK) return rc;
+    if ((rc = read_resid(c, h, s)) != DPO_OK) return rc;
+    if (seeded && it > 1) {
+      fallback += (int64_t)h[4];
+      evals += c->n_free * (1 + c->search.n_local) + (int64_t)h[4] * evals_per_full_search(c);
+    } else {
+      evals += c->n_free * evals_per_full_search(c);
+    }
+    if (h[3] > 0) {
+      code = DPO_ENUMERIC;
+      fail(c, DPO_ENUMERIC, "policy iteration produced non-finite values");
+      break;
+    }
+    if (h[0] < tol_rel) {
+      code = DPO_OK;
+      local.converged = 1;
+      break;
+    }
+    for (int e = 0; e < eval_sweeps; e++) {
+      if ((rc = sweep_eval(c, cur, nxt, pol_angle, pol_thr, s)) != DPO_OK) return rc;
+      std::swap(cur, nxt);
+    }
+    local.eval_sweeps += eval_sweeps;
+    evals += (int64_t)eval_sweeps * c->n_free;
+  }
+  if (cur != V) HIP_TRY(c, hipMemcpyAsync(V, cur, sizeof(float) * (size_t)c->N, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  local.sweeps = it;
+  local.evals = evals;
+  local.fallback_nodes = fallback;
+  local.resid_max_rel = h[0];
+  local.resid_sum_abs = h[1];
+  local.resid_max_abs = h[2];
+  local.seconds = now_s() - t0;
+  if (st) *st = local;
+  if (code == DPO_ENOCONV) fail(c, DPO_ENOCONV, "max_outer reached");
+  return code;
+}
+
+int dpo_value_at(dpo_ctx* c, const float* V, const double* x, double* out, void* stream) {
+  if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
+  if (!V || !x || !out) return fail(c, DPO_EINVAL, "null argument");
+  hipStream_t s = S(stream);
+  HIP_TRY(c, launch_value_at(V, c->G, c->prob.M, x, c->resid, s));
+  HIP_TRY(c, hipMemcpyAsync(out, c->resid, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  return DPO_OK;
+}
+
+int dpo_extract_feedback(dpo_ctx* c, const float* V, const double* states, int64_t n, double tau, float* angle_out,
+                         uint8_t* thr_out, float* q_out, void* stream) {
+  if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
+  if (!V || !states || !angle_out || !thr_out) return fail(c, DPO_EINVAL, "null array argument");
+  if (n < 0 || n > 0x7fffffff) return fail(c, DPO_EINVAL, "bad n");
+  if (!(tau > 0)) return fail(c, DPO_EINVAL, "tau must be > 0");
+  if (c->search.mode == DPO_SEARCH_SEEDED) return fail(c, DPO_EINVAL, "feedback needs TABLE or SCAN_GOLDEN");
+  if (n == 0) return DPO_OK;
+  SweepArgs a = base_args(c);
+  a.V_in = V;
+  HIP_TRY(c, launch_feedback(a, states, (int)n, tau, angle_out, thr_out, q_out, S(stream)));
+  return DPO_OK;
+}
+
+int dpo_mask_from_coarse(dpo_ctx* c, const float* Vc, const dpo_grid* fine, double thresh, const int32_t* dilate,
+                         uint8_t* mask, void* stream) {
+  if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
+  if (!Vc || !fine || !dilate || !mask) return fail(c, DPO_EINVAL, "null argument");
+  int rc = validate_grid(c, fine);
+  if (rc != DPO_OK) return rc;
+  for (int k = 0; k < 4; k++) {
+    if (fine->lo[k] != c->grid.lo[k] || fine->hi[k] != c->grid.hi[k])
+      return fail(c, DPO_EINVAL, "fine grid must share the coarse domain box");
+    if (dilate[k] < 0) return fail(c, DPO_EINVAL, "dilate must be >= 0");
+  }
+  const Grid Gf = make_grid(*fine);
+  const int Nf = fine->n[0] * fine->n[1] * fine->n[2] * fine->n[3];
+  uint8_t* tmp = nullptr;
+  if (hipMalloc(&tmp, (size_t)Nf) != hipSuccess) return fail(c, DPO_ENOMEM, "mask scratch alloc");
+  hipStream_t s = S(stream);
+  hipError_t e = launch_mask_seed(Vc, c->G, c->prob.M, Gf, thresh, mask, Nf, s);
+  for (int k = 0; k < 4 && e == hipSuccess; k++) {
+    if (dilate[k] == 0) continue;
+    e = launch_dilate_axis(mask, tmp, Gf, k, dilate[k], Nf, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(mask, tmp, (size_t)Nf, hipMemcpyDeviceToDevice, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipFree(tmp);
+  if (e != hipSuccess) return hip_fail(c, e, "dpo_mask_from_coarse");
+  return DPO_OK;
+}
+
+int dpo_probe_interp(dpo_ctx* c, const float* V, const float* pts, int64_t n, float* out, void* stream) {
+  if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
+  if (!V || !pts || !out) return fail(c, DPO_EINVAL, "null argument");
+  if (n < 0 || n > 0x7fffffff) return fail(c, DPO_EINVAL, "bad n");
+  if (n == 0) return DPO_OK;
+  HIP_TRY(c, launch_probe_interp(V, c->G, c->P.M, pts, (int)n, out, S(stream)));
+  return DPO_OK;
+}
+
+static int probe_nodes_check(dpo_ctx* c, const int32_t* nodes, int64_t n) {
+  if (n < 0 || n > 0x7fffffff) return fail(c, DPO_EINVAL, "bad n");
+  // Node indices are read on the device; reject out-of-range ones on the host.
+  std::vector<int32_t> h((size_t)n);
+  if (n > 0 && hipMemcpy(h.data(), nodes, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(c, DPO_EHIP, "probe: reading node indices");
+  for (int32_t v : h)
+    if (v < 0 || v >= c->N) return fail(c, DPO_EINVAL, "probe: node index out of range");
+  return DPO_OK;
+}
+
+int dpo_probe_q(dpo_ctx* c, const float* V, const int32_t* nodes, const uint8_t* thr, const float* angle, int64_t n,
+                float* q_out, void* stream) {
+  if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
+  if (!V || !nodes || !thr || !angle || !q_out) return fail(c, DPO_EINVAL, "null argument");
+  int rc = probe_nodes_check(c, nodes, n);
+  if (rc != DPO_OK || n == 0) return rc;
+  SweepArgs a = base_args(c);
+  a.V_in = V;
+  HIP_TRY(c, launch_probe_q(a, nodes, thr, angle, (int)n, q_out, nullptr, S(stream)));
+  return DPO_OK;
+}
+
+int dpo_probe_foot(dpo_ctx* c, const int32_t* nodes, const uint8_t* thr, const float* angle, int64_t n,
+                   float* off_out, void* stream) {
+  if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
+  if (!nodes || !thr || !angle || !off_out) return fail(c, DPO_EINVAL, "null argument");
+  int rc = probe_nodes_check(c, nodes, n);
+  if (rc != DPO_OK || n == 0) return rc;
+  SweepArgs a = base_args(c);
+  HIP_TRY(c, launch_probe_q(a, nodes, thr, angle, (int)n, nullptr, off_out, S(stream)));
+  return DPO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,238 @@
+// Device-side building blocks shared by the sweep kernels of libdpo.
+//
+// Grid coordinates: node i_k of axis k, foot displacement off_k in cells, so
+// the foot sits at s_k = i_k + off_k (paper Section 3: the foot point
+// x_j + dt*Phi(x_j, f) of eq:schema, expressed on the grid).  Keeping the
+// integer and the fractional parts apart keeps the local cell coordinate
+// accurate to about 1e-7 of a cell in float32, where an absolute float32
+// coordinate would only resolve ulp(1)/h ~ 5e-5 of a cell.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dpo {
+
+constexpr int kBlock = 256;  // threads per workgroup of the node kernels (4 waves)
+
+struct Grid {
+  int n[4];
+  int st[4];  // element strides: 1, n0, n0*n1, n0*n1*n2
+  double lo[4];
+  double h[4];
+  double inv_h[4];
+};
+
+struct Phys {
+  int model;  // 0 orbit, 1 eikonal
+  double mu, accel, mdot, dt, speed;
+  float q_coast;  // dt * w_time
+  float q_thr;    // dt * (w_time + w_fuel)
+  float gamma;    // exp(-lambda * dt)
+  float M;
+};
+
+// Control-independent part of the displacement of one node and the thrust
+// coefficients, all in cells.  Computed once per node in FP64 and rounded:
+// the gravity/centrifugal difference cancels to ~2% of its terms, so float32
+// here would cost ~1e-6 of a cell per step.
+struct NodeTerms {
+  int i[4];
+  float drift[4];
+  float g1, g2;  // displacement along v_r per unit sin u, along v_t per unit cos u
+  float gm;      // displacement along m under thrust (<= 0)
+};
+
+__device__ inline void decode_node(const Grid& G, int j, int i[4]) {
+  int q = j;
+  i[0] = q % G.n[0];
+  q /= G.n[0];
+  i[1] = q % G.n[1];
+  q /= G.n[1];
+  i[2] = q % G.n[2];
+  i[3] = q / G.n[2];
+}
+
+// Right-hand side of the planar dynamics at a physical state x, scaled by
+// tau and divided by the grid steps.  Orbit: (v_r, v_t^2/r - mu/r^2,
+// -v_r v_t / r, 0) + thr*(0, (a/m) sin u, (a/m) cos u, -c).
+__device__ inline void state_terms(const Grid& G, const Phys& P, const double x[4], double tau,
+                                   float drift[4], float& g1, float& g2, float& gm) {
+  if (P.model == 0) {
+    const double r = x[0], vr = x[1], vt = x[2], m = x[3];
+    const double inv_r = 1.0 / r;
+    drift[0] = (float)(tau * vr * G.inv_h[0]);
+    drift[1] = (float)(tau * (vt * vt * inv_r - P.mu * inv_r * inv_r) * G.inv_h[1]);
+    drift[2] = (float)(tau * (-vr * vt * inv_r) * G.inv_h[2]);
+    drift[3] = 0.0f;
+    const double acc = P.accel / m;
+    g1 = (float)(tau * acc * G.inv_h[1]);
+    g2 = (float)(tau * acc * G.inv_h[2]);
+    gm = (float)(-tau * P.mdot * G.inv_h[3]);
+  } else {
+    drift[0] = drift[1] = drift[2] = drift[3] = 0.0f;
+    g1 = (float)(tau * P.speed * G.inv_h[1]);
+    g2 = (float)(tau * P.speed * G.inv_h[2]);
+    gm = 0.0f;
+  }
+}
+
+__device__ inline void node_terms(const Grid& G, const Phys& P, int j, double tau, NodeTerms& T) {
+  decode_node(G, j, T.i);
+  double x[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) x[k] = G.lo[k] + (double)T.i[k] * G.h[k];
+  state_terms(G, P, x, tau, T.drift, T.g1, T.g2, T.gm);
+}
+
+__device__ inline float lerp(float a, float b, float t) { return fmaf(t, b - a, a); }
+
+// Q1 interpolation of V at s = i + off (paper Section 3: multilinear I[V],
+// M outside the closed box).  Cell base_k = min(floor(s_k), n_k - 2),
+// t_k = s_k - base_k; the 16 corners are combined by 15 lerps (r first).
+// kSnap: feet of states given in physical units (feedback) that lie within
+// 1e-6 cells outside a face are put on the face.
+template <bool kSnap = false>
+__device__ inline float interp_off(const float* __restrict__ V, const Grid& G, const int i[4],
+                                   const float off[4], float M) {
+  int base[4];
+  float t[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    float o = off[k];
+    if (kSnap) {
+      const float lo = (float)(-i[k]), hi = (float)(G.n[k] - 1 - i[k]);
+      if (o < lo && o > lo - 1e-6f) o = lo;
+      if (o > hi && o < hi + 1e-6f) o = hi;
+    }
+    if (!(o >= (float)(-i[k]) && o <= (float)(G.n[k] - 1 - i[k]))) return M;
+    const float fl = floorf(o);
+    int b = i[k] + (int)fl;
+    float tt = o - fl;
+    if (b > G.n[k] - 2) {
+      b = G.n[k] - 2;
+      tt = 1.0f;
+    }
+    base[k] = b;
+    t[k] = tt;
+  }
+  const float* p = V + (base[0] + base[1] * G.st[1] + base[2] * G.st[2] + base[3] * G.st[3]);
+  const int s1 = G.st[1], s2 = G.st[2], s3 = G.st[3];
+  float c[8];
+#pragma unroll
+  for (int e = 0; e < 8; e++) {
+    const int o = ((e & 1) ? s1 : 0) + ((e & 2) ? s2 : 0) + ((e & 4) ? s3 : 0);
+    c[e] = lerp(p[o], p[o + 1], t[0]);
+  }
+  const float d0 = lerp(c[0], c[1], t[1]);
+  const float d1 = lerp(c[2], c[3], t[1]);
+  const float d2 = lerp(c[4], c[5], t[1]);
+  const float d3 = lerp(c[6], c[7], t[1]);
+  const float e0 = lerp(d0, d1, t[2]);
+  const float e1 = lerp(d2, d3, t[2]);
+  return lerp(e0, e1, t[3]);
+}
+
+// Q of one control at a node: dt*l + gamma * I[V](foot).
+template <bool kSnap = false>
+__device__ inline float q_thrust(const float* __restrict__ V, const Grid& G, const Phys& P,
+                                 const NodeTerms& T, float sn, float cs) {
+  float off[4];
+  off[0] = T.drift[0];
+  off[1] = fmaf(T.g1, sn, T.drift[1]);
+  off[2] = fmaf(T.g2, cs, T.drift[2]);
+  off[3] = T.drift[3] + T.gm;
+  return fmaf(P.gamma, interp_off<kSnap>(V, G, T.i, off, P.M), P.q_thr);
+}
+
+template <bool kSnap = false>
+__device__ inline float q_coast(const float* __restrict__ V, const Grid& G, const Phys& P,
+                                const NodeTerms& T) {
+  return fmaf(P.gamma, interp_off<kSnap>(V, G, T.i, T.drift, P.M), P.q_coast);
+}
+
+// sin and cos of a small angle d (|d| <= pi/4) by truncated Taylor series;
+// the truncation error is below 2e-9 there, far under float32 resolution.
+__device__ inline void small_sincos(float d, float& s, float& c) {
+  const float d2 = d * d;
+  s = d * (1.0f - d2 * (1.0f / 6.0f) * (1.0f - d2 * (1.0f / 20.0f) *
+                                                   (1.0f - d2 * (1.0f / 42.0f) * (1.0f - d2 * (1.0f / 72.0f)))));
+  c = 1.0f - d2 * 0.5f * (1.0f - d2 * (1.0f / 12.0f) *
+                                     (1.0f - d2 * (1.0f / 30.0f) * (1.0f - d2 * (1.0f / 56.0f) * (1.0f - d2 * (1.0f / 90.0f)))));
+}
+
+__device__ inline float wrap_pi(float u) {
+  const float two_pi = 6.283185307179586f;
+  const float pi = 3.14159265358979f;
+  if (u < -pi) u += two_pi;
+  if (u >= pi) u -= two_pi;
+  return u;
+}
+
+// Workgroup -> tile remap: the hardware deals consecutive workgroups round
+// robin over the 8 XCDs; giving each XCD a contiguous run of tiles keeps the
+// gather footprint of neighbouring tiles in that XCD's L2.
+__device__ inline int xcd_tile(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7;
+  const int x = b & 7, local = b >> 3;
+  return x * q + (x < r ? x : r) + local;
+}
+
+// Per-workgroup partials: max rel, sum |dV|, max |dV|, non-finite count,
+// fallback count.
+constexpr int kPartial = 5;
+
+// Wave64 + workgroup reduction of one node kernel's residual partials,
+// written to partial[block*kPartial + 0..4] in a fixed order.
+__device__ inline void block_residual(double rel, double sum, double mabs, double bad,
+                                      double fb, double* __restrict__ partial, int block) {
+  __shared__ double red[kPartial][kBlock / 64];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    rel = fmax(rel, __shfl_xor(rel, o, 64));
+    sum += __shfl_xor(sum, o, 64);
+    mabs = fmax(mabs, __shfl_xor(mabs, o, 64));
+    bad += __shfl_xor(bad, o, 64);
+    fb += __shfl_xor(fb, o, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wave] = rel;
+    red[1][wave] = sum;
+    red[2][wave] = mabs;
+    red[3][wave] = bad;
+    red[4][wave] = fb;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = red[0][0], b = red[1][0], c = red[2][0], d = red[3][0], e = red[4][0];
+    for (int w = 1; w < kBlock / 64; w++) {
+      a = fmax(a, red[0][w]);
+      b += red[1][w];
+      c = fmax(c, red[2][w]);
+      d += red[3][w];
+      e += red[4][w];
+    }
+    partial[kPartial * block + 0] = a;
+    partial[kPartial * block + 1] = b;
+    partial[kPartial * block + 2] = c;
+    partial[kPartial * block + 3] = d;
+    partial[kPartial * block + 4] = e;
+  }
+}
+
+// Per-node residual contribution: |dV| is exact in FP64 for float inputs.
+__device__ inline void node_residual(float v_old, float v_new, double& rel, double& sum,
+                                     double& mabs, double& bad) {
+  if (!isfinite(v_new)) {
+    bad += 1.0;
+    return;
+  }
+  const double d = fabs((double)v_new - (double)v_old);
+  const double den = fmax(1.0, fabs((double)v_new));
+  rel = fmax(rel, d / den);
+  sum += d;
+  mabs = fmax(mabs, d);
+}
+
+}  // namespace dpo

@@ -1,0 +1,66 @@
+// Internal interface between the host library and the HIP kernels of libdpo.
+#pragma once
+
+#include "dpo_device.h"
+
+namespace dpo {
+
+struct TargetBox {
+  double c[4], w[4];
+};
+
+// Everything a node kernel needs, passed by value as the kernel argument.
+struct SweepArgs {
+  Grid G;
+  Phys P;
+  const float* V_in;
+  float* V_out;
+  float* pol_ang;             // out, nullable
+  uint8_t* pol_thr;           // out, nullable
+  const float* pol_ang_in;    // frozen policy (evaluation sweep)
+  const uint8_t* pol_thr_in;  // frozen policy (evaluation sweep)
+  const float* seed;          // seeded search
+  const int* free_idx;
+  int n_free;
+  const float* tab_sin;  // tabulated controls (TABLE) or scan samples (SCAN_GOLDEN)
+  const float* tab_cos;
+  const float* tab_ang;
+  int n_ang;
+  int n_golden;
+  float half_width;  // golden bracket half width, 2*pi/n_scan
+  int n_local;
+  float local_half_width;
+  float fallback_tol;
+  double* partial;  // kPartial doubles per workgroup
+  int mode;         // search mode (feedback)
+  double w_time, w_fuel, lambda;
+};
+
+inline int blocks_for(long long n, int per = kBlock) { return (int)((n + per - 1) / per); }
+
+// Launch wrappers (asynchronous on `stream`); each returns the launch status.
+hipError_t launch_classify(const Grid& G, const TargetBox& tb, const uint8_t* mask, uint8_t* kind, int N,
+                           hipStream_t s);
+int compact_chunks(int N);
+hipError_t launch_compact(const uint8_t* kind, int N, int* counts, int* offsets, int* free_idx,
+                          hipStream_t s);
+hipError_t launch_init_value(const uint8_t* kind, float M, float* V, int N, hipStream_t s);
+hipError_t launch_sweep_table(const SweepArgs& a, hipStream_t s);
+hipError_t launch_sweep_scan_golden(const SweepArgs& a, hipStream_t s);
+hipError_t launch_sweep_seeded(const SweepArgs& a, hipStream_t s);
+hipError_t launch_policy_eval(const SweepArgs& a, hipStream_t s);
+hipError_t launch_resid_final(const double* partial, int nblocks, double* out, hipStream_t s);
+hipError_t launch_value_at(const float* V, const Grid& G, double M, const double x[4], double* out,
+                           hipStream_t s);
+hipError_t launch_feedback(const SweepArgs& a, const double* states, int n, double tau, float* ang,
+                           uint8_t* thr, float* q, hipStream_t s);
+hipError_t launch_mask_seed(const float* Vc, const Grid& Gc, double M, const Grid& Gf, double thresh,
+                            uint8_t* seed, int Nf, hipStream_t s);
+hipError_t launch_dilate_axis(const uint8_t* in, uint8_t* out, const Grid& G, int axis, int d, int N,
+                              hipStream_t s);
+hipError_t launch_probe_interp(const float* V, const Grid& G, float M, const float* pts, int n,
+                               float* out, hipStream_t s);
+hipError_t launch_probe_q(const SweepArgs& a, const int* nodes, const uint8_t* thr, const float* ang,
+                          int n, float* q_out, float* off_out, hipStream_t s);
+
+}  // namespace dpo

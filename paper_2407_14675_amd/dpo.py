@@ -1,0 +1,283 @@
+"""Thin Python binding of libdpo.so (the C ABI in include/dpo.h).
+
+Argument marshalling only: every step of the sweep runs in the HIP kernels of
+libdpo.  PyTorch supplies device memory (contiguous CUDA tensors on ROCm) and
+the current stream.  If the library is missing the import fails loudly; there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdpo.so")
+
+DPO_OK, DPO_ENOCONV, DPO_EINVAL, DPO_ENOMEM, DPO_EHIP, DPO_ENUMERIC = 0, 1, -1, -2, -3, -4
+MODELS = {"orbit": 0, "eikonal": 1}
+SEARCH = {"table": 0, "scan_golden": 1, "seeded": 2}
+KIND_FREE, KIND_TARGET, KIND_INACTIVE = 0, 1, 2
+
+
+class DpoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libdpo error {code}: {msg}")
+        self.code = code
+
+
+class Grid(C.Structure):
+    _fields_ = [("n", C.c_int32 * 4), ("lo", C.c_double * 4), ("hi", C.c_double * 4)]
+
+
+class Problem(C.Structure):
+    _fields_ = [("model", C.c_int32), ("mu", C.c_double), ("accel", C.c_double), ("mdot", C.c_double),
+                ("dt", C.c_double), ("lam", C.c_double), ("w_time", C.c_double), ("w_fuel", C.c_double),
+                ("M", C.c_double), ("speed", C.c_double), ("tgt_c", C.c_double * 4),
+                ("tgt_w", C.c_double * 4)]
+
+
+class Search(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("n_angles", C.c_int32), ("n_scan", C.c_int32),
+                ("n_golden", C.c_int32), ("n_local", C.c_int32), ("local_half_width", C.c_double),
+                ("fallback_tol", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("sweeps", C.c_int64), ("eval_sweeps", C.c_int64), ("evals", C.c_int64),
+                ("fallback_nodes", C.c_int64), ("resid_max_rel", C.c_double),
+                ("resid_sum_abs", C.c_double), ("resid_max_abs", C.c_double), ("seconds", C.c_double),
+                ("stalled", C.c_int32), ("converged", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load():
+    """Load libdpo.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libdpo.so not built at {LIB_PATH}: run `python -m paper_2407_14675_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+    sig = {
+        "dpo_create": [C.POINTER(Grid), C.POINTER(Problem), C.POINTER(Search), vp, C.POINTER(vp)],
+        "dpo_destroy": [vp],
+        "dpo_last_error": [vp],
+        "dpo_sizes": [vp, C.POINTER(i64), C.POINTER(i64)],
+        "dpo_get_kind": [vp, vp, vp],
+        "dpo_set_search": [vp, C.POINTER(Search)],
+        "dpo_init_value": [vp, vp, vp],
+        "dpo_bellman_sweep": [vp, vp, vp, vp, vp, vp, vp],
+        "dpo_bellman_sweep_seeded": [vp, vp, vp, vp, vp, vp, vp, vp],
+        "dpo_policy_eval_sweep": [vp, vp, vp, vp, vp, vp, vp],
+        "dpo_solve_vi": [vp, vp, vp, vp, dbl, i64, i32, C.POINTER(Stats), vp],
+        "dpo_solve_pi": [vp, vp, vp, vp, dbl, i32, i64, vp, C.POINTER(Stats), vp],
+        "dpo_value_at": [vp, vp, vp, vp, vp],
+        "dpo_extract_feedback": [vp, vp, vp, i64, dbl, vp, vp, vp, vp],
+        "dpo_mask_from_coarse": [vp, vp, C.POINTER(Grid), dbl, vp, vp, vp],
+        "dpo_probe_interp": [vp, vp, vp, i64, vp, vp],
+        "dpo_probe_q": [vp, vp, vp, vp, vp, i64, vp, vp],
+        "dpo_probe_foot": [vp, vp, vp, vp, i64, vp, vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    lib.dpo_destroy.restype = None
+    lib.dpo_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def grid_struct(problem):
+    g = Grid()
+    g.n[:] = [int(v) for v in problem["n"]]
+    g.lo[:] = [float(v) for v in problem["lo"]]
+    g.hi[:] = [float(v) for v in problem["hi"]]
+    return g
+
+
+def problem_struct(problem):
+    p = Problem()
+    p.model = MODELS[problem["model"]]
+    for f in ("mu", "accel", "mdot", "dt", "lam", "w_time", "w_fuel", "M", "speed"):
+        setattr(p, f, float(problem[f]))
+    p.tgt_c[:] = [float(v) for v in problem["tgt_c"]]
+    p.tgt_w[:] = [float(v) for v in problem["tgt_w"]]
+    return p
+
+
+def search_struct(search):
+    s = Search()
+    s.mode = SEARCH[search["mode"]]
+    s.n_angles = int(search.get("n_angles", 0))
+    s.n_scan = int(search.get("n_scan", 0))
+    s.n_golden = int(search.get("n_golden", 0))
+    s.n_local = int(search.get("n_local", 0))
+    s.local_half_width = float(search.get("local_half_width", 0.0))
+    s.fallback_tol = float(search.get("fallback_tol", 0.0))
+    return s
+
+
+def _p(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "libdpo needs contiguous device tensors"
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """One problem (grid + physics + search) on the device."""
+
+    def __init__(self, problem, mask=None, device="cuda"):
+        self.lib = load()
+        self.problem = problem
+        self.device = torch.device(device)
+        n = problem["n"]
+        self.shape = (n[3], n[2], n[1], n[0])
+        self.N = n[0] * n[1] * n[2] * n[3]
+        if mask is not None:
+            mask = mask.to(self.device, torch.uint8).contiguous().reshape(-1)
+            assert mask.numel() == self.N
+        self._g, self._pr, self._s = grid_struct(problem), problem_struct(problem), search_struct(problem["search"])
+        h = C.c_void_p()
+        torch.cuda.synchronize(self.device)
+        rc = self.lib.dpo_create(C.byref(self._g), C.byref(self._pr), C.byref(self._s), _p(mask), C.byref(h))
+        if rc != DPO_OK:
+            raise DpoError(rc, self.lib.dpo_last_error(None).decode())
+        self.h = h
+        nn, nf = C.c_int64(), C.c_int64()
+        self.lib.dpo_sizes(self.h, C.byref(nn), C.byref(nf))
+        self.n_free = nf.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dpo_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow=(DPO_OK,)):
+        if rc not in allow:
+            raise DpoError(rc, self.lib.dpo_last_error(self.h).decode())
+        return rc
+
+    # ---------------------------------------------------------- buffers
+    def empty_value(self):
+        return torch.empty(self.shape, dtype=torch.float32, device=self.device)
+
+    def empty_policy(self):
+        return (torch.zeros(self.shape, dtype=torch.float32, device=self.device),
+                torch.zeros(self.shape, dtype=torch.uint8, device=self.device))
+
+    def set_search(self, search):
+        self._s = search_struct(search)
+        self._check(self.lib.dpo_set_search(self.h, C.byref(self._s)))
+
+    def kind(self):
+        k = torch.empty(self.shape, dtype=torch.uint8, device=self.device)
+        self._check(self.lib.dpo_get_kind(self.h, _p(k), _stream()))
+        return k
+
+    def init_value(self, V=None):
+        V = self.empty_value() if V is None else V
+        self._check(self.lib.dpo_init_value(self.h, _p(V), _stream()))
+        return V
+
+    # ------------------------------------------------------------ sweeps
+    def bellman_sweep(self, V_in, V_out, pol_ang=None, pol_thr=None, resid=None):
+        return self._check(self.lib.dpo_bellman_sweep(self.h, _p(V_in), _p(V_out), _p(pol_ang), _p(pol_thr),
+                                                       _p(resid), _stream()))
+
+    def bellman_sweep_seeded(self, V_in, V_out, pol_ang, pol_thr, seed, resid=None):
+        return self._check(self.lib.dpo_bellman_sweep_seeded(self.h, _p(V_in), _p(V_out), _p(pol_ang),
+                                                              _p(pol_thr), _p(seed), _p(resid), _stream()))
+
+    def policy_eval_sweep(self, V_in, V_out, pol_ang, pol_thr, resid=None):
+        return self._check(self.lib.dpo_policy_eval_sweep(self.h, _p(V_in), _p(V_out), _p(pol_ang), _p(pol_thr),
+                                                           _p(resid), _stream()))
+
+    # ----------------------------------------------------------- solvers
+    def solve_vi(self, V, pol_ang, pol_thr, tol_rel=1e-6, max_sweeps=100000, check_every=16):
+        st = Stats()
+        rc = self.lib.dpo_solve_vi(self.h, _p(V), _p(pol_ang), _p(pol_thr), float(tol_rel), int(max_sweeps),
+                                   int(check_every), C.byref(st), _stream())
+        self._check(rc, allow=(DPO_OK, DPO_ENOCONV))
+        return rc, st.as_dict()
+
+    def solve_pi(self, V, pol_ang, pol_thr, tol_rel=1e-6, eval_sweeps=20, max_outer=100000, seed=None):
+        st = Stats()
+        rc = self.lib.dpo_solve_pi(self.h, _p(V), _p(pol_ang), _p(pol_thr), float(tol_rel), int(eval_sweeps),
+                                   int(max_outer), _p(seed), C.byref(st), _stream())
+        self._check(rc, allow=(DPO_OK, DPO_ENOCONV))
+        return rc, st.as_dict()
+
+    # ------------------------------------------------- read-out / feedback
+    def value_at(self, V, x):
+        xs = (C.c_double * 4)(*[float(v) for v in x])
+        out = C.c_double()
+        self._check(self.lib.dpo_value_at(self.h, _p(V), xs, C.byref(out), _stream()))
+        return out.value
+
+    def feedback(self, V, states, tau=None):
+        states = torch.as_tensor(states, dtype=torch.float64).to(self.device).contiguous().reshape(-1, 4)
+        n = states.shape[0]
+        ang = torch.empty(n, dtype=torch.float32, device=self.device)
+        thr = torch.empty(n, dtype=torch.uint8, device=self.device)
+        q = torch.empty(n, dtype=torch.float32, device=self.device)
+        tau = self.problem["dt"] if tau is None else tau
+        self._check(self.lib.dpo_extract_feedback(self.h, _p(V), _p(states), n, float(tau), _p(ang), _p(thr),
+                                                  _p(q), _stream()))
+        return ang, thr, q
+
+    def mask_from_coarse(self, Vc, fine_problem, thresh, dilate):
+        g = grid_struct(fine_problem)
+        n = fine_problem["n"]
+        mask = torch.empty((n[3], n[2], n[1], n[0]), dtype=torch.uint8, device=self.device)
+        dil = (C.c_int32 * 4)(*[int(d) for d in dilate])
+        self._check(self.lib.dpo_mask_from_coarse(self.h, _p(Vc), C.byref(g), float(thresh), dil, _p(mask),
+                                                  _stream()))
+        return mask
+
+    # ------------------------------------------------------------ probes
+    def probe_interp(self, V, pts):
+        pts = torch.as_tensor(pts, dtype=torch.float32).to(self.device).contiguous().reshape(-1, 4)
+        out = torch.empty(pts.shape[0], dtype=torch.float32, device=self.device)
+        self._check(self.lib.dpo_probe_interp(self.h, _p(V), _p(pts), pts.shape[0], _p(out), _stream()))
+        return out
+
+    def probe_q(self, V, nodes, thr, angle):
+        nodes = torch.as_tensor(nodes, dtype=torch.int32).to(self.device).contiguous()
+        thr = torch.as_tensor(thr, dtype=torch.uint8).to(self.device).contiguous()
+        angle = torch.as_tensor(angle, dtype=torch.float32).to(self.device).contiguous()
+        q = torch.empty(nodes.numel(), dtype=torch.float32, device=self.device)
+        torch.cuda.synchronize(self.device)
+        self._check(self.lib.dpo_probe_q(self.h, _p(V), _p(nodes), _p(thr), _p(angle), nodes.numel(), _p(q),
+                                         _stream()))
+        return q
+
+    def probe_foot(self, nodes, thr, angle):
+        nodes = torch.as_tensor(nodes, dtype=torch.int32).to(self.device).contiguous()
+        thr = torch.as_tensor(thr, dtype=torch.uint8).to(self.device).contiguous()
+        angle = torch.as_tensor(angle, dtype=torch.float32).to(self.device).contiguous()
+        off = torch.empty((nodes.numel(), 4), dtype=torch.float32, device=self.device)
+        torch.cuda.synchronize(self.device)
+        self._check(self.lib.dpo_probe_foot(self.h, _p(nodes), _p(thr), _p(angle), nodes.numel(), _p(off),
+                                            _stream()))
+        return off

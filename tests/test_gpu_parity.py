@@ -1,0 +1,376 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerances (derived from float32 arithmetic on the device against the FP64
+oracle):
+  * one Q evaluation or one sweep: |d| <= 1e-5 * max(1, |V|)
+  * converged value function: |d| <= 1e-4 * max(1, |V_oracle|)
+  * policy, on nodes whose oracle tie margin is at least 1e-4 * max(1, |V|):
+    tabulated search: same control index on >= 99.9 %; continuous search:
+    same throttle on >= 99.9 %, the device angle reaches the oracle's minimal
+    Q within 1e-5 * max(1, |V|), and the angle agrees to 1.2e-3 rad (twice
+    the final golden width) wherever Q is sharp enough to determine it
+    (see check_thrust_angles).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.core import KIND_FREE, Oracle, mask_from_coarse
+from paper_2407_14675_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dpo():
+    from paper_2407_14675_amd import dpo as mod
+    mod.load()
+    return mod
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dtype).contiguous()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel_err(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.abs(a - b) / np.maximum(1.0, np.abs(b))
+
+
+def wrapped(du):
+    return np.abs((np.asarray(du) + np.pi) % (2 * np.pi) - np.pi)
+
+
+ANGLE_TOL = 1.2e-3   # twice the final golden-section width
+
+
+def check_thrust_angles(o, V, free_clear, thr_g, ang_g, thr_o, ang_o):
+    """Thrust angles of the continuous search.
+
+    What is unique is the minimal Q: at every node where both choose thrust,
+    the device angle must reach the oracle's minimum within the per-evaluation
+    tolerance (Q is evaluated by the oracle in FP64 at both angles).  The angle
+    itself is compared only where Q rises by at least 1e-5*max(1,|V|) within
+    ANGLE_TOL on both sides of the oracle's angle; elsewhere Q is flatter than
+    float32 resolves and every angle in the flat band is a correct answer.
+    """
+    both = free_clear & (thr_g == 1) & (thr_o == 1)
+    nodes = np.flatnonzero(both.reshape(-1))
+    if nodes.size == 0:
+        return 0, 0
+    one = np.ones(nodes.size, dtype=np.uint8)
+    uo = ang_o.reshape(-1)[nodes]
+    ug = ang_g.reshape(-1)[nodes].astype(np.float64)
+    q_o = o.q_many(V, nodes, one, uo)
+    q_g = o.q_many(V, nodes, one, ug)
+    scale = np.maximum(1.0, np.abs(q_o))
+    assert np.all(q_g - q_o <= 1e-5 * scale), np.max((q_g - q_o) / scale)
+    q_lo = o.q_many(V, nodes, one, uo - ANGLE_TOL)
+    q_hi = o.q_many(V, nodes, one, uo + ANGLE_TOL)
+    sharp = (np.minimum(q_lo, q_hi) - q_o) >= 1e-5 * scale
+    if sharp.sum():
+        assert (wrapped(ug[sharp] - uo[sharp]) <= ANGLE_TOL).mean() >= 0.999
+    return int(nodes.size), int(sharp.sum())
+
+
+# ------------------------------------------------------------- a1 kinds
+@pytest.mark.parametrize("n", [(12, 12, 12, 12), (7, 9, 5, 6)])
+def test_classification_and_compaction(dpo, n):
+    p = inputs.with_grid(inputs.CONFIG0, n)
+    _say("classify", n)
+    rng = np.random.default_rng(5)
+    mask = (rng.random(tuple(reversed(n))) < 0.6).astype(np.uint8)
+    o = Oracle(p, mask=mask)
+    ctx = dpo.Context(p, mask=dev(mask, torch.uint8))
+    k = host(ctx.kind())
+    np.testing.assert_array_equal(k, o.kind)
+    assert ctx.n_free == int((o.kind == KIND_FREE).sum())
+
+
+# ----------------------------------------------------- a2..a4 probes
+def test_probe_interp_multilinear(dpo):
+    p = inputs.orbit_problem((5, 6, 7, 4))
+    _say("probe_interp")
+    o = Oracle(p)
+    rng = np.random.default_rng(11)
+    V = rng.uniform(-3, 3, size=(4, 7, 6, 5))
+    n = np.array(p["n"])
+    pts = rng.random((5000, 4)) * (n - 1)
+    pts[:50] = np.floor(pts[:50])          # nodes
+    pts[50:60, 0] = n[0] - 1               # top faces
+    pts[60:70, 3] = 0.0                    # bottom faces
+    ctx = dpo.Context(p)
+    got = host(ctx.probe_interp(dev(V), pts))
+    Vf = V.astype(np.float32).astype(np.float64)
+    want = np.array([o.interp(Vf, s.astype(np.float32).astype(np.float64)) for s in pts])
+    assert np.max(np.abs(got - want)) < 2e-6 * 3
+    out = np.array([[-1e-3, 1, 1, 1], [1, 1, 1, n[3] - 1 + 1e-3]], dtype=np.float32)
+    assert np.all(host(ctx.probe_interp(dev(V), out)) == p["M"])
+
+
+def test_probe_foot_matches_oracle(dpo):
+    p = inputs.CONFIG0
+    _say("probe_foot")
+    o = Oracle(p)
+    nodes = inputs.random_nodes(p, 3000, seed=7)
+    rng = np.random.default_rng(8)
+    thr = rng.integers(0, 2, size=nodes.size).astype(np.uint8)
+    ang = rng.uniform(-math.pi, math.pi, size=nodes.size).astype(np.float32)
+    ctx = dpo.Context(p)
+    off = host(ctx.probe_foot(nodes, thr, ang))
+    lo = np.array(p["lo"])
+    h = (np.array(p["hi"]) - lo) / (np.array(p["n"]) - 1)
+    for c in range(nodes.size):
+        x = o.node_coords(int(nodes[c]))
+        z = o.step(x, int(thr[c]), float(ang[c]))
+        want = (z - x) / h
+        np.testing.assert_allclose(off[c], want, atol=2e-6, rtol=0)
+
+
+def test_probe_q_matches_oracle(dpo):
+    p = inputs.CONFIG0
+    _say("probe_q")
+    o = Oracle(p)
+    V = inputs.random_value(p, seed=3, frac_M=0.05).astype(np.float32)
+    nodes = inputs.random_nodes(p, 4000, seed=9)
+    rng = np.random.default_rng(10)
+    thr = rng.integers(0, 2, size=nodes.size).astype(np.uint8)
+    ang = rng.uniform(-math.pi, math.pi, size=nodes.size).astype(np.float32)
+    ctx = dpo.Context(p)
+    q = host(ctx.probe_q(dev(V), nodes, thr, ang))
+    want = np.array([o.q(V.astype(np.float64), int(j), int(t), float(a)) for j, t, a in zip(nodes, thr, ang)])
+    assert np.max(rel_err(q, want)) < 1e-5
+
+
+# ------------------------------------------------------- a5..a8 sweeps
+def _sweep_both(dpo, p, V, mask=None, search=None):
+    o = Oracle(p, mask=mask)
+    ctx = dpo.Context(p, mask=None if mask is None else dev(mask, torch.uint8))
+    if search is not None:
+        ctx.set_search(search)
+    Vin = dev(V)
+    Vout = Vin.clone()
+    ang, thr = ctx.empty_policy()
+    resid = torch.zeros(5, dtype=torch.float64, device="cuda")
+    ctx.bellman_sweep(Vin, Vout, ang, thr, resid)
+    Vo, ango, thro, margin = o.bellman_sweep(V.astype(np.float32).astype(np.float64), search=search)
+    return o, ctx, host(Vout), host(ang), host(thr), host(resid), Vo, ango, thro, margin
+
+
+@pytest.mark.parametrize("which", ["random", "converged"])
+def test_table_sweep_parity(dpo, which):
+    p = inputs.CONFIG0
+    _say("table sweep", which)
+    if which == "random":
+        V = inputs.random_value(p, seed=21, frac_M=0.1)
+    else:
+        V = np.load("tests/golden/cfg0_vi.npz")["V"]
+    V32 = V.astype(np.float32)
+    o, ctx, Vg, ag, tg, res, Vo, ao, to, margin = _sweep_both(dpo, p, V32)
+    free = o.kind == KIND_FREE
+    assert np.max(rel_err(Vg[free], Vo[free])) < 1e-5
+    clear = free & (margin >= 1e-4 * np.maximum(1.0, np.abs(Vo)))
+    agree = (tg[clear] == to[clear]) & ((to[clear] == 0) | (wrapped(ag[clear] - ao[clear]) < 1e-6))
+    # coast or not, the best thrust angle is the same table entry where no tie
+    assert agree.mean() >= 0.999
+    # FP64 residual of the same float arrays
+    want = o.residual(V32.astype(np.float64), Vg.astype(np.float64))
+    assert res[0] == want["max_rel"] and res[2] == want["max_abs"]
+    assert res[1] == pytest.approx(want["sum_abs"], rel=1e-12)
+    assert res[3] == 0
+
+
+def test_scan_golden_sweep_parity(dpo):
+    p = inputs.with_grid(inputs.CONFIG1, (10, 10, 10, 10))
+    _say("scan-golden sweep")
+    V = inputs.random_value(p, seed=23, low=0, high=30)
+    # smooth it so that Q(u) is unimodal enough for the search to be meaningful
+    ax = [np.linspace(p["lo"][k], p["hi"][k], p["n"][k]) for k in range(4)]
+    R, VR, VT, MM = np.meshgrid(*ax, indexing="ij")
+    V = (400 * (R - 1.05) ** 2 + 900 * VR ** 2 + 2000 * (VT - 0.976) ** 2 + 50 * (1 - MM)).transpose(3, 2, 1, 0)
+    V32 = V.astype(np.float32)
+    o, ctx, Vg, ag, tg, res, Vo, ao, to, margin = _sweep_both(dpo, p, V32)
+    free = o.kind == KIND_FREE
+    assert np.max(rel_err(Vg[free], Vo[free])) < 1e-5
+    clear = free & (margin >= 1e-4 * np.maximum(1.0, np.abs(Vo)))
+    same_thr = tg[clear] == to[clear]
+    assert same_thr.mean() >= 0.999
+    n_thr, n_sharp = check_thrust_angles(o, V32.astype(np.float64), clear, tg, ag, to, ao)
+    _say("  thrust nodes", n_thr, "sharp", n_sharp)
+
+
+def test_policy_eval_parity(dpo):
+    p = inputs.CONFIG0
+    _say("policy eval")
+    o = Oracle(p)
+    V = inputs.random_value(p, seed=31, frac_M=0.1).astype(np.float32)
+    rng = np.random.default_rng(32)
+    thr = rng.integers(0, 2, size=o.shape).astype(np.uint8)
+    ang = rng.uniform(-math.pi, math.pi, size=o.shape).astype(np.float32)
+    ctx = dpo.Context(p)
+    Vin = dev(V)
+    Vout = Vin.clone()
+    resid = torch.zeros(5, dtype=torch.float64, device="cuda")
+    ctx.policy_eval_sweep(Vin, Vout, dev(ang), dev(thr, torch.uint8), resid)
+    Vo = o.policy_eval_sweep(V.astype(np.float64), ang.astype(np.float64), thr)
+    free = o.kind == KIND_FREE
+    assert np.max(rel_err(host(Vout)[free], Vo[free])) < 1e-5
+
+
+# ------------------------------------------------------------- solvers
+def test_cfg0_value_iteration_parity(dpo):
+    """12^4, 16 angles + coast, VI to convergence vs the stored oracle solution."""
+    p = inputs.CONFIG0
+    _say("cfg0 VI")
+    gold = np.load("tests/golden/cfg0_vi.npz")
+    o = Oracle(p)
+    ctx = dpo.Context(p)
+    V = ctx.init_value()
+    ang, thr = ctx.empty_policy()
+    rc, st = ctx.solve_vi(V, ang, thr, tol_rel=1e-7, max_sweeps=20000, check_every=8)
+    _say("  sweeps", st["sweeps"], "resid", st["resid_max_rel"], "seconds", st["seconds"])
+    assert st["converged"] or st["stalled"]
+    Vg = host(V)
+    free = o.kind == KIND_FREE
+    err = rel_err(Vg, gold["V"])
+    assert err[free].max() <= 1e-4, err.max()
+    # policy agreement away from ties (margin from one oracle sweep at the fixed point)
+    _, _, _, margin = o.bellman_sweep(gold["V"])
+    clear = free & (margin >= 1e-4 * np.maximum(1.0, np.abs(gold["V"])))
+    tg, ag = host(thr), host(ang)
+    agree = (tg[clear] == gold["thr"][clear]) & (wrapped(ag[clear] - gold["angle"][clear]) < 1e-6)
+    assert agree.mean() >= 0.999
+    assert ctx.value_at(V, inputs.X0) == pytest.approx(o.value_at(gold["V"], inputs.X0), rel=1e-4)
+
+
+def test_pi_matches_vi_on_device(dpo):
+    """Value and policy iteration on the device reach the same fixed point."""
+    p = inputs.CONFIG0
+    _say("cfg0 PI vs VI")
+    ctx = dpo.Context(p)
+    V1 = ctx.init_value()
+    a1, t1 = ctx.empty_policy()
+    ctx.solve_vi(V1, a1, t1, tol_rel=1e-7, max_sweeps=20000, check_every=8)
+    V2 = ctx.init_value()
+    a2, t2 = ctx.empty_policy()
+    rc, st = ctx.solve_pi(V2, a2, t2, tol_rel=1e-7, eval_sweeps=20, max_outer=5000)
+    _say("  PI outer", st["sweeps"], "evals", st["evals"])
+    assert np.max(rel_err(host(V2), host(V1))) <= 1e-4
+
+
+def test_small_pi_scan_golden_parity(dpo):
+    """Modified PI (scan 64 + golden 12, 20 evaluation sweeps) on 10^4 against the oracle."""
+    p = inputs.with_grid(inputs.CONFIG1, (10, 10, 10, 10))
+    _say("small PI scan-golden")
+    o = Oracle(p)
+    ref = o.solve_pi(tol_abs=1e-8, eval_sweeps=20)
+    assert ref["converged"]
+    ctx = dpo.Context(p)
+    V = ctx.init_value()
+    ang, thr = ctx.empty_policy()
+    rc, st = ctx.solve_pi(V, ang, thr, tol_rel=1e-7, eval_sweeps=20, max_outer=5000)
+    _say("  outer", st["sweeps"], "oracle outer", ref["outer"])
+    free = o.kind == KIND_FREE
+    Vg = host(V)
+    assert rel_err(Vg, ref["V"])[free].max() <= 1e-4
+    _, _, _, margin = o.bellman_sweep(ref["V"])
+    clear = free & (margin >= 1e-4 * np.maximum(1.0, np.abs(ref["V"])))
+    tg, ag = host(thr), host(ang)
+    assert (tg[clear] == ref["thr"][clear]).mean() >= 0.999
+    n_thr, n_sharp = check_thrust_angles(o, ref["V"], clear, tg, ag, ref["thr"], ref["angle"])
+    _say("  thrust nodes", n_thr, "sharp", n_sharp)
+
+
+def test_eikonal_on_device(dpo):
+    """2-D minimum time: exact |x|/s on the axis nodes (float32 rounding)."""
+    p = inputs.eikonal_problem(17)
+    _say("eikonal")
+    ctx = dpo.Context(p)
+    V = ctx.init_value()
+    ang, thr = ctx.empty_policy()
+    rc, st = ctx.solve_vi(V, ang, thr, tol_rel=0.0, max_sweeps=400, check_every=8)
+    Vg = host(V)
+    h = 2.0 / 16
+    for i in range(-8, 9):
+        assert Vg[0, 8 + i, 8, 0] == pytest.approx(abs(i) * h, abs=2e-6)
+        assert Vg[0, 8, 8 + i, 0] == pytest.approx(abs(i) * h, abs=2e-6)
+
+
+# ---------------------------------------------------- a9 read-out, feedback
+def test_value_at_and_feedback_parity(dpo):
+    p = inputs.CONFIG0
+    _say("value_at / feedback")
+    gold = np.load("tests/golden/cfg0_vi.npz")
+    o = Oracle(p)
+    ctx = dpo.Context(p)
+    Vd = dev(gold["V"])
+    V32 = gold["V"].astype(np.float32).astype(np.float64)
+    states = inputs.random_states(p, 500, seed=41)
+    for x in states[:50]:
+        assert ctx.value_at(Vd, x) == pytest.approx(o.value_at(V32, x), rel=1e-12, abs=1e-9)
+    ang, thr, q = ctx.feedback(Vd, states)
+    ao, to, qo = o.feedback(V32, states)
+    assert np.max(rel_err(host(q), qo)) < 1e-5
+    qo_margin = []
+    agree = (host(thr) == to)
+    assert agree.mean() >= 0.98
+
+
+# ----------------------------------------------------------- a1 mask
+def test_mask_from_coarse_parity(dpo):
+    _say("mask")
+    gold = np.load("tests/golden/cfg0_vi.npz")
+    Vc32 = gold["V"].astype(np.float32)
+    fine = inputs.with_grid(inputs.CONFIG1, (24, 24, 24, 24))
+    thresh = inputs.MASK_THRESHOLD_FRAC * inputs.CONFIG0["M"]
+    want = mask_from_coarse(inputs.CONFIG0, Vc32.astype(np.float64), fine, inputs.MASK_DILATE, thresh)
+    ctx = dpo.Context(inputs.CONFIG0)
+    got = host(ctx.mask_from_coarse(dev(Vc32), fine, thresh, inputs.MASK_DILATE))
+    np.testing.assert_array_equal(got, want)
+
+
+# ------------------------------------------------------------ ABI errors
+def test_abi_error_paths(dpo):
+    _say("abi errors")
+    import copy
+    p = copy.deepcopy(inputs.CONFIG0)
+    bad = inputs.with_grid(p, (1, 12, 12, 12))
+    with pytest.raises(dpo.DpoError) as e:
+        dpo.Context(bad)
+    assert e.value.code == dpo.DPO_EINVAL
+    p2 = copy.deepcopy(p)
+    p2["search"] = dict(mode="scan_golden", n_scan=4, n_golden=12)
+    with pytest.raises(dpo.DpoError):
+        dpo.Context(p2)
+    ctx = dpo.Context(p)
+    V = ctx.init_value()
+    with pytest.raises(dpo.DpoError) as e:
+        ctx.bellman_sweep(V, V)
+    assert e.value.code == dpo.DPO_EINVAL
+    with pytest.raises(dpo.DpoError):
+        ctx.probe_q(V, np.array([ctx.N + 5]), np.array([1]), np.array([0.0]))
+    # non-finite values are reported, not hidden
+    Vn = V.clone()
+    Vn.view(-1)[int(np.flatnonzero(host(ctx.kind()).reshape(-1) == 0)[0])] = float("nan")
+    ang, thr = ctx.empty_policy()
+    with pytest.raises(dpo.DpoError) as e:
+        ctx.solve_vi(Vn, ang, thr, tol_rel=1e-7, max_sweeps=16, check_every=1)
+    assert e.value.code == dpo.DPO_ENUMERIC
+    # max_sweeps exhausted -> ENOCONV with valid output
+    V = ctx.init_value()
+    rc, st = ctx.solve_vi(V, ang, thr, tol_rel=1e-12, max_sweeps=5, check_every=1)
+    assert rc == dpo.DPO_ENOCONV and st["sweeps"] == 5
