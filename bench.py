@@ -85,6 +85,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-converge", action="store_true", help="skip the time-to-converge run")
+    ap.add_argument("--path", type=int, default=0, help="sweep kernel path: 0 auto, 1 direct, 2 factorised")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding along the "
@@ -109,6 +110,7 @@ def main():
     p1 = inputs.CONFIG1
     mask = c0.mask_from_coarse(Vc, p1, inputs.MASK_THRESHOLD_FRAC * p1["M"], inputs.MASK_DILATE)
     ctx = dpo.Context(p1, mask=mask)
+    ctx.set_kernel_path(args.path)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
     n_free = ctx.n_free
@@ -207,7 +209,7 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "k_sweep_scan_golden",
+            "kernel": "k_sweep_fast<1>" if ctx.kernel_path() == 2 else "k_sweep_direct<1>",
             "achieved": achieved_tflops,
             "peak": VALU_PEAK_TFLOPS,
             "unit": "TFLOP/s",

@@ -58,7 +58,8 @@ enum { DPO_KIND_FREE = 0, DPO_KIND_TARGET = 1, DPO_KIND_INACTIVE = 2 };
 
 /* Closed uniform grid (paper Section 3, "Grid and polar coordinates"):
  * node i_k of axis k sits at lo[k] + i_k*(hi[k]-lo[k])/(n[k]-1).  Axis order
- * (r, v_r, v_t, m).  Requires n[k] >= 2 and lo[k] < hi[k]. */
+ * (r, v_r, v_t, m).  Requires 2 <= n[k] <= 256, lo[k] < hi[k] and at most
+ * 2^30 nodes in total. */
 typedef struct {
   int32_t n[4];
   double lo[4], hi[4];
@@ -135,6 +136,17 @@ int dpo_sizes(const dpo_ctx* ctx, int64_t* n_nodes, int64_t* n_free);
 
 /* Copy the node kinds (DPO_KIND_*) into a device u8[N]. */
 int dpo_get_kind(dpo_ctx* ctx, uint8_t* kind, void* stream);
+
+/* Kernel path of the Bellman sweeps: 0 = automatic, 1 = direct (every
+ * evaluation gathers its 16 corners), 2 = factorised (thrust feet share their
+ * r and m cells, so each node collapses its neighbourhood over r and m once;
+ * applies when every thrust foot stays within two cells along v_r and v_t and
+ * one cell along m).  Both give the same Q1 values up to rounding order.
+ * Returns DPO_EINVAL for 2 where it does not apply. */
+int dpo_set_kernel_path(dpo_ctx* ctx, int32_t path);
+
+/* The path the sweeps take now: 1 direct, 2 factorised (negative on error). */
+int dpo_kernel_path(const dpo_ctx* ctx);
 
 /* Replace the search settings (same rules as in dpo_create). */
 int dpo_set_search(dpo_ctx* ctx, const dpo_search* search);

@@ -7,6 +7,7 @@
 // host synchronises only to read the FP64 residual every few sweeps.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -28,7 +29,13 @@ struct dpo_ctx {
   TargetBox tb;
   int64_t N = 0, n_free = 0;
   uint8_t* kind = nullptr;
-  int* free_idx = nullptr;
+  uint32_t* free_node = nullptr;  // packed coordinates of the free nodes, node order
+  double* rinv = nullptr;         // 1/r per r node (FP64)
+  float* gtab = nullptr;          // [2][n_m]: thrust displacement per unit sin (v_r) / cos (v_t)
+  double c0 = 0, c1 = 0, c2 = 0;  // dt/h for r, v_r, v_t
+  float gm = 0;                   // thrust displacement along m
+  bool fast_ok = false;           // the factorised thrust kernel applies
+  int path = 0;                   // 0 auto, 1 direct, 2 fast
   float* tab = nullptr;  // [3][n_ang]: sin, cos, angle
   int n_ang = 0;
   int tab_cap = 0;
@@ -67,6 +74,7 @@ int validate_grid(dpo_ctx* c, const dpo_grid* g) {
     if (g->n[k] < 2) return fail(c, DPO_EINVAL, "grid: n[k] must be >= 2");
     if (!(g->lo[k] < g->hi[k]) || !std::isfinite(g->lo[k]) || !std::isfinite(g->hi[k]))
       return fail(c, DPO_EINVAL, "grid: need finite lo[k] < hi[k]");
+    if (g->n[k] > 256) return fail(c, DPO_EINVAL, "grid: at most 256 nodes per axis");
     N *= g->n[k];
   }
   if (N > 0x7fffffffLL / 2) return fail(c, DPO_EINVAL, "grid: too many nodes (limit 2^30)");
@@ -148,8 +156,15 @@ SweepArgs base_args(const dpo_ctx* c) {
   std::memset(&a, 0, sizeof(a));
   a.G = c->G;
   a.P = c->P;
-  a.free_idx = c->free_idx;
+  a.free_node = c->free_node;
   a.n_free = (int)c->n_free;
+  a.rinv = c->rinv;
+  a.g1tab = c->gtab;
+  a.g2tab = c->gtab + c->grid.n[3];
+  a.c0 = c->c0;
+  a.c1 = c->c1;
+  a.c2 = c->c2;
+  a.gm = c->gm;
   a.tab_sin = c->tab;
   a.tab_cos = c->tab + c->n_ang;
   a.tab_ang = c->tab + 2 * c->n_ang;
@@ -199,6 +214,8 @@ int64_t evals_per_full_search(const dpo_ctx* c) {
   return 1 + c->search.n_scan + (c->search.n_golden > 0 ? 2 + c->search.n_golden : 0);
 }
 
+bool use_fast(const dpo_ctx* c) { return c->path == 2 || (c->path == 0 && c->fast_ok); }
+
 int sweep_full(dpo_ctx* c, const float* Vin, float* Vout, float* ang, uint8_t* thr, hipStream_t s) {
   SweepArgs a = base_args(c);
   a.V_in = Vin;
@@ -206,7 +223,10 @@ int sweep_full(dpo_ctx* c, const float* Vin, float* Vout, float* ang, uint8_t* t
   a.pol_ang = ang;
   a.pol_thr = thr;
   if (a.n_free == 0) return DPO_OK;
-  hipError_t e = c->search.mode == DPO_SEARCH_TABLE ? launch_sweep_table(a, s) : launch_sweep_scan_golden(a, s);
+  const int mode = c->search.mode == DPO_SEARCH_TABLE ? 0 : 1;
+  hipError_t e;
+  if (use_fast(c)) e = launch_sweep_fast(a, mode, s);
+  else e = mode == 0 ? launch_sweep_table(a, s) : launch_sweep_scan_golden(a, s);
   if (e != hipSuccess) return hip_fail(c, e, "bellman sweep launch");
   return DPO_OK;
 }
@@ -220,19 +240,20 @@ int sweep_seeded(dpo_ctx* c, const float* Vin, float* Vout, float* ang, uint8_t*
   a.pol_thr = thr;
   a.seed = seed;
   if (a.n_free == 0) return DPO_OK;
-  hipError_t e = launch_sweep_seeded(a, s);
+  hipError_t e = use_fast(c) ? launch_sweep_fast(a, 2, s) : launch_sweep_seeded(a, s);
   if (e != hipSuccess) return hip_fail(c, e, "seeded sweep launch");
   return DPO_OK;
 }
 
-int sweep_eval(dpo_ctx* c, const float* Vin, float* Vout, const float* ang, const uint8_t* thr, hipStream_t s) {
+int sweep_eval(dpo_ctx* c, const float* Vin, float* Vout, const float* ang, const uint8_t* thr, bool want_resid,
+               hipStream_t s) {
   SweepArgs a = base_args(c);
   a.V_in = Vin;
   a.V_out = Vout;
   a.pol_ang_in = ang;
   a.pol_thr_in = thr;
   if (a.n_free == 0) return DPO_OK;
-  hipError_t e = launch_policy_eval(a, s);
+  hipError_t e = launch_policy_eval(a, want_resid, s);
   if (e != hipSuccess) return hip_fail(c, e, "policy eval launch");
   return DPO_OK;
 }
@@ -290,14 +311,49 @@ int dpo_create(const dpo_grid* grid, const dpo_problem* prob, const dpo_search* 
     }
     return code;
   };
-  if (hipMalloc(&c->kind, (size_t)N) != hipSuccess || hipMalloc(&c->free_idx, sizeof(int) * (size_t)N) != hipSuccess ||
+  if (hipMalloc(&c->kind, (size_t)N) != hipSuccess || hipMalloc(&c->free_node, sizeof(uint32_t) * (size_t)N) != hipSuccess ||
+      hipMalloc(&c->rinv, sizeof(double) * grid->n[0]) != hipSuccess ||
+      hipMalloc(&c->gtab, sizeof(float) * 2 * grid->n[3]) != hipSuccess ||
       hipMalloc(&counts, sizeof(int) * nch) != hipSuccess || hipMalloc(&offsets, sizeof(int) * (nch + 1)) != hipSuccess ||
       hipMalloc(&c->resid, sizeof(double) * kPartial) != hipSuccess) {
     c->err = "device allocation failed in dpo_create";
     return cleanup(DPO_ENOMEM);
   }
+  // Per-axis tables: 1/r per r node (FP64), thrust displacement per m plane.
+  {
+    std::vector<double> rinv(grid->n[0]);
+    for (int i = 0; i < grid->n[0]; i++) {
+      const double r = grid->lo[0] + i * c->G.h[0];
+      rinv[i] = prob->model == DPO_MODEL_ORBIT ? 1.0 / r : 0.0;
+    }
+    const int nm = grid->n[3];
+    std::vector<float> gt(2 * nm);
+    double gmax = 0;
+    for (int i = 0; i < nm; i++) {
+      const double m = grid->lo[3] + i * c->G.h[3];
+      const double acc = prob->model == DPO_MODEL_ORBIT ? prob->accel / m : prob->speed;
+      const double g1 = prob->dt * acc * c->G.inv_h[1], g2 = prob->dt * acc * c->G.inv_h[2];
+      gt[i] = (float)g1;
+      gt[nm + i] = (float)g2;
+      gmax = std::max(gmax, std::max(std::fabs(g1), std::fabs(g2)));
+    }
+    c->c0 = prob->dt * c->G.inv_h[0];
+    c->c1 = prob->dt * c->G.inv_h[1];
+    c->c2 = prob->dt * c->G.inv_h[2];
+    const double gm = prob->model == DPO_MODEL_ORBIT ? -prob->dt * prob->mdot * c->G.inv_h[3] : 0.0;
+    c->gm = (float)gm;
+    // the factorised thrust kernel needs every thrust foot of a node within two
+    // cells per moving axis and within one m cell
+    c->fast_ok = gmax < 0.45 && gm > -1.0 && gm <= 0.0;
+    hipError_t e1 = hipMemcpy(c->rinv, rinv.data(), sizeof(double) * rinv.size(), hipMemcpyHostToDevice);
+    hipError_t e2 = hipMemcpy(c->gtab, gt.data(), sizeof(float) * gt.size(), hipMemcpyHostToDevice);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+      c->err = "dpo_create: table upload failed";
+      return cleanup(DPO_EHIP);
+    }
+  }
   hipError_t e = launch_classify(c->G, c->tb, active_mask, c->kind, N, nullptr);
-  if (e == hipSuccess) e = launch_compact(c->kind, N, counts, offsets, c->free_idx, nullptr);
+  if (e == hipSuccess) e = launch_compact(c->G, c->kind, N, counts, offsets, c->free_node, nullptr);
   int total = 0;
   if (e == hipSuccess) e = hipMemcpy(&total, offsets + nch, sizeof(int), hipMemcpyDeviceToHost);
   if (e != hipSuccess) {
@@ -318,7 +374,9 @@ int dpo_create(const dpo_grid* grid, const dpo_problem* prob, const dpo_search* 
 void dpo_destroy(dpo_ctx* c) {
   if (!c) return;
   if (c->kind) hipFree(c->kind);
-  if (c->free_idx) hipFree(c->free_idx);
+  if (c->free_node) hipFree(c->free_node);
+  if (c->rinv) hipFree(c->rinv);
+  if (c->gtab) hipFree(c->gtab);
   if (c->tab) hipFree(c->tab);
   if (c->partial) hipFree(c->partial);
   if (c->resid) hipFree(c->resid);
@@ -338,6 +396,19 @@ int dpo_get_kind(dpo_ctx* c, uint8_t* kind, void* stream) {
   if (!kind) return fail(c, DPO_EINVAL, "kind is NULL");
   HIP_TRY(c, hipMemcpyAsync(kind, c->kind, (size_t)c->N, hipMemcpyDeviceToDevice, S(stream)));
   return DPO_OK;
+}
+
+int dpo_set_kernel_path(dpo_ctx* c, int32_t path) {
+  if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
+  if (path < 0 || path > 2) return fail(c, DPO_EINVAL, "path must be 0 (auto), 1 (direct) or 2 (factorised)");
+  if (path == 2 && !c->fast_ok) return fail(c, DPO_EINVAL, "the factorised kernel does not apply to this problem");
+  c->path = path;
+  return DPO_OK;
+}
+
+int dpo_kernel_path(const dpo_ctx* c) {
+  if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
+  return use_fast(c) ? 2 : 1;
 }
 
 int dpo_set_search(dpo_ctx* c, const dpo_search* search) {
@@ -382,7 +453,7 @@ int dpo_policy_eval_sweep(dpo_ctx* c, const float* V_in, float* V_out, const flo
   if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
   if (!V_in || !V_out || !pol_angle || !pol_thr) return fail(c, DPO_EINVAL, "null array argument");
   if (V_in == V_out) return fail(c, DPO_EINVAL, "V_in and V_out must differ (Jacobi sweep)");
-  int rc = sweep_eval(c, V_in, V_out, pol_angle, pol_thr, S(stream));
+  int rc = sweep_eval(c, V_in, V_out, pol_angle, pol_thr, resid != nullptr, S(stream));
   if (rc != DPO_OK) return rc;
   return finish_resid(c, resid, S(stream));
 }
@@ -493,7 +564,7 @@ int dpo_solve_pi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, doubl
       break;
     }
     for (int e = 0; e < eval_sweeps; e++) {
-      if ((rc = sweep_eval(c, cur, nxt, pol_angle, pol_thr, s)) != DPO_OK) return rc;
+      if ((rc = sweep_eval(c, cur, nxt, pol_angle, pol_thr, false, s)) != DPO_OK) return rc;
       std::swap(cur, nxt);
     }
     local.eval_sweeps += eval_sweeps;

@@ -77,6 +77,18 @@ __device__ inline void state_terms(const Grid& G, const Phys& P, const double x[
   }
 }
 
+__device__ inline uint32_t pack_node(const int i[4]) {
+  return (uint32_t)i[0] | ((uint32_t)i[1] << 8) | ((uint32_t)i[2] << 16) | ((uint32_t)i[3] << 24);
+}
+
+__device__ inline int unpack_node(const Grid& G, uint32_t p, int i[4]) {
+  i[0] = (int)(p & 0xffu);
+  i[1] = (int)((p >> 8) & 0xffu);
+  i[2] = (int)((p >> 16) & 0xffu);
+  i[3] = (int)(p >> 24);
+  return i[0] + i[1] * G.st[1] + i[2] * G.st[2] + i[3] * G.st[3];
+}
+
 __device__ inline void node_terms(const Grid& G, const Phys& P, int j, double tau, NodeTerms& T) {
   decode_node(G, j, T.i);
   double x[4];
@@ -85,7 +97,8 @@ __device__ inline void node_terms(const Grid& G, const Phys& P, int j, double ta
   state_terms(G, P, x, tau, T.drift, T.g1, T.g2, T.gm);
 }
 
-__device__ inline float lerp(float a, float b, float t) { return fmaf(t, b - a, a); }
+// (1 - t) a + t b, exact at t = 0 and t = 1 (feet on nodes and faces).
+__device__ inline float lerp(float a, float b, float t) { return fmaf(t, b, fmaf(-t, a, a)); }
 
 // Q1 interpolation of V at s = i + off (paper Section 3: multilinear I[V],
 // M outside the closed box).  Cell base_k = min(floor(s_k), n_k - 2),

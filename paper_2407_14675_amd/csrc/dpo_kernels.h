@@ -20,8 +20,14 @@ struct SweepArgs {
   const float* pol_ang_in;    // frozen policy (evaluation sweep)
   const uint8_t* pol_thr_in;  // frozen policy (evaluation sweep)
   const float* seed;          // seeded search
-  const int* free_idx;
+  const uint32_t* free_node;  // packed coordinates (8 bits per axis, r lowest) of the free nodes
   int n_free;
+  // per-axis / per-plane tables (FP64 1/r; thrust displacement per unit sin/cos per mass plane)
+  const double* rinv;
+  const float* g1tab;
+  const float* g2tab;
+  double c0, c1, c2;  // dt / h_k for axes r, v_r, v_t
+  float gm;           // thrust displacement along m (cells)
   const float* tab_sin;  // tabulated controls (TABLE) or scan samples (SCAN_GOLDEN)
   const float* tab_cos;
   const float* tab_ang;
@@ -42,13 +48,14 @@ inline int blocks_for(long long n, int per = kBlock) { return (int)((n + per - 1
 hipError_t launch_classify(const Grid& G, const TargetBox& tb, const uint8_t* mask, uint8_t* kind, int N,
                            hipStream_t s);
 int compact_chunks(int N);
-hipError_t launch_compact(const uint8_t* kind, int N, int* counts, int* offsets, int* free_idx,
-                          hipStream_t s);
+hipError_t launch_compact(const Grid& G, const uint8_t* kind, int N, int* counts, int* offsets,
+                          uint32_t* free_node, hipStream_t s);
 hipError_t launch_init_value(const uint8_t* kind, float M, float* V, int N, hipStream_t s);
 hipError_t launch_sweep_table(const SweepArgs& a, hipStream_t s);
 hipError_t launch_sweep_scan_golden(const SweepArgs& a, hipStream_t s);
 hipError_t launch_sweep_seeded(const SweepArgs& a, hipStream_t s);
-hipError_t launch_policy_eval(const SweepArgs& a, hipStream_t s);
+hipError_t launch_policy_eval(const SweepArgs& a, bool want_resid, hipStream_t s);
+hipError_t launch_sweep_fast(const SweepArgs& a, int mode, hipStream_t s);
 hipError_t launch_resid_final(const double* partial, int nblocks, double* out, hipStream_t s);
 hipError_t launch_value_at(const float* V, const Grid& G, double M, const double x[4], double* out,
                            hipStream_t s);

@@ -87,9 +87,9 @@ __global__ __launch_bounds__(1024) void k_scan_counts(const int* __restrict__ co
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scatter_free(const uint8_t* __restrict__ kind, int N,
+__global__ __launch_bounds__(kBlock) void k_scatter_free(Grid G, const uint8_t* __restrict__ kind, int N,
                                                          const int* __restrict__ offsets,
-                                                         int* __restrict__ free_idx) {
+                                                         uint32_t* __restrict__ free_node) {
   __shared__ int wave_tot[kBlock / 64];
   __shared__ int running;
   const int base = blockIdx.x * kChunk;
@@ -105,7 +105,11 @@ __global__ __launch_bounds__(kBlock) void k_scatter_free(const uint8_t* __restri
     __syncthreads();
     int wave_off = 0;
     for (int w = 0; w < wave; w++) wave_off += wave_tot[w];
-    if (f) free_idx[running + wave_off + below] = j;
+    if (f) {
+      int i[4];
+      decode_node(G, j, i);
+      free_node[running + wave_off + below] = pack_node(i);
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
       int s = 0;
@@ -123,63 +127,51 @@ __global__ __launch_bounds__(kBlock) void k_init_value(const uint8_t* __restrict
 }
 
 // --------------------------------------------------------------- a2..a8
-// Tabulated search: coast, then n_ang thrust angles; first strict minimum.
-__global__ __launch_bounds__(kBlock) void k_sweep_table(SweepArgs a) {
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int t = tile * kBlock + threadIdx.x;
-  double rel = 0, sum = 0, mabs = 0, bad = 0;
-  if (t < a.n_free) {
-    const int j = a.free_idx[t];
-    NodeTerms T;
-    node_terms(a.G, a.P, j, a.P.dt, T);
-    const float qc = q_coast(a.V_in, a.G, a.P, T);
-    float bq = INFINITY;
-    int bk = 0;
-    for (int k = 0; k < a.n_ang; k++) {
-      const float q = q_thrust(a.V_in, a.G, a.P, T, a.tab_sin[k], a.tab_cos[k]);
-      if (q < bq) {
-        bq = q;
-        bk = k;
-      }
-    }
-    const bool thr = bq < qc;
-    const float v = thr ? bq : qc;
-    a.V_out[j] = v;
-    if (a.pol_ang) a.pol_ang[j] = a.tab_ang[bk];
-    if (a.pol_thr) a.pol_thr[j] = thr ? 1 : 0;
-    node_residual(a.V_in[j], v, rel, sum, mabs, bad);
+// Node terms from the packed coordinates of a free node and the per-axis
+// tables: FP64 for the control-independent drift, float for the rest.
+__device__ inline int node_terms_tab(const SweepArgs& a, uint32_t packed, NodeTerms& T) {
+  const int j = unpack_node(a.G, packed, T.i);
+  if (a.P.model == 0) {
+    const double ri = a.rinv[T.i[0]];
+    const double vr = a.G.lo[1] + (double)T.i[1] * a.G.h[1];
+    const double vt = a.G.lo[2] + (double)T.i[2] * a.G.h[2];
+    T.drift[0] = (float)(a.c0 * vr);
+    T.drift[1] = (float)(a.c1 * (vt * vt * ri - a.P.mu * ri * ri));
+    T.drift[2] = (float)(-a.c2 * vr * vt * ri);
+  } else {
+    T.drift[0] = T.drift[1] = T.drift[2] = 0.0f;
   }
-  block_residual(rel, sum, mabs, bad, 0.0, a.partial, blockIdx.x);
+  T.drift[3] = 0.0f;
+  T.g1 = a.g1tab[T.i[3]];
+  T.g2 = a.g2tab[T.i[3]];
+  T.gm = a.gm;
+  return j;
 }
 
-// Golden-section refinement in offsets d from the centre angle u0 whose
-// sin/cos are (s0, c0): angles u0 + d use a rotation by d.
+// Golden-section refinement around the centre angle u0 (sin/cos s0, c0):
+// the angles u0 + d are formed by rotating (s0, c0) by d.  qf(sin, cos)
+// returns Q of thrust at that angle.  The best evaluated point is kept
+// (strict <, evaluation order).
 struct GoldenState {
   float best_q, best_d;
 };
 
-template <bool kSnap>
-__device__ inline float q_at_offset(const SweepArgs& a, const NodeTerms& T, float s0, float c0,
-                                    float d) {
-  float sd, cd;
-  small_sincos(d, sd, cd);
-  const float sn = fmaf(s0, cd, c0 * sd);
-  const float cs = fmaf(c0, cd, -s0 * sd);
-  return q_thrust<kSnap>(a.V_in, a.G, a.P, T, sn, cs);
-}
-
-template <bool kSnap = false>
-__device__ inline void golden(const SweepArgs& a, const NodeTerms& T, float s0, float c0,
-                              float half, int steps, GoldenState& g) {
+template <class QF>
+__device__ inline void golden(const QF& qf, float s0, float c0, float half, int steps, GoldenState& g) {
+  auto q_at = [&](float d) {
+    float sd, cd;
+    small_sincos(d, sd, cd);
+    return qf(fmaf(s0, cd, c0 * sd), fmaf(c0, cd, -s0 * sd));
+  };
   const float rho = 0.6180339887498949f;
   float lo = -half, hi = half;
   float x1 = hi - rho * (hi - lo), x2 = lo + rho * (hi - lo);
-  float f1 = q_at_offset<kSnap>(a, T, s0, c0, x1);
+  float f1 = q_at(x1);
   if (f1 < g.best_q) {
     g.best_q = f1;
     g.best_d = x1;
   }
-  float f2 = q_at_offset<kSnap>(a, T, s0, c0, x2);
+  float f2 = q_at(x2);
   if (f2 < g.best_q) {
     g.best_q = f2;
     g.best_d = x2;
@@ -190,7 +182,7 @@ __device__ inline void golden(const SweepArgs& a, const NodeTerms& T, float s0, 
       x2 = x1;
       f2 = f1;
       x1 = hi - rho * (hi - lo);
-      f1 = q_at_offset<kSnap>(a, T, s0, c0, x1);
+      f1 = q_at(x1);
       if (f1 < g.best_q) {
         g.best_q = f1;
         g.best_d = x1;
@@ -200,7 +192,7 @@ __device__ inline void golden(const SweepArgs& a, const NodeTerms& T, float s0, 
       x1 = x2;
       f1 = f2;
       x2 = lo + rho * (hi - lo);
-      f2 = q_at_offset<kSnap>(a, T, s0, c0, x2);
+      f2 = q_at(x2);
       if (f2 < g.best_q) {
         g.best_q = f2;
         g.best_d = x2;
@@ -209,73 +201,83 @@ __device__ inline void golden(const SweepArgs& a, const NodeTerms& T, float s0, 
   }
 }
 
-// Full search of one node: scan of n_ang tabulated angles, golden section
-// around the best sample, coast comparison.
-template <bool kSnap = false>
-__device__ inline void full_search(const SweepArgs& a, const NodeTerms& T, float& v, float& ang,
-                                   int& thr) {
-  const float qc = q_coast<kSnap>(a.V_in, a.G, a.P, T);
-  float bq = INFINITY;
-  int bk = 0;
+// Exhaustive pass over the n_ang tabulated angles: first strict minimum.
+template <class QF>
+__device__ inline void scan_table(const QF& qf, const SweepArgs& a, float& bq, int& bk) {
+  bq = INFINITY;
+  bk = 0;
   for (int k = 0; k < a.n_ang; k++) {
-    const float q = q_thrust<kSnap>(a.V_in, a.G, a.P, T, a.tab_sin[k], a.tab_cos[k]);
+    const float q = qf(a.tab_sin[k], a.tab_cos[k]);
     if (q < bq) {
       bq = q;
       bk = k;
     }
   }
+}
+
+// Full search: scan, golden section around the best sample (if n_golden > 0),
+// then thrust iff strictly below the coast value qc.
+template <class QF>
+__device__ inline void full_search(const QF& qf, const SweepArgs& a, float qc, float& v, float& ang, int& thr) {
+  float bq;
+  int bk;
+  scan_table(qf, a, bq, bk);
   GoldenState g{bq, 0.0f};
-  if (a.n_golden > 0) golden<kSnap>(a, T, a.tab_sin[bk], a.tab_cos[bk], a.half_width, a.n_golden, g);
+  if (a.n_golden > 0) golden(qf, a.tab_sin[bk], a.tab_cos[bk], a.half_width, a.n_golden, g);
   thr = g.best_q < qc ? 1 : 0;
   v = thr ? g.best_q : qc;
   ang = wrap_pi(a.tab_ang[bk] + g.best_d);
 }
 
-__global__ __launch_bounds__(kBlock) void k_sweep_scan_golden(SweepArgs a) {
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int t = tile * kBlock + threadIdx.x;
-  double rel = 0, sum = 0, mabs = 0, bad = 0;
-  if (t < a.n_free) {
-    const int j = a.free_idx[t];
-    NodeTerms T;
-    node_terms(a.G, a.P, j, a.P.dt, T);
-    float v, ang;
-    int thr;
-    full_search(a, T, v, ang, thr);
-    a.V_out[j] = v;
-    if (a.pol_ang) a.pol_ang[j] = ang;
-    if (a.pol_thr) a.pol_thr[j] = (uint8_t)thr;
-    node_residual(a.V_in[j], v, rel, sum, mabs, bad);
+// Seeded local search: the seed angle, then a golden section with n_local - 3
+// steps on [seed - w, seed + w] (n_local thrust evaluations), then coast.  A
+// node whose result differs from its current value by more than
+// fallback_tol * max(1, |V|) repeats the full search.
+template <class QF>
+__device__ inline int seeded_search(const QF& qf, const SweepArgs& a, float seed, float qc, float vin, float& v,
+                                    float& ang, int& thr) {
+  float s0, c0;
+  sincosf(seed, &s0, &c0);
+  GoldenState g{qf(s0, c0), 0.0f};
+  golden(qf, s0, c0, a.local_half_width, a.n_local - 3, g);
+  thr = g.best_q < qc ? 1 : 0;
+  v = thr ? g.best_q : qc;
+  ang = wrap_pi(seed + g.best_d);
+  if (fabsf(v - vin) > a.fallback_tol * fmaxf(1.0f, fabsf(vin))) {
+    full_search(qf, a, qc, v, ang, thr);
+    return 1;
   }
-  block_residual(rel, sum, mabs, bad, 0.0, a.partial, blockIdx.x);
+  return 0;
 }
 
-// Seeded local search: the seed angle itself, then golden section with
-// n_local - 1 further evaluations on [seed - w, seed + w], then coast.  A node
-// whose result differs from its current value by more than
-// fallback_tol*max(1, |V|) repeats the full search.
-__global__ __launch_bounds__(kBlock) void k_sweep_seeded(SweepArgs a) {
+// ---- direct path: every evaluation gathers its 16 corners from V.
+// Used for any problem; the fast path below covers the orbit workloads.
+template <int kMode>
+__global__ __launch_bounds__(kBlock) void k_sweep_direct(SweepArgs a) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int t = tile * kBlock + threadIdx.x;
   double rel = 0, sum = 0, mabs = 0, bad = 0;
   int fell_back = 0;
   if (t < a.n_free) {
-    const int j = a.free_idx[t];
     NodeTerms T;
-    node_terms(a.G, a.P, j, a.P.dt, T);
-    const float seed = a.seed[j];
-    float s0, c0;
-    sincosf(seed, &s0, &c0);
-    GoldenState g{q_thrust(a.V_in, a.G, a.P, T, s0, c0), 0.0f};
-    golden(a, T, s0, c0, a.local_half_width, a.n_local - 3, g);
-    const float qc = q_coast(a.V_in, a.G, a.P, T);
-    int thr = g.best_q < qc ? 1 : 0;
-    float v = thr ? g.best_q : qc;
-    float ang = wrap_pi(seed + g.best_d);
-    const float vin = a.V_in[j];
-    if (fabsf(v - vin) > a.fallback_tol * fmaxf(1.0f, fabsf(vin))) {
-      full_search(a, T, v, ang, thr);
-      fell_back = 1;
+    const int j = node_terms_tab(a, a.free_node[t], T);
+    const float* __restrict__ V = a.V_in;
+    auto qf = [&](float sn, float cs) { return q_thrust(V, a.G, a.P, T, sn, cs); };
+    const float qc = q_coast(V, a.G, a.P, T);
+    const float vin = V[j];
+    float v, ang;
+    int thr;
+    if (kMode == 0) {
+      float bq;
+      int bk;
+      scan_table(qf, a, bq, bk);
+      thr = bq < qc ? 1 : 0;
+      v = thr ? bq : qc;
+      ang = a.tab_ang[bk];
+    } else if (kMode == 1) {
+      full_search(qf, a, qc, v, ang, thr);
+    } else {
+      fell_back = seeded_search(qf, a, a.seed[j], qc, vin, v, ang, thr);
     }
     a.V_out[j] = v;
     if (a.pol_ang) a.pol_ang[j] = ang;
@@ -285,27 +287,213 @@ __global__ __launch_bounds__(kBlock) void k_sweep_seeded(SweepArgs a) {
   block_residual(rel, sum, mabs, bad, (double)fell_back, a.partial, blockIdx.x);
 }
 
-// Frozen-policy sweep (eq:p_eval applied once).
+// ---- fast path for thrust controls.
+// Under thrust the r displacement (v_r * dt) and the m displacement (-c*dt)
+// do not depend on the angle, so every thrust foot of a node shares its r and
+// m cell and weights; only the v_r and v_t displacements move, by at most
+// |g| < 0.5 cell around the coast foot.  The node therefore collapses its
+// neighbourhood over r and m once (36 corner values, 27 lerps) into a 3 x 3
+// patch over (v_r, v_t), and every thrust evaluation is the bilinear
+// interpolant of the patch cell its foot falls in: the same Q1 value as the
+// 16-corner sum, with the lerps reordered.  Along each of v_r, v_t the feet
+// span at most two regions split at one threshold (a node or a domain face);
+// a region outside the domain has the constant value M.  The four region
+// pairs are stored per thread in LDS as Q = A + B dv + C dt + D dv dt in the
+// displacements dv = g1 sin u, dt = g2 cos u from the coast foot.
+struct Regions {
+  int b0;     // first cell (node index) of region 0; region 1 is cell b0 + 1
+  float bnd;  // region 1 <=> displacement offset >= bnd (node offsets)
+  bool ok0, ok1;
+};
+
+// Smallest float above x (x finite; 0 maps to the smallest normal float).
+__device__ inline float next_up(float x) {
+  if (x == 0.0f) return 1.17549435e-38f;
+  return __int_as_float(__float_as_int(x) + (x > 0.0f ? 1 : -1));
+}
+
+__device__ inline Regions axis_regions(int i, int n, float d, float g) {
+  Regions R;
+  const float ag = fabsf(g) + 1e-6f;  // margin over the rounding of d + g*s
+  const float lo = d - ag, hi = d + ag;
+  const float top = (float)(n - 1 - i), bot = (float)(-i);
+  if (hi < bot || lo > top) {  // every foot outside
+    R.b0 = 0;
+    R.bnd = INFINITY;
+    R.ok0 = R.ok1 = false;
+    return R;
+  }
+  const float k = floorf(hi);
+  const int kk = i + (int)k;
+  if (kk >= n - 1) {  // reaches the top face: last cell, then outside (the face itself is inside)
+    R.b0 = n - 2;
+    R.bnd = next_up(top);
+    R.ok0 = true;
+    R.ok1 = false;
+  } else if (k > lo) {  // crosses node kk (kk == 0: the bottom face)
+    R.b0 = kk - 1;
+    R.bnd = k;
+    R.ok0 = kk - 1 >= 0;
+    R.ok1 = true;
+  } else {  // one cell
+    R.b0 = kk;
+    R.bnd = INFINITY;
+    R.ok0 = true;
+    R.ok1 = false;
+  }
+  return R;
+}
+
+struct FastNode {
+  float g1, g2;  // thrust displacement per unit sin u (v_r) and cos u (v_t), cells
+  float bv, bt;  // region thresholds as displacements from the coast foot
+  const float4* coef;
+};
+
+__device__ inline float fast_q(const FastNode& F, float sn, float cs) {
+  const float dv = F.g1 * sn, dt = F.g2 * cs;
+  const int idx = (dv >= F.bv ? 2 * kBlock : 0) + (dt >= F.bt ? kBlock : 0);
+  const float4 c = F.coef[idx];
+  return fmaf(fmaf(c.w, dt, c.y), dv, fmaf(c.z, dt, c.x));
+}
+
+__device__ inline void fast_setup(const SweepArgs& a, const NodeTerms& T, float4 (*coef)[kBlock], FastNode& F) {
+  const Grid& G = a.G;
+  F.g1 = T.g1;
+  F.g2 = T.g2;
+  F.coef = &coef[0][threadIdx.x];
+  // r cell (shared by all controls)
+  const float o0 = T.drift[0];
+  bool ok = o0 >= (float)(-T.i[0]) && o0 <= (float)(G.n[0] - 1 - T.i[0]);
+  int br = 0, bm = 0;
+  float tr = 0.0f, tm = 0.0f;
+  if (ok) {
+    const float fl = floorf(o0);
+    br = T.i[0] + (int)fl;
+    tr = o0 - fl;
+    if (br > G.n[0] - 2) {
+      br = G.n[0] - 2;
+      tr = 1.0f;
+    }
+  }
+  // m cell under thrust
+  const float om = T.gm;
+  ok = ok && om >= (float)(-T.i[3]) && om <= (float)(G.n[3] - 1 - T.i[3]);
+  if (ok) {
+    const float fl = floorf(om);
+    bm = T.i[3] + (int)fl;
+    tm = om - fl;
+    if (bm > G.n[3] - 2) {
+      bm = G.n[3] - 2;
+      tm = 1.0f;
+    }
+  }
+  const Regions Rv = axis_regions(T.i[1], G.n[1], T.drift[1], T.g1);
+  const Regions Rt = axis_regions(T.i[2], G.n[2], T.drift[2], T.g2);
+  F.bv = Rv.bnd - T.drift[1];
+  F.bt = Rt.bnd - T.drift[2];
+  const float qM = fmaf(a.P.gamma, a.P.M, a.P.q_thr);
+  float W[3][3];
+  if (ok) {
+    const float* __restrict__ base = a.V_in + br + bm * G.st[3];
+    const int s3 = G.st[3];
+#pragma unroll
+    for (int p = 0; p < 3; p++) {
+      const int v = min(max(Rv.b0 + p, 0), G.n[1] - 1);
+#pragma unroll
+      for (int q = 0; q < 3; q++) {
+        const int w = min(max(Rt.b0 + q, 0), G.n[2] - 1);
+        const float* pp = base + v * G.st[1] + w * G.st[2];
+        const float lo = lerp(pp[0], pp[1], tr);
+        const float hi = lerp(pp[s3], pp[s3 + 1], tr);
+        W[p][q] = lerp(lo, hi, tm);
+      }
+    }
+  }
+  const float gam = a.P.gamma, q0 = a.P.q_thr;
+#pragma unroll
+  for (int av = 0; av < 2; av++) {
+#pragma unroll
+    for (int bt = 0; bt < 2; bt++) {
+      float4 c = make_float4(qM, 0.0f, 0.0f, 0.0f);
+      const bool valid = ok && (av ? Rv.ok1 : Rv.ok0) && (bt ? Rt.ok1 : Rt.ok0);
+      if (valid) {
+        const float w00 = W[av][bt], w10 = W[av + 1][bt], w01 = W[av][bt + 1], w11 = W[av + 1][bt + 1];
+        // local coordinates of the coast foot in this cell
+        const float tv = T.drift[1] - (float)(Rv.b0 + av - T.i[1]);
+        const float tt = T.drift[2] - (float)(Rt.b0 + bt - T.i[2]);
+        const float cv = w10 - w00, ct = w01 - w00, dd = (w11 - w10) - (w01 - w00);
+        const float A = lerp(lerp(w00, w10, tv), lerp(w01, w11, tv), tt);
+        c.x = fmaf(gam, A, q0);
+        c.y = gam * fmaf(dd, tt, cv);
+        c.z = gam * fmaf(dd, tv, ct);
+        c.w = gam * dd;
+      }
+      coef[av * 2 + bt][threadIdx.x] = c;
+    }
+  }
+}
+
+template <int kMode>
+__global__ __launch_bounds__(kBlock) void k_sweep_fast(SweepArgs a) {
+  __shared__ float4 s_coef[4][kBlock];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int t = tile * kBlock + threadIdx.x;
+  double rel = 0, sum = 0, mabs = 0, bad = 0;
+  int fell_back = 0;
+  if (t < a.n_free) {
+    NodeTerms T;
+    const int j = node_terms_tab(a, a.free_node[t], T);
+    FastNode F;
+    fast_setup(a, T, s_coef, F);
+    auto qf = [&](float sn, float cs) { return fast_q(F, sn, cs); };
+    const float qc = q_coast(a.V_in, a.G, a.P, T);
+    const float vin = a.V_in[j];
+    float v, ang;
+    int thr;
+    if (kMode == 0) {
+      float bq;
+      int bk;
+      scan_table(qf, a, bq, bk);
+      thr = bq < qc ? 1 : 0;
+      v = thr ? bq : qc;
+      ang = a.tab_ang[bk];
+    } else if (kMode == 1) {
+      full_search(qf, a, qc, v, ang, thr);
+    } else {
+      fell_back = seeded_search(qf, a, a.seed[j], qc, vin, v, ang, thr);
+    }
+    a.V_out[j] = v;
+    if (a.pol_ang) a.pol_ang[j] = ang;
+    if (a.pol_thr) a.pol_thr[j] = (uint8_t)thr;
+    node_residual(vin, v, rel, sum, mabs, bad);
+  }
+  block_residual(rel, sum, mabs, bad, (double)fell_back, a.partial, blockIdx.x);
+}
+
+// Frozen-policy sweep (eq:p_eval applied once).  The residual reduction is
+// only compiled in when a caller asks for it; the policy-iteration loop does
+// not, since it stops on the residual of the greedy step.
+template <bool kResid>
 __global__ __launch_bounds__(kBlock) void k_policy_eval(SweepArgs a) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int t = tile * kBlock + threadIdx.x;
   double rel = 0, sum = 0, mabs = 0, bad = 0;
   if (t < a.n_free) {
-    const int j = a.free_idx[t];
     NodeTerms T;
-    node_terms(a.G, a.P, j, a.P.dt, T);
+    const int j = node_terms_tab(a, a.free_node[t], T);
     float v;
     if (a.pol_thr_in[j]) {
       float sn, cs;
-      sincosf(a.pol_ang_in[j], &sn, &cs);
+      __sincosf(a.pol_ang_in[j], &sn, &cs);
       v = q_thrust(a.V_in, a.G, a.P, T, sn, cs);
     } else {
       v = q_coast(a.V_in, a.G, a.P, T);
     }
     a.V_out[j] = v;
-    node_residual(a.V_in[j], v, rel, sum, mabs, bad);
+    if (kResid) node_residual(a.V_in[j], v, rel, sum, mabs, bad);
   }
-  block_residual(rel, sum, mabs, bad, 0.0, a.partial, blockIdx.x);
+  if (kResid) block_residual(rel, sum, mabs, bad, 0.0, a.partial, blockIdx.x);
 }
 
 // Final FP64 reduction of the workgroup partials in a fixed order.
@@ -410,22 +598,17 @@ __global__ __launch_bounds__(kBlock) void k_feedback(SweepArgs a, const double* 
   b.P.gamma = (float)exp(-a.lambda * tau);
   float v, ang;
   int thr;
+  auto qf = [&](float sn, float cs) { return q_thrust<true>(b.V_in, b.G, b.P, T, sn, cs); };
+  const float qc = q_coast<true>(b.V_in, b.G, b.P, T);
   if (a.mode == 0) {
-    const float qc = q_coast<true>(b.V_in, b.G, b.P, T);
-    float bq = INFINITY;
-    int bk = 0;
-    for (int k = 0; k < b.n_ang; k++) {
-      const float q = q_thrust<true>(b.V_in, b.G, b.P, T, b.tab_sin[k], b.tab_cos[k]);
-      if (q < bq) {
-        bq = q;
-        bk = k;
-      }
-    }
+    float bq;
+    int bk;
+    scan_table(qf, b, bq, bk);
     thr = bq < qc ? 1 : 0;
     v = thr ? bq : qc;
     ang = b.tab_ang[bk];
   } else {
-    full_search<true>(b, T, v, ang, thr);
+    full_search(qf, b, qc, v, ang, thr);
   }
   ang_out[c] = ang;
   thr_out[c] = (uint8_t)thr;
@@ -542,8 +725,8 @@ hipError_t launch_classify(const Grid& G, const TargetBox& tb, const uint8_t* ma
 
 int compact_chunks(int N) { return blocks_for(N, kChunk); }
 
-hipError_t launch_compact(const uint8_t* kind, int N, int* counts, int* offsets, int* free_idx,
-                          hipStream_t s) {
+hipError_t launch_compact(const Grid& G, const uint8_t* kind, int N, int* counts, int* offsets,
+                          uint32_t* free_node, hipStream_t s) {
   const int nch = compact_chunks(N);
   hipLaunchKernelGGL(k_count_free, dim3(nch), dim3(kBlock), 0, s, kind, N, counts);
   hipError_t e = hipGetLastError();
@@ -551,7 +734,7 @@ hipError_t launch_compact(const uint8_t* kind, int N, int* counts, int* offsets,
   hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, counts, nch, offsets);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_scatter_free, dim3(nch), dim3(kBlock), 0, s, kind, N, offsets, free_idx);
+  hipLaunchKernelGGL(k_scatter_free, dim3(nch), dim3(kBlock), 0, s, G, kind, N, offsets, free_node);
   return hipGetLastError();
 }
 
@@ -560,19 +743,26 @@ hipError_t launch_init_value(const uint8_t* kind, float M, float* V, int N, hipS
 }
 
 hipError_t launch_sweep_table(const SweepArgs& a, hipStream_t s) {
-  DPO_LAUNCH(k_sweep_table, blocks_for(a.n_free), kBlock, s, a);
+  DPO_LAUNCH(k_sweep_direct<0>, blocks_for(a.n_free), kBlock, s, a);
 }
 
 hipError_t launch_sweep_scan_golden(const SweepArgs& a, hipStream_t s) {
-  DPO_LAUNCH(k_sweep_scan_golden, blocks_for(a.n_free), kBlock, s, a);
+  DPO_LAUNCH(k_sweep_direct<1>, blocks_for(a.n_free), kBlock, s, a);
 }
 
 hipError_t launch_sweep_seeded(const SweepArgs& a, hipStream_t s) {
-  DPO_LAUNCH(k_sweep_seeded, blocks_for(a.n_free), kBlock, s, a);
+  DPO_LAUNCH(k_sweep_direct<2>, blocks_for(a.n_free), kBlock, s, a);
 }
 
-hipError_t launch_policy_eval(const SweepArgs& a, hipStream_t s) {
-  DPO_LAUNCH(k_policy_eval, blocks_for(a.n_free), kBlock, s, a);
+hipError_t launch_sweep_fast(const SweepArgs& a, int mode, hipStream_t s) {
+  if (mode == 0) DPO_LAUNCH(k_sweep_fast<0>, blocks_for(a.n_free), kBlock, s, a);
+  if (mode == 1) DPO_LAUNCH(k_sweep_fast<1>, blocks_for(a.n_free), kBlock, s, a);
+  DPO_LAUNCH(k_sweep_fast<2>, blocks_for(a.n_free), kBlock, s, a);
+}
+
+hipError_t launch_policy_eval(const SweepArgs& a, bool want_resid, hipStream_t s) {
+  if (want_resid) DPO_LAUNCH(k_policy_eval<true>, blocks_for(a.n_free), kBlock, s, a);
+  DPO_LAUNCH(k_policy_eval<false>, blocks_for(a.n_free), kBlock, s, a);
 }
 
 hipError_t launch_resid_final(const double* partial, int nblocks, double* out, hipStream_t s) {

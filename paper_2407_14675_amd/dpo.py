@@ -73,6 +73,8 @@ def load():
         "dpo_sizes": [vp, C.POINTER(i64), C.POINTER(i64)],
         "dpo_get_kind": [vp, vp, vp],
         "dpo_set_search": [vp, C.POINTER(Search)],
+        "dpo_set_kernel_path": [vp, i32],
+        "dpo_kernel_path": [vp],
         "dpo_init_value": [vp, vp, vp],
         "dpo_bellman_sweep": [vp, vp, vp, vp, vp, vp, vp],
         "dpo_bellman_sweep_seeded": [vp, vp, vp, vp, vp, vp, vp, vp],
@@ -185,6 +187,16 @@ class Context:
     def empty_policy(self):
         return (torch.zeros(self.shape, dtype=torch.float32, device=self.device),
                 torch.zeros(self.shape, dtype=torch.uint8, device=self.device))
+
+    def set_kernel_path(self, path):
+        """0 automatic, 1 direct 16-corner gathers, 2 factorised thrust kernel."""
+        self._check(self.lib.dpo_set_kernel_path(self.h, int(path)))
+
+    def kernel_path(self):
+        rc = self.lib.dpo_kernel_path(self.h)
+        if rc < 0:
+            raise DpoError(rc, self.lib.dpo_last_error(self.h).decode())
+        return rc
 
     def set_search(self, search):
         self._s = search_struct(search)
