@@ -181,6 +181,15 @@ int dpo_bellman_sweep_seeded(dpo_ctx* ctx, const float* V_in, float* V_out, floa
 int dpo_policy_eval_sweep(dpo_ctx* ctx, const float* V_in, float* V_out, const float* pol_angle,
                           const uint8_t* pol_thr, double* resid, void* stream);
 
+/* Frozen-policy sweep for the policy chosen by the most recent
+ * dpo_bellman_sweep / dpo_bellman_sweep_seeded on this context: the sweep
+ * stores, per free node, the cell and cell coordinates of its chosen
+ * control's foot, so this sweep is one descriptor load, 16 gathers and 15
+ * lerps per node (the evaluation sweep of policy iteration, eq:p_eval).
+ * Same fixed-node rule as dpo_bellman_sweep; no residual.  DPO_EINVAL if no
+ * Bellman sweep has run on ctx. */
+int dpo_policy_eval_sweep_last(dpo_ctx* ctx, const float* V_in, float* V_out, void* stream);
+
 /* --------------------------------------------------------------- solvers */
 
 /* Value iteration (paper Section 3, "Policy Iteration", first display):

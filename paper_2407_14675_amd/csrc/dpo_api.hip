@@ -43,6 +43,9 @@ struct dpo_ctx {
   int partial_blocks = 0;
   double* resid = nullptr;  // kPartial doubles
   float* work = nullptr;    // second value buffer of the solvers
+  int* desc_code = nullptr;  // foot descriptors of the greedy step's controls (policy iteration)
+  float2* desc_w = nullptr;
+  bool desc_valid = false;    // a sweep has written them
   std::string err;
 };
 
@@ -203,6 +206,14 @@ int ensure_work(dpo_ctx* c) {
   return DPO_OK;
 }
 
+int ensure_desc(dpo_ctx* c) {
+  if (c->desc_code) return DPO_OK;
+  const size_t n = (size_t)(c->n_free > 0 ? c->n_free : 1);
+  if (hipMalloc(&c->desc_code, sizeof(int) * n) != hipSuccess || hipMalloc(&c->desc_w, sizeof(float2) * n) != hipSuccess)
+    return fail(c, DPO_ENOMEM, "descriptor alloc");
+  return DPO_OK;
+}
+
 int read_resid(dpo_ctx* c, double h[kPartial], hipStream_t s) {
   HIP_TRY(c, hipMemcpyAsync(h, c->resid, sizeof(double) * kPartial, hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
@@ -216,12 +227,18 @@ int64_t evals_per_full_search(const dpo_ctx* c) {
 
 bool use_fast(const dpo_ctx* c) { return c->path == 2 || (c->path == 0 && c->fast_ok); }
 
-int sweep_full(dpo_ctx* c, const float* Vin, float* Vout, float* ang, uint8_t* thr, hipStream_t s) {
+int sweep_full(dpo_ctx* c, const float* Vin, float* Vout, float* ang, uint8_t* thr, hipStream_t s,
+               bool desc = false) {
   SweepArgs a = base_args(c);
   a.V_in = Vin;
   a.V_out = Vout;
   a.pol_ang = ang;
   a.pol_thr = thr;
+  if (desc) {
+    a.desc_code = c->desc_code;
+    a.desc_w = c->desc_w;
+    c->desc_valid = true;
+  }
   if (a.n_free == 0) return DPO_OK;
   const int mode = c->search.mode == DPO_SEARCH_TABLE ? 0 : 1;
   hipError_t e;
@@ -232,13 +249,18 @@ int sweep_full(dpo_ctx* c, const float* Vin, float* Vout, float* ang, uint8_t* t
 }
 
 int sweep_seeded(dpo_ctx* c, const float* Vin, float* Vout, float* ang, uint8_t* thr, const float* seed,
-                 hipStream_t s) {
+                 hipStream_t s, bool desc = false) {
   SweepArgs a = base_args(c);
   a.V_in = Vin;
   a.V_out = Vout;
   a.pol_ang = ang;
   a.pol_thr = thr;
   a.seed = seed;
+  if (desc) {
+    a.desc_code = c->desc_code;
+    a.desc_w = c->desc_w;
+    c->desc_valid = true;
+  }
   if (a.n_free == 0) return DPO_OK;
   hipError_t e = use_fast(c) ? launch_sweep_fast(a, 2, s) : launch_sweep_seeded(a, s);
   if (e != hipSuccess) return hip_fail(c, e, "seeded sweep launch");
@@ -255,6 +277,19 @@ int sweep_eval(dpo_ctx* c, const float* Vin, float* Vout, const float* ang, cons
   if (a.n_free == 0) return DPO_OK;
   hipError_t e = launch_policy_eval(a, want_resid, s);
   if (e != hipSuccess) return hip_fail(c, e, "policy eval launch");
+  return DPO_OK;
+}
+
+// Frozen-policy sweep driven by the descriptors of the last greedy sweep.
+int sweep_eval_desc(dpo_ctx* c, const float* Vin, float* Vout, hipStream_t s) {
+  SweepArgs a = base_args(c);
+  a.V_in = Vin;
+  a.V_out = Vout;
+  a.desc_code_in = c->desc_code;
+  a.desc_w_in = c->desc_w;
+  if (a.n_free == 0) return DPO_OK;
+  hipError_t e = launch_policy_eval_desc(a, s);
+  if (e != hipSuccess) return hip_fail(c, e, "policy eval (descriptor) launch");
   return DPO_OK;
 }
 
@@ -381,6 +416,8 @@ void dpo_destroy(dpo_ctx* c) {
   if (c->partial) hipFree(c->partial);
   if (c->resid) hipFree(c->resid);
   if (c->work) hipFree(c->work);
+  if (c->desc_code) hipFree(c->desc_code);
+  if (c->desc_w) hipFree(c->desc_w);
   delete c;
 }
 
@@ -432,7 +469,9 @@ int dpo_bellman_sweep(dpo_ctx* c, const float* V_in, float* V_out, float* pol_an
   if (!V_in || !V_out) return fail(c, DPO_EINVAL, "V_in / V_out is NULL");
   if (V_in == V_out) return fail(c, DPO_EINVAL, "V_in and V_out must differ (Jacobi sweep)");
   if (c->search.mode == DPO_SEARCH_SEEDED) return fail(c, DPO_EINVAL, "SEEDED mode: use dpo_bellman_sweep_seeded");
-  int rc = sweep_full(c, V_in, V_out, pol_angle, pol_thr, S(stream));
+  int rc = ensure_desc(c);
+  if (rc != DPO_OK) return rc;
+  rc = sweep_full(c, V_in, V_out, pol_angle, pol_thr, S(stream), true);
   if (rc != DPO_OK) return rc;
   return finish_resid(c, resid, S(stream));
 }
@@ -443,7 +482,9 @@ int dpo_bellman_sweep_seeded(dpo_ctx* c, const float* V_in, float* V_out, float*
   if (!V_in || !V_out || !seed_angle) return fail(c, DPO_EINVAL, "V_in / V_out / seed_angle is NULL");
   if (V_in == V_out) return fail(c, DPO_EINVAL, "V_in and V_out must differ (Jacobi sweep)");
   if (c->search.mode != DPO_SEARCH_SEEDED) return fail(c, DPO_EINVAL, "search mode is not SEEDED");
-  int rc = sweep_seeded(c, V_in, V_out, pol_angle, pol_thr, seed_angle, S(stream));
+  int rc = ensure_desc(c);
+  if (rc != DPO_OK) return rc;
+  rc = sweep_seeded(c, V_in, V_out, pol_angle, pol_thr, seed_angle, S(stream), true);
   if (rc != DPO_OK) return rc;
   return finish_resid(c, resid, S(stream));
 }
@@ -456,6 +497,14 @@ int dpo_policy_eval_sweep(dpo_ctx* c, const float* V_in, float* V_out, const flo
   int rc = sweep_eval(c, V_in, V_out, pol_angle, pol_thr, resid != nullptr, S(stream));
   if (rc != DPO_OK) return rc;
   return finish_resid(c, resid, S(stream));
+}
+
+int dpo_policy_eval_sweep_last(dpo_ctx* c, const float* V_in, float* V_out, void* stream) {
+  if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
+  if (!V_in || !V_out) return fail(c, DPO_EINVAL, "V_in / V_out is NULL");
+  if (V_in == V_out) return fail(c, DPO_EINVAL, "V_in and V_out must differ (Jacobi sweep)");
+  if (!c->desc_code || !c->desc_valid) return fail(c, DPO_EINVAL, "no Bellman sweep has chosen a policy yet");
+  return sweep_eval_desc(c, V_in, V_out, S(stream));
 }
 
 int dpo_solve_vi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, double tol_rel, int64_t max_sweeps,
@@ -528,6 +577,7 @@ int dpo_solve_pi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, doubl
   if (!seeded && c->search.mode == DPO_SEARCH_SEEDED) return fail(c, DPO_EINVAL, "SEEDED mode needs seed_angle");
   int rc = ensure_work(c);
   if (rc != DPO_OK) return rc;
+  if ((rc = ensure_desc(c)) != DPO_OK) return rc;
   hipStream_t s = S(stream);
   dpo_stats local;
   std::memset(&local, 0, sizeof(local));
@@ -540,8 +590,8 @@ int dpo_solve_pi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, doubl
   int64_t it = 0, evals = 0, fallback = 0;
   while (it < max_outer) {
     // greedy step: policy improvement together with T V
-    if (seeded && it > 0) rc = sweep_seeded(c, cur, nxt, pol_angle, pol_thr, seed_angle, s);
-    else rc = sweep_full(c, cur, nxt, pol_angle, pol_thr, s);
+    if (seeded && it > 0) rc = sweep_seeded(c, cur, nxt, pol_angle, pol_thr, seed_angle, s, true);
+    else rc = sweep_full(c, cur, nxt, pol_angle, pol_thr, s, true);
     if (rc != DPO_OK) return rc;
     it++;
     std::swap(cur, nxt);
@@ -564,7 +614,7 @@ int dpo_solve_pi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, doubl
       break;
     }
     for (int e = 0; e < eval_sweeps; e++) {
-      if ((rc = sweep_eval(c, cur, nxt, pol_angle, pol_thr, false, s)) != DPO_OK) return rc;
+      if ((rc = sweep_eval_desc(c, cur, nxt, s)) != DPO_OK) return rc;
       std::swap(cur, nxt);
     }
     local.eval_sweeps += eval_sweeps;

@@ -100,16 +100,27 @@ __device__ inline void node_terms(const Grid& G, const Phys& P, int j, double ta
 // (1 - t) a + t b, exact at t = 0 and t = 1 (feet on nodes and faces).
 __device__ inline float lerp(float a, float b, float t) { return fmaf(t, b, fmaf(-t, a, a)); }
 
-// Q1 interpolation of V at s = i + off (paper Section 3: multilinear I[V],
-// M outside the closed box).  Cell base_k = min(floor(s_k), n_k - 2),
-// t_k = s_k - base_k; the 16 corners are combined by 15 lerps (r first).
+// Cell of the foot s = i + off (paper Section 3: Q1 on the closed box):
+// false if s_k lies outside [0, n_k - 1] on some axis; else the cell base
+// base_k = min(floor(s_k), n_k - 2) and the local coordinate t_k = s_k - base_k.
 // kSnap: feet of states given in physical units (feedback) that lie within
 // 1e-6 cells outside a face are put on the face.
+// One axis of the foot's cell: inside iff 0 <= i + o <= n - 1; then
+// b = min(floor(i + o), n - 2) and t = i + o - b.
+__device__ inline bool axis_cell(int i, int n, float o, int& b, float& t) {
+  if (!(o >= (float)(-i) && o <= (float)(n - 1 - i))) return false;
+  const float fl = floorf(o);
+  b = i + (int)fl;
+  t = o - fl;
+  if (b > n - 2) {
+    b = n - 2;
+    t = 1.0f;
+  }
+  return true;
+}
+
 template <bool kSnap = false>
-__device__ inline float interp_off(const float* __restrict__ V, const Grid& G, const int i[4],
-                                   const float off[4], float M) {
-  int base[4];
-  float t[4];
+__device__ inline bool foot_cell(const Grid& G, const int i[4], const float off[4], int base[4], float t[4]) {
 #pragma unroll
   for (int k = 0; k < 4; k++) {
     float o = off[k];
@@ -118,18 +129,13 @@ __device__ inline float interp_off(const float* __restrict__ V, const Grid& G, c
       if (o < lo && o > lo - 1e-6f) o = lo;
       if (o > hi && o < hi + 1e-6f) o = hi;
     }
-    if (!(o >= (float)(-i[k]) && o <= (float)(G.n[k] - 1 - i[k]))) return M;
-    const float fl = floorf(o);
-    int b = i[k] + (int)fl;
-    float tt = o - fl;
-    if (b > G.n[k] - 2) {
-      b = G.n[k] - 2;
-      tt = 1.0f;
-    }
-    base[k] = b;
-    t[k] = tt;
+    if (!axis_cell(i[k], G.n[k], o, base[k], t[k])) return false;
   }
-  const float* p = V + (base[0] + base[1] * G.st[1] + base[2] * G.st[2] + base[3] * G.st[3]);
+  return true;
+}
+
+// 16-corner Q1 value of the cell whose lowest corner is p: 15 lerps, r first.
+__device__ inline float cell_value(const float* __restrict__ p, const Grid& G, const float t[4]) {
   const int s1 = G.st[1], s2 = G.st[2], s3 = G.st[3];
   float c[8];
 #pragma unroll
@@ -144,6 +150,17 @@ __device__ inline float interp_off(const float* __restrict__ V, const Grid& G, c
   const float e0 = lerp(d0, d1, t[2]);
   const float e1 = lerp(d2, d3, t[2]);
   return lerp(e0, e1, t[3]);
+}
+
+// Q1 interpolation of V at s = i + off (paper Section 3: multilinear I[V],
+// M outside the closed box).
+template <bool kSnap = false>
+__device__ inline float interp_off(const float* __restrict__ V, const Grid& G, const int i[4],
+                                   const float off[4], float M) {
+  int base[4];
+  float t[4];
+  if (!foot_cell<kSnap>(G, i, off, base, t)) return M;
+  return cell_value(V + (base[0] + base[1] * G.st[1] + base[2] * G.st[2] + base[3] * G.st[3]), G, t);
 }
 
 // Q of one control at a node: dt*l + gamma * I[V](foot).

@@ -38,6 +38,16 @@ struct SweepArgs {
   float local_half_width;
   float fallback_tol;
   double* partial;  // kPartial doubles per workgroup
+  // Foot descriptor of each free node's chosen control (free-list order),
+  // written by the greedy sweep when desc_code is set and read by the
+  // frozen-policy sweep.  desc_code: bits 0-29 flat index of the cell's lowest
+  // corner, bit 30 foot outside the domain, bit 31 throttle.  desc_w: the
+  // cell coordinates along v_r and v_t; those along r and m follow from the
+  // node and the throttle and are recomputed bit-identically.
+  int* desc_code;
+  float2* desc_w;
+  const int* desc_code_in;
+  const float2* desc_w_in;
   int mode;         // search mode (feedback)
   double w_time, w_fuel, lambda;
 };
@@ -55,6 +65,7 @@ hipError_t launch_sweep_table(const SweepArgs& a, hipStream_t s);
 hipError_t launch_sweep_scan_golden(const SweepArgs& a, hipStream_t s);
 hipError_t launch_sweep_seeded(const SweepArgs& a, hipStream_t s);
 hipError_t launch_policy_eval(const SweepArgs& a, bool want_resid, hipStream_t s);
+hipError_t launch_policy_eval_desc(const SweepArgs& a, hipStream_t s);
 hipError_t launch_sweep_fast(const SweepArgs& a, int mode, hipStream_t s);
 hipError_t launch_resid_final(const double* partial, int nblocks, double* out, hipStream_t s);
 hipError_t launch_value_at(const float* V, const Grid& G, double M, const double x[4], double* out,

@@ -129,13 +129,20 @@ __global__ __launch_bounds__(kBlock) void k_init_value(const uint8_t* __restrict
 // --------------------------------------------------------------- a2..a8
 // Node terms from the packed coordinates of a free node and the per-axis
 // tables: FP64 for the control-independent drift, float for the rest.
+// The r displacement dt*v_r/h_r (cells) of nodes in v_r row i1.
+__device__ inline float drift_r(const SweepArgs& a, int i1) {
+  if (a.P.model != 0) return 0.0f;
+  const double vr = a.G.lo[1] + (double)i1 * a.G.h[1];
+  return (float)(a.c0 * vr);
+}
+
 __device__ inline int node_terms_tab(const SweepArgs& a, uint32_t packed, NodeTerms& T) {
   const int j = unpack_node(a.G, packed, T.i);
   if (a.P.model == 0) {
     const double ri = a.rinv[T.i[0]];
     const double vr = a.G.lo[1] + (double)T.i[1] * a.G.h[1];
     const double vt = a.G.lo[2] + (double)T.i[2] * a.G.h[2];
-    T.drift[0] = (float)(a.c0 * vr);
+    T.drift[0] = drift_r(a, T.i[1]);
     T.drift[1] = (float)(a.c1 * (vt * vt * ri - a.P.mu * ri * ri));
     T.drift[2] = (float)(-a.c2 * vr * vt * ri);
   } else {
@@ -215,18 +222,49 @@ __device__ inline void scan_table(const QF& qf, const SweepArgs& a, float& bq, i
   }
 }
 
+// sin/cos of the angle d away from the one with sin/cos (s0, c0), formed
+// exactly as the golden section forms them.
+__device__ inline void rotate(float s0, float c0, float d, float& sn, float& cs) {
+  float sd, cd;
+  small_sincos(d, sd, cd);
+  sn = fmaf(s0, cd, c0 * sd);
+  cs = fmaf(c0, cd, -s0 * sd);
+}
+
+// The outcome of the search at one node.
+struct Choice {
+  float v;       // min Q
+  float ang;     // best thrust angle in [-pi, pi)
+  float sn, cs;  // sin/cos of the best thrust angle as evaluated
+  int thr;       // 1 = thrust
+};
+
 // Full search: scan, golden section around the best sample (if n_golden > 0),
 // then thrust iff strictly below the coast value qc.
 template <class QF>
-__device__ inline void full_search(const QF& qf, const SweepArgs& a, float qc, float& v, float& ang, int& thr) {
+__device__ inline void full_search(const QF& qf, const SweepArgs& a, float qc, Choice& ch) {
   float bq;
   int bk;
   scan_table(qf, a, bq, bk);
   GoldenState g{bq, 0.0f};
   if (a.n_golden > 0) golden(qf, a.tab_sin[bk], a.tab_cos[bk], a.half_width, a.n_golden, g);
-  thr = g.best_q < qc ? 1 : 0;
-  v = thr ? g.best_q : qc;
-  ang = wrap_pi(a.tab_ang[bk] + g.best_d);
+  ch.thr = g.best_q < qc ? 1 : 0;
+  ch.v = ch.thr ? g.best_q : qc;
+  ch.ang = wrap_pi(a.tab_ang[bk] + g.best_d);
+  rotate(a.tab_sin[bk], a.tab_cos[bk], g.best_d, ch.sn, ch.cs);
+}
+
+// Tabulated search: first strict minimum over the table, coast on ties.
+template <class QF>
+__device__ inline void table_search(const QF& qf, const SweepArgs& a, float qc, Choice& ch) {
+  float bq;
+  int bk;
+  scan_table(qf, a, bq, bk);
+  ch.thr = bq < qc ? 1 : 0;
+  ch.v = ch.thr ? bq : qc;
+  ch.ang = a.tab_ang[bk];
+  ch.sn = a.tab_sin[bk];
+  ch.cs = a.tab_cos[bk];
 }
 
 // Seeded local search: the seed angle, then a golden section with n_local - 3
@@ -234,20 +272,36 @@ __device__ inline void full_search(const QF& qf, const SweepArgs& a, float qc, f
 // node whose result differs from its current value by more than
 // fallback_tol * max(1, |V|) repeats the full search.
 template <class QF>
-__device__ inline int seeded_search(const QF& qf, const SweepArgs& a, float seed, float qc, float vin, float& v,
-                                    float& ang, int& thr) {
+__device__ inline int seeded_search(const QF& qf, const SweepArgs& a, float seed, float qc, float vin, Choice& ch) {
   float s0, c0;
   sincosf(seed, &s0, &c0);
   GoldenState g{qf(s0, c0), 0.0f};
   golden(qf, s0, c0, a.local_half_width, a.n_local - 3, g);
-  thr = g.best_q < qc ? 1 : 0;
-  v = thr ? g.best_q : qc;
-  ang = wrap_pi(seed + g.best_d);
-  if (fabsf(v - vin) > a.fallback_tol * fmaxf(1.0f, fabsf(vin))) {
-    full_search(qf, a, qc, v, ang, thr);
+  ch.thr = g.best_q < qc ? 1 : 0;
+  ch.v = ch.thr ? g.best_q : qc;
+  ch.ang = wrap_pi(seed + g.best_d);
+  rotate(s0, c0, g.best_d, ch.sn, ch.cs);
+  if (fabsf(ch.v - vin) > a.fallback_tol * fmaxf(1.0f, fabsf(vin))) {
+    full_search(qf, a, qc, ch);
     return 1;
   }
   return 0;
+}
+
+// Foot descriptor of the chosen control (see SweepArgs::desc_code).
+__device__ inline void write_desc(const SweepArgs& a, int t, const NodeTerms& T, const Choice& ch) {
+  float off[4];
+  off[0] = T.drift[0];
+  off[1] = ch.thr ? fmaf(T.g1, ch.sn, T.drift[1]) : T.drift[1];
+  off[2] = ch.thr ? fmaf(T.g2, ch.cs, T.drift[2]) : T.drift[2];
+  off[3] = T.drift[3] + (ch.thr ? T.gm : 0.0f);
+  int base[4];
+  float w[4];
+  const bool inside = foot_cell(a.G, T.i, off, base, w);
+  const unsigned flat = inside ? (unsigned)(base[0] + base[1] * a.G.st[1] + base[2] * a.G.st[2] + base[3] * a.G.st[3])
+                               : (1u << 30);
+  a.desc_code[t] = (int)(flat | ((unsigned)ch.thr << 31));
+  a.desc_w[t] = inside ? make_float2(w[1], w[2]) : make_float2(0.0f, 0.0f);
 }
 
 // ---- direct path: every evaluation gathers its 16 corners from V.
@@ -265,24 +319,15 @@ __global__ __launch_bounds__(kBlock) void k_sweep_direct(SweepArgs a) {
     auto qf = [&](float sn, float cs) { return q_thrust(V, a.G, a.P, T, sn, cs); };
     const float qc = q_coast(V, a.G, a.P, T);
     const float vin = V[j];
-    float v, ang;
-    int thr;
-    if (kMode == 0) {
-      float bq;
-      int bk;
-      scan_table(qf, a, bq, bk);
-      thr = bq < qc ? 1 : 0;
-      v = thr ? bq : qc;
-      ang = a.tab_ang[bk];
-    } else if (kMode == 1) {
-      full_search(qf, a, qc, v, ang, thr);
-    } else {
-      fell_back = seeded_search(qf, a, a.seed[j], qc, vin, v, ang, thr);
-    }
-    a.V_out[j] = v;
-    if (a.pol_ang) a.pol_ang[j] = ang;
-    if (a.pol_thr) a.pol_thr[j] = (uint8_t)thr;
-    node_residual(vin, v, rel, sum, mabs, bad);
+    Choice ch;
+    if (kMode == 0) table_search(qf, a, qc, ch);
+    else if (kMode == 1) full_search(qf, a, qc, ch);
+    else fell_back = seeded_search(qf, a, a.seed[j], qc, vin, ch);
+    a.V_out[j] = ch.v;
+    if (a.pol_ang) a.pol_ang[j] = ch.ang;
+    if (a.pol_thr) a.pol_thr[j] = (uint8_t)ch.thr;
+    if (a.desc_code) write_desc(a, t, T, ch);
+    node_residual(vin, ch.v, rel, sum, mabs, bad);
   }
   block_residual(rel, sum, mabs, bad, (double)fell_back, a.partial, blockIdx.x);
 }
@@ -449,24 +494,15 @@ __global__ __launch_bounds__(kBlock) void k_sweep_fast(SweepArgs a) {
     auto qf = [&](float sn, float cs) { return fast_q(F, sn, cs); };
     const float qc = q_coast(a.V_in, a.G, a.P, T);
     const float vin = a.V_in[j];
-    float v, ang;
-    int thr;
-    if (kMode == 0) {
-      float bq;
-      int bk;
-      scan_table(qf, a, bq, bk);
-      thr = bq < qc ? 1 : 0;
-      v = thr ? bq : qc;
-      ang = a.tab_ang[bk];
-    } else if (kMode == 1) {
-      full_search(qf, a, qc, v, ang, thr);
-    } else {
-      fell_back = seeded_search(qf, a, a.seed[j], qc, vin, v, ang, thr);
-    }
-    a.V_out[j] = v;
-    if (a.pol_ang) a.pol_ang[j] = ang;
-    if (a.pol_thr) a.pol_thr[j] = (uint8_t)thr;
-    node_residual(vin, v, rel, sum, mabs, bad);
+    Choice ch;
+    if (kMode == 0) table_search(qf, a, qc, ch);
+    else if (kMode == 1) full_search(qf, a, qc, ch);
+    else fell_back = seeded_search(qf, a, a.seed[j], qc, vin, ch);
+    a.V_out[j] = ch.v;
+    if (a.pol_ang) a.pol_ang[j] = ch.ang;
+    if (a.pol_thr) a.pol_thr[j] = (uint8_t)ch.thr;
+    if (a.desc_code) write_desc(a, t, T, ch);
+    node_residual(vin, ch.v, rel, sum, mabs, bad);
   }
   block_residual(rel, sum, mabs, bad, (double)fell_back, a.partial, blockIdx.x);
 }
@@ -494,6 +530,51 @@ __global__ __launch_bounds__(kBlock) void k_policy_eval(SweepArgs a) {
     if (kResid) node_residual(a.V_in[j], v, rel, sum, mabs, bad);
   }
   if (kResid) block_residual(rel, sum, mabs, bad, 0.0, a.partial, blockIdx.x);
+}
+
+// Frozen-policy sweep from the foot descriptors written by the last greedy
+// sweep: per node the packed coordinates and the 12-byte descriptor in one
+// coalesced trip, the r and m cell coordinates recomputed, 16 gathers and 15
+// lerps.  Each workgroup owns kDescNpt * kBlock consecutive free nodes; every
+// thread handles kDescNpt of them so their loads are in flight together.
+constexpr int kDescNpt = 2;
+
+__global__ __launch_bounds__(kBlock) void k_policy_eval_desc(SweepArgs a) {
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int t0 = tile * (kDescNpt * kBlock) + threadIdx.x;
+  uint32_t packed[kDescNpt];
+  int code[kDescNpt];
+  float2 w[kDescNpt];
+#pragma unroll
+  for (int k = 0; k < kDescNpt; k++) {
+    const int t = t0 + k * kBlock;
+    if (t < a.n_free) {
+      packed[k] = a.free_node[t];
+      code[k] = a.desc_code_in[t];
+      w[k] = a.desc_w_in[t];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kDescNpt; k++) {
+    const int t = t0 + k * kBlock;
+    if (t >= a.n_free) continue;
+    int i[4];
+    const int j = unpack_node(a.G, packed[k], i);
+    const bool thr = code[k] < 0;
+    float I = a.P.M;
+    if (!(code[k] & (1 << 30))) {
+      // r and m cell coordinates, exactly as the greedy sweep formed them
+      const float o0 = drift_r(a, i[1]);
+      int b0, b3;
+      float tt[4];
+      axis_cell(i[0], a.G.n[0], o0, b0, tt[0]);
+      axis_cell(i[3], a.G.n[3], thr ? a.gm : 0.0f, b3, tt[3]);
+      tt[1] = w[k].x;
+      tt[2] = w[k].y;
+      I = cell_value(a.V_in + (code[k] & 0x3fffffff), a.G, tt);
+    }
+    a.V_out[j] = fmaf(a.P.gamma, I, thr ? a.P.q_thr : a.P.q_coast);
+  }
 }
 
 // Final FP64 reduction of the workgroup partials in a fixed order.
@@ -596,23 +677,14 @@ __global__ __launch_bounds__(kBlock) void k_feedback(SweepArgs a, const double* 
   b.P.q_coast = (float)(tau * (double)a.w_time);
   b.P.q_thr = (float)(tau * ((double)a.w_time + (double)a.w_fuel));
   b.P.gamma = (float)exp(-a.lambda * tau);
-  float v, ang;
-  int thr;
   auto qf = [&](float sn, float cs) { return q_thrust<true>(b.V_in, b.G, b.P, T, sn, cs); };
   const float qc = q_coast<true>(b.V_in, b.G, b.P, T);
-  if (a.mode == 0) {
-    float bq;
-    int bk;
-    scan_table(qf, b, bq, bk);
-    thr = bq < qc ? 1 : 0;
-    v = thr ? bq : qc;
-    ang = b.tab_ang[bk];
-  } else {
-    full_search(qf, b, qc, v, ang, thr);
-  }
-  ang_out[c] = ang;
-  thr_out[c] = (uint8_t)thr;
-  if (q_out) q_out[c] = v;
+  Choice ch;
+  if (a.mode == 0) table_search(qf, b, qc, ch);
+  else full_search(qf, b, qc, ch);
+  ang_out[c] = ch.ang;
+  thr_out[c] = (uint8_t)ch.thr;
+  if (q_out) q_out[c] = ch.v;
 }
 
 // Reachability seed: FP64 Q1 value of the coarse V at every fine node.
@@ -763,6 +835,10 @@ hipError_t launch_sweep_fast(const SweepArgs& a, int mode, hipStream_t s) {
 hipError_t launch_policy_eval(const SweepArgs& a, bool want_resid, hipStream_t s) {
   if (want_resid) DPO_LAUNCH(k_policy_eval<true>, blocks_for(a.n_free), kBlock, s, a);
   DPO_LAUNCH(k_policy_eval<false>, blocks_for(a.n_free), kBlock, s, a);
+}
+
+hipError_t launch_policy_eval_desc(const SweepArgs& a, hipStream_t s) {
+  DPO_LAUNCH(k_policy_eval_desc, blocks_for(a.n_free, kDescNpt * kBlock), kBlock, s, a);
 }
 
 hipError_t launch_resid_final(const double* partial, int nblocks, double* out, hipStream_t s) {

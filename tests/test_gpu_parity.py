@@ -312,6 +312,31 @@ def test_policy_eval_parity(dpo):
     assert np.max(rel_err(host(Vout)[free], Vo[free])) < 1e-5
 
 
+@pytest.mark.parametrize("path", [1, 2])
+def test_policy_eval_of_last_sweep(dpo, path):
+    """The descriptor-driven evaluation sweep equals the oracle's frozen-policy
+    sweep for the policy the Bellman sweep just chose."""
+    p = inputs.with_grid(inputs.CONFIG1, (10, 10, 10, 10))
+    _say("policy eval of last sweep, path", path)
+    V32 = inputs.random_value(p, seed=33, low=0, high=40).astype(np.float32)
+    o = Oracle(p)
+    ctx = dpo.Context(p)
+    ctx.set_kernel_path(path)
+    Vin = dev(V32)
+    Vg = Vin.clone()
+    ang, thr = ctx.empty_policy()
+    ctx.bellman_sweep(Vin, Vg, ang, thr)
+    W = Vin.clone()
+    ctx.policy_eval_sweep_last(Vg, W)
+    # the oracle evaluates the device's chosen policy on the device's T V
+    Vg_h = host(Vg).astype(np.float64)
+    want = o.policy_eval_sweep(Vg_h, host(ang).astype(np.float64), host(thr))
+    free = o.kind == KIND_FREE
+    tol = sweep_tol(Vg_h, want)
+    assert np.all(np.abs(host(W) - want)[free] <= tol[free])
+    np.testing.assert_array_equal(host(W)[~free], V32[~free])
+
+
 # ------------------------------------------------------------- solvers
 def test_cfg0_value_iteration_parity(dpo):
     """12^4, 16 angles + coast, VI to convergence vs the stored oracle solution."""
