@@ -37,6 +37,7 @@ struct dpo_ctx {
   bool fast_ok = false;           // the factorised thrust kernel applies
   int path = 0;                   // 0 auto, 1 direct, 2 fast
   float* tab = nullptr;  // [3][n_ang]: sin, cos, angle
+  float* rot = nullptr;  // [2][kRot]: golden-section rotation constants (scan bracket, local bracket)
   int n_ang = 0;
   int tab_cap = 0;
   double* partial = nullptr;
@@ -117,8 +118,34 @@ int validate_search(dpo_ctx* c, const dpo_search* s) {
 
 hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+constexpr int kRot = 2 + 2 * 64;
+
+// Rotation constants of the golden section on [u0 - half, u0 + half]: sin/cos
+// of half*rho^3 (the two interior points), then of L0*rho^(k+4), L0 = 2*half,
+// the move of the new point at step k (FP64, rounded to float).
+void golden_rotations(double half, float* out) {
+  const double rho = (std::sqrt(5.0) - 1.0) / 2.0;
+  const double first = half * rho * rho * rho;
+  out[0] = (float)std::sin(first);
+  out[1] = (float)std::cos(first);
+  double step = 2.0 * half * rho * rho * rho * rho;
+  for (int k = 0; k < 64; k++) {
+    out[2 + 2 * k] = (float)std::sin(step);
+    out[3 + 2 * k] = (float)std::cos(step);
+    step *= rho;
+  }
+}
+
 // Tabulated angles u_k = -pi + 2*pi*k/K (FP64, rounded to float).
 int upload_table(dpo_ctx* c) {
+  if (!c->rot && hipMalloc(&c->rot, sizeof(float) * 2 * kRot) != hipSuccess) return fail(c, DPO_ENOMEM, "rotation table alloc");
+  {
+    std::vector<float> r(2 * kRot, 0.0f);
+    const double pi = 3.14159265358979323846;
+    golden_rotations(2.0 * pi / (double)(c->search.n_scan > 0 ? c->search.n_scan : 8), r.data());
+    golden_rotations(c->search.local_half_width > 0 ? c->search.local_half_width : 0.1, r.data() + kRot);
+    HIP_TRY(c, hipMemcpy(c->rot, r.data(), sizeof(float) * 2 * kRot, hipMemcpyHostToDevice));
+  }
   const int K = c->search.mode == DPO_SEARCH_TABLE ? c->search.n_angles : c->search.n_scan;
   if (K > c->tab_cap) {
     if (c->tab) hipFree(c->tab);
@@ -173,6 +200,8 @@ SweepArgs base_args(const dpo_ctx* c) {
   a.tab_ang = c->tab + 2 * c->n_ang;
   a.n_ang = c->n_ang;
   a.n_golden = c->search.n_golden;
+  a.rot_scan = c->rot;
+  a.rot_local = c->rot + kRot;
   a.half_width = (float)(2.0 * 3.14159265358979323846 / (double)(c->search.n_scan > 0 ? c->search.n_scan : 1));
   a.n_local = c->search.n_local;
   a.local_half_width = (float)c->search.local_half_width;
@@ -413,6 +442,7 @@ void dpo_destroy(dpo_ctx* c) {
   if (c->rinv) hipFree(c->rinv);
   if (c->gtab) hipFree(c->gtab);
   if (c->tab) hipFree(c->tab);
+  if (c->rot) hipFree(c->rot);
   if (c->partial) hipFree(c->partial);
   if (c->resid) hipFree(c->resid);
   if (c->work) hipFree(c->work);

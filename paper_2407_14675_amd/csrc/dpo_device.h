@@ -134,14 +134,21 @@ __device__ inline bool foot_cell(const Grid& G, const int i[4], const float off[
   return true;
 }
 
-// 16-corner Q1 value of the cell whose lowest corner is p: 15 lerps, r first.
+// Two r-adjacent corners fetched by one dword-aligned 8-byte load.
+struct __attribute__((aligned(4))) CornerPair {
+  float lo, hi;
+};
+
+// 16-corner Q1 value of the cell whose lowest corner is p: 15 lerps, r first
+// (the 8 r-adjacent corner pairs are 8 loads).
 __device__ inline float cell_value(const float* __restrict__ p, const Grid& G, const float t[4]) {
   const int s1 = G.st[1], s2 = G.st[2], s3 = G.st[3];
   float c[8];
 #pragma unroll
   for (int e = 0; e < 8; e++) {
     const int o = ((e & 1) ? s1 : 0) + ((e & 2) ? s2 : 0) + ((e & 4) ? s3 : 0);
-    c[e] = lerp(p[o], p[o + 1], t[0]);
+    const CornerPair v = *reinterpret_cast<const CornerPair*>(p + o);
+    c[e] = lerp(v.lo, v.hi, t[0]);
   }
   const float d0 = lerp(c[0], c[1], t[1]);
   const float d1 = lerp(c[2], c[3], t[1]);
@@ -179,16 +186,6 @@ template <bool kSnap = false>
 __device__ inline float q_coast(const float* __restrict__ V, const Grid& G, const Phys& P,
                                 const NodeTerms& T) {
   return fmaf(P.gamma, interp_off<kSnap>(V, G, T.i, T.drift, P.M), P.q_coast);
-}
-
-// sin and cos of a small angle d (|d| <= pi/4) by truncated Taylor series;
-// the truncation error is below 2e-9 there, far under float32 resolution.
-__device__ inline void small_sincos(float d, float& s, float& c) {
-  const float d2 = d * d;
-  s = d * (1.0f - d2 * (1.0f / 6.0f) * (1.0f - d2 * (1.0f / 20.0f) *
-                                                   (1.0f - d2 * (1.0f / 42.0f) * (1.0f - d2 * (1.0f / 72.0f)))));
-  c = 1.0f - d2 * 0.5f * (1.0f - d2 * (1.0f / 12.0f) *
-                                     (1.0f - d2 * (1.0f / 30.0f) * (1.0f - d2 * (1.0f / 56.0f) * (1.0f - d2 * (1.0f / 90.0f)))));
 }
 
 __device__ inline float wrap_pi(float u) {

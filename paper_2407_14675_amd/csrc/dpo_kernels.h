@@ -34,6 +34,8 @@ struct SweepArgs {
   int n_ang;
   int n_golden;
   float half_width;  // golden bracket half width, 2*pi/n_scan
+  const float* rot_scan;   // golden-section rotation constants for half_width (see golden())
+  const float* rot_local;  // the same for local_half_width
   int n_local;
   float local_half_width;
   float fallback_tol;

@@ -155,55 +155,84 @@ __device__ inline int node_terms_tab(const SweepArgs& a, uint32_t packed, NodeTe
   return j;
 }
 
-// Golden-section refinement around the centre angle u0 (sin/cos s0, c0):
-// the angles u0 + d are formed by rotating (s0, c0) by d.  qf(sin, cos)
-// returns Q of thrust at that angle.  The best evaluated point is kept
-// (strict <, evaluation order).
+// Golden-section refinement around the centre angle u0 (sin/cos s0, c0) on
+// [u0 - half, u0 + half]: two interior points u0 -+ half*rho^3, then one new
+// point per step; the best evaluated point is kept (strict <, evaluation
+// order).  The new point of step k is the previous point on the kept side
+// moved by L0*rho^(k+4) (L0 = 2*half), because 2*rho - 1 = rho^3 and
+// rho^2 - rho^3 = rho^4; its sin/cos are formed by rotating the previous
+// point's sin/cos with the per-step constants rot = (sin, cos) of
+// half*rho^3, then of L0*rho^(k+4) for k = 0, 1, ...  qf(sin, cos) returns
+// the thrust Q at that angle.  Offsets from u0 are tracked in float for the
+// stored angle.
 struct GoldenState {
-  float best_q, best_d;
+  float best_q, best_d;  // best Q and its offset from u0
+  float best_s, best_c;  // its sin/cos as evaluated
 };
 
 template <class QF>
-__device__ inline void golden(const QF& qf, float s0, float c0, float half, int steps, GoldenState& g) {
-  auto q_at = [&](float d) {
-    float sd, cd;
-    small_sincos(d, sd, cd);
-    return qf(fmaf(s0, cd, c0 * sd), fmaf(c0, cd, -s0 * sd));
-  };
+__device__ inline void golden(const QF& qf, float s0, float c0, float half, int steps, const float* __restrict__ rot,
+                              GoldenState& g) {
   const float rho = 0.6180339887498949f;
   float lo = -half, hi = half;
   float x1 = hi - rho * (hi - lo), x2 = lo + rho * (hi - lo);
-  float f1 = q_at(x1);
+  const float sp = rot[0], cp = rot[1];
+  float s1 = fmaf(s0, cp, -c0 * sp), c1 = fmaf(c0, cp, s0 * sp);  // u0 - half*rho^3
+  float s2 = fmaf(s0, cp, c0 * sp), c2 = fmaf(c0, cp, -s0 * sp);  // u0 + half*rho^3
+  float f1 = qf(s1, c1);
   if (f1 < g.best_q) {
     g.best_q = f1;
     g.best_d = x1;
+    g.best_s = s1;
+    g.best_c = c1;
   }
-  float f2 = q_at(x2);
+  float f2 = qf(s2, c2);
   if (f2 < g.best_q) {
     g.best_q = f2;
     g.best_d = x2;
+    g.best_s = s2;
+    g.best_c = c2;
   }
   for (int it = 0; it < steps; it++) {
-    if (f1 < f2) {
+    const float sd = rot[2 + 2 * it], cd = rot[3 + 2 * it];
+    const bool left = f1 < f2;  // keep [lo, x2]; new point left of x1
+    float xn, sn, cn;
+    if (left) {
       hi = x2;
       x2 = x1;
       f2 = f1;
-      x1 = hi - rho * (hi - lo);
-      f1 = q_at(x1);
-      if (f1 < g.best_q) {
-        g.best_q = f1;
-        g.best_d = x1;
-      }
+      xn = hi - rho * (hi - lo);
+      sn = fmaf(s1, cd, -c1 * sd);
+      cn = fmaf(c1, cd, s1 * sd);
+      s2 = s1;
+      c2 = c1;
     } else {
       lo = x1;
       x1 = x2;
       f1 = f2;
-      x2 = lo + rho * (hi - lo);
-      f2 = q_at(x2);
-      if (f2 < g.best_q) {
-        g.best_q = f2;
-        g.best_d = x2;
-      }
+      xn = lo + rho * (hi - lo);
+      sn = fmaf(s2, cd, c2 * sd);
+      cn = fmaf(c2, cd, -s2 * sd);
+      s1 = s2;
+      c1 = c2;
+    }
+    const float fn = qf(sn, cn);
+    if (left) {
+      x1 = xn;
+      s1 = sn;
+      c1 = cn;
+      f1 = fn;
+    } else {
+      x2 = xn;
+      s2 = sn;
+      c2 = cn;
+      f2 = fn;
+    }
+    if (fn < g.best_q) {
+      g.best_q = fn;
+      g.best_d = xn;
+      g.best_s = sn;
+      g.best_c = cn;
     }
   }
 }
@@ -222,15 +251,6 @@ __device__ inline void scan_table(const QF& qf, const SweepArgs& a, float& bq, i
   }
 }
 
-// sin/cos of the angle d away from the one with sin/cos (s0, c0), formed
-// exactly as the golden section forms them.
-__device__ inline void rotate(float s0, float c0, float d, float& sn, float& cs) {
-  float sd, cd;
-  small_sincos(d, sd, cd);
-  sn = fmaf(s0, cd, c0 * sd);
-  cs = fmaf(c0, cd, -s0 * sd);
-}
-
 // The outcome of the search at one node.
 struct Choice {
   float v;       // min Q
@@ -246,12 +266,13 @@ __device__ inline void full_search(const QF& qf, const SweepArgs& a, float qc, C
   float bq;
   int bk;
   scan_table(qf, a, bq, bk);
-  GoldenState g{bq, 0.0f};
-  if (a.n_golden > 0) golden(qf, a.tab_sin[bk], a.tab_cos[bk], a.half_width, a.n_golden, g);
+  GoldenState g{bq, 0.0f, a.tab_sin[bk], a.tab_cos[bk]};
+  if (a.n_golden > 0) golden(qf, a.tab_sin[bk], a.tab_cos[bk], a.half_width, a.n_golden, a.rot_scan, g);
   ch.thr = g.best_q < qc ? 1 : 0;
   ch.v = ch.thr ? g.best_q : qc;
   ch.ang = wrap_pi(a.tab_ang[bk] + g.best_d);
-  rotate(a.tab_sin[bk], a.tab_cos[bk], g.best_d, ch.sn, ch.cs);
+  ch.sn = g.best_s;
+  ch.cs = g.best_c;
 }
 
 // Tabulated search: first strict minimum over the table, coast on ties.
@@ -275,12 +296,13 @@ template <class QF>
 __device__ inline int seeded_search(const QF& qf, const SweepArgs& a, float seed, float qc, float vin, Choice& ch) {
   float s0, c0;
   sincosf(seed, &s0, &c0);
-  GoldenState g{qf(s0, c0), 0.0f};
-  golden(qf, s0, c0, a.local_half_width, a.n_local - 3, g);
+  GoldenState g{qf(s0, c0), 0.0f, s0, c0};
+  golden(qf, s0, c0, a.local_half_width, a.n_local - 3, a.rot_local, g);
   ch.thr = g.best_q < qc ? 1 : 0;
   ch.v = ch.thr ? g.best_q : qc;
   ch.ang = wrap_pi(seed + g.best_d);
-  rotate(s0, c0, g.best_d, ch.sn, ch.cs);
+  ch.sn = g.best_s;
+  ch.cs = g.best_c;
   if (fabsf(ch.v - vin) > a.fallback_tol * fmaxf(1.0f, fabsf(vin))) {
     full_search(qf, a, qc, ch);
     return 1;
@@ -391,67 +413,63 @@ __device__ inline Regions axis_regions(int i, int n, float d, float g) {
 
 struct FastNode {
   float g1, g2;  // thrust displacement per unit sin u (v_r) and cos u (v_t), cells
-  float bv, bt;  // region thresholds as displacements from the coast foot
+  float d1, d2;  // coast displacements along v_r and v_t
+  float bv, bt;  // region 1 <=> offset >= threshold (the same float test as foot_cell)
   const float4* coef;
 };
 
 __device__ inline float fast_q(const FastNode& F, float sn, float cs) {
-  const float dv = F.g1 * sn, dt = F.g2 * cs;
-  const int idx = (dv >= F.bv ? 2 * kBlock : 0) + (dt >= F.bt ? kBlock : 0);
+  const float ov = fmaf(F.g1, sn, F.d1), ot = fmaf(F.g2, cs, F.d2);
+  const int idx = (ov >= F.bv ? 2 * kBlock : 0) + (ot >= F.bt ? kBlock : 0);
   const float4 c = F.coef[idx];
+  const float dv = ov - F.d1, dt = ot - F.d2;
   return fmaf(fmaf(c.w, dt, c.y), dv, fmaf(c.z, dt, c.x));
 }
 
-__device__ inline void fast_setup(const SweepArgs& a, const NodeTerms& T, float4 (*coef)[kBlock], FastNode& F) {
+// Lerp along r of the corner pair (p[0], p[1]), fetched by one 8-byte load.
+__device__ inline float lerp_pair(const float* p, float t) {
+  const CornerPair v = *reinterpret_cast<const CornerPair*>(p);
+  return lerp(v.lo, v.hi, t);
+}
+
+// Per-node set-up of the thrust evaluations; returns the coast Q, which is
+// the same Q1 value read from the patch (plane i_m, coast cell).
+__device__ inline float fast_setup(const SweepArgs& a, const NodeTerms& T, float4 (*coef)[kBlock], FastNode& F) {
   const Grid& G = a.G;
   F.g1 = T.g1;
   F.g2 = T.g2;
+  F.d1 = T.drift[1];
+  F.d2 = T.drift[2];
   F.coef = &coef[0][threadIdx.x];
-  // r cell (shared by all controls)
-  const float o0 = T.drift[0];
-  bool ok = o0 >= (float)(-T.i[0]) && o0 <= (float)(G.n[0] - 1 - T.i[0]);
+  // r cell, shared by every control
   int br = 0, bm = 0;
   float tr = 0.0f, tm = 0.0f;
-  if (ok) {
-    const float fl = floorf(o0);
-    br = T.i[0] + (int)fl;
-    tr = o0 - fl;
-    if (br > G.n[0] - 2) {
-      br = G.n[0] - 2;
-      tr = 1.0f;
-    }
-  }
-  // m cell under thrust
-  const float om = T.gm;
-  ok = ok && om >= (float)(-T.i[3]) && om <= (float)(G.n[3] - 1 - T.i[3]);
-  if (ok) {
-    const float fl = floorf(om);
-    bm = T.i[3] + (int)fl;
-    tm = om - fl;
-    if (bm > G.n[3] - 2) {
-      bm = G.n[3] - 2;
-      tm = 1.0f;
-    }
-  }
+  const bool ok_r = axis_cell(T.i[0], G.n[0], T.drift[0], br, tr);
+  // m cell under thrust; the coast foot stays on plane i_m
+  const bool ok_m = axis_cell(T.i[3], G.n[3], T.gm, bm, tm);
+  const int m_lo = ok_m ? bm : T.i[3];
+  const int m_hi = ok_m ? bm + 1 : T.i[3];
+  const int coast_plane = T.i[3];  // either m_lo or m_hi
   const Regions Rv = axis_regions(T.i[1], G.n[1], T.drift[1], T.g1);
   const Regions Rt = axis_regions(T.i[2], G.n[2], T.drift[2], T.g2);
-  F.bv = Rv.bnd - T.drift[1];
-  F.bt = Rt.bnd - T.drift[2];
+  F.bv = Rv.bnd;
+  F.bt = Rt.bnd;
   const float qM = fmaf(a.P.gamma, a.P.M, a.P.q_thr);
-  float W[3][3];
-  if (ok) {
-    const float* __restrict__ base = a.V_in + br + bm * G.st[3];
-    const int s3 = G.st[3];
+  float W[3][3], Wc[3][3];
+  if (ok_r) {
+    const float* __restrict__ base = a.V_in + br;
+    const int so = (m_hi - m_lo) * G.st[3];
 #pragma unroll
     for (int p = 0; p < 3; p++) {
       const int v = min(max(Rv.b0 + p, 0), G.n[1] - 1);
 #pragma unroll
       for (int q = 0; q < 3; q++) {
         const int w = min(max(Rt.b0 + q, 0), G.n[2] - 1);
-        const float* pp = base + v * G.st[1] + w * G.st[2];
-        const float lo = lerp(pp[0], pp[1], tr);
-        const float hi = lerp(pp[s3], pp[s3 + 1], tr);
+        const float* pp = base + v * G.st[1] + w * G.st[2] + m_lo * G.st[3];
+        const float lo = lerp_pair(pp, tr);
+        const float hi = lerp_pair(pp + so, tr);
         W[p][q] = lerp(lo, hi, tm);
+        Wc[p][q] = coast_plane == m_lo ? lo : hi;
       }
     }
   }
@@ -461,7 +479,7 @@ __device__ inline void fast_setup(const SweepArgs& a, const NodeTerms& T, float4
 #pragma unroll
     for (int bt = 0; bt < 2; bt++) {
       float4 c = make_float4(qM, 0.0f, 0.0f, 0.0f);
-      const bool valid = ok && (av ? Rv.ok1 : Rv.ok0) && (bt ? Rt.ok1 : Rt.ok0);
+      const bool valid = ok_r && ok_m && (av ? Rv.ok1 : Rv.ok0) && (bt ? Rt.ok1 : Rt.ok0);
       if (valid) {
         const float w00 = W[av][bt], w10 = W[av + 1][bt], w01 = W[av][bt + 1], w11 = W[av + 1][bt + 1];
         // local coordinates of the coast foot in this cell
@@ -477,6 +495,23 @@ __device__ inline void fast_setup(const SweepArgs& a, const NodeTerms& T, float4
       coef[av * 2 + bt][threadIdx.x] = c;
     }
   }
+  // coast: the cell of (d1, d2) on plane i_m, by the same region tests
+  const int av = T.drift[1] >= Rv.bnd ? 1 : 0;
+  const int bt = T.drift[2] >= Rt.bnd ? 1 : 0;
+  const bool cvalid = ok_r && (av ? Rv.ok1 : Rv.ok0) && (bt ? Rt.ok1 : Rt.ok0);
+  float Ic = a.P.M;
+  if (cvalid) {
+    const float tv = T.drift[1] - (float)(Rv.b0 + av - T.i[1]);
+    const float tt = T.drift[2] - (float)(Rt.b0 + bt - T.i[2]);
+    float w00, w10, w01, w11;
+    // select the coast cell of the 3 x 3 patch (av, bt in {0, 1})
+    w00 = av ? (bt ? Wc[1][1] : Wc[1][0]) : (bt ? Wc[0][1] : Wc[0][0]);
+    w10 = av ? (bt ? Wc[2][1] : Wc[2][0]) : (bt ? Wc[1][1] : Wc[1][0]);
+    w01 = av ? (bt ? Wc[1][2] : Wc[1][1]) : (bt ? Wc[0][2] : Wc[0][1]);
+    w11 = av ? (bt ? Wc[2][2] : Wc[2][1]) : (bt ? Wc[1][2] : Wc[1][1]);
+    Ic = lerp(lerp(w00, w10, tv), lerp(w01, w11, tv), tt);
+  }
+  return fmaf(a.P.gamma, Ic, a.P.q_coast);
 }
 
 template <int kMode>
@@ -490,9 +525,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep_fast(SweepArgs a) {
     NodeTerms T;
     const int j = node_terms_tab(a, a.free_node[t], T);
     FastNode F;
-    fast_setup(a, T, s_coef, F);
+    const float qc = fast_setup(a, T, s_coef, F);
     auto qf = [&](float sn, float cs) { return fast_q(F, sn, cs); };
-    const float qc = q_coast(a.V_in, a.G, a.P, T);
     const float vin = a.V_in[j];
     Choice ch;
     if (kMode == 0) table_search(qf, a, qc, ch);
