@@ -145,6 +145,9 @@ int dpo_get_kind(dpo_ctx* ctx, uint8_t* kind, void* stream);
  * Returns DPO_EINVAL for 2 where it does not apply. */
 int dpo_set_kernel_path(dpo_ctx* ctx, int32_t path);
 
+/* Workgroup size of the factorised sweeps (64, 128, ..., 512; default 256). */
+int dpo_set_block(dpo_ctx* ctx, int32_t block);
+
 /* The path the sweeps take now: 1 direct, 2 factorised (negative on error). */
 int dpo_kernel_path(const dpo_ctx* ctx);
 
@@ -247,6 +250,62 @@ int dpo_probe_q(dpo_ctx* ctx, const float* V, const int32_t* nodes, const uint8_
  * float[n*4]): s_k - i_k as used by the sweep. */
 int dpo_probe_foot(dpo_ctx* ctx, const int32_t* nodes, const uint8_t* thr, const float* angle,
                    int64_t n, float* off_out, void* stream);
+
+/* ------------------------------------------------------------ batched solve */
+
+/* Many transfer problems solved together by value iteration (paper Section 3):
+ * each sweep is ONE kernel launch over the tiles of every problem still
+ * running; a per-problem FP64 residual stops a problem once its relative
+ * residual max|dV|/max(1,|V|) is below tol_rel (its tiles then exit at once).
+ * The host captures S sweeps into a hipGraph and replays it, synchronising
+ * once per replay.  Each problem gets its own grid and physics; the search
+ * (TABLE or SCAN_GOLDEN) is shared, and the factorised sweep must apply to
+ * every problem. */
+typedef struct dpo_batch dpo_batch;
+
+typedef struct {
+  int64_t sweeps;        /* sweeps until this problem stopped */
+  double resid_max_rel;  /* its last residual (FP64) */
+  double resid_sum_abs;
+  double resid_max_abs;
+  int32_t converged;     /* 1 if stopped by the tolerance */
+  int32_t status;        /* 0 running at the end, 1 converged, 2 non-finite values */
+} dpo_batch_stats;
+
+/* Create: grids, probs are host arrays of n_prob entries (copied). */
+int dpo_batch_create(int32_t n_prob, const dpo_grid* grids, const dpo_problem* probs, const dpo_search* search,
+                     dpo_batch** out);
+void dpo_batch_destroy(dpo_batch* b);
+const char* dpo_batch_last_error(const dpo_batch* b);
+
+/* Node and free-node counts per problem (host int64[n_prob], nullable). */
+int dpo_batch_sizes(const dpo_batch* b, int64_t* n_nodes, int64_t* n_free);
+
+/* V: host array of n_prob device pointers, each float[N_p]; V[p] := 0 on its
+ * target nodes, M elsewhere. */
+int dpo_batch_init_value(dpo_batch* b, float* const* V, void* stream);
+
+/* Value iteration of all problems from the given V (in/out, host array of
+ * device pointers).  pol_angle / pol_thr: host arrays of device pointers, or
+ * NULL.  sweeps_per_graph: even, 2..256; block: 64..512 (multiple of 64).
+ * stats: host array of n_prob (nullable); *seconds: wall time (nullable).
+ * Synchronises `stream` first and runs on the batch's own stream.  Returns
+ * DPO_ENOCONV if some problem did not converge within max_sweeps. */
+int dpo_batch_solve_vi(dpo_batch* b, float* const* V, float* const* pol_angle, uint8_t* const* pol_thr, double tol_rel,
+                       int64_t max_sweeps, int32_t sweeps_per_graph, int32_t block, dpo_batch_stats* stats,
+                       double* seconds, void* stream);
+
+/* The same problems solved one after another by dpo_solve_vi (reference for
+ * the batched form); same arguments as dpo_batch_solve_vi plus check_every. */
+int dpo_batch_solve_sequential(dpo_batch* b, float* const* V, float* const* pol_angle, uint8_t* const* pol_thr,
+                               double tol_rel, int64_t max_sweeps, int32_t check_every, dpo_batch_stats* stats,
+                               double* seconds, void* stream);
+
+/* Autotuning probe: seconds per batched sweep for (block, sweeps_per_graph),
+ * timed over `replays` graph replays on scratch buffers (the solve's data is
+ * not touched). */
+int dpo_batch_time_config(dpo_batch* b, int32_t block, int32_t sweeps_per_graph, int32_t replays,
+                          double* seconds_per_sweep);
 
 #ifdef __cplusplus
 }

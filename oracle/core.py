@@ -276,7 +276,7 @@ class Oracle:
             i.append(j % n[k])
             j //= n[k]
         lo, hi = self.problem["lo"], self.problem["hi"]
-        return np.array([lo[k] + i[k] * (hi[k] - lo[k]) / (n[k] - 1) for k in range(4)])
+        return np.array([lo[k] + i[k] * ((hi[k] - lo[k]) / (n[k] - 1)) for k in range(4)])
 
 
 def mask_from_coarse(coarse_problem, Vc, fine_problem, dilate, thresh=None):

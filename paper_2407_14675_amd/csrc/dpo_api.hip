@@ -36,6 +36,8 @@ struct dpo_ctx {
   float gm = 0;                   // thrust displacement along m
   bool fast_ok = false;           // the factorised thrust kernel applies
   int path = 0;                   // 0 auto, 1 direct, 2 fast
+  int block = kBlock;             // workgroup size of the factorised sweeps
+  int last_blocks = 0;            // workgroups of the last kernel that wrote residual partials
   float* tab = nullptr;  // [3][n_ang]: sin, cos, angle
   float* rot = nullptr;  // [2][kRot]: golden-section rotation constants (scan bracket, local bracket)
   int n_ang = 0;
@@ -214,12 +216,12 @@ SweepArgs base_args(const dpo_ctx* c) {
   return a;
 }
 
-int sweep_blocks(const dpo_ctx* c) { return blocks_for(c->n_free); }
+bool use_fast(const dpo_ctx* c);
 
 // Final FP64 reduction of the last node kernel's partials into `out`.
 int finish_resid(dpo_ctx* c, double* out, hipStream_t s) {
   if (!out) return DPO_OK;
-  const int nb = sweep_blocks(c);
+  const int nb = c->last_blocks;
   if (nb == 0) {
     HIP_TRY(c, hipMemsetAsync(out, 0, sizeof(double) * kPartial, s));
     return DPO_OK;
@@ -271,8 +273,9 @@ int sweep_full(dpo_ctx* c, const float* Vin, float* Vout, float* ang, uint8_t* t
   if (a.n_free == 0) return DPO_OK;
   const int mode = c->search.mode == DPO_SEARCH_TABLE ? 0 : 1;
   hipError_t e;
-  if (use_fast(c)) e = launch_sweep_fast(a, mode, s);
+  if (use_fast(c)) e = launch_sweep_fast(a, mode, c->block, s);
   else e = mode == 0 ? launch_sweep_table(a, s) : launch_sweep_scan_golden(a, s);
+  c->last_blocks = blocks_for(c->n_free, use_fast(c) ? c->block : kBlock);
   if (e != hipSuccess) return hip_fail(c, e, "bellman sweep launch");
   return DPO_OK;
 }
@@ -291,7 +294,8 @@ int sweep_seeded(dpo_ctx* c, const float* Vin, float* Vout, float* ang, uint8_t*
     c->desc_valid = true;
   }
   if (a.n_free == 0) return DPO_OK;
-  hipError_t e = use_fast(c) ? launch_sweep_fast(a, 2, s) : launch_sweep_seeded(a, s);
+  hipError_t e = use_fast(c) ? launch_sweep_fast(a, 2, c->block, s) : launch_sweep_seeded(a, s);
+  c->last_blocks = blocks_for(c->n_free, use_fast(c) ? c->block : kBlock);
   if (e != hipSuccess) return hip_fail(c, e, "seeded sweep launch");
   return DPO_OK;
 }
@@ -305,6 +309,7 @@ int sweep_eval(dpo_ctx* c, const float* Vin, float* Vout, const float* ang, cons
   a.pol_thr_in = thr;
   if (a.n_free == 0) return DPO_OK;
   hipError_t e = launch_policy_eval(a, want_resid, s);
+  if (want_resid) c->last_blocks = blocks_for(c->n_free, kBlock);
   if (e != hipSuccess) return hip_fail(c, e, "policy eval launch");
   return DPO_OK;
 }
@@ -425,7 +430,7 @@ int dpo_create(const dpo_grid* grid, const dpo_problem* prob, const dpo_search* 
     return cleanup(DPO_EHIP);
   }
   c->n_free = total;
-  c->partial_blocks = blocks_for(total > 0 ? total : 1);
+  c->partial_blocks = blocks_for(total > 0 ? total : 1, 64);
   if (hipMalloc(&c->partial, sizeof(double) * kPartial * c->partial_blocks) != hipSuccess) {
     c->err = "device allocation failed in dpo_create";
     return cleanup(DPO_ENOMEM);
@@ -470,6 +475,13 @@ int dpo_set_kernel_path(dpo_ctx* c, int32_t path) {
   if (path < 0 || path > 2) return fail(c, DPO_EINVAL, "path must be 0 (auto), 1 (direct) or 2 (factorised)");
   if (path == 2 && !c->fast_ok) return fail(c, DPO_EINVAL, "the factorised kernel does not apply to this problem");
   c->path = path;
+  return DPO_OK;
+}
+
+int dpo_set_block(dpo_ctx* c, int32_t block) {
+  if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
+  if (block < 64 || block > 512 || block % 64) return fail(c, DPO_EINVAL, "block must be 64, 128, ..., 512");
+  c->block = block;
   return DPO_OK;
 }
 
@@ -757,6 +769,337 @@ int dpo_probe_foot(dpo_ctx* c, const int32_t* nodes, const uint8_t* thr, const f
   SweepArgs a = base_args(c);
   HIP_TRY(c, launch_probe_q(a, nodes, thr, angle, (int)n, nullptr, off_out, S(stream)));
   return DPO_OK;
+}
+
+}  // extern "C"
+
+// ============================================================ batched solve
+struct dpo_batch {
+  int n = 0;
+  std::vector<dpo_ctx*> ctx;
+  dpo_search search;
+  int mode = 0;
+  hipStream_t stream = nullptr;
+  std::vector<float*> Vb;  // second value buffer per problem
+  BatchProblem* d_probs = nullptr;
+  int* d_tile_begin = nullptr;
+  int* d_state = nullptr;  // [3][n]: done, done_buf, sweeps
+  double* d_partial = nullptr;
+  double* d_resid = nullptr;
+  int partial_cap = 0;
+  std::string err;
+};
+
+namespace {
+
+int bfail(dpo_batch* b, int code, const std::string& msg) {
+  if (b) b->err = msg;
+  else g_err = msg;
+  return code;
+}
+
+#define BHIP_TRY(b, call)                                                            \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess) return bfail((b), DPO_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Upload the per-problem records for workgroup size `block`, with value
+// buffers A = V[p], B = Vb[p]; returns the number of tiles.
+int batch_tables(dpo_batch* b, int block, float* const* V, float* const* ang, uint8_t* const* thr, int* n_tiles) {
+  std::vector<BatchProblem> h(b->n);
+  std::vector<int> tb(b->n + 1, 0);
+  for (int p = 0; p < b->n; p++) {
+    dpo_ctx* c = b->ctx[p];
+    h[p].a = base_args(c);
+    h[p].a.V_in = V[p];
+    h[p].a.V_out = b->Vb[p];
+    h[p].a.pol_ang = ang ? ang[p] : nullptr;
+    h[p].a.pol_thr = thr ? thr[p] : nullptr;
+    h[p].a.partial = nullptr;
+    h[p].tile_begin = tb[p];
+    tb[p + 1] = tb[p] + blocks_for(c->n_free, block);
+  }
+  if (tb[b->n] > b->partial_cap) return bfail(b, DPO_EINVAL, "batch: too many tiles for the partial buffer");
+  BHIP_TRY(b, hipMemcpyAsync(b->d_probs, h.data(), sizeof(BatchProblem) * b->n, hipMemcpyHostToDevice, b->stream));
+  BHIP_TRY(b, hipMemcpyAsync(b->d_tile_begin, tb.data(), sizeof(int) * (b->n + 1), hipMemcpyHostToDevice, b->stream));
+  BHIP_TRY(b, hipStreamSynchronize(b->stream));
+  *n_tiles = tb[b->n];
+  return DPO_OK;
+}
+
+BatchArgs batch_args(dpo_batch* b, double tol) {
+  BatchArgs a;
+  a.probs = b->d_probs;
+  a.tile_begin = b->d_tile_begin;
+  a.n_prob = b->n;
+  a.done = b->d_state;
+  a.done_buf = b->d_state + b->n;
+  a.sweeps = b->d_state + 2 * b->n;
+  a.partial = b->d_partial;
+  a.resid = b->d_resid;
+  a.tol = tol;
+  return a;
+}
+
+// Capture S sweeps (sweep + per-problem stop decision each) into a graph.
+int batch_graph(dpo_batch* b, const BatchArgs& a, int block, int n_tiles, int S, hipGraphExec_t* exec) {
+  hipGraph_t g = nullptr;
+  BHIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int s = 0; s < S && e == hipSuccess; s++) {
+    e = launch_batch_sweep(a, b->mode, block, n_tiles, s & 1, b->stream);
+    if (e == hipSuccess) e = launch_batch_reduce(a, s & 1, b->stream);
+  }
+  hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) hipGraphDestroy(g);
+    return bfail(b, DPO_EHIP, std::string("batch graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) return bfail(b, DPO_EHIP, std::string("batch graph instantiate: ") + hipGetErrorString(e));
+  return DPO_OK;
+}
+
+int check_batch_cfg(dpo_batch* b, int block, int S) {
+  if (block < 64 || block > 512 || block % 64) return bfail(b, DPO_EINVAL, "batch: block must be 64, 128, ..., 512");
+  if (S < 2 || S > 256 || (S & 1)) return bfail(b, DPO_EINVAL, "batch: sweeps per graph must be even, in [2, 256]");
+  return DPO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dpo_batch_create(int32_t n_prob, const dpo_grid* grids, const dpo_problem* probs, const dpo_search* search,
+                     dpo_batch** out) {
+  if (!out) return bfail(nullptr, DPO_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n_prob < 1 || n_prob > 4096 || !grids || !probs || !search) return bfail(nullptr, DPO_EINVAL, "batch: bad arguments");
+  if (search->mode != DPO_SEARCH_TABLE && search->mode != DPO_SEARCH_SCAN_GOLDEN)
+    return bfail(nullptr, DPO_EINVAL, "batch: search must be TABLE or SCAN_GOLDEN");
+  dpo_batch* b = new dpo_batch();
+  b->n = n_prob;
+  b->search = *search;
+  b->mode = search->mode == DPO_SEARCH_TABLE ? 0 : 1;
+  auto bail = [&](int code) {
+    if (code != DPO_OK) {
+      g_err = b->err;
+      dpo_batch_destroy(b);
+    }
+    return code;
+  };
+  int tiles64 = 0;
+  for (int p = 0; p < n_prob; p++) {
+    dpo_ctx* c = nullptr;
+    int rc = dpo_create(&grids[p], &probs[p], search, nullptr, &c);
+    if (rc != DPO_OK) {
+      b->err = "batch problem " + std::to_string(p) + ": " + g_err;
+      return bail(rc);
+    }
+    b->ctx.push_back(c);
+    if (!c->fast_ok) {
+      b->err = "batch problem " + std::to_string(p) + ": the factorised sweep does not apply";
+      return bail(DPO_EINVAL);
+    }
+    float* vb = nullptr;
+    if (hipMalloc(&vb, sizeof(float) * (size_t)c->N) != hipSuccess) {
+      b->err = "batch: value buffer alloc";
+      return bail(DPO_ENOMEM);
+    }
+    b->Vb.push_back(vb);
+    tiles64 += blocks_for(c->n_free, 64);
+  }
+  b->partial_cap = tiles64 > 0 ? tiles64 : 1;
+  if (hipMalloc(&b->d_probs, sizeof(BatchProblem) * n_prob) != hipSuccess ||
+      hipMalloc(&b->d_tile_begin, sizeof(int) * (n_prob + 1)) != hipSuccess ||
+      hipMalloc(&b->d_state, sizeof(int) * 3 * n_prob) != hipSuccess ||
+      hipMalloc(&b->d_partial, sizeof(double) * kPartial * b->partial_cap) != hipSuccess ||
+      hipMalloc(&b->d_resid, sizeof(double) * kPartial * n_prob) != hipSuccess) {
+    b->err = "batch: table alloc";
+    return bail(DPO_ENOMEM);
+  }
+  if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+    b->err = "batch: stream create";
+    return bail(DPO_EHIP);
+  }
+  *out = b;
+  return DPO_OK;
+}
+
+void dpo_batch_destroy(dpo_batch* b) {
+  if (!b) return;
+  if (b->stream) hipStreamSynchronize(b->stream);
+  for (dpo_ctx* c : b->ctx) dpo_destroy(c);
+  for (float* v : b->Vb) hipFree(v);
+  if (b->d_probs) hipFree(b->d_probs);
+  if (b->d_tile_begin) hipFree(b->d_tile_begin);
+  if (b->d_state) hipFree(b->d_state);
+  if (b->d_partial) hipFree(b->d_partial);
+  if (b->d_resid) hipFree(b->d_resid);
+  if (b->stream) hipStreamDestroy(b->stream);
+  delete b;
+}
+
+const char* dpo_batch_last_error(const dpo_batch* b) { return b ? b->err.c_str() : g_err.c_str(); }
+
+int dpo_batch_sizes(const dpo_batch* b, int64_t* n_nodes, int64_t* n_free) {
+  if (!b) return bfail(nullptr, DPO_EINVAL, "batch is NULL");
+  for (int p = 0; p < b->n; p++) {
+    if (n_nodes) n_nodes[p] = b->ctx[p]->N;
+    if (n_free) n_free[p] = b->ctx[p]->n_free;
+  }
+  return DPO_OK;
+}
+
+int dpo_batch_init_value(dpo_batch* b, float* const* V, void* stream) {
+  if (!b) return bfail(nullptr, DPO_EINVAL, "batch is NULL");
+  if (!V) return bfail(b, DPO_EINVAL, "V is NULL");
+  for (int p = 0; p < b->n; p++) {
+    int rc = dpo_init_value(b->ctx[p], V[p], stream);
+    if (rc != DPO_OK) return bfail(b, rc, b->ctx[p]->err);
+  }
+  return DPO_OK;
+}
+
+int dpo_batch_solve_vi(dpo_batch* b, float* const* V, float* const* pol_angle, uint8_t* const* pol_thr, double tol_rel,
+                       int64_t max_sweeps, int32_t sweeps_per_graph, int32_t block, dpo_batch_stats* stats,
+                       double* seconds, void* stream) {
+  if (!b) return bfail(nullptr, DPO_EINVAL, "batch is NULL");
+  if (!V) return bfail(b, DPO_EINVAL, "V is NULL");
+  for (int p = 0; p < b->n; p++)
+    if (!V[p] || (pol_angle && !pol_angle[p]) || (pol_thr && !pol_thr[p])) return bfail(b, DPO_EINVAL, "null array");
+  if (max_sweeps < 1 || !(tol_rel >= 0)) return bfail(b, DPO_EINVAL, "bad max_sweeps / tol");
+  int rc = check_batch_cfg(b, block, sweeps_per_graph);
+  if (rc != DPO_OK) return rc;
+  const int n = b->n;
+  BHIP_TRY(b, hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
+  const double t0 = now_s();
+  for (int p = 0; p < n; p++)
+    BHIP_TRY(b, hipMemcpyAsync(b->Vb[p], V[p], sizeof(float) * (size_t)b->ctx[p]->N, hipMemcpyDeviceToDevice, b->stream));
+  int n_tiles = 0;
+  if ((rc = batch_tables(b, block, V, pol_angle, pol_thr, &n_tiles)) != DPO_OK) return rc;
+  BHIP_TRY(b, hipMemsetAsync(b->d_state, 0, sizeof(int) * 3 * n, b->stream));
+  const BatchArgs a = batch_args(b, tol_rel);
+  hipGraphExec_t exec = nullptr;
+  if ((rc = batch_graph(b, a, block, n_tiles, sweeps_per_graph, &exec)) != DPO_OK) return rc;
+  std::vector<int> state(3 * n, 0);
+  int64_t done_sweeps = 0;
+  hipError_t e = hipSuccess;
+  while (done_sweeps < max_sweeps) {
+    e = hipGraphLaunch(exec, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(state.data(), b->d_state, sizeof(int) * n, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) break;
+    done_sweeps += sweeps_per_graph;
+    bool all = true;
+    for (int p = 0; p < n; p++) all = all && state[p] != 0;
+    if (all) break;
+  }
+  hipGraphExecDestroy(exec);
+  if (e != hipSuccess) return bfail(b, DPO_EHIP, std::string("batch solve: ") + hipGetErrorString(e));
+  std::vector<double> res(kPartial * n);
+  BHIP_TRY(b, hipMemcpy(state.data(), b->d_state, sizeof(int) * 3 * n, hipMemcpyDeviceToHost));
+  BHIP_TRY(b, hipMemcpy(res.data(), b->d_resid, sizeof(double) * kPartial * n, hipMemcpyDeviceToHost));
+  int code = DPO_OK;
+  for (int p = 0; p < n; p++) {
+    // S is even: an unfinished problem's last iterate is in buffer A = V[p]
+    if (state[p] != 0 && state[n + p] == 1)
+      BHIP_TRY(b, hipMemcpyAsync(V[p], b->Vb[p], sizeof(float) * (size_t)b->ctx[p]->N, hipMemcpyDeviceToDevice, b->stream));
+    if (state[p] == 2) code = DPO_ENUMERIC;
+    else if (state[p] == 0 && code == DPO_OK) code = DPO_ENOCONV;
+    if (stats) {
+      stats[p].sweeps = state[2 * n + p];
+      stats[p].resid_max_rel = res[kPartial * p + 0];
+      stats[p].resid_sum_abs = res[kPartial * p + 1];
+      stats[p].resid_max_abs = res[kPartial * p + 2];
+      stats[p].converged = state[p] == 1;
+      stats[p].status = state[p];
+    }
+  }
+  BHIP_TRY(b, hipStreamSynchronize(b->stream));
+  if (seconds) *seconds = now_s() - t0;
+  if (code == DPO_ENUMERIC) bfail(b, code, "batch: non-finite values");
+  else if (code == DPO_ENOCONV) bfail(b, code, "batch: max_sweeps reached");
+  return code;
+}
+
+int dpo_batch_time_config(dpo_batch* b, int32_t block, int32_t sweeps_per_graph, int32_t replays,
+                          double* seconds_per_sweep) {
+  if (!b) return bfail(nullptr, DPO_EINVAL, "batch is NULL");
+  if (!seconds_per_sweep || replays < 1) return bfail(b, DPO_EINVAL, "bad arguments");
+  int rc = check_batch_cfg(b, block, sweeps_per_graph);
+  if (rc != DPO_OK) return rc;
+  const int n = b->n;
+  std::vector<float*> A(n, nullptr);
+  auto free_all = [&]() {
+    for (float* v : A)
+      if (v) hipFree(v);
+  };
+  for (int p = 0; p < n; p++) {
+    if (hipMalloc(&A[p], sizeof(float) * (size_t)b->ctx[p]->N) != hipSuccess) {
+      free_all();
+      return bfail(b, DPO_ENOMEM, "autotune buffer alloc");
+    }
+    hipError_t e = launch_init_value(b->ctx[p]->kind, b->ctx[p]->P.M, A[p], (int)b->ctx[p]->N, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->Vb[p], A[p], sizeof(float) * (size_t)b->ctx[p]->N, hipMemcpyDeviceToDevice, b->stream);
+    if (e != hipSuccess) {
+      free_all();
+      return bfail(b, DPO_EHIP, "autotune init");
+    }
+  }
+  int n_tiles = 0;
+  rc = batch_tables(b, block, A.data(), nullptr, nullptr, &n_tiles);
+  hipGraphExec_t exec = nullptr;
+  if (rc == DPO_OK && hipMemsetAsync(b->d_state, 0, sizeof(int) * 3 * n, b->stream) != hipSuccess) rc = DPO_EHIP;
+  if (rc == DPO_OK) rc = batch_graph(b, batch_args(b, -1.0), block, n_tiles, sweeps_per_graph, &exec);
+  if (rc != DPO_OK) {
+    free_all();
+    return rc;
+  }
+  // replays as the solver issues them: graph, read-back of the stop flags, sync
+  std::vector<int> flags(n, 0);
+  hipError_t e = hipGraphLaunch(exec, b->stream);  // warm-up
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  const double t0 = now_s();
+  for (int r = 0; r < replays && e == hipSuccess; r++) {
+    e = hipGraphLaunch(exec, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(flags.data(), b->d_state, sizeof(int) * n, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  }
+  const double elapsed = now_s() - t0;
+  hipGraphExecDestroy(exec);
+  hipStreamSynchronize(b->stream);
+  free_all();
+  if (e != hipSuccess) return bfail(b, DPO_EHIP, std::string("autotune timing: ") + hipGetErrorString(e));
+  *seconds_per_sweep = elapsed / ((double)replays * sweeps_per_graph);
+  return DPO_OK;
+}
+
+int dpo_batch_solve_sequential(dpo_batch* b, float* const* V, float* const* pol_angle, uint8_t* const* pol_thr,
+                               double tol_rel, int64_t max_sweeps, int32_t check_every, dpo_batch_stats* stats,
+                               double* seconds, void* stream) {
+  if (!b) return bfail(nullptr, DPO_EINVAL, "batch is NULL");
+  if (!V || !pol_angle || !pol_thr) return bfail(b, DPO_EINVAL, "null array");
+  const double t0 = now_s();
+  int code = DPO_OK;
+  for (int p = 0; p < b->n; p++) {
+    dpo_stats st;
+    int rc = dpo_solve_vi(b->ctx[p], V[p], pol_angle[p], pol_thr[p], tol_rel, max_sweeps, check_every, &st, stream);
+    if (rc < 0) return bfail(b, rc, b->ctx[p]->err);
+    if (rc == DPO_ENOCONV && code == DPO_OK) code = DPO_ENOCONV;
+    if (stats) {
+      stats[p].sweeps = st.sweeps;
+      stats[p].resid_max_rel = st.resid_max_rel;
+      stats[p].resid_sum_abs = st.resid_sum_abs;
+      stats[p].resid_max_abs = st.resid_max_abs;
+      stats[p].converged = st.converged;
+      stats[p].status = st.converged ? 1 : 0;
+    }
+  }
+  if (seconds) *seconds = now_s() - t0;
+  return code;
 }
 
 }  // extern "C"

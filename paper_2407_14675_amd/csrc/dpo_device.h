@@ -13,7 +13,8 @@
 
 namespace dpo {
 
-constexpr int kBlock = 256;  // threads per workgroup of the node kernels (4 waves)
+constexpr int kBlock = 256;     // threads per workgroup of the node kernels (4 waves)
+constexpr int kMaxBlock = 512;  // largest workgroup of the factorised sweeps
 
 struct Grid {
   int n[4];
@@ -58,6 +59,7 @@ __device__ inline void decode_node(const Grid& G, int j, int i[4]) {
 // -v_r v_t / r, 0) + thr*(0, (a/m) sin u, (a/m) cos u, -c).
 __device__ inline void state_terms(const Grid& G, const Phys& P, const double x[4], double tau,
                                    float drift[4], float& g1, float& g2, float& gm) {
+#pragma clang fp contract(off)
   if (P.model == 0) {
     const double r = x[0], vr = x[1], vt = x[2], m = x[3];
     const double inv_r = 1.0 / r;
@@ -90,6 +92,7 @@ __device__ inline int unpack_node(const Grid& G, uint32_t p, int i[4]) {
 }
 
 __device__ inline void node_terms(const Grid& G, const Phys& P, int j, double tau, NodeTerms& T) {
+#pragma clang fp contract(off)
   decode_node(G, j, T.i);
   double x[4];
 #pragma unroll
@@ -210,10 +213,11 @@ __device__ inline int xcd_tile(int b, int nb) {
 constexpr int kPartial = 5;
 
 // Wave64 + workgroup reduction of one node kernel's residual partials,
-// written to partial[block*kPartial + 0..4] in a fixed order.
+// written to partial[block*kPartial + 0..4] in a fixed order (any workgroup
+// size that is a multiple of 64, up to kMaxBlock).
 __device__ inline void block_residual(double rel, double sum, double mabs, double bad,
                                       double fb, double* __restrict__ partial, int block) {
-  __shared__ double red[kPartial][kBlock / 64];
+  __shared__ double red[kPartial][kMaxBlock / 64];
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
     rel = fmax(rel, __shfl_xor(rel, o, 64));
@@ -233,7 +237,8 @@ __device__ inline void block_residual(double rel, double sum, double mabs, doubl
   __syncthreads();
   if (threadIdx.x == 0) {
     double a = red[0][0], b = red[1][0], c = red[2][0], d = red[3][0], e = red[4][0];
-    for (int w = 1; w < kBlock / 64; w++) {
+    const int nw = (int)(blockDim.x >> 6);
+    for (int w = 1; w < nw; w++) {
       a = fmax(a, red[0][w]);
       b += red[1][w];
       c = fmax(c, red[2][w]);

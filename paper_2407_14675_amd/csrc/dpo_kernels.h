@@ -56,6 +56,27 @@ struct SweepArgs {
 
 inline int blocks_for(long long n, int per = kBlock) { return (int)((n + per - 1) / per); }
 
+// Per-problem record of the batched sweep (device table).
+struct BatchProblem {
+  SweepArgs a;     // V_in = buffer A, V_out = buffer B for parity 0
+  int tile_begin;  // first tile (workgroup) of this problem
+};
+
+struct BatchArgs {
+  const BatchProblem* probs;
+  const int* tile_begin;  // n_prob + 1 entries
+  int n_prob;
+  int* done;      // 0 running, 1 converged, 2 non-finite values
+  int* done_buf;  // buffer holding the last iterate once done (0 = A, 1 = B)
+  int* sweeps;    // sweeps done per problem
+  double* partial;
+  double* resid;  // kPartial per problem
+  double tol;
+};
+
+hipError_t launch_batch_sweep(const BatchArgs& b, int mode, int block, int n_tiles, int parity, hipStream_t s);
+hipError_t launch_batch_reduce(const BatchArgs& b, int parity, hipStream_t s);
+
 // Launch wrappers (asynchronous on `stream`); each returns the launch status.
 hipError_t launch_classify(const Grid& G, const TargetBox& tb, const uint8_t* mask, uint8_t* kind, int N,
                            hipStream_t s);
@@ -68,7 +89,7 @@ hipError_t launch_sweep_scan_golden(const SweepArgs& a, hipStream_t s);
 hipError_t launch_sweep_seeded(const SweepArgs& a, hipStream_t s);
 hipError_t launch_policy_eval(const SweepArgs& a, bool want_resid, hipStream_t s);
 hipError_t launch_policy_eval_desc(const SweepArgs& a, hipStream_t s);
-hipError_t launch_sweep_fast(const SweepArgs& a, int mode, hipStream_t s);
+hipError_t launch_sweep_fast(const SweepArgs& a, int mode, int block, hipStream_t s);
 hipError_t launch_resid_final(const double* partial, int nblocks, double* out, hipStream_t s);
 hipError_t launch_value_at(const float* V, const Grid& G, double M, const double x[4], double* out,
                            hipStream_t s);

@@ -1,0 +1,406 @@
+// Device-side search machinery shared by the single-problem and the batched
+// sweep kernels: node terms from the per-axis tables, the tabulated scan,
+// the golden section, the seeded local search, the foot descriptors of the
+// chosen control, and the factorised thrust evaluation.
+//
+// Paper: arXiv 2407.14675, Section 3 (eq:schema; minimisation by tabulation
+// and golden-section refinement).
+#pragma once
+
+#include "dpo_kernels.h"
+
+namespace dpo {
+
+// Node terms from the packed coordinates of a free node and the per-axis
+// tables: FP64 for the control-independent drift, float for the rest.
+// Node coordinates are formed as lo + i*h with the product rounded before the
+// sum (no fused multiply-add), the plain definition of the grid: a node whose
+// coordinate is exactly zero (the middle v_r node of an odd grid) then gets
+// exactly zero, and its feet on a face stay on the face.
+//
+// The r displacement dt*v_r/h_r (cells) of nodes in v_r row i1.
+__device__ inline float drift_r(const SweepArgs& a, int i1) {
+#pragma clang fp contract(off)
+  if (a.P.model != 0) return 0.0f;
+  const double vr = a.G.lo[1] + (double)i1 * a.G.h[1];
+  return (float)(a.c0 * vr);
+}
+
+__device__ inline int node_terms_tab(const SweepArgs& a, uint32_t packed, NodeTerms& T) {
+#pragma clang fp contract(off)
+  const int j = unpack_node(a.G, packed, T.i);
+  if (a.P.model == 0) {
+    const double ri = a.rinv[T.i[0]];
+    const double vr = a.G.lo[1] + (double)T.i[1] * a.G.h[1];
+    const double vt = a.G.lo[2] + (double)T.i[2] * a.G.h[2];
+    T.drift[0] = drift_r(a, T.i[1]);
+    T.drift[1] = (float)(a.c1 * (vt * vt * ri - a.P.mu * ri * ri));
+    T.drift[2] = (float)(-a.c2 * vr * vt * ri);
+  } else {
+    T.drift[0] = T.drift[1] = T.drift[2] = 0.0f;
+  }
+  T.drift[3] = 0.0f;
+  T.g1 = a.g1tab[T.i[3]];
+  T.g2 = a.g2tab[T.i[3]];
+  T.gm = a.gm;
+  return j;
+}
+
+// Golden-section refinement around the centre angle u0 (sin/cos s0, c0) on
+// [u0 - half, u0 + half]: two interior points u0 -+ half*rho^3, then one new
+// point per step; the best evaluated point is kept (strict <, evaluation
+// order).  The new point of step k is the previous point on the kept side
+// moved by L0*rho^(k+4) (L0 = 2*half), because 2*rho - 1 = rho^3 and
+// rho^2 - rho^3 = rho^4; its sin/cos are formed by rotating the previous
+// point's sin/cos with the per-step constants rot = (sin, cos) of
+// half*rho^3, then of L0*rho^(k+4) for k = 0, 1, ...  qf(sin, cos) returns
+// the thrust Q at that angle.  Offsets from u0 are tracked in float for the
+// stored angle.
+struct GoldenState {
+  float best_q, best_d;  // best Q and its offset from u0
+  float best_s, best_c;  // its sin/cos as evaluated
+};
+
+template <class QF>
+__device__ inline void golden(const QF& qf, float s0, float c0, float half, int steps, const float* __restrict__ rot,
+                              GoldenState& g) {
+  const float rho = 0.6180339887498949f;
+  float lo = -half, hi = half;
+  float x1 = hi - rho * (hi - lo), x2 = lo + rho * (hi - lo);
+  const float sp = rot[0], cp = rot[1];
+  float s1 = fmaf(s0, cp, -c0 * sp), c1 = fmaf(c0, cp, s0 * sp);  // u0 - half*rho^3
+  float s2 = fmaf(s0, cp, c0 * sp), c2 = fmaf(c0, cp, -s0 * sp);  // u0 + half*rho^3
+  float f1 = qf(s1, c1);
+  if (f1 < g.best_q) {
+    g.best_q = f1;
+    g.best_d = x1;
+    g.best_s = s1;
+    g.best_c = c1;
+  }
+  float f2 = qf(s2, c2);
+  if (f2 < g.best_q) {
+    g.best_q = f2;
+    g.best_d = x2;
+    g.best_s = s2;
+    g.best_c = c2;
+  }
+  for (int it = 0; it < steps; it++) {
+    const float sd = rot[2 + 2 * it], cd = rot[3 + 2 * it];
+    const bool left = f1 < f2;  // keep [lo, x2]; new point left of x1
+    float xn, sn, cn;
+    if (left) {
+      hi = x2;
+      x2 = x1;
+      f2 = f1;
+      xn = hi - rho * (hi - lo);
+      sn = fmaf(s1, cd, -c1 * sd);
+      cn = fmaf(c1, cd, s1 * sd);
+      s2 = s1;
+      c2 = c1;
+    } else {
+      lo = x1;
+      x1 = x2;
+      f1 = f2;
+      xn = lo + rho * (hi - lo);
+      sn = fmaf(s2, cd, c2 * sd);
+      cn = fmaf(c2, cd, -s2 * sd);
+      s1 = s2;
+      c1 = c2;
+    }
+    const float fn = qf(sn, cn);
+    if (left) {
+      x1 = xn;
+      s1 = sn;
+      c1 = cn;
+      f1 = fn;
+    } else {
+      x2 = xn;
+      s2 = sn;
+      c2 = cn;
+      f2 = fn;
+    }
+    if (fn < g.best_q) {
+      g.best_q = fn;
+      g.best_d = xn;
+      g.best_s = sn;
+      g.best_c = cn;
+    }
+  }
+}
+
+// Exhaustive pass over the n_ang tabulated angles: first strict minimum.
+template <class QF>
+__device__ inline void scan_table(const QF& qf, const SweepArgs& a, float& bq, int& bk) {
+  bq = INFINITY;
+  bk = 0;
+  for (int k = 0; k < a.n_ang; k++) {
+    const float q = qf(a.tab_sin[k], a.tab_cos[k]);
+    if (q < bq) {
+      bq = q;
+      bk = k;
+    }
+  }
+}
+
+// The outcome of the search at one node.
+struct Choice {
+  float v;       // min Q
+  float ang;     // best thrust angle in [-pi, pi)
+  float sn, cs;  // sin/cos of the best thrust angle as evaluated
+  int thr;       // 1 = thrust
+};
+
+// Full search: scan, golden section around the best sample (if n_golden > 0),
+// then thrust iff strictly below the coast value qc.
+template <class QF>
+__device__ inline void full_search(const QF& qf, const SweepArgs& a, float qc, Choice& ch) {
+  float bq;
+  int bk;
+  scan_table(qf, a, bq, bk);
+  GoldenState g{bq, 0.0f, a.tab_sin[bk], a.tab_cos[bk]};
+  if (a.n_golden > 0) golden(qf, a.tab_sin[bk], a.tab_cos[bk], a.half_width, a.n_golden, a.rot_scan, g);
+  ch.thr = g.best_q < qc ? 1 : 0;
+  ch.v = ch.thr ? g.best_q : qc;
+  ch.ang = wrap_pi(a.tab_ang[bk] + g.best_d);
+  ch.sn = g.best_s;
+  ch.cs = g.best_c;
+}
+
+// Tabulated search: first strict minimum over the table, coast on ties.
+template <class QF>
+__device__ inline void table_search(const QF& qf, const SweepArgs& a, float qc, Choice& ch) {
+  float bq;
+  int bk;
+  scan_table(qf, a, bq, bk);
+  ch.thr = bq < qc ? 1 : 0;
+  ch.v = ch.thr ? bq : qc;
+  ch.ang = a.tab_ang[bk];
+  ch.sn = a.tab_sin[bk];
+  ch.cs = a.tab_cos[bk];
+}
+
+// Seeded local search: the seed angle, then a golden section with n_local - 3
+// steps on [seed - w, seed + w] (n_local thrust evaluations), then coast.  A
+// node whose result differs from its current value by more than
+// fallback_tol * max(1, |V|) repeats the full search.
+template <class QF>
+__device__ inline int seeded_search(const QF& qf, const SweepArgs& a, float seed, float qc, float vin, Choice& ch) {
+  float s0, c0;
+  sincosf(seed, &s0, &c0);
+  GoldenState g{qf(s0, c0), 0.0f, s0, c0};
+  golden(qf, s0, c0, a.local_half_width, a.n_local - 3, a.rot_local, g);
+  ch.thr = g.best_q < qc ? 1 : 0;
+  ch.v = ch.thr ? g.best_q : qc;
+  ch.ang = wrap_pi(seed + g.best_d);
+  ch.sn = g.best_s;
+  ch.cs = g.best_c;
+  if (fabsf(ch.v - vin) > a.fallback_tol * fmaxf(1.0f, fabsf(vin))) {
+    full_search(qf, a, qc, ch);
+    return 1;
+  }
+  return 0;
+}
+
+// Foot descriptor of the chosen control (see SweepArgs::desc_code).
+__device__ inline void write_desc(const SweepArgs& a, int t, const NodeTerms& T, const Choice& ch) {
+  float off[4];
+  off[0] = T.drift[0];
+  off[1] = ch.thr ? fmaf(T.g1, ch.sn, T.drift[1]) : T.drift[1];
+  off[2] = ch.thr ? fmaf(T.g2, ch.cs, T.drift[2]) : T.drift[2];
+  off[3] = T.drift[3] + (ch.thr ? T.gm : 0.0f);
+  int base[4];
+  float w[4];
+  const bool inside = foot_cell(a.G, T.i, off, base, w);
+  const unsigned flat = inside ? (unsigned)(base[0] + base[1] * a.G.st[1] + base[2] * a.G.st[2] + base[3] * a.G.st[3])
+                               : (1u << 30);
+  a.desc_code[t] = (int)(flat | ((unsigned)ch.thr << 31));
+  a.desc_w[t] = inside ? make_float2(w[1], w[2]) : make_float2(0.0f, 0.0f);
+}
+
+// ---- fast path for thrust controls.
+// Under thrust the r displacement (v_r * dt) and the m displacement (-c*dt)
+// do not depend on the angle, so every thrust foot of a node shares its r and
+// m cell and weights; only the v_r and v_t displacements move, by at most
+// |g| < 0.5 cell around the coast foot.  The node therefore collapses its
+// neighbourhood over r and m once (36 corner values, 27 lerps) into a 3 x 3
+// patch over (v_r, v_t), and every thrust evaluation is the bilinear
+// interpolant of the patch cell its foot falls in: the same Q1 value as the
+// 16-corner sum, with the lerps reordered.  Along each of v_r, v_t the feet
+// span at most two regions split at one threshold (a node or a domain face);
+// a region outside the domain has the constant value M.  The four region
+// pairs are stored per thread in LDS as Q = A + B dv + C dt + D dv dt in the
+// displacements dv = g1 sin u, dt = g2 cos u from the coast foot.
+struct Regions {
+  int b0;     // first cell (node index) of region 0; region 1 is cell b0 + 1
+  float bnd;  // region 1 <=> displacement offset >= bnd (node offsets)
+  bool ok0, ok1;
+};
+
+// Smallest float above x (x finite; 0 maps to the smallest normal float).
+__device__ inline float next_up(float x) {
+  if (x == 0.0f) return 1.17549435e-38f;
+  return __int_as_float(__float_as_int(x) + (x > 0.0f ? 1 : -1));
+}
+
+__device__ inline Regions axis_regions(int i, int n, float d, float g) {
+  Regions R;
+  const float ag = fabsf(g) + 1e-6f;  // margin over the rounding of d + g*s
+  const float lo = d - ag, hi = d + ag;
+  const float top = (float)(n - 1 - i), bot = (float)(-i);
+  if (hi < bot || lo > top) {  // every foot outside
+    R.b0 = 0;
+    R.bnd = INFINITY;
+    R.ok0 = R.ok1 = false;
+    return R;
+  }
+  const float k = floorf(hi);
+  const int kk = i + (int)k;
+  if (kk >= n - 1) {  // reaches the top face: last cell, then outside (the face itself is inside)
+    R.b0 = n - 2;
+    R.bnd = next_up(top);
+    R.ok0 = true;
+    R.ok1 = false;
+  } else if (k > lo) {  // crosses node kk (kk == 0: the bottom face)
+    R.b0 = kk - 1;
+    R.bnd = k;
+    R.ok0 = kk - 1 >= 0;
+    R.ok1 = true;
+  } else {  // one cell
+    R.b0 = kk;
+    R.bnd = INFINITY;
+    R.ok0 = true;
+    R.ok1 = false;
+  }
+  return R;
+}
+
+struct FastNode {
+  float g1, g2;  // thrust displacement per unit sin u (v_r) and cos u (v_t), cells
+  float d1, d2;  // coast displacements along v_r and v_t
+  float bv, bt;  // region 1 <=> offset >= threshold (the same float test as foot_cell)
+  const float4* coef;  // this thread's first region pair in LDS
+  int cs;              // LDS stride between region pairs (the workgroup size)
+};
+
+__device__ inline float fast_q(const FastNode& F, float sn, float cs) {
+  const float ov = fmaf(F.g1, sn, F.d1), ot = fmaf(F.g2, cs, F.d2);
+  const int idx = (ov >= F.bv ? 2 * F.cs : 0) + (ot >= F.bt ? F.cs : 0);
+  const float4 c = F.coef[idx];
+  const float dv = ov - F.d1, dt = ot - F.d2;
+  return fmaf(fmaf(c.w, dt, c.y), dv, fmaf(c.z, dt, c.x));
+}
+
+// Lerp along r of the corner pair (p[0], p[1]), fetched by one 8-byte load.
+__device__ inline float lerp_pair(const float* p, float t) {
+  const CornerPair v = *reinterpret_cast<const CornerPair*>(p);
+  return lerp(v.lo, v.hi, t);
+}
+
+// Per-node set-up of the thrust evaluations; returns the coast Q, which is
+// the same Q1 value read from the patch (plane i_m, coast cell).
+// lds: 4 * blockDim.x float4, laid out [region pair][thread].
+__device__ inline float fast_setup(const SweepArgs& a, const NodeTerms& T, float4* lds, FastNode& F) {
+  const Grid& G = a.G;
+  F.g1 = T.g1;
+  F.g2 = T.g2;
+  F.d1 = T.drift[1];
+  F.d2 = T.drift[2];
+  F.cs = blockDim.x;
+  F.coef = lds + threadIdx.x;
+  // r cell, shared by every control
+  int br = 0, bm = 0;
+  float tr = 0.0f, tm = 0.0f;
+  const bool ok_r = axis_cell(T.i[0], G.n[0], T.drift[0], br, tr);
+  // m cell under thrust; the coast foot stays on plane i_m
+  const bool ok_m = axis_cell(T.i[3], G.n[3], T.gm, bm, tm);
+  const int m_lo = ok_m ? bm : T.i[3];
+  const int m_hi = ok_m ? bm + 1 : T.i[3];
+  const int coast_plane = T.i[3];  // either m_lo or m_hi
+  const Regions Rv = axis_regions(T.i[1], G.n[1], T.drift[1], T.g1);
+  const Regions Rt = axis_regions(T.i[2], G.n[2], T.drift[2], T.g2);
+  F.bv = Rv.bnd;
+  F.bt = Rt.bnd;
+  const float qM = fmaf(a.P.gamma, a.P.M, a.P.q_thr);
+  float W[3][3], Wc[3][3];
+  if (ok_r) {
+    const float* __restrict__ base = a.V_in + br;
+    const int so = (m_hi - m_lo) * G.st[3];
+#pragma unroll
+    for (int p = 0; p < 3; p++) {
+      const int v = min(max(Rv.b0 + p, 0), G.n[1] - 1);
+#pragma unroll
+      for (int q = 0; q < 3; q++) {
+        const int w = min(max(Rt.b0 + q, 0), G.n[2] - 1);
+        const float* pp = base + v * G.st[1] + w * G.st[2] + m_lo * G.st[3];
+        const float lo = lerp_pair(pp, tr);
+        const float hi = lerp_pair(pp + so, tr);
+        W[p][q] = lerp(lo, hi, tm);
+        Wc[p][q] = coast_plane == m_lo ? lo : hi;
+      }
+    }
+  }
+  const float gam = a.P.gamma, q0 = a.P.q_thr;
+#pragma unroll
+  for (int av = 0; av < 2; av++) {
+#pragma unroll
+    for (int bt = 0; bt < 2; bt++) {
+      float4 c = make_float4(qM, 0.0f, 0.0f, 0.0f);
+      const bool valid = ok_r && ok_m && (av ? Rv.ok1 : Rv.ok0) && (bt ? Rt.ok1 : Rt.ok0);
+      if (valid) {
+        const float w00 = W[av][bt], w10 = W[av + 1][bt], w01 = W[av][bt + 1], w11 = W[av + 1][bt + 1];
+        // local coordinates of the coast foot in this cell
+        const float tv = T.drift[1] - (float)(Rv.b0 + av - T.i[1]);
+        const float tt = T.drift[2] - (float)(Rt.b0 + bt - T.i[2]);
+        const float cv = w10 - w00, ct = w01 - w00, dd = (w11 - w10) - (w01 - w00);
+        const float A = lerp(lerp(w00, w10, tv), lerp(w01, w11, tv), tt);
+        c.x = fmaf(gam, A, q0);
+        c.y = gam * fmaf(dd, tt, cv);
+        c.z = gam * fmaf(dd, tv, ct);
+        c.w = gam * dd;
+      }
+      lds[(av * 2 + bt) * blockDim.x + threadIdx.x] = c;
+    }
+  }
+  // coast: the cell of (d1, d2) on plane i_m, by the same region tests
+  const int av = T.drift[1] >= Rv.bnd ? 1 : 0;
+  const int bt = T.drift[2] >= Rt.bnd ? 1 : 0;
+  const bool cvalid = ok_r && (av ? Rv.ok1 : Rv.ok0) && (bt ? Rt.ok1 : Rt.ok0);
+  float Ic = a.P.M;
+  if (cvalid) {
+    const float tv = T.drift[1] - (float)(Rv.b0 + av - T.i[1]);
+    const float tt = T.drift[2] - (float)(Rt.b0 + bt - T.i[2]);
+    float w00, w10, w01, w11;
+    // select the coast cell of the 3 x 3 patch (av, bt in {0, 1})
+    w00 = av ? (bt ? Wc[1][1] : Wc[1][0]) : (bt ? Wc[0][1] : Wc[0][0]);
+    w10 = av ? (bt ? Wc[2][1] : Wc[2][0]) : (bt ? Wc[1][1] : Wc[1][0]);
+    w01 = av ? (bt ? Wc[1][2] : Wc[1][1]) : (bt ? Wc[0][2] : Wc[0][1]);
+    w11 = av ? (bt ? Wc[2][2] : Wc[2][1]) : (bt ? Wc[1][2] : Wc[1][1]);
+    Ic = lerp(lerp(w00, w10, tv), lerp(w01, w11, tv), tt);
+  }
+  return fmaf(a.P.gamma, Ic, a.P.q_coast);
+}
+
+
+// One free node of a sweep on the factorised path: search, outputs and the
+// residual contributions.  kMode: 0 tabulated, 1 scan + golden, 2 seeded.
+template <int kMode>
+__device__ inline void fast_node(const SweepArgs& a, int t, float4* lds, double& rel, double& sum, double& mabs,
+                                 double& bad, int& fell_back) {
+  NodeTerms T;
+  const int j = node_terms_tab(a, a.free_node[t], T);
+  FastNode F;
+  const float qc = fast_setup(a, T, lds, F);
+  auto qf = [&](float sn, float cs) { return fast_q(F, sn, cs); };
+  const float vin = a.V_in[j];
+  Choice ch;
+  if (kMode == 0) table_search(qf, a, qc, ch);
+  else if (kMode == 1) full_search(qf, a, qc, ch);
+  else fell_back = seeded_search(qf, a, a.seed[j], qc, vin, ch);
+  a.V_out[j] = ch.v;
+  if (a.pol_ang) a.pol_ang[j] = ch.ang;
+  if (a.pol_thr) a.pol_thr[j] = (uint8_t)ch.thr;
+  if (a.desc_code) write_desc(a, t, T, ch);
+  node_residual(vin, ch.v, rel, sum, mabs, bad);
+}
+
+}  // namespace dpo

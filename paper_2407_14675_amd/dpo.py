@@ -44,6 +44,14 @@ class Search(C.Structure):
                 ("fallback_tol", C.c_double)]
 
 
+class BatchStats(C.Structure):
+    _fields_ = [("sweeps", C.c_int64), ("resid_max_rel", C.c_double), ("resid_sum_abs", C.c_double),
+                ("resid_max_abs", C.c_double), ("converged", C.c_int32), ("status", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class Stats(C.Structure):
     _fields_ = [("sweeps", C.c_int64), ("eval_sweeps", C.c_int64), ("evals", C.c_int64),
                 ("fallback_nodes", C.c_int64), ("resid_max_rel", C.c_double),
@@ -88,6 +96,15 @@ def load():
         "dpo_probe_interp": [vp, vp, vp, i64, vp, vp],
         "dpo_probe_q": [vp, vp, vp, vp, vp, i64, vp, vp],
         "dpo_probe_foot": [vp, vp, vp, vp, i64, vp, vp],
+        "dpo_set_block": [vp, i32],
+        "dpo_batch_create": [i32, vp, vp, C.POINTER(Search), C.POINTER(vp)],
+        "dpo_batch_destroy": [vp],
+        "dpo_batch_last_error": [vp],
+        "dpo_batch_sizes": [vp, vp, vp],
+        "dpo_batch_init_value": [vp, vp, vp],
+        "dpo_batch_solve_vi": [vp, vp, vp, vp, dbl, i64, i32, i32, vp, vp, vp],
+        "dpo_batch_solve_sequential": [vp, vp, vp, vp, dbl, i64, i32, vp, vp, vp],
+        "dpo_batch_time_config": [vp, i32, i32, i32, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -95,6 +112,8 @@ def load():
         fn.restype = C.c_int
     lib.dpo_destroy.restype = None
     lib.dpo_last_error.restype = C.c_char_p
+    lib.dpo_batch_destroy.restype = None
+    lib.dpo_batch_last_error.restype = C.c_char_p
     _lib = lib
     return lib
 
@@ -199,6 +218,10 @@ class Context:
             raise DpoError(rc, self.lib.dpo_last_error(self.h).decode())
         return rc
 
+    def set_block(self, block):
+        """Workgroup size of the factorised sweeps (64..512, multiple of 64)."""
+        self._check(self.lib.dpo_set_block(self.h, int(block)))
+
     def set_search(self, search):
         self._s = search_struct(search)
         self._check(self.lib.dpo_set_search(self.h, C.byref(self._s)))
@@ -298,3 +321,87 @@ class Context:
         self._check(self.lib.dpo_probe_foot(self.h, _p(nodes), _p(thr), _p(angle), nodes.numel(), _p(off),
                                             _stream()))
         return off
+
+
+def _ptr_array(tensors):
+    arr = (C.c_void_p * len(tensors))()
+    for i, t in enumerate(tensors):
+        arr[i] = None if t is None else _p(t).value
+    return arr
+
+
+class Batch:
+    """Many problems (own grid and physics, shared search) solved together by
+    value iteration: one kernel launch per sweep for all running problems,
+    S sweeps per hipGraph replay."""
+
+    def __init__(self, problems, device="cuda"):
+        self.lib = load()
+        self.problems = list(problems)
+        self.device = torch.device(device)
+        n = len(self.problems)
+        grids = (Grid * n)(*[grid_struct(p) for p in self.problems])
+        probs = (Problem * n)(*[problem_struct(p) for p in self.problems])
+        self._s = search_struct(self.problems[0]["search"])
+        h = C.c_void_p()
+        torch.cuda.synchronize(self.device)
+        rc = self.lib.dpo_batch_create(n, grids, probs, C.byref(self._s), C.byref(h))
+        if rc != DPO_OK:
+            raise DpoError(rc, self.lib.dpo_batch_last_error(None).decode())
+        self.h = h
+        self.n = n
+        nn = (C.c_int64 * n)()
+        nf = (C.c_int64 * n)()
+        self.lib.dpo_batch_sizes(self.h, nn, nf)
+        self.n_nodes = list(nn)
+        self.n_free = list(nf)
+        self.shapes = [(p["n"][3], p["n"][2], p["n"][1], p["n"][0]) for p in self.problems]
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dpo_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow=(DPO_OK,)):
+        if rc not in allow:
+            raise DpoError(rc, self.lib.dpo_batch_last_error(self.h).decode())
+        return rc
+
+    def init_values(self):
+        Vs = [torch.empty(s, dtype=torch.float32, device=self.device) for s in self.shapes]
+        self._check(self.lib.dpo_batch_init_value(self.h, _ptr_array(Vs), _stream()))
+        return Vs
+
+    def empty_policies(self):
+        return ([torch.zeros(s, dtype=torch.float32, device=self.device) for s in self.shapes],
+                [torch.zeros(s, dtype=torch.uint8, device=self.device) for s in self.shapes])
+
+    def solve_vi(self, Vs, angs=None, thrs=None, tol_rel=1e-6, max_sweeps=100000, sweeps_per_graph=16, block=256):
+        st = (BatchStats * self.n)()
+        sec = C.c_double()
+        rc = self.lib.dpo_batch_solve_vi(self.h, _ptr_array(Vs), None if angs is None else _ptr_array(angs),
+                                         None if thrs is None else _ptr_array(thrs), float(tol_rel), int(max_sweeps),
+                                         int(sweeps_per_graph), int(block), st, C.byref(sec), _stream())
+        self._check(rc, allow=(DPO_OK, DPO_ENOCONV))
+        return rc, [s.as_dict() for s in st], sec.value
+
+    def solve_sequential(self, Vs, angs, thrs, tol_rel=1e-6, max_sweeps=100000, check_every=16):
+        st = (BatchStats * self.n)()
+        sec = C.c_double()
+        rc = self.lib.dpo_batch_solve_sequential(self.h, _ptr_array(Vs), _ptr_array(angs), _ptr_array(thrs),
+                                                 float(tol_rel), int(max_sweeps), int(check_every), st,
+                                                 C.byref(sec), _stream())
+        self._check(rc, allow=(DPO_OK, DPO_ENOCONV))
+        return rc, [s.as_dict() for s in st], sec.value
+
+    def time_config(self, block, sweeps_per_graph, replays=2):
+        out = C.c_double()
+        self._check(self.lib.dpo_batch_time_config(self.h, int(block), int(sweeps_per_graph), int(replays),
+                                                   C.byref(out)))
+        return out.value

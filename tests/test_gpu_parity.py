@@ -201,6 +201,30 @@ def test_probe_foot_matches_oracle(dpo):
         np.testing.assert_allclose(off[c], want, atol=2e-6, rtol=0)
 
 
+def test_feet_on_faces_match_oracle(dpo):
+    """Odd grids have a node with v_r exactly 0; there the v_t displacement of
+    the coast is exactly 0, so on the v_t faces the coast foot lies on the face
+    (inside).  Device and oracle must agree on every coast foot and Q."""
+    p = inputs.orbit_problem((7, 7, 7, 7), target_radius=1.068, accel=1.04e-3)
+    _say("feet on faces")
+    o = Oracle(p)
+    ctx = dpo.Context(p)
+    nodes = np.arange(o.N, dtype=np.int64)
+    thr = np.zeros(o.N, dtype=np.uint8)
+    off = host(ctx.probe_foot(nodes, thr, np.zeros(o.N, np.float32)))
+    n = np.array(p["n"])
+    i = np.stack([nodes % n[0], (nodes // n[0]) % n[1], (nodes // (n[0] * n[1])) % n[2],
+                  nodes // (n[0] * n[1] * n[2])], axis=1)
+    s = i + off
+    inside = np.all((s >= 0) & (s <= n - 1), axis=1)
+    V = inputs.random_value(p, seed=5, low=0, high=30)
+    q_or = o.q_many(V, nodes, thr, np.zeros(o.N))
+    inside_or = q_or < p["M"]  # outside gives dt + M
+    np.testing.assert_array_equal(inside, inside_or)
+    q = host(ctx.probe_q(dev(V), nodes, thr, np.zeros(o.N, np.float32)))
+    assert np.max(rel_err(q, q_or)) < 1e-5
+
+
 def test_probe_q_matches_oracle(dpo):
     p = inputs.CONFIG0
     _say("probe_q")
