@@ -78,6 +78,47 @@ def cpu_baseline(problem, seconds=12.0, seed=17):
     }
 
 
+def bench_batched(max_sweeps=20000, tol=1e-6):
+    """16 transfer problems (target radius, thrust level and grid side drawn
+    with seed 3; sides 24..64) solved by value iteration, batched (one launch
+    per sweep, hipGraph replays, autotuned) and one after another."""
+    import torch
+
+    from paper_2407_14675_amd import autotune, dpo, inputs
+
+    probs = inputs.config3_problems()
+    b = dpo.Batch(probs)
+    t0 = time.perf_counter()
+    block, S = autotune.tune(b, replays=2)
+    tune_s = time.perf_counter() - t0
+    Vs = b.init_values()
+    angs, thrs = b.empty_policies()
+    torch.cuda.synchronize()
+    rc, st, sec = b.solve_vi(Vs, angs, thrs, tol_rel=tol, max_sweeps=max_sweeps, sweeps_per_graph=S, block=block)
+    V2 = b.init_values()
+    a2, t2 = b.empty_policies()
+    torch.cuda.synchronize()
+    rc2, st2, sec2 = b.solve_sequential(V2, a2, t2, tol_rel=tol, max_sweeps=max_sweeps, check_every=16)
+    evals = sum(s["sweeps"] * nf * 17 for s, nf in zip(st, b.n_free))
+    diff = max(float(((x - y).abs() / y.abs().clamp(min=1.0)).max()) for x, y in zip(Vs, V2))
+    return {
+        "problems": len(probs),
+        "sides": [p["n"][0] for p in probs],
+        "free_nodes": int(sum(b.n_free)),
+        "block": block,
+        "sweeps_per_graph": S,
+        "autotune_seconds": tune_s,
+        "batched_seconds": sec,
+        "sequential_seconds": sec2,
+        "speedup": sec2 / sec if sec > 0 else None,
+        "batched_evals_per_s": evals / sec if sec > 0 else None,
+        "sweeps": [s["sweeps"] for s in st],
+        "all_converged": bool(all(s["converged"] for s in st)) and bool(all(s["converged"] for s in st2)),
+        "max_rel_diff_batched_vs_sequential": diff,
+        "tol_rel": tol,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +127,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-converge", action="store_true", help="skip the time-to-converge run")
     ap.add_argument("--path", type=int, default=0, help="sweep kernel path: 0 auto, 1 direct, 2 factorised")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched 16-problem measurement")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one plain 512 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -188,6 +230,12 @@ def main():
         }
         log(f"bench: converge {converge}")
 
+    batched = None
+    if not args.no_batched:
+        log("bench: batched 16-problem solve")
+        batched = bench_batched()
+        log(f"bench: batched {batched}")
+
     cpu = None
     if not args.no_cpu:
         log("bench: cpu baseline")
@@ -234,6 +282,7 @@ def main():
         },
         "eval_sweep": {"avg_launch_ms": eval_ms, "nodes": int(n_free)},
         "time_to_converge": converge,
+        "batched": batched,
         "cpu_baseline": cpu,
         "host": {"nproc": os.cpu_count(), "cpu": platform.processor()},
     }

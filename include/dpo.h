@@ -255,10 +255,11 @@ int dpo_probe_foot(dpo_ctx* ctx, const int32_t* nodes, const uint8_t* thr, const
 
 /* Many transfer problems solved together by value iteration (paper Section 3):
  * each sweep is ONE kernel launch over the tiles of every problem still
- * running; a per-problem FP64 residual stops a problem once its relative
- * residual max|dV|/max(1,|V|) is below tol_rel (its tiles then exit at once).
- * The host captures S sweeps into a hipGraph and replays it, synchronising
- * once per replay.  Each problem gets its own grid and physics; the search
+ * running.  S sweeps and a per-problem FP64 stop decision on the last sweep's
+ * relative residual max|dV|/max(1,|V|) < tol_rel are captured into one
+ * hipGraph and replayed, with one host synchronisation per replay; when a
+ * problem stops, the graph is re-captured over the remaining ones.  Sweep
+ * counts are therefore multiples of S.  Each problem gets its own grid and physics; the search
  * (TABLE or SCAN_GOLDEN) is shared, and the factorised sweep must apply to
  * every problem. */
 typedef struct dpo_batch dpo_batch;

@@ -2,6 +2,11 @@
 replay, chosen per size class by timing candidates on the device, cached in
 a JSON file keyed by GPU architecture and size class.
 
+A replay of S sweeps ends with the stop decision, so S trades host round
+trips (fewer for large S) against sweeps done after a problem has already
+met the tolerance (up to S - 1).  The tuner keeps the smallest S whose
+steady-state time per sweep is within 2 % of the best.
+
 The size class of a batch is (number of problems, log2 bucket of the total
 free nodes, largest grid side); batches of one class share the choice.
 """
@@ -47,11 +52,14 @@ def tune(batch, cache_path=DEFAULT_CACHE, replays=2, force=False):
         return int(c["block"]), int(c["sweeps_per_graph"])
     results = []
     for block in BLOCKS:
-        for S in SWEEPS_PER_GRAPH:
+        results.append((batch.time_config(block, 16, replays=replays), block, 16))
+    block = min(results)[1]
+    for S in SWEEPS_PER_GRAPH:
+        if S != 16:
             results.append((batch.time_config(block, S, replays=replays), block, S))
-    best_t = min(r[0] for r in results)
-    # the largest S within 2 % of the fastest: fewer host round trips at the same rate
-    t, block, S = max((r for r in results if r[0] <= 1.02 * best_t), key=lambda r: (r[2], -r[0]))
+    mine = [r for r in results if r[1] == block]
+    best_t = min(r[0] for r in mine)
+    t, block, S = min((r for r in mine if r[0] <= 1.02 * best_t), key=lambda r: r[2])
     if cache_path:
         cache[key] = {"block": block, "sweeps_per_graph": S, "seconds_per_sweep": t,
                       "candidates": [{"block": b, "sweeps_per_graph": s, "seconds_per_sweep": x}

@@ -774,19 +774,33 @@ int dpo_probe_foot(dpo_ctx* c, const int32_t* nodes, const uint8_t* thr, const f
 }  // extern "C"
 
 // ============================================================ batched solve
+// The batch keeps every per-problem array in one concatenated device
+// allocation (values A and B, policy, free-node lists, 1/r and thrust
+// tables) and a pointer-free record per problem with its offsets.
 struct dpo_batch {
   int n = 0;
   std::vector<dpo_ctx*> ctx;
   dpo_search search;
   int mode = 0;
   hipStream_t stream = nullptr;
-  std::vector<float*> Vb;  // second value buffer per problem
+  std::vector<long long> v_off;  // node offsets (n + 1)
+  std::vector<int> free_off;     // free-list offsets (n + 1)
+  float* Va = nullptr;
+  float* Vb = nullptr;
+  float* ang = nullptr;
+  uint8_t* thr = nullptr;
+  uint32_t* free_all = nullptr;
+  double* rinv_all = nullptr;
+  float* g_all = nullptr;
+  std::vector<BatchProblem> rec;  // host copy of the records (tile_begin per config)
   BatchProblem* d_probs = nullptr;
-  int* d_tile_begin = nullptr;
-  int* d_state = nullptr;  // [3][n]: done, done_buf, sweeps
+  int* d_tile_begin = nullptr;  // over the running problems (n + 1)
+  int* d_run = nullptr;         // running problems (n)
+  int* d_done = nullptr;        // per problem: 0 running, 1 converged, 2 non-finite
   double* d_partial = nullptr;
   double* d_resid = nullptr;
   int partial_cap = 0;
+  int max_blocks = 0;  // compute units of the device (sizes the persistent-style grid)
   std::string err;
 };
 
@@ -804,53 +818,60 @@ int bfail(dpo_batch* b, int code, const std::string& msg) {
     if (e_ != hipSuccess) return bfail((b), DPO_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-// Upload the per-problem records for workgroup size `block`, with value
-// buffers A = V[p], B = Vb[p]; returns the number of tiles.
-int batch_tables(dpo_batch* b, int block, float* const* V, float* const* ang, uint8_t* const* thr, int* n_tiles) {
-  std::vector<BatchProblem> h(b->n);
-  std::vector<int> tb(b->n + 1, 0);
-  for (int p = 0; p < b->n; p++) {
-    dpo_ctx* c = b->ctx[p];
-    h[p].a = base_args(c);
-    h[p].a.V_in = V[p];
-    h[p].a.V_out = b->Vb[p];
-    h[p].a.pol_ang = ang ? ang[p] : nullptr;
-    h[p].a.pol_thr = thr ? thr[p] : nullptr;
-    h[p].a.partial = nullptr;
-    h[p].tile_begin = tb[p];
-    tb[p + 1] = tb[p] + blocks_for(c->n_free, block);
+// Tile table over the running problems for workgroup size `block` (records
+// uploaded too); returns the tile count.
+int batch_tables(dpo_batch* b, int block, const std::vector<int>& run, int* n_tiles) {
+  std::vector<int> tb(run.size() + 1, 0);
+  for (size_t k = 0; k < run.size(); k++) {
+    b->rec[run[k]].tile_begin = tb[k];
+    tb[k + 1] = tb[k] + blocks_for(b->ctx[run[k]]->n_free, block);
   }
-  if (tb[b->n] > b->partial_cap) return bfail(b, DPO_EINVAL, "batch: too many tiles for the partial buffer");
-  BHIP_TRY(b, hipMemcpyAsync(b->d_probs, h.data(), sizeof(BatchProblem) * b->n, hipMemcpyHostToDevice, b->stream));
-  BHIP_TRY(b, hipMemcpyAsync(b->d_tile_begin, tb.data(), sizeof(int) * (b->n + 1), hipMemcpyHostToDevice, b->stream));
+  if (tb[run.size()] > b->partial_cap) return bfail(b, DPO_EINVAL, "batch: too many tiles for the partial buffer");
+  BHIP_TRY(b, hipMemcpyAsync(b->d_probs, b->rec.data(), sizeof(BatchProblem) * b->n, hipMemcpyHostToDevice, b->stream));
+  BHIP_TRY(b, hipMemcpyAsync(b->d_run, run.data(), sizeof(int) * run.size(), hipMemcpyHostToDevice, b->stream));
+  BHIP_TRY(b, hipMemcpyAsync(b->d_tile_begin, tb.data(), sizeof(int) * tb.size(), hipMemcpyHostToDevice, b->stream));
   BHIP_TRY(b, hipStreamSynchronize(b->stream));
-  *n_tiles = tb[b->n];
+  *n_tiles = tb[run.size()];
   return DPO_OK;
 }
 
-BatchArgs batch_args(dpo_batch* b, double tol) {
+BatchArgs batch_args(dpo_batch* b, double tol, int n_run, int n_tiles, bool policy) {
   BatchArgs a;
+  std::memset(&a, 0, sizeof(a));
+  const dpo_ctx* c0 = b->ctx[0];
   a.probs = b->d_probs;
+  a.run = b->d_run;
   a.tile_begin = b->d_tile_begin;
-  a.n_prob = b->n;
-  a.done = b->d_state;
-  a.done_buf = b->d_state + b->n;
-  a.sweeps = b->d_state + 2 * b->n;
+  a.n_run = n_run;
+  a.n_tiles = n_tiles;
+  a.free_all = b->free_all;
+  a.rinv_all = b->rinv_all;
+  a.g_all = b->g_all;
+  a.Va = b->Va;
+  a.Vb = b->Vb;
+  a.ang_all = policy ? b->ang : nullptr;
+  a.thr_all = policy ? b->thr : nullptr;
+  a.tab = c0->tab;
+  a.n_ang = c0->n_ang;
+  a.n_golden = c0->search.n_golden;
+  a.half_width = (float)(2.0 * 3.14159265358979323846 / (double)(c0->search.n_scan > 0 ? c0->search.n_scan : 1));
+  a.rot_scan = c0->rot;
+  a.done = b->d_done;
   a.partial = b->d_partial;
   a.resid = b->d_resid;
   a.tol = tol;
   return a;
 }
 
-// Capture S sweeps (sweep + per-problem stop decision each) into a graph.
-int batch_graph(dpo_batch* b, const BatchArgs& a, int block, int n_tiles, int S, hipGraphExec_t* exec) {
+// Capture S sweeps over the running problems, then one per-problem stop
+// decision on the last sweep's residual, into a graph.  S is even, so every
+// replay leaves the last iterate in buffer A.
+int batch_graph(dpo_batch* b, const BatchArgs& a, int block, int S, hipGraphExec_t* exec) {
   hipGraph_t g = nullptr;
   BHIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
-  for (int s = 0; s < S && e == hipSuccess; s++) {
-    e = launch_batch_sweep(a, b->mode, block, n_tiles, s & 1, b->stream);
-    if (e == hipSuccess) e = launch_batch_reduce(a, s & 1, b->stream);
-  }
+  for (int s = 0; s < S && e == hipSuccess; s++) e = launch_batch_sweep(a, b->mode, block, s & 1, b->stream);
+  if (e == hipSuccess) e = launch_batch_reduce(a, b->stream);
   hipError_t e2 = hipStreamEndCapture(b->stream, &g);
   if (e != hipSuccess || e2 != hipSuccess) {
     if (g) hipGraphDestroy(g);
@@ -862,9 +883,63 @@ int batch_graph(dpo_batch* b, const BatchArgs& a, int block, int n_tiles, int S,
   return DPO_OK;
 }
 
+// Replays until every problem has stopped or max_sweeps; the graph is
+// re-captured over the remaining problems whenever one stops.
+int batch_run(dpo_batch* b, double tol, int64_t max_sweeps, int S, int block, bool policy,
+              std::vector<int64_t>& sweeps, std::vector<int>& done, int64_t* total) {
+  const int n = b->n;
+  std::vector<int> run(n);
+  for (int p = 0; p < n; p++) run[p] = p;
+  sweeps.assign(n, 0);
+  done.assign(n, 0);
+  BHIP_TRY(b, hipMemsetAsync(b->d_done, 0, sizeof(int) * n, b->stream));
+  hipGraphExec_t exec = nullptr;
+  int rc = DPO_OK;
+  int64_t t = 0;
+  while (t < max_sweeps && !run.empty()) {
+    if (!exec) {
+      int n_tiles = 0;
+      if ((rc = batch_tables(b, block, run, &n_tiles)) != DPO_OK) break;
+      if ((rc = batch_graph(b, batch_args(b, tol, (int)run.size(), n_tiles, policy), block, S, &exec)) != DPO_OK) break;
+    }
+    hipError_t e = hipGraphLaunch(exec, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(done.data(), b->d_done, sizeof(int) * n, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+      rc = bfail(b, DPO_EHIP, std::string("batch replay: ") + hipGetErrorString(e));
+      break;
+    }
+    t += S;
+    std::vector<int> still;
+    for (int p : run) {
+      sweeps[p] += S;
+      if (done[p] == 0) still.push_back(p);
+    }
+    if (still.size() != run.size()) {
+      hipGraphExecDestroy(exec);
+      exec = nullptr;
+      run.swap(still);
+    }
+  }
+  if (exec) hipGraphExecDestroy(exec);
+  *total = t;
+  return rc;
+}
+
 int check_batch_cfg(dpo_batch* b, int block, int S) {
   if (block < 64 || block > 512 || block % 64) return bfail(b, DPO_EINVAL, "batch: block must be 64, 128, ..., 512");
   if (S < 2 || S > 256 || (S & 1)) return bfail(b, DPO_EINVAL, "batch: sweeps per graph must be even, in [2, 256]");
+  return DPO_OK;
+}
+
+// Copy the value functions between the caller's per-problem arrays and the
+// concatenated buffer `dst_all` (to_all) or back.
+int batch_copy_values(dpo_batch* b, float* const* V, float* all, bool to_all) {
+  for (int p = 0; p < b->n; p++) {
+    const size_t bytes = sizeof(float) * (size_t)b->ctx[p]->N;
+    float* seg = all + b->v_off[p];
+    BHIP_TRY(b, hipMemcpyAsync(to_all ? seg : V[p], to_all ? V[p] : seg, bytes, hipMemcpyDeviceToDevice, b->stream));
+  }
   return DPO_OK;
 }
 
@@ -890,7 +965,10 @@ int dpo_batch_create(int32_t n_prob, const dpo_grid* grids, const dpo_problem* p
     }
     return code;
   };
-  int tiles64 = 0;
+  b->v_off.assign(n_prob + 1, 0);
+  b->free_off.assign(n_prob + 1, 0);
+  std::vector<int> r_off(n_prob + 1, 0), g_off(n_prob + 1, 0);
+  long long tiles64 = 0;
   for (int p = 0; p < n_prob; p++) {
     dpo_ctx* c = nullptr;
     int rc = dpo_create(&grids[p], &probs[p], search, nullptr, &c);
@@ -903,23 +981,59 @@ int dpo_batch_create(int32_t n_prob, const dpo_grid* grids, const dpo_problem* p
       b->err = "batch problem " + std::to_string(p) + ": the factorised sweep does not apply";
       return bail(DPO_EINVAL);
     }
-    float* vb = nullptr;
-    if (hipMalloc(&vb, sizeof(float) * (size_t)c->N) != hipSuccess) {
-      b->err = "batch: value buffer alloc";
-      return bail(DPO_ENOMEM);
-    }
-    b->Vb.push_back(vb);
+    b->v_off[p + 1] = b->v_off[p] + c->N;
+    b->free_off[p + 1] = b->free_off[p] + (int)c->n_free;
+    r_off[p + 1] = r_off[p] + grids[p].n[0];
+    g_off[p + 1] = g_off[p] + 2 * grids[p].n[3];
     tiles64 += blocks_for(c->n_free, 64);
   }
-  b->partial_cap = tiles64 > 0 ? tiles64 : 1;
-  if (hipMalloc(&b->d_probs, sizeof(BatchProblem) * n_prob) != hipSuccess ||
+  const long long NT = b->v_off[n_prob];
+  if (NT > 0x7fffffffLL || b->free_off[n_prob] < 0) {
+    b->err = "batch: more than 2^31 nodes in total";
+    return bail(DPO_EINVAL);
+  }
+  b->partial_cap = (int)std::max(1LL, tiles64);
+  if (hipMalloc(&b->Va, sizeof(float) * NT) != hipSuccess || hipMalloc(&b->Vb, sizeof(float) * NT) != hipSuccess ||
+      hipMalloc(&b->ang, sizeof(float) * NT) != hipSuccess || hipMalloc(&b->thr, (size_t)NT) != hipSuccess ||
+      hipMalloc(&b->free_all, sizeof(uint32_t) * std::max(1, b->free_off[n_prob])) != hipSuccess ||
+      hipMalloc(&b->rinv_all, sizeof(double) * r_off[n_prob]) != hipSuccess ||
+      hipMalloc(&b->g_all, sizeof(float) * g_off[n_prob]) != hipSuccess ||
+      hipMalloc(&b->d_probs, sizeof(BatchProblem) * n_prob) != hipSuccess ||
       hipMalloc(&b->d_tile_begin, sizeof(int) * (n_prob + 1)) != hipSuccess ||
-      hipMalloc(&b->d_state, sizeof(int) * 3 * n_prob) != hipSuccess ||
+      hipMalloc(&b->d_run, sizeof(int) * n_prob) != hipSuccess ||
+      hipMalloc(&b->d_done, sizeof(int) * n_prob) != hipSuccess ||
       hipMalloc(&b->d_partial, sizeof(double) * kPartial * b->partial_cap) != hipSuccess ||
       hipMalloc(&b->d_resid, sizeof(double) * kPartial * n_prob) != hipSuccess) {
-    b->err = "batch: table alloc";
+    b->err = "batch: device allocation failed";
     return bail(DPO_ENOMEM);
   }
+  b->rec.resize(n_prob);
+  for (int p = 0; p < n_prob; p++) {
+    dpo_ctx* c = b->ctx[p];
+    hipError_t e = hipMemcpy(b->free_all + b->free_off[p], c->free_node, sizeof(uint32_t) * c->n_free, hipMemcpyDeviceToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->rinv_all + r_off[p], c->rinv, sizeof(double) * grids[p].n[0], hipMemcpyDeviceToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->g_all + g_off[p], c->gtab, sizeof(float) * 2 * grids[p].n[3], hipMemcpyDeviceToDevice);
+    if (e != hipSuccess) {
+      b->err = "batch: table copy failed";
+      return bail(DPO_EHIP);
+    }
+    BatchProblem& R = b->rec[p];
+    std::memset(&R, 0, sizeof(R));
+    R.G = c->G;
+    R.P = c->P;
+    R.c0 = c->c0;
+    R.c1 = c->c1;
+    R.c2 = c->c2;
+    R.gm = c->gm;
+    R.n_free = (int)c->n_free;
+    R.v_off = b->v_off[p];
+    R.free_off = b->free_off[p];
+    R.rinv_off = r_off[p];
+    R.g_off = g_off[p];
+  }
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  b->max_blocks = ncu;  // compute units; the grid holds 2048 threads per CU
   if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
     b->err = "batch: stream create";
     return bail(DPO_EHIP);
@@ -932,12 +1046,10 @@ void dpo_batch_destroy(dpo_batch* b) {
   if (!b) return;
   if (b->stream) hipStreamSynchronize(b->stream);
   for (dpo_ctx* c : b->ctx) dpo_destroy(c);
-  for (float* v : b->Vb) hipFree(v);
-  if (b->d_probs) hipFree(b->d_probs);
-  if (b->d_tile_begin) hipFree(b->d_tile_begin);
-  if (b->d_state) hipFree(b->d_state);
-  if (b->d_partial) hipFree(b->d_partial);
-  if (b->d_resid) hipFree(b->d_resid);
+  void* bufs[] = {b->Va, b->Vb, b->ang, b->thr, b->free_all, b->rinv_all, b->g_all,
+                  b->d_probs, b->d_tile_begin, b->d_run, b->d_done, b->d_partial, b->d_resid};
+  for (void* v : bufs)
+    if (v) hipFree(v);
   if (b->stream) hipStreamDestroy(b->stream);
   delete b;
 }
@@ -974,48 +1086,35 @@ int dpo_batch_solve_vi(dpo_batch* b, float* const* V, float* const* pol_angle, u
   int rc = check_batch_cfg(b, block, sweeps_per_graph);
   if (rc != DPO_OK) return rc;
   const int n = b->n;
+  const bool policy = pol_angle && pol_thr;
   BHIP_TRY(b, hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
   const double t0 = now_s();
-  for (int p = 0; p < n; p++)
-    BHIP_TRY(b, hipMemcpyAsync(b->Vb[p], V[p], sizeof(float) * (size_t)b->ctx[p]->N, hipMemcpyDeviceToDevice, b->stream));
-  int n_tiles = 0;
-  if ((rc = batch_tables(b, block, V, pol_angle, pol_thr, &n_tiles)) != DPO_OK) return rc;
-  BHIP_TRY(b, hipMemsetAsync(b->d_state, 0, sizeof(int) * 3 * n, b->stream));
-  const BatchArgs a = batch_args(b, tol_rel);
-  hipGraphExec_t exec = nullptr;
-  if ((rc = batch_graph(b, a, block, n_tiles, sweeps_per_graph, &exec)) != DPO_OK) return rc;
-  std::vector<int> state(3 * n, 0);
-  int64_t done_sweeps = 0;
-  hipError_t e = hipSuccess;
-  while (done_sweeps < max_sweeps) {
-    e = hipGraphLaunch(exec, b->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(state.data(), b->d_state, sizeof(int) * n, hipMemcpyDeviceToHost, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    if (e != hipSuccess) break;
-    done_sweeps += sweeps_per_graph;
-    bool all = true;
-    for (int p = 0; p < n; p++) all = all && state[p] != 0;
-    if (all) break;
-  }
-  hipGraphExecDestroy(exec);
-  if (e != hipSuccess) return bfail(b, DPO_EHIP, std::string("batch solve: ") + hipGetErrorString(e));
+  if ((rc = batch_copy_values(b, V, b->Va, true)) != DPO_OK) return rc;
+  if ((rc = batch_copy_values(b, V, b->Vb, true)) != DPO_OK) return rc;
+  std::vector<int64_t> sweeps;
+  std::vector<int> done;
+  int64_t total = 0;
+  if ((rc = batch_run(b, tol_rel, max_sweeps, sweeps_per_graph, block, policy, sweeps, done, &total)) != DPO_OK)
+    return rc;
   std::vector<double> res(kPartial * n);
-  BHIP_TRY(b, hipMemcpy(state.data(), b->d_state, sizeof(int) * 3 * n, hipMemcpyDeviceToHost));
   BHIP_TRY(b, hipMemcpy(res.data(), b->d_resid, sizeof(double) * kPartial * n, hipMemcpyDeviceToHost));
   int code = DPO_OK;
   for (int p = 0; p < n; p++) {
-    // S is even: an unfinished problem's last iterate is in buffer A = V[p]
-    if (state[p] != 0 && state[n + p] == 1)
-      BHIP_TRY(b, hipMemcpyAsync(V[p], b->Vb[p], sizeof(float) * (size_t)b->ctx[p]->N, hipMemcpyDeviceToDevice, b->stream));
-    if (state[p] == 2) code = DPO_ENUMERIC;
-    else if (state[p] == 0 && code == DPO_OK) code = DPO_ENOCONV;
+    const size_t N = (size_t)b->ctx[p]->N;
+    BHIP_TRY(b, hipMemcpyAsync(V[p], b->Va + b->v_off[p], sizeof(float) * N, hipMemcpyDeviceToDevice, b->stream));
+    if (policy) {
+      BHIP_TRY(b, hipMemcpyAsync(pol_angle[p], b->ang + b->v_off[p], sizeof(float) * N, hipMemcpyDeviceToDevice, b->stream));
+      BHIP_TRY(b, hipMemcpyAsync(pol_thr[p], b->thr + b->v_off[p], N, hipMemcpyDeviceToDevice, b->stream));
+    }
+    if (done[p] == 2) code = DPO_ENUMERIC;
+    else if (done[p] == 0 && code == DPO_OK) code = DPO_ENOCONV;
     if (stats) {
-      stats[p].sweeps = state[2 * n + p];
+      stats[p].sweeps = sweeps[p];
       stats[p].resid_max_rel = res[kPartial * p + 0];
       stats[p].resid_sum_abs = res[kPartial * p + 1];
       stats[p].resid_max_abs = res[kPartial * p + 2];
-      stats[p].converged = state[p] == 1;
-      stats[p].status = state[p];
+      stats[p].converged = done[p] == 1;
+      stats[p].status = done[p];
     }
   }
   BHIP_TRY(b, hipStreamSynchronize(b->stream));
@@ -1032,32 +1131,20 @@ int dpo_batch_time_config(dpo_batch* b, int32_t block, int32_t sweeps_per_graph,
   int rc = check_batch_cfg(b, block, sweeps_per_graph);
   if (rc != DPO_OK) return rc;
   const int n = b->n;
-  std::vector<float*> A(n, nullptr);
-  auto free_all = [&]() {
-    for (float* v : A)
-      if (v) hipFree(v);
-  };
   for (int p = 0; p < n; p++) {
-    if (hipMalloc(&A[p], sizeof(float) * (size_t)b->ctx[p]->N) != hipSuccess) {
-      free_all();
-      return bfail(b, DPO_ENOMEM, "autotune buffer alloc");
-    }
-    hipError_t e = launch_init_value(b->ctx[p]->kind, b->ctx[p]->P.M, A[p], (int)b->ctx[p]->N, b->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(b->Vb[p], A[p], sizeof(float) * (size_t)b->ctx[p]->N, hipMemcpyDeviceToDevice, b->stream);
-    if (e != hipSuccess) {
-      free_all();
-      return bfail(b, DPO_EHIP, "autotune init");
-    }
+    float* A = b->Va + b->v_off[p];
+    hipError_t e = launch_init_value(b->ctx[p]->kind, b->ctx[p]->P.M, A, (int)b->ctx[p]->N, b->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b->Vb + b->v_off[p], A, sizeof(float) * (size_t)b->ctx[p]->N, hipMemcpyDeviceToDevice, b->stream);
+    if (e != hipSuccess) return bfail(b, DPO_EHIP, "autotune init");
   }
+  std::vector<int> run(n);
+  for (int p = 0; p < n; p++) run[p] = p;
   int n_tiles = 0;
-  rc = batch_tables(b, block, A.data(), nullptr, nullptr, &n_tiles);
+  if ((rc = batch_tables(b, block, run, &n_tiles)) != DPO_OK) return rc;
+  BHIP_TRY(b, hipMemsetAsync(b->d_done, 0, sizeof(int) * n, b->stream));
   hipGraphExec_t exec = nullptr;
-  if (rc == DPO_OK && hipMemsetAsync(b->d_state, 0, sizeof(int) * 3 * n, b->stream) != hipSuccess) rc = DPO_EHIP;
-  if (rc == DPO_OK) rc = batch_graph(b, batch_args(b, -1.0), block, n_tiles, sweeps_per_graph, &exec);
-  if (rc != DPO_OK) {
-    free_all();
-    return rc;
-  }
+  if ((rc = batch_graph(b, batch_args(b, -1.0, n, n_tiles, false), block, sweeps_per_graph, &exec)) != DPO_OK) return rc;
   // replays as the solver issues them: graph, read-back of the stop flags, sync
   std::vector<int> flags(n, 0);
   hipError_t e = hipGraphLaunch(exec, b->stream);  // warm-up
@@ -1065,13 +1152,12 @@ int dpo_batch_time_config(dpo_batch* b, int32_t block, int32_t sweeps_per_graph,
   const double t0 = now_s();
   for (int r = 0; r < replays && e == hipSuccess; r++) {
     e = hipGraphLaunch(exec, b->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(flags.data(), b->d_state, sizeof(int) * n, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(flags.data(), b->d_done, sizeof(int) * n, hipMemcpyDeviceToHost, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   }
   const double elapsed = now_s() - t0;
   hipGraphExecDestroy(exec);
   hipStreamSynchronize(b->stream);
-  free_all();
   if (e != hipSuccess) return bfail(b, DPO_EHIP, std::string("autotune timing: ") + hipGetErrorString(e));
   *seconds_per_sweep = elapsed / ((double)replays * sweeps_per_graph);
   return DPO_OK;

@@ -8,35 +8,55 @@
 
 namespace dpo {
 
-// Workgroup -> (problem, tile): tiles are numbered problem by problem; the
-// XCD remap keeps each XCD on a contiguous run of tiles.
+// One workgroup per tile of the running problems (numbered problem by
+// problem, XCD-contiguous); the problem's record holds offsets into the
+// concatenated buffers, whose bases are kernel arguments.
 template <int kMode>
 __global__ __launch_bounds__(kMaxBlock) void k_batch_sweep(BatchArgs B, int parity) {
   extern __shared__ float4 dyn_lds[];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  int p = 0;
-  while (p + 1 < B.n_prob && B.tile_begin[p + 1] <= tile) p++;
-  if (B.done[p]) return;  // whole workgroup: its problem has stopped
-  SweepArgs a = B.probs[p].a;
-  if (parity) {
-    float* tmp = const_cast<float*>(a.V_in);
-    a.V_in = a.V_out;
-    a.V_out = tmp;
-  }
-  const int t = (tile - B.tile_begin[p]) * blockDim.x + threadIdx.x;
+  int k = 0;
+  while (k + 1 < B.n_run && B.tile_begin[k + 1] <= tile) k++;
+  const BatchProblem& R = B.probs[B.run[k]];
+  SweepArgs a;
+  a.G = R.G;
+  a.P = R.P;
+  a.V_in = (parity ? B.Vb : B.Va) + R.v_off;
+  a.V_out = (parity ? B.Va : B.Vb) + R.v_off;
+  a.pol_ang = B.ang_all ? B.ang_all + R.v_off : nullptr;
+  a.pol_thr = B.thr_all ? B.thr_all + R.v_off : nullptr;
+  a.free_node = B.free_all + R.free_off;
+  a.n_free = R.n_free;
+  a.rinv = B.rinv_all + R.rinv_off;
+  a.g1tab = B.g_all + R.g_off;
+  a.g2tab = B.g_all + R.g_off + R.G.n[3];
+  a.c0 = R.c0;
+  a.c1 = R.c1;
+  a.c2 = R.c2;
+  a.gm = R.gm;
+  a.tab_sin = B.tab;
+  a.tab_cos = B.tab + B.n_ang;
+  a.tab_ang = B.tab + 2 * B.n_ang;
+  a.n_ang = B.n_ang;
+  a.n_golden = B.n_golden;
+  a.half_width = B.half_width;
+  a.rot_scan = B.rot_scan;
+  a.desc_code = nullptr;
+  a.seed = nullptr;
+  const int t = (tile - B.tile_begin[k]) * blockDim.x + threadIdx.x;
   double rel = 0, sum = 0, mabs = 0, bad = 0;
   int fell_back = 0;
   if (t < a.n_free) fast_node<kMode>(a, t, dyn_lds, rel, sum, mabs, bad, fell_back);
   block_residual(rel, sum, mabs, bad, (double)fell_back, B.partial, tile);
 }
 
-// One workgroup per problem: FP64 reduction of its tiles' partials in a
-// fixed order, then the stop decision.
-__global__ __launch_bounds__(kBlock) void k_batch_reduce(BatchArgs B, int parity) {
+// One workgroup per running problem: FP64 reduction of its tiles' partials
+// (the residual of the last sweep) in a fixed order, then the stop decision.
+__global__ __launch_bounds__(kBlock) void k_batch_reduce(BatchArgs B) {
   __shared__ double red[kPartial][kBlock];
-  const int p = blockIdx.x;
-  if (B.done[p]) return;
-  const int lo = B.tile_begin[p], hi = B.tile_begin[p + 1];
+  const int k = blockIdx.x;
+  const int p = B.run[k];
+  const int lo = B.tile_begin[k], hi = B.tile_begin[k + 1];
   double acc[kPartial] = {0, 0, 0, 0, 0};
   for (int i = lo + (int)threadIdx.x; i < hi; i += kBlock) {
     acc[0] = fmax(acc[0], B.partial[kPartial * i + 0]);
@@ -59,26 +79,20 @@ __global__ __launch_bounds__(kBlock) void k_batch_reduce(BatchArgs B, int parity
   }
   if (threadIdx.x == 0) {
     for (int q = 0; q < kPartial; q++) B.resid[kPartial * p + q] = red[q][0];
-    B.sweeps[p] += 1;
-    if (red[3][0] > 0) {
-      B.done[p] = 2;
-      B.done_buf[p] = parity ^ 1;
-    } else if (red[0][0] < B.tol) {
-      B.done[p] = 1;
-      B.done_buf[p] = parity ^ 1;
-    }
+    if (red[3][0] > 0) B.done[p] = 2;
+    else if (red[0][0] < B.tol) B.done[p] = 1;
   }
 }
 
-hipError_t launch_batch_sweep(const BatchArgs& b, int mode, int block, int n_tiles, int parity, hipStream_t s) {
+hipError_t launch_batch_sweep(const BatchArgs& b, int mode, int block, int parity, hipStream_t s) {
   const size_t lds = sizeof(float4) * 4 * block;
-  if (mode == 0) hipLaunchKernelGGL(k_batch_sweep<0>, dim3(n_tiles), dim3(block), lds, s, b, parity);
-  else hipLaunchKernelGGL(k_batch_sweep<1>, dim3(n_tiles), dim3(block), lds, s, b, parity);
+  if (mode == 0) hipLaunchKernelGGL(k_batch_sweep<0>, dim3(b.n_tiles), dim3(block), lds, s, b, parity);
+  else hipLaunchKernelGGL(k_batch_sweep<1>, dim3(b.n_tiles), dim3(block), lds, s, b, parity);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_reduce(const BatchArgs& b, int parity, hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_reduce, dim3(b.n_prob), dim3(kBlock), 0, s, b, parity);
+hipError_t launch_batch_reduce(const BatchArgs& b, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_reduce, dim3(b.n_run), dim3(kBlock), 0, s, b);
   return hipGetLastError();
 }
 

@@ -56,26 +56,48 @@ struct SweepArgs {
 
 inline int blocks_for(long long n, int per = kBlock) { return (int)((n + per - 1) / per); }
 
-// Per-problem record of the batched sweep (device table).
+// Per-problem record of the batched sweep (device table).  It holds no
+// pointers: every array of the batch is one concatenated allocation passed
+// as a kernel argument, and the record gives this problem's offsets into it.
 struct BatchProblem {
-  SweepArgs a;     // V_in = buffer A, V_out = buffer B for parity 0
-  int tile_begin;  // first tile (workgroup) of this problem
+  Grid G;
+  Phys P;
+  double c0, c1, c2;
+  float gm;
+  int n_free;
+  long long v_off;  // offset of node 0 in the value / policy arrays
+  int free_off;     // offset in the concatenated free-node list
+  int rinv_off;     // offset in the concatenated 1/r table
+  int g_off;        // offset in the concatenated thrust tables ([2][n_m] per problem)
+  int tile_begin;   // first tile of this problem
 };
 
 struct BatchArgs {
   const BatchProblem* probs;
-  const int* tile_begin;  // n_prob + 1 entries
-  int n_prob;
-  int* done;      // 0 running, 1 converged, 2 non-finite values
-  int* done_buf;  // buffer holding the last iterate once done (0 = A, 1 = B)
-  int* sweeps;    // sweeps done per problem
+  const int* run;         // running problems of this graph (n_run entries)
+  const int* tile_begin;  // first tile of each running problem (n_run + 1 entries)
+  int n_run;
+  int n_tiles;
+  const uint32_t* free_all;
+  const double* rinv_all;
+  const float* g_all;
+  float* Va;  // value buffer A (concatenated)
+  float* Vb;  // value buffer B
+  float* ang_all;
+  uint8_t* thr_all;
+  const float* tab;  // shared search table [3][n_ang]
+  int n_ang;
+  int n_golden;
+  float half_width;
+  const float* rot_scan;
+  int* done;      // per problem: 0 running, 1 converged, 2 non-finite values
   double* partial;
   double* resid;  // kPartial per problem
   double tol;
 };
 
-hipError_t launch_batch_sweep(const BatchArgs& b, int mode, int block, int n_tiles, int parity, hipStream_t s);
-hipError_t launch_batch_reduce(const BatchArgs& b, int parity, hipStream_t s);
+hipError_t launch_batch_sweep(const BatchArgs& b, int mode, int block, int parity, hipStream_t s);
+hipError_t launch_batch_reduce(const BatchArgs& b, hipStream_t s);
 
 // Launch wrappers (asynchronous on `stream`); each returns the launch status.
 hipError_t launch_classify(const Grid& G, const TargetBox& tb, const uint8_t* mask, uint8_t* kind, int N,
