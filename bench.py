@@ -13,7 +13,7 @@ angles + coast): a 48^4 node is active where the coarse value interpolated at
 the node is below 0.98*M, dilated by one cell per axis.
 
 Prints one JSON line with the node-control evaluations per second, the
-roofline of the dominant kernel (the greedy sweep), the time to a converged
+roofline of the dominant kernel (the evaluation sweep, HBM-bound), the time to a converged
 value function, and the CPU oracle timed on a bounded sample.
 """
 import argparse
@@ -32,13 +32,43 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TFLOPS = 78.6
 
-# Algorithmic FP32 work of one node-control evaluation (see the design doc,
-# "Roofline"): control part of the dynamics (2 FMA = 4 flops), per-axis
-# classification (floor, subtract, two compares: 4 x 4 = 16), 15 lerps
-# (subtract + FMA = 3 flops each: 45), Q (1 FMA = 2), min (1 compare) = 68.
-FLOPS_PER_EVAL = 68
-# Gather bytes of one evaluation: 16 float32 corners.
+# Algorithmic HBM bytes per active node of one frozen-policy evaluation sweep:
+# packed node coordinates (4), foot cell code (4), foot weights in v_r and v_t
+# (8), the node's share of the value array read once (4), value written (4).
+EVAL_BYTES_PER_NODE = 24
+# Greedy sweep: packed coordinates (4) + value read (4) + value, angle and
+# throttle written (4 + 4 + 1) + the foot descriptor written (12).
+GREEDY_BYTES_PER_NODE = 29
+# Gather bytes of one evaluation done naively: 16 float32 corners.
 GATHER_BYTES_PER_EVAL = 64
+
+# HBM traffic of the evaluation sweep measured with rocprofv3 counters, with
+# the hash of the kernel sources it was measured on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_policy_eval_desc_cfg1_48x4_traffic.json")
+KERNEL_SOURCES = ["dpo_kernels.hip", "dpo_device.h", "dpo_kernels.h", "dpo_search.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2407_14675_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """Bytes per launch from the committed counter summary, or None when the
+    kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except OSError:
+        return None
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def log(*a):
@@ -185,11 +215,13 @@ def main():
     value = evals / elapsed
     log(f"bench: {args.steps} steps in {elapsed:.4f}s, {value:.3e} evals/s")
 
-    # ---- dominant kernel: greedy sweep, average launch time by HIP events on
-    # the stream the library launches on (torch's current stream)
+    # ---- kernel timings by HIP events on the stream the library launches on
+    # (torch's current stream).  The evaluation sweep takes E of every E + 1
+    # sweeps of a step and dominates the step time; the greedy sweep is the
+    # arithmetic-bound one.
     stream = torch.cuda.current_stream()
     W = V.clone()
-    reps = 10
+    reps = 20
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ctx.bellman_sweep(V, W, ang, thr)
     ev0.record(stream)
@@ -200,8 +232,8 @@ def main():
     greedy_ms = ev0.elapsed_time(ev1) / reps
     evals_per_greedy = n_free * (1 + 64 + 2 + 12)
     greedy_evals_s = evals_per_greedy / (greedy_ms * 1e-3)
-    achieved_tflops = greedy_evals_s * FLOPS_PER_EVAL / 1e12
     # evaluation sweep of policy iteration (descriptors of the greedy sweep above)
+    ctx.policy_eval_sweep_last(V, W)
     ev0.record(stream)
     for _ in range(reps):
         ctx.policy_eval_sweep_last(V, W)
@@ -209,6 +241,11 @@ def main():
     torch.cuda.synchronize()
     eval_ms = ev0.elapsed_time(ev1) / reps
     log(f"bench: greedy sweep {greedy_ms:.4f} ms ({greedy_evals_s:.3e} evals/s), eval sweep {eval_ms:.4f} ms")
+    eval_bytes = EVAL_BYTES_PER_NODE * n_free
+    eval_gbs = eval_bytes / (eval_ms * 1e-3) / 1e9
+    traffic = measured_traffic()
+    step_bytes = (GREEDY_BYTES_PER_NODE + E * EVAL_BYTES_PER_NODE) * n_free
+    step_gbs = step_bytes / (elapsed / args.steps) / 1e9
 
     # ---- time to a converged value function from V0 (separate run)
     converge = None
@@ -264,23 +301,35 @@ def main():
             "eval_sweeps": E,
         },
         "roofline": {
-            "bound": "alu",
+            "bound": "hbm",
+            "kernel": "k_policy_eval_desc",
+            "achieved": eval_gbs,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": eval_gbs / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes": eval_bytes,
+            "bytes_per_node": EVAL_BYTES_PER_NODE,
+            "nodes_per_launch": int(n_free),
+            "avg_launch_ms": eval_ms,
+            "launches_per_step": E,
+        },
+        "greedy_sweep": {
             "kernel": "k_sweep_fast<1>" if ctx.kernel_path() == 2 else "k_sweep_direct<1>",
-            "achieved": achieved_tflops,
-            "peak": VALU_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved_tflops / VALU_PEAK_TFLOPS,
-            "traffic": None,
+            "bound": "alu",
             "avg_launch_ms": greedy_ms,
             "evals_per_launch": evals_per_greedy,
-            "flops_per_eval": FLOPS_PER_EVAL,
+            "evals_per_s": greedy_evals_s,
+            "hbm_bytes_per_node": GREEDY_BYTES_PER_NODE,
+            "hbm_frac": GREEDY_BYTES_PER_NODE * n_free / (greedy_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         },
         "gather_roofline": {
-            "evals_per_s": greedy_evals_s,
-            "hbm_gather_rate": HBM_PEAK_GBS * 1e9 / GATHER_BYTES_PER_EVAL,
-            "frac": greedy_evals_s / (HBM_PEAK_GBS * 1e9 / GATHER_BYTES_PER_EVAL),
+            "step_algorithmic_bytes": step_bytes,
+            "step_achieved_GBs": step_gbs,
+            "step_frac": step_gbs / HBM_PEAK_GBS,
+            "naive_gather_bytes_per_eval": GATHER_BYTES_PER_EVAL,
+            "naive_gather_frac": value * GATHER_BYTES_PER_EVAL / 1e9 / HBM_PEAK_GBS,
         },
-        "eval_sweep": {"avg_launch_ms": eval_ms, "nodes": int(n_free)},
         "time_to_converge": converge,
         "batched": batched,
         "cpu_baseline": cpu,
