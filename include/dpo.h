@@ -105,6 +105,7 @@ typedef struct {
   int64_t eval_sweeps;    /* frozen-policy sweeps */
   int64_t evals;          /* node-control Q evaluations */
   int64_t fallback_nodes; /* SEEDED: nodes that repeated the full search */
+  int64_t verify_steps;   /* seeded policy iteration: full-search greedy steps after the first */
   double resid_max_rel;   /* last max |dV|/max(1,|V|) over free nodes (FP64) */
   double resid_sum_abs;   /* last sum |dV| (FP64) */
   double resid_max_abs;   /* last max |dV| (FP64) */
@@ -207,7 +208,16 @@ int dpo_solve_vi(dpo_ctx* ctx, float* V, float* pol_angle, uint8_t* pol_thr, dou
  * frozen-policy sweeps): stops when the residual of the greedy step is below
  * tol_rel; V then holds T V and the policy its argmin.  seed_angle (device,
  * nullable) enables the SEEDED greedy step for every outer iteration after the
- * first.  Returns DPO_ENOCONV after max_outer greedy steps. */
+ * first, until a seeded step meets tol_rel or 8 seeded steps in a row bring
+ * no new lowest residual; from then on the greedy steps
+ * use the full search again (SCAN_GOLDEN parameters of the context's search)
+ * and the solve stops at the first full step that meets tol_rel, so the
+ * result is certified by the same rule as an unseeded solve.  seed_angle may
+ * be pol_angle itself (each node reads its seed before its angle is
+ * overwritten), which warm-starts every node from its previous optimum as in
+ * paper Section 3, "Efficient computation of the minimum".
+ * Returns DPO_ENOCONV after max_outer greedy steps, or when 32 full-search
+ * greedy steps in a row bring no new lowest residual (stats->stalled). */
 int dpo_solve_pi(dpo_ctx* ctx, float* V, float* pol_angle, uint8_t* pol_thr, double tol_rel,
                  int32_t eval_sweeps, int64_t max_outer, const float* seed_angle,
                  dpo_stats* stats, void* stream);
@@ -307,6 +317,77 @@ int dpo_batch_solve_sequential(dpo_batch* b, float* const* V, float* const* pol_
  * not touched). */
 int dpo_batch_time_config(dpo_batch* b, int32_t block, int32_t sweeps_per_graph, int32_t replays,
                           double* seconds_per_sweep);
+
+/* ------------------------------------------------- learned control proposal */
+
+/* A 4 -> 128 -> 128 -> 3 perceptron (exact erf GELU after each hidden layer)
+ * from a node's grid position, scaled to [-1, 1] per axis as
+ * 2*i_k/(n_k-1) - 1, to (cos u, sin u, throttle logit).  Its angle seeds the
+ * SEEDED search (the learned form of the warm-started minimisation of paper
+ * Section 3, "Efficient computation of the minimum"); the paper itself has no
+ * network, so every choice below is this library's.
+ *  Parameters: float32[DPO_MLP_PARAMS] in the order W1[128][4], b1[128],
+ *  W2[128][128], b2[128], W3[3][128], b3[3] (row = output unit).  The middle
+ *  layer runs on the matrix cores with bfloat16 operands (h1 and W2 forward;
+ *  delta2, h1 and W2 backward, rounded to nearest even) and float32
+ *  accumulation; everything else is float32.
+ *  Loss of a sample with target (c*, s*, t*), t* in {0, 1}:
+ *      t* ((c - c*)^2 + (s - s*)^2) + BCE(logit, t*),   mean over the batch.
+ *  Training: Adam (default lr 1e-3, betas 0.9 / 0.999, eps 1e-8), FP32
+ *  moments, bias-corrected with the network's own step count.
+ *  Samples x are float32[n][4] (16-byte aligned), targets float32[n][4]
+ *  (c*, s*, t*, unused). */
+#define DPO_MLP_PARAMS 17539
+typedef struct dpo_mlp dpo_mlp;
+
+/* Create with the given parameters (host, nullable = zeros); Adam state zero. */
+int dpo_mlp_create(const float* params, dpo_mlp** out);
+void dpo_mlp_destroy(dpo_mlp* m);
+const char* dpo_mlp_last_error(const dpo_mlp* m);
+/* Host copies in/out; set_params also clears the Adam state and step count.
+ * Both synchronise the device. */
+int dpo_mlp_set_params(dpo_mlp* m, const float* params);
+int dpo_mlp_get_params(dpo_mlp* m, float* params);
+/* Gradient of the last dpo_mlp_grad / dpo_mlp_train batch (host float[P]). */
+int dpo_mlp_get_grad(dpo_mlp* m, float* grad);
+int dpo_mlp_set_adam(dpo_mlp* m, double lr, double beta1, double beta2, double eps);
+/* Adam steps taken since the last set_params. */
+int64_t dpo_mlp_steps(const dpo_mlp* m);
+
+/* y (device float[n][3]) = network(x). */
+int dpo_mlp_forward(dpo_mlp* m, const float* x, int64_t n, float* y, void* stream);
+
+/* Gradient of the mean loss over the n samples (1 <= n <= 65536) into grad
+ * (device float[P], nullable) and the mean loss into *loss (device, nullable);
+ * parameters are not changed. */
+int dpo_mlp_grad(dpo_mlp* m, const float* x, const float* tgt, int64_t n, float* grad, float* loss,
+                 void* stream);
+
+/* One epoch: ceil(n/batch) Adam steps over the samples in the order perm
+ * (host int32[n] of indices in [0, n), checked; NULL = 0..n-1), batch b taking
+ * positions [b*batch, min(n, (b+1)*batch)).  loss_hist (device
+ * float[ceil(n/batch)], nullable) receives each batch's mean loss before its
+ * step.  1 <= batch <= 65536. */
+int dpo_mlp_train(dpo_mlp* m, const float* x, const float* tgt, int64_t n, const int32_t* perm, int32_t batch,
+                  float* loss_hist, void* stream);
+
+/* Seed angles atan2(s, c) of the network at every free node of ctx, written
+ * to seed_angle[j] (device float[N]; other entries untouched), for
+ * dpo_bellman_sweep_seeded and dpo_solve_pi. */
+int dpo_mlp_propose(dpo_mlp* m, const dpo_ctx* ctx, float* seed_angle, void* stream);
+
+/* Ordered list (node order) of the free nodes with V < thresh, as packed grid
+ * coordinates i0 | i1<<8 | i2<<16 | i3<<24 into nodes (device u32, capacity
+ * n_free); *n_out (host) = their count.  Synchronises stream. */
+int dpo_feasible_nodes(dpo_ctx* ctx, const float* V, double thresh, uint32_t* nodes, int64_t* n_out,
+                       void* stream);
+
+/* Training pairs from a policy: for t < n, node = nodes[sel[t]] (sel: host
+ * int32[n], checked against [0, n_nodes)); x[t] = the node's scaled position,
+ * tgt[t] = (cos, sin) of pol_angle at the node and its throttle (0/1).
+ * Synchronises stream. */
+int dpo_gather_pairs(dpo_ctx* ctx, const uint32_t* nodes, int64_t n_nodes, const int32_t* sel, int64_t n,
+                     const float* pol_angle, const uint8_t* pol_thr, float* x, float* tgt, void* stream);
 
 #ifdef __cplusplus
 }

@@ -11,7 +11,7 @@ from . import build as _build
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 MODELS = {"orbit": 0, "eikonal": 1}
-SEARCH_MODES = {"table": 0, "scan_golden": 1}
+SEARCH_MODES = {"table": 0, "scan_golden": 1, "seeded": 2}
 KIND_FREE, KIND_TARGET, KIND_INACTIVE = 0, 1, 2
 
 
@@ -37,7 +37,8 @@ class ProblemStruct(C.Structure):
 
 class SearchStruct(C.Structure):
     _fields_ = [("mode", C.c_int32), ("n_angles", C.c_int32), ("n_scan", C.c_int32),
-                ("n_golden", C.c_int32)]
+                ("n_golden", C.c_int32), ("n_local", C.c_int32), ("local_half_width", C.c_double),
+                ("fallback_tol", C.c_double)]
 
 
 def problem_struct(p):
@@ -59,6 +60,9 @@ def search_struct(sr):
     s.n_angles = int(sr.get("n_angles", 0))
     s.n_scan = int(sr.get("n_scan", 0))
     s.n_golden = int(sr.get("n_golden", 0))
+    s.n_local = int(sr.get("n_local", 0))
+    s.local_half_width = float(sr.get("local_half_width", 0.0))
+    s.fallback_tol = float(sr.get("fallback_tol", 0.0))
     return s
 
 
@@ -95,6 +99,7 @@ def load(precision="f64"):
     lib.or_residual.argtypes = [i64, vp, vp, vp, vp]
     lib.or_bellman_sweep.argtypes = [P, vp, S, vp, vp, vp, vp, vp]
     lib.or_bellman_nodes.argtypes = [P, vp, S, vp, vp, i64, vp, vp, vp, vp]
+    lib.or_bellman_sweep_seeded.argtypes = [P, vp, S, vp, vp, vp, vp, vp, vp, vp]
     lib.or_policy_eval_sweep.argtypes = [P, vp, vp, vp, vp, vp]
     lib.or_solve_vi.argtypes = [P, vp, S, vp, vp, vp, C.c_double, C.c_double, i64, vp]
     lib.or_solve_vi.restype = i64
@@ -197,6 +202,20 @@ class Oracle:
         self.lib.or_bellman_sweep(C.byref(self.ps), _ptr(self.kind), C.byref(ss), _ptr(Vin),
                                   _ptr(Vout), _ptr(ang), _ptr(thr), _ptr(margin))
         return Vout, ang, thr, margin
+
+    def bellman_sweep_seeded(self, V, seed, search=None):
+        """Seeded sweep; returns V, angle, throttle, margin and the fallback flags."""
+        Vin = self._arr(V)
+        sd = self._arr(seed)
+        ss = self.ss if search is None else search_struct(search)
+        Vout = np.empty_like(Vin)
+        ang = np.empty_like(Vin)
+        thr = np.empty(self.shape, dtype=np.uint8)
+        margin = np.empty_like(Vin)
+        fb = np.empty(self.shape, dtype=np.uint8)
+        self.lib.or_bellman_sweep_seeded(C.byref(self.ps), _ptr(self.kind), C.byref(ss), _ptr(Vin), _ptr(sd),
+                                         _ptr(Vout), _ptr(ang), _ptr(thr), _ptr(margin), _ptr(fb))
+        return Vout, ang, thr, margin, fb
 
     def bellman_nodes(self, V, nodes, search=None):
         Vin = self._arr(V)

@@ -65,8 +65,13 @@ typedef struct {
 
 typedef struct {
   int32_t mode; /* 0 = discrete table of n_angles thrust angles plus coast,
-                   1 = scan of n_scan angles, golden-section refinement */
+                   1 = scan of n_scan angles, golden-section refinement,
+                   2 = seeded: golden section around a given angle, with the
+                       mode-1 search as fallback */
   int32_t n_angles, n_scan, n_golden;
+  int32_t n_local;         /* mode 2: thrust evaluations of the local search */
+  double local_half_width; /* mode 2: half-width of its bracket (rad) */
+  double fallback_tol;     /* mode 2: relative change that triggers the fallback */
 } or_search;
 
 enum { KIND_FREE = 0, KIND_TARGET = 1, KIND_INACTIVE = 2 };
@@ -316,6 +321,32 @@ static choice search_table(const qfun *f, int K) {
   return c;
 }
 
+/* Golden-section search (ratio (sqrt 5 - 1)/2) on [center - half, center +
+ * half]: two interior evaluations, then one per iteration.  best_q and best_u
+ * hold the best point evaluated so far (strict <, in evaluation order). */
+static void golden_refine(const qfun *f, real center, real half, int iters, real *best_q, real *best_u) {
+  const real rho = (real)((sqrt(5.0) - 1.0) / 2.0);
+  real a = center - half, b = center + half;
+  real x1 = b - rho * (b - a), x2 = a + rho * (b - a);
+  real f1 = qeval(f, 1, x1);
+  if (f1 < *best_q) { *best_q = f1; *best_u = x1; }
+  real f2 = qeval(f, 1, x2);
+  if (f2 < *best_q) { *best_q = f2; *best_u = x2; }
+  for (int it = 0; it < iters; it++) {
+    if (f1 < f2) {
+      b = x2; x2 = x1; f2 = f1;
+      x1 = b - rho * (b - a);
+      f1 = qeval(f, 1, x1);
+      if (f1 < *best_q) { *best_q = f1; *best_u = x1; }
+    } else {
+      a = x1; x1 = x2; f1 = f2;
+      x2 = a + rho * (b - a);
+      f2 = qeval(f, 1, x2);
+      if (f2 < *best_q) { *best_q = f2; *best_u = x2; }
+    }
+  }
+}
+
 /* Scan of n_scan angles u_s = -pi + 2*pi*s/n_scan, then golden-section search
  * (ratio (sqrt 5 - 1)/2) on [u_s* - 2*pi/n_scan, u_s* + 2*pi/n_scan]: two
  * interior evaluations, then one per iteration.  The best evaluated point
@@ -343,29 +374,8 @@ static choice search_scan_golden(const qfun *f, int n_scan, int n_golden) {
   }
   free(qs);
 
-  if (n_golden > 0) {
-    const real rho = (real)((sqrt(5.0) - 1.0) / 2.0);
-    real half = (real)(2.0 * OR_PI / (double)n_scan);
-    real a = best_u - half, b = best_u + half;
-    real x1 = b - rho * (b - a), x2 = a + rho * (b - a);
-    real f1 = qeval(f, 1, x1);
-    if (f1 < best_q) { best_q = f1; best_u = x1; }
-    real f2 = qeval(f, 1, x2);
-    if (f2 < best_q) { best_q = f2; best_u = x2; }
-    for (int it = 0; it < n_golden; it++) {
-      if (f1 < f2) {
-        b = x2; x2 = x1; f2 = f1;
-        x1 = b - rho * (b - a);
-        f1 = qeval(f, 1, x1);
-        if (f1 < best_q) { best_q = f1; best_u = x1; }
-      } else {
-        a = x1; x1 = x2; f1 = f2;
-        x2 = a + rho * (b - a);
-        f2 = qeval(f, 1, x2);
-        if (f2 < best_q) { best_q = f2; best_u = x2; }
-      }
-    }
-  }
+  if (n_golden > 0)
+    golden_refine(f, best_u, (real)(2.0 * OR_PI / (double)n_scan), n_golden, &best_q, &best_u);
 
   real q_coast = qeval(f, 0, 0);
   choice c;
@@ -380,6 +390,28 @@ static choice search_scan_golden(const qfun *f, int n_scan, int n_golden) {
 static choice search(const qfun *f, const or_search *sr) {
   if (sr->mode == 0) return search_table(f, sr->n_angles);
   return search_scan_golden(f, sr->n_scan, sr->n_golden);
+}
+
+/* Seeded search (the warm-started minimisation of Section 3, "Efficient
+ * computation of the minimum", with the seed given per node): Q at the seed,
+ * then golden_refine on [seed - w, seed + w] with n_local - 3 iterations, so
+ * n_local thrust evaluations in all; thrust iff its best Q is strictly below
+ * the coast Q.  Where the result differs from the node's current value vin
+ * by more than fallback_tol * max(1, |vin|), the node repeats the full
+ * mode-1 search and *fell_back is set. */
+static choice search_seeded(const qfun *f, const or_search *sr, real seed, real vin, int *fell_back) {
+  real best_q = qeval(f, 1, seed), best_u = seed;
+  golden_refine(f, seed, (real)sr->local_half_width, sr->n_local - 3, &best_q, &best_u);
+  real q_coast = qeval(f, 0, 0);
+  choice c;
+  c.angle = wrap_angle(best_u);
+  c.thr = best_q < q_coast;
+  c.q = c.thr ? best_q : q_coast;
+  c.margin = fabs(best_q - q_coast);
+  real den = fabs(vin) > 1 ? fabs(vin) : 1;
+  *fell_back = fabs(c.q - vin) > (real)sr->fallback_tol * den;
+  if (*fell_back) return search_scan_golden(f, sr->n_scan, sr->n_golden);
+  return c;
 }
 
 /* ------------------------------------------------------------- sweeps */
@@ -446,6 +478,35 @@ void or_bellman_nodes(const or_problem *p, const uint8_t *kind_at_nodes, const o
     pol_ang[c] = ch.angle;
     pol_thr[c] = (uint8_t)ch.thr;
     margin[c] = ch.margin;
+  }
+}
+
+/* One Jacobi Bellman sweep with the seeded search (sr->mode is ignored):
+ * seed[j] is the proposed thrust angle of node j; fell_back (nullable) marks
+ * the nodes that repeated the full search. */
+void or_bellman_sweep_seeded(const or_problem *p, const uint8_t *kind, const or_search *sr, const real *Vin,
+                             const real *seed, real *Vout, real *pol_ang, uint8_t *pol_thr, real *margin,
+                             uint8_t *fell_back) {
+  int64_t N = n_total(p);
+  for (int64_t j = 0; j < N; j++) {
+    if (kind[j] != KIND_FREE) {
+      Vout[j] = Vin[j];
+      if (pol_ang) pol_ang[j] = 0;
+      if (pol_thr) pol_thr[j] = 0;
+      if (margin) margin[j] = INFINITY;
+      if (fell_back) fell_back[j] = 0;
+      continue;
+    }
+    int i[4];
+    node_index(p, j, i);
+    qfun f = {p, Vin, i, NULL, (real)p->dt};
+    int fb = 0;
+    choice c = search_seeded(&f, sr, seed[j], Vin[j], &fb);
+    Vout[j] = c.q;
+    if (pol_ang) pol_ang[j] = c.angle;
+    if (pol_thr) pol_thr[j] = (uint8_t)c.thr;
+    if (margin) margin[j] = c.margin;
+    if (fell_back) fell_back[j] = (uint8_t)fb;
   }
 }
 

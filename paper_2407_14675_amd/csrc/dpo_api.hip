@@ -17,6 +17,7 @@
 
 #include "../../include/dpo.h"
 #include "dpo_kernels.h"
+#include "dpo_mlp.h"
 
 using namespace dpo;
 
@@ -630,30 +631,63 @@ int dpo_solve_pi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, doubl
   int code = DPO_ENOCONV;
   double h[kPartial] = {0, 0, 0, 0, 0};
   int64_t it = 0, evals = 0, fallback = 0;
+  // Seeded solves run seeded greedy steps until their residual meets tol_rel,
+  // then full-search steps until a full step meets it: a local search that
+  // settled in the wrong basin is self-consistent (its residual is zero), so
+  // only the full search can certify the fixed point.
+  bool verify = false;
+  double seeded_best = INFINITY, full_best = INFINITY;
+  int seeded_stall = 0, full_stall = 0;
   while (it < max_outer) {
     // greedy step: policy improvement together with T V
-    if (seeded && it > 0) rc = sweep_seeded(c, cur, nxt, pol_angle, pol_thr, seed_angle, s, true);
+    const bool use_seed = seeded && it > 0 && !verify;
+    if (use_seed) rc = sweep_seeded(c, cur, nxt, pol_angle, pol_thr, seed_angle, s, true);
     else rc = sweep_full(c, cur, nxt, pol_angle, pol_thr, s, true);
     if (rc != DPO_OK) return rc;
     it++;
     std::swap(cur, nxt);
     if ((rc = finish_resid(c, c->resid, s)) != DPO_OK) return rc;
     if ((rc = read_resid(c, h, s)) != DPO_OK) return rc;
-    if (seeded && it > 1) {
+    if (use_seed) {
       fallback += (int64_t)h[4];
       evals += c->n_free * (1 + c->search.n_local) + (int64_t)h[4] * evals_per_full_search(c);
     } else {
       evals += c->n_free * evals_per_full_search(c);
+      if (seeded && it > 1) local.verify_steps++;
     }
     if (h[3] > 0) {
       code = DPO_ENUMERIC;
       fail(c, DPO_ENUMERIC, "policy iteration produced non-finite values");
       break;
     }
+    if (use_seed) {
+      // seeds that move with the iterate (warm starts) may never settle:
+      // leave the seeded phase after 8 seeded steps without a new best residual
+      if (h[0] < seeded_best) {
+        seeded_best = h[0];
+        seeded_stall = 0;
+      } else if (++seeded_stall >= 8) {
+        verify = true;
+      }
+    }
     if (h[0] < tol_rel) {
-      code = DPO_OK;
-      local.converged = 1;
-      break;
+      if (use_seed) {
+        verify = true;
+      } else {
+        code = DPO_OK;
+        local.converged = 1;
+        break;
+      }
+    }
+    if (!use_seed) {
+      // float32 rounding floors the residual; stop after 32 full steps without a new lowest one
+      if (h[0] < full_best) {
+        full_best = h[0];
+        full_stall = 0;
+      } else if (++full_stall >= 32) {
+        local.stalled = 1;
+        break;
+      }
     }
     for (int e = 0; e < eval_sweeps; e++) {
       if ((rc = sweep_eval_desc(c, cur, nxt, s)) != DPO_OK) return rc;
@@ -672,7 +706,7 @@ int dpo_solve_pi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, doubl
   local.resid_max_abs = h[2];
   local.seconds = now_s() - t0;
   if (st) *st = local;
-  if (code == DPO_ENOCONV) fail(c, DPO_ENOCONV, "max_outer reached");
+  if (code == DPO_ENOCONV) fail(c, DPO_ENOCONV, local.stalled ? "policy iteration stalled" : "max_outer reached");
   return code;
 }
 
@@ -771,7 +805,72 @@ int dpo_probe_foot(dpo_ctx* c, const int32_t* nodes, const uint8_t* thr, const f
   return DPO_OK;
 }
 
+
+/* ------------------------------------------------- training pairs for the network */
+
+int dpo_feasible_nodes(dpo_ctx* c, const float* V, double thresh, uint32_t* nodes, int64_t* n_out, void* stream) {
+  if (!c || !V || !nodes || !n_out) return fail(c, DPO_EINVAL, "NULL argument");
+  if (!std::isfinite(thresh)) return fail(c, DPO_EINVAL, "thresh must be finite");
+  const int N = (int)c->N;
+  const int nch = compact_chunks(N);
+  uint8_t* flag = nullptr;
+  int* counts = nullptr;
+  int* offsets = nullptr;
+  auto release = [&]() {
+    if (flag) (void)hipFree(flag);
+    if (counts) (void)hipFree(counts);
+    if (offsets) (void)hipFree(offsets);
+  };
+  if (hipMalloc(&flag, (size_t)N) != hipSuccess || hipMalloc(&counts, sizeof(int) * nch) != hipSuccess ||
+      hipMalloc(&offsets, sizeof(int) * (nch + 1)) != hipSuccess) {
+    release();
+    return fail(c, DPO_ENOMEM, "dpo_feasible_nodes: scratch allocation");
+  }
+  hipError_t e = launch_feasible_flags(c->kind, V, (float)thresh, flag, N, S(stream));
+  if (e == hipSuccess) e = launch_compact(c->G, flag, N, counts, offsets, nodes, S(stream));
+  int total = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&total, offsets + nch, sizeof(int), hipMemcpyDeviceToHost, S(stream));
+  if (e == hipSuccess) e = hipStreamSynchronize(S(stream));
+  release();
+  if (e != hipSuccess) return hip_fail(c, e, "dpo_feasible_nodes");
+  *n_out = total;
+  return DPO_OK;
+}
+
+int dpo_gather_pairs(dpo_ctx* c, const uint32_t* nodes, int64_t n_nodes, const int32_t* sel, int64_t n,
+                     const float* pol_angle, const uint8_t* pol_thr, float* x, float* tgt, void* stream) {
+  if (!c || !nodes || !pol_angle || !pol_thr || !x || !tgt || (n > 0 && !sel))
+    return fail(c, DPO_EINVAL, "NULL argument");
+  if (n < 0 || n > 0x7fffffffLL - kBlock) return fail(c, DPO_EINVAL, "n out of range");
+  if (n_nodes < 0 || n_nodes > c->n_free) return fail(c, DPO_EINVAL, "n_nodes must be in [0, n_free]");
+  if ((reinterpret_cast<uintptr_t>(x) & 15u) || (reinterpret_cast<uintptr_t>(tgt) & 15u))
+    return fail(c, DPO_EINVAL, "x and tgt must be 16-byte aligned");
+  for (int64_t t = 0; t < n; t++)
+    if (sel[t] < 0 || sel[t] >= n_nodes) return fail(c, DPO_EINVAL, "sel entries must lie in [0, n_nodes)");
+  if (n == 0) return DPO_OK;
+  int* dsel = nullptr;
+  if (hipMalloc(&dsel, sizeof(int) * (size_t)n) != hipSuccess) return fail(c, DPO_ENOMEM, "dpo_gather_pairs");
+  hipError_t e = hipMemcpyAsync(dsel, sel, sizeof(int) * (size_t)n, hipMemcpyHostToDevice, S(stream));
+  if (e == hipSuccess)
+    e = launch_gather_pairs(c->G, nodes, dsel, (int)n, pol_angle, pol_thr, reinterpret_cast<float4*>(x),
+                            reinterpret_cast<float4*>(tgt), S(stream));
+  if (e == hipSuccess) e = hipStreamSynchronize(S(stream));
+  (void)hipFree(dsel);
+  if (e != hipSuccess) return hip_fail(c, e, "dpo_gather_pairs");
+  return DPO_OK;
+}
+
 }  // extern "C"
+
+dpo::CtxView dpo::ctx_view(const dpo_ctx* c) {
+  CtxView v;
+  v.G = c->G;
+  v.free_node = c->free_node;
+  v.n_free = c->n_free;
+  v.N = c->N;
+  v.kind = c->kind;
+  return v;
+}
 
 // ============================================================ batched solve
 // The batch keeps every per-problem array in one concatenated device

@@ -54,7 +54,7 @@ class BatchStats(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("sweeps", C.c_int64), ("eval_sweeps", C.c_int64), ("evals", C.c_int64),
-                ("fallback_nodes", C.c_int64), ("resid_max_rel", C.c_double),
+                ("fallback_nodes", C.c_int64), ("verify_steps", C.c_int64), ("resid_max_rel", C.c_double),
                 ("resid_sum_abs", C.c_double), ("resid_max_abs", C.c_double), ("seconds", C.c_double),
                 ("stalled", C.c_int32), ("converged", C.c_int32)]
 
@@ -105,6 +105,20 @@ def load():
         "dpo_batch_solve_vi": [vp, vp, vp, vp, dbl, i64, i32, i32, vp, vp, vp],
         "dpo_batch_solve_sequential": [vp, vp, vp, vp, dbl, i64, i32, vp, vp, vp],
         "dpo_batch_time_config": [vp, i32, i32, i32, vp],
+        "dpo_mlp_create": [vp, C.POINTER(vp)],
+        "dpo_mlp_destroy": [vp],
+        "dpo_mlp_last_error": [vp],
+        "dpo_mlp_set_params": [vp, vp],
+        "dpo_mlp_get_params": [vp, vp],
+        "dpo_mlp_get_grad": [vp, vp],
+        "dpo_mlp_set_adam": [vp, dbl, dbl, dbl, dbl],
+        "dpo_mlp_steps": [vp],
+        "dpo_mlp_forward": [vp, vp, i64, vp, vp],
+        "dpo_mlp_grad": [vp, vp, vp, i64, vp, vp, vp],
+        "dpo_mlp_train": [vp, vp, vp, i64, vp, i32, vp, vp],
+        "dpo_mlp_propose": [vp, vp, vp, vp],
+        "dpo_feasible_nodes": [vp, vp, dbl, vp, C.POINTER(i64), vp],
+        "dpo_gather_pairs": [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -114,6 +128,9 @@ def load():
     lib.dpo_last_error.restype = C.c_char_p
     lib.dpo_batch_destroy.restype = None
     lib.dpo_batch_last_error.restype = C.c_char_p
+    lib.dpo_mlp_destroy.restype = None
+    lib.dpo_mlp_last_error.restype = C.c_char_p
+    lib.dpo_mlp_steps.restype = C.c_int64
     _lib = lib
     return lib
 
@@ -295,6 +312,26 @@ class Context:
                                                   _stream()))
         return mask
 
+    # -------------------------------------------- training pairs (network)
+    def feasible_nodes(self, V, thresh):
+        """Packed coordinates (int32 view of u32) of the free nodes with V < thresh, in node order."""
+        nodes = torch.empty(max(1, self.n_free), dtype=torch.int32, device=self.device)
+        n = C.c_int64()
+        self._check(self.lib.dpo_feasible_nodes(self.h, _p(V), float(thresh), _p(nodes), C.byref(n), _stream()))
+        return nodes[: n.value]
+
+    def gather_pairs(self, nodes, sel, pol_ang, pol_thr):
+        """Inputs (n x 4, scaled positions) and targets (cos, sin, throttle, 0) at nodes[sel]."""
+        import numpy as np
+
+        sel = np.ascontiguousarray(sel, dtype=np.int32)
+        n = sel.shape[0]
+        x = torch.empty((n, 4), dtype=torch.float32, device=self.device)
+        tgt = torch.empty((n, 4), dtype=torch.float32, device=self.device)
+        self._check(self.lib.dpo_gather_pairs(self.h, _p(nodes), nodes.numel(), sel.ctypes.data_as(C.c_void_p), n,
+                                              _p(pol_ang), _p(pol_thr), _p(x), _p(tgt), _stream()))
+        return x, tgt
+
     # ------------------------------------------------------------ probes
     def probe_interp(self, V, pts):
         pts = torch.as_tensor(pts, dtype=torch.float32).to(self.device).contiguous().reshape(-1, 4)
@@ -405,3 +442,105 @@ class Batch:
         self._check(self.lib.dpo_batch_time_config(self.h, int(block), int(sweeps_per_graph), int(replays),
                                                    C.byref(out)))
         return out.value
+
+
+MLP_PARAMS = 17539
+
+
+class Mlp:
+    """The control-proposal network on the device (parameters, Adam state)."""
+
+    def __init__(self, params=None, device="cuda"):
+        import numpy as np
+
+        self.lib = load()
+        self.device = torch.device(device)
+        h = C.c_void_p()
+        buf = None
+        if params is not None:
+            buf = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+            assert buf.size == MLP_PARAMS
+        torch.cuda.synchronize(self.device)
+        rc = self.lib.dpo_mlp_create(None if buf is None else buf.ctypes.data_as(C.c_void_p), C.byref(h))
+        if rc != DPO_OK:
+            raise DpoError(rc, self.lib.dpo_mlp_last_error(None).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dpo_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != DPO_OK:
+            raise DpoError(rc, self.lib.dpo_mlp_last_error(self.h).decode())
+
+    def params(self):
+        import numpy as np
+
+        out = np.empty(MLP_PARAMS, dtype=np.float32)
+        self._check(self.lib.dpo_mlp_get_params(self.h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def set_params(self, params):
+        import numpy as np
+
+        buf = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+        assert buf.size == MLP_PARAMS
+        self._check(self.lib.dpo_mlp_set_params(self.h, buf.ctypes.data_as(C.c_void_p)))
+
+    def last_grad(self):
+        import numpy as np
+
+        out = np.empty(MLP_PARAMS, dtype=np.float32)
+        self._check(self.lib.dpo_mlp_get_grad(self.h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def set_adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._check(self.lib.dpo_mlp_set_adam(self.h, float(lr), float(beta1), float(beta2), float(eps)))
+
+    def steps(self):
+        return int(self.lib.dpo_mlp_steps(self.h))
+
+    def forward(self, x):
+        x = x.contiguous()
+        y = torch.empty((x.shape[0], 3), dtype=torch.float32, device=self.device)
+        self._check(self.lib.dpo_mlp_forward(self.h, _p(x), x.shape[0], _p(y), _stream()))
+        return y
+
+    def grad(self, x, tgt):
+        """(gradient tensor, mean loss tensor) of the batch; parameters unchanged."""
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        self._check(self.lib.dpo_mlp_grad(self.h, _p(x.contiguous()), _p(tgt.contiguous()), x.shape[0], _p(g),
+                                          _p(loss), _stream()))
+        return g, loss
+
+    def train_epoch(self, x, tgt, perm=None, batch=4096):
+        """One epoch of Adam steps; returns the per-batch loss tensor."""
+        import numpy as np
+
+        n = x.shape[0]
+        steps = (n + batch - 1) // batch if batch > 0 else 1
+        hist = torch.empty(max(1, steps), dtype=torch.float32, device=self.device)
+        pp = None
+        if perm is not None:
+            perm = np.ascontiguousarray(perm, dtype=np.int32)
+            assert perm.size == n
+            pp = perm.ctypes.data_as(C.c_void_p)
+        self._check(self.lib.dpo_mlp_train(self.h, _p(x.contiguous()), _p(tgt.contiguous()), n, pp, int(batch),
+                                           _p(hist), _stream()))
+        return hist
+
+    def propose(self, ctx, seed=None):
+        """Seed angles at every free node of ctx (float32, node-shaped; other nodes 0)."""
+        if seed is None:
+            seed = torch.zeros(ctx.shape, dtype=torch.float32, device=self.device)
+        self._check(self.lib.dpo_mlp_propose(self.h, ctx.h, _p(seed), _stream()))
+        return seed

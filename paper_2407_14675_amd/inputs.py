@@ -188,3 +188,50 @@ def mlp_init(seed=4, widths=(4, 128, 128, 3)):
         b = rng.uniform(-bound, bound, size=(fan_out,))
         params.append((W, b))
     return params
+
+
+def mlp_params32(seed=4):
+    """mlp_init flattened in the library's parameter order (W1, b1, W2, b2,
+    W3, b3), float32."""
+    return np.concatenate([a.reshape(-1) for W, b in mlp_init(seed) for a in (W, b)]).astype(np.float32)
+
+
+# Learned control proposal: training pairs come from the converged solution
+# at nodes whose value is not the exit penalty (V < 0.98 M, the mask's
+# threshold; on these grids the numerical diffusion of the penalty leaves
+# almost no value below M/2), sampled without replacement, seed 4; batch
+# 4096, 20 epochs, each epoch in its own random order.
+MLP_PAIRS = 2_000_000
+MLP_BATCH = 4096
+MLP_EPOCHS = 20
+MLP_SEED = 4
+MLP_FEASIBLE_FRAC = 0.98
+
+# Seeded greedy step: 8 thrust evaluations on [seed - w, seed + w], full
+# scan + golden search where the result moves the node's value by more than
+# 1e-5 relative.
+SEEDED = dict(mode="seeded", n_scan=64, n_golden=12, n_local=8, local_half_width=0.1, fallback_tol=1e-5)
+
+
+def mlp_pair_selection(n_feasible, n_pairs=MLP_PAIRS, seed=MLP_SEED):
+    """Indices of the training pairs among the feasible nodes (int32)."""
+    rng = np.random.default_rng(seed)
+    k = min(int(n_pairs), int(n_feasible))
+    return np.sort(rng.choice(int(n_feasible), size=k, replace=False)).astype(np.int32)
+
+
+def mlp_epoch_orders(n, epochs=MLP_EPOCHS, seed=MLP_SEED):
+    """One random permutation of range(n) per epoch (int32)."""
+    rng = np.random.default_rng(seed + 1000)
+    return [rng.permutation(int(n)).astype(np.int32) for _ in range(epochs)]
+
+
+def mlp_random_samples(n, seed, thrust_frac=0.6):
+    """Synthetic network samples: inputs uniform in [-1, 1]^4; targets
+    (cos u, sin u, throttle, 0) with u uniform and throttle Bernoulli."""
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-1.0, 1.0, size=(n, 4))
+    u = rng.uniform(-math.pi, math.pi, size=n)
+    t = (rng.random(n) < thrust_frac).astype(np.float64)
+    tgt = np.stack([np.cos(u), np.sin(u), t, np.zeros(n)], axis=1)
+    return x.astype(np.float32), tgt.astype(np.float32)

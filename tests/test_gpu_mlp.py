@@ -1,0 +1,247 @@
+"""Control-proposal network on the device: forward and gradient parity with
+the FP64 reference (the same bfloat16 operand rounding on the 128 x 128
+layer), Adam, determinism, the pair and proposal kernels, and the seeded
+policy iteration it feeds."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp as ref
+from oracle.core import KIND_FREE, Oracle
+from paper_2407_14675_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+BLOCKS = [("W1", 0, 512), ("b1", 512, 640), ("W2", 640, 17024), ("b2", 17024, 17152), ("W3", 17152, 17536),
+          ("b3", 17536, 17539)]
+
+
+@pytest.fixture(scope="module")
+def dpo():
+    from paper_2407_14675_amd import dpo as mod
+    mod.load()
+    return mod
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def theta64(p32):
+    return np.asarray(p32, dtype=np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("n", [1, 64, 333])
+def test_forward_matches_reference(dpo, n):
+    print("mlp forward", n, flush=True)
+    p32 = inputs.mlp_params32(seed=4)
+    net = dpo.Mlp(p32)
+    x, _ = inputs.mlp_random_samples(n, seed=100 + n)
+    y = host(net.forward(dev(x)))
+    yr, _ = ref.forward(theta64(p32), x.astype(np.float64), bf16_ops=True)
+    err = np.abs(y - yr).max()
+    print("  max |y - y_ref| =", err, flush=True)
+    assert err <= 2e-3
+
+
+@pytest.mark.parametrize("n", [1, 64, 333, 4096])
+def test_gradient_matches_reference(dpo, n):
+    """Per parameter block: max |g - g_ref| <= 2e-2 * max |g_ref| (bf16
+    operands on both sides; FP32 vs FP64 elsewhere)."""
+    print("mlp gradient", n, flush=True)
+    p32 = inputs.mlp_params32(seed=4)
+    net = dpo.Mlp(p32)
+    x, t = inputs.mlp_random_samples(n, seed=200 + n)
+    g, loss = net.grad(dev(x), dev(t))
+    g, loss = host(g), float(host(loss)[0])
+    Lr, gr = ref.loss_grad(theta64(p32), x.astype(np.float64), t[:, :3].astype(np.float64), bf16_ops=True)
+    assert abs(loss - Lr) <= 1e-5 * max(1.0, abs(Lr))
+    for name, lo, hi in BLOCKS:
+        scale = np.abs(gr[lo:hi]).max()
+        err = np.abs(g[lo:hi] - gr[lo:hi]).max()
+        print(f"  {name}: max err {err:.3e} of max |g| {scale:.3e}", flush=True)
+        assert err <= 2e-2 * scale, name
+    np.testing.assert_array_equal(net.last_grad(), g)
+    np.testing.assert_array_equal(net.params(), p32)  # no update
+
+
+def test_adam_steps_match_reference(dpo):
+    """Two Adam steps: the device update equals the FP64 Adam formula applied
+    to the device's own gradient, to float32 rounding."""
+    print("mlp adam", flush=True)
+    p32 = inputs.mlp_params32(seed=4)
+    net = dpo.Mlp(p32)
+    x, t = inputs.mlp_random_samples(512, seed=7)
+    th = theta64(p32)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    for step in (1, 2):
+        net.train_epoch(dev(x), dev(t), batch=512)
+        g = net.last_grad().astype(np.float64)
+        th, m, v = ref.adam_step(th, g, m, v, step)
+        got = net.params().astype(np.float64)
+        assert np.abs(got - th).max() <= 1e-6 * (1e-3 * step) + 1e-7
+    assert net.steps() == 2
+
+
+def test_training_lowers_loss_and_is_deterministic(dpo):
+    """A smooth synthetic control law is learnt (mean loss falls by half in a
+    few epochs), and two runs from the same start agree bit for bit."""
+    print("mlp training", flush=True)
+    n = 8192
+    rng = np.random.default_rng(5)
+    x = rng.uniform(-1, 1, size=(n, 4)).astype(np.float32)
+    u = 1.5 * x[:, 0] - 0.8 * x[:, 1] * x[:, 2] + 0.3
+    thr = (x[:, 3] + 0.2 * x[:, 0] > 0).astype(np.float32)
+    t = np.stack([np.cos(u), np.sin(u), thr, np.zeros(n)], axis=1).astype(np.float32)
+    runs = []
+    for _ in range(2):
+        net = dpo.Mlp(inputs.mlp_params32(seed=4))
+        hist = []
+        for e, order in enumerate(inputs.mlp_epoch_orders(n, epochs=6)):
+            hist.append(host(net.train_epoch(dev(x), dev(t), perm=order, batch=1024)))
+        runs.append((np.concatenate(hist), net.params()))
+    first, last = runs[0][0][:4].mean(), runs[0][0][-4:].mean()
+    print("  loss", first, "->", last, flush=True)
+    assert last < 0.5 * first
+    np.testing.assert_array_equal(runs[0][0], runs[1][0])
+    np.testing.assert_array_equal(runs[0][1], runs[1][1])
+
+
+def test_bad_arguments_raise(dpo):
+    net = dpo.Mlp(inputs.mlp_params32(seed=4))
+    x, t = inputs.mlp_random_samples(10, seed=1)
+    with pytest.raises(dpo.DpoError):
+        net.train_epoch(dev(x), dev(t), perm=np.arange(1, 11), batch=4)  # index 10 out of range
+    with pytest.raises(dpo.DpoError):
+        net.train_epoch(dev(x), dev(t), batch=0)
+    bad = inputs.mlp_params32(seed=4)
+    bad[5] = np.nan
+    with pytest.raises(dpo.DpoError):
+        net.set_params(bad)
+
+
+def small_solution(dpo, n=(10, 10, 10, 10)):
+    p = inputs.orbit_problem(n, search=inputs.SCAN_GOLDEN, name="mlp_small")
+    ctx = dpo.Context(p)
+    V = ctx.init_value()
+    a, t = ctx.empty_policy()
+    ctx.solve_pi(V, a, t, tol_rel=1e-6, eval_sweeps=20, max_outer=2000)
+    return p, ctx, V, a, t
+
+
+def test_feasible_nodes_and_pairs(dpo):
+    print("pairs", flush=True)
+    p, ctx, V, a, t = small_solution(dpo)
+    thresh = 0.98 * p["M"]  # on this coarse grid few values are below M/2
+    nodes = ctx.feasible_nodes(V, thresh)
+    kind = host(ctx.kind()).reshape(-1)
+    Vh = host(V).reshape(-1)
+    want = np.flatnonzero((kind == KIND_FREE) & (Vh < thresh))
+    n = p["n"]
+    pk = host(nodes).astype(np.int64) & 0xFFFFFFFF
+    idx = [(pk >> (8 * k)) & 0xFF for k in range(4)]
+    flat = idx[0] + n[0] * (idx[1] + n[1] * (idx[2] + n[2] * idx[3]))
+    np.testing.assert_array_equal(flat, want)
+    assert want.size > 100
+    sel = inputs.mlp_pair_selection(len(want), n_pairs=len(want) // 2, seed=4)
+    x, tgt = ctx.gather_pairs(nodes, sel, a, t)
+    x, tgt = host(x), host(tgt)
+    j = want[sel]
+    for k in range(4):
+        ik = idx[k][sel]
+        np.testing.assert_allclose(x[:, k], 2.0 * ik / (n[k] - 1) - 1.0, atol=1e-6)
+    ah, th = host(a).reshape(-1)[j], host(t).reshape(-1)[j]
+    np.testing.assert_allclose(tgt[:, 0], np.cos(ah), atol=2e-6)
+    np.testing.assert_allclose(tgt[:, 1], np.sin(ah), atol=2e-6)
+    np.testing.assert_array_equal(tgt[:, 2], th.astype(np.float32))
+    with pytest.raises(dpo.DpoError):
+        ctx.gather_pairs(nodes, np.array([len(want)], dtype=np.int32), a, t)
+
+
+def test_propose_matches_forward(dpo):
+    print("propose", flush=True)
+    p = inputs.orbit_problem((9, 11, 7, 13), search=inputs.SCAN_GOLDEN, name="propose")
+    ctx = dpo.Context(p)
+    net = dpo.Mlp(inputs.mlp_params32(seed=4))
+    seed = host(net.propose(ctx)).reshape(-1)
+    kind = host(ctx.kind()).reshape(-1)
+    free = np.flatnonzero(kind == KIND_FREE)
+    n = p["n"]
+    i0 = free % n[0]
+    i1 = (free // n[0]) % n[1]
+    i2 = (free // (n[0] * n[1])) % n[2]
+    i3 = free // (n[0] * n[1] * n[2])
+    # the kernel's float32 scaling: float(2 i) / float(n - 1) - 1
+    x = np.stack([np.float32(2 * i) / np.float32(m - 1) - np.float32(1.0) for i, m in zip((i0, i1, i2, i3), n)],
+                 axis=1).astype(np.float32)
+    y = host(net.forward(dev(x)))
+    want = np.arctan2(y[:, 1], y[:, 0])
+    d = np.abs(np.angle(np.exp(1j * (seed[free].astype(np.float64) - want))))
+    # atan2 in float32 on both sides; (cos, sin) of an untrained network can be tiny
+    assert np.all(d <= 1e-6 / np.maximum(np.hypot(y[:, 0], y[:, 1]), 1e-3))
+    assert np.all(seed[kind != KIND_FREE] == 0.0)
+
+
+def train_on_solution(dpo, ctx, p, V, a, t, epochs=20, batch=4096):
+    nodes = ctx.feasible_nodes(V, inputs.MLP_FEASIBLE_FRAC * p["M"])
+    sel = inputs.mlp_pair_selection(nodes.numel(), n_pairs=inputs.MLP_PAIRS, seed=inputs.MLP_SEED)
+    x, tgt = ctx.gather_pairs(nodes, sel, a, t)
+    net = dpo.Mlp(inputs.mlp_params32(seed=inputs.MLP_SEED))
+    hist = [host(net.train_epoch(x, tgt, perm=o, batch=batch)).mean()
+            for o in inputs.mlp_epoch_orders(x.shape[0], epochs=epochs)]
+    return net, hist, x.shape[0]
+
+
+@pytest.mark.parametrize("accel", [1e-3, 5e-4])
+def test_nn_seeded_pi_matches_plain(dpo, accel):
+    """Downscaled config-2 physics (24 x 24 x 24 x 16, dt 0.02, fuel weight
+    0.1): plain PI, a network trained on its solution (a = 1e-3), then PI
+    whose greedy steps search 8 angles around the network's proposal with the
+    full search as fallback.  The seeded solve reaches the plain value within
+    1e-4 relative; a = 5e-4 is held out of training."""
+    print("nn-seeded PI, a =", accel, flush=True)
+    base = inputs.config2(accel=1e-3, n=(24, 24, 24, 16))
+    cb = dpo.Context(base)
+    Vb = cb.init_value()
+    ab, tb = cb.empty_policy()
+    rc, st = cb.solve_pi(Vb, ab, tb, tol_rel=1e-6, eval_sweeps=20, max_outer=5000)
+    assert rc == dpo.DPO_OK
+    Vh, kh = host(Vb), host(cb.kind())
+    for frac in (0.5, 0.98):
+        print(f"  free nodes with V < {frac} M: {int(((kh == KIND_FREE) & (Vh < frac * base['M'])).sum())} "
+              f"of {cb.n_free}", flush=True)
+    net, hist, npairs = train_on_solution(dpo, cb, base, Vb, ab, tb, batch=512)
+    print("  pairs", npairs, "loss", hist[0], "->", hist[-1], flush=True)
+    assert hist[-1] < hist[0]
+
+    p = inputs.config2(accel=accel, n=(24, 24, 24, 16))
+    ctx = dpo.Context(p)
+    V = ctx.init_value()
+    a, t = ctx.empty_policy()
+    rc, plain = ctx.solve_pi(V, a, t, tol_rel=1e-6, eval_sweeps=20, max_outer=5000)
+    assert rc == dpo.DPO_OK
+    ctx.set_search(inputs.SEEDED)
+    seed = net.propose(ctx)
+    V2 = ctx.init_value()
+    a2, t2 = ctx.empty_policy()
+    rc, seeded = ctx.solve_pi(V2, a2, t2, tol_rel=1e-6, eval_sweeps=20, max_outer=5000, seed=seed)
+    assert rc == dpo.DPO_OK
+    kind = host(ctx.kind())
+    free = kind == KIND_FREE
+    Vp, Vs = host(V), host(V2)
+    err = (np.abs(Vs - Vp) / np.maximum(1.0, np.abs(Vp)))[free].max()
+    greedy_nodes = ctx.n_free * max(1, seeded["sweeps"] - 1)
+    print(f"  plain: outer {plain['sweeps']} evals {plain['evals']:.3e} {plain['seconds']:.3f}s | seeded: outer "
+          f"{seeded['sweeps']} (full-search checks {seeded['verify_steps']}) evals {seeded['evals']:.3e} "
+          f"{seeded['seconds']:.3f}s fallback {seeded['fallback_nodes'] / greedy_nodes:.3f} | max rel err {err:.2e}",
+          flush=True)
+    assert err <= 1e-4
+    assert seeded["evals"] < plain["evals"]

@@ -262,6 +262,70 @@ def test_golden_search_matches_brute_force():
     assert bad <= 0.01 * len(free)
 
 
+def _smooth_value(p):
+    ax = grid_coords(p)
+    R, VR, VT, MM = np.meshgrid(ax[0], ax[1], ax[2], ax[3], indexing="ij")
+    V = (200 * (R - 1.05) ** 2 + 300 * VR ** 2 + 500 * (VT - 0.976) ** 2 + 10 * (1 - MM))
+    return V.transpose(3, 2, 1, 0).copy()
+
+
+def test_seeded_search_at_the_enumerated_optimum():
+    """Seeded at the argmin of a 2^14-angle enumeration, with a bracket of one
+    enumeration step and no fallback, the local search returns a value it
+    attains at its own angle, no worse than the enumeration and the coast and
+    below them by at most the enumeration's resolution."""
+    p = inputs.orbit_problem((6, 6, 6, 6), search=inputs.SCAN_GOLDEN, accel=2e-2)
+    o = Oracle(p)
+    V = _smooth_value(p)
+    free = np.flatnonzero(o.kind.reshape(-1) == KIND_FREE)
+    seed = np.zeros(o.shape)
+    qb = {}
+    for j in free:
+        q, u = o.brute_thrust_min(V, j, 1 << 14)
+        seed.reshape(-1)[j] = u
+        qb[j] = q
+    sr = dict(inputs.SCAN_GOLDEN, mode="seeded", n_local=8, local_half_width=2 * math.pi / (1 << 14),
+              fallback_tol=1e30)
+    Vs, ang, thr, margin, fb = o.bellman_sweep_seeded(V, seed, search=sr)
+    assert fb.sum() == 0
+    for j in free:
+        qc = o.q(V, j, 0, 0.0)
+        assert Vs.reshape(-1)[j] <= min(qb[j], qc)
+        assert Vs.reshape(-1)[j] >= min(qb[j], qc) - 1e-5 * max(1.0, abs(qb[j]))
+        assert thr.reshape(-1)[j] == (1 if Vs.reshape(-1)[j] < qc else 0)
+        attained = o.q(V, j, int(thr.reshape(-1)[j]), ang.reshape(-1)[j])
+        assert abs(attained - Vs.reshape(-1)[j]) <= 1e-12 * max(1.0, abs(attained))
+
+
+def test_seeded_search_reduces_to_scan_golden():
+    """Seeded at the best scan sample with the scan's own bracket and
+    n_local = n_golden + 3, the seeded search performs exactly the scan +
+    golden search's refinement, so the two sweeps agree bit for bit; with a
+    zero fallback tolerance every node repeats the full search."""
+    p = inputs.orbit_problem((6, 6, 6, 6), search=inputs.SCAN_GOLDEN, accel=2e-2)
+    o = Oracle(p)
+    V = _smooth_value(p)
+    ns, ng = inputs.SCAN_GOLDEN["n_scan"], inputs.SCAN_GOLDEN["n_golden"]
+    free = np.flatnonzero(o.kind.reshape(-1) == KIND_FREE)
+    us = -math.pi + 2 * math.pi * np.arange(ns) / ns
+    q = o.q_many(V, np.repeat(free, ns), np.ones(free.size * ns), np.tile(us, free.size)).reshape(free.size, ns)
+    seed = np.zeros(o.shape)
+    seed.reshape(-1)[free] = us[np.argmin(q, axis=1)]
+    Vg, ag, tg, _ = o.bellman_sweep(V)
+    sr = dict(inputs.SCAN_GOLDEN, mode="seeded", n_local=ng + 3, local_half_width=2 * math.pi / ns,
+              fallback_tol=1e30)
+    Vs, as_, ts, _, fb = o.bellman_sweep_seeded(V, seed, search=sr)
+    assert fb.sum() == 0
+    np.testing.assert_array_equal(Vs, Vg)
+    np.testing.assert_array_equal(ts, tg)
+    np.testing.assert_array_equal(as_, ag)
+    # zero tolerance: the fallback is the full search itself
+    sr0 = dict(sr, n_local=5, local_half_width=0.3, fallback_tol=0.0)
+    Vz, az, tz, _, fz = o.bellman_sweep_seeded(V, np.zeros(o.shape), search=sr0)
+    assert fz.reshape(-1)[free].all()
+    np.testing.assert_array_equal(Vz, Vg)
+
+
 def test_table_search_is_exhaustive_first_minimum():
     """Discrete table: the result is the first minimum over (coast, u_0..u_K-1),
     coast winning exact ties."""
