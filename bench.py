@@ -149,6 +149,112 @@ def bench_batched(max_sweeps=20000, tol=1e-6):
     }
 
 
+MLP_FLOPS_PER_SAMPLE = 6 * (4 * 128 + 128 * 128 + 128 * 3)  # forward 2 x MAC, backward 4 x MAC
+
+
+def rel_diff(A, B, free):
+    d = (A - B).abs() / B.abs().clamp(min=1.0)
+    d[~free] = 0
+    return float(d.max()), int((d > 1e-4).sum())
+
+
+def bench_large(accels=(1e-3,), with_seeded=True):
+    """96 x 96 x 96 x 64 problems (dt 0.02, fuel weight 0.1): value iteration
+    to 1e-3 then policy iteration to 1e-6 (the reference solution); then, for
+    the first thrust level, plain policy iteration from V0 against policy
+    iteration seeded by the control-proposal network trained on the reference
+    solution (2M pairs, 20 epochs)."""
+    import torch
+
+    from paper_2407_14675_amd import dpo, inputs
+
+    out = {"grid": [96, 96, 96, 64], "problems": []}
+    net = None
+    for accel in accels:
+        p = inputs.config2(accel=accel)
+        ctx = dpo.Context(p)
+        free = ctx.kind() == 0
+        V = ctx.init_value()
+        a, t = ctx.empty_policy()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc1, st1 = ctx.solve_vi(V, a, t, tol_rel=1e-3, max_sweeps=20000, check_every=16)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rc2, st2 = ctx.solve_pi(V, a, t, tol_rel=1e-6, eval_sweeps=20, max_outer=3000)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        rec = {
+            "accel": accel, "nodes": ctx.N, "free_nodes": ctx.n_free,
+            "vi_sweeps": st1["sweeps"], "vi_seconds": t1 - t0,
+            "pi_outer": st2["sweeps"], "pi_eval_sweeps": st2["eval_sweeps"], "pi_seconds": t2 - t1,
+            "seconds": t2 - t0, "converged": bool(st2["converged"]), "resid_max_rel": st2["resid_max_rel"],
+            "V_x0": ctx.value_at(V, inputs.X0),
+        }
+        log(f"bench: large a={accel}: {rec}")
+        # plain policy iteration from V0 (same stop rule), compared with the reference
+        Vp = ctx.init_value()
+        ap, tp = ctx.empty_policy()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, stp = ctx.solve_pi(Vp, ap, tp, tol_rel=1e-6, eval_sweeps=20, max_outer=3000)
+        torch.cuda.synchronize()
+        rec["pi_from_v0"] = {"seconds": time.perf_counter() - t0, "outer": stp["sweeps"], "evals": stp["evals"],
+                             "converged": bool(stp["converged"])}
+        rec["pi_from_v0"]["max_rel_diff_vs_reference"], rec["pi_from_v0"]["nodes_over_1e-4"] = rel_diff(Vp, V, free)
+        del Vp, ap, tp
+        if with_seeded:
+            if net is None:
+                nodes = ctx.feasible_nodes(V, inputs.MLP_FEASIBLE_FRAC * p["M"])
+                sel = inputs.mlp_pair_selection(nodes.numel())
+                x, tgt = ctx.gather_pairs(nodes, sel, a, t)
+                net = dpo.Mlp(inputs.mlp_params32())
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for order in inputs.mlp_epoch_orders(x.shape[0]):
+                    hist = net.train_epoch(x, tgt, perm=order, batch=inputs.MLP_BATCH)
+                torch.cuda.synchronize()
+                train_s = time.perf_counter() - t0
+                samples = x.shape[0] * inputs.MLP_EPOCHS
+                rec["mlp_training"] = {
+                    "pairs": int(x.shape[0]), "feasible_nodes": int(nodes.numel()), "epochs": inputs.MLP_EPOCHS,
+                    "batch": inputs.MLP_BATCH, "seconds": train_s, "final_loss": float(hist.mean()),
+                    "tflops": samples * MLP_FLOPS_PER_SAMPLE / train_s / 1e12,
+                    "mfma_bf16_peak_tflops": 2500.0,
+                }
+                del x, tgt, nodes
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            seed = net.propose(ctx)
+            torch.cuda.synchronize()
+            prop_s = time.perf_counter() - t0
+            ctx.set_search(inputs.SEEDED)
+            Vs = ctx.init_value()
+            as_, ts = ctx.empty_policy()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, sts = ctx.solve_pi(Vs, as_, ts, tol_rel=1e-6, eval_sweeps=20, max_outer=3000, seed=seed)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            greedy_nodes = ctx.n_free * max(1, sts["sweeps"] - 1 - sts["verify_steps"])
+            rec["nn_seeded"] = {
+                "seconds": sec, "propose_seconds": prop_s, "outer": sts["sweeps"], "verify_steps": sts["verify_steps"],
+                "evals": sts["evals"], "fallback_fraction": sts["fallback_nodes"] / greedy_nodes,
+                "converged": bool(sts["converged"]),
+                "speedup_vs_plain_pi": rec["pi_from_v0"]["seconds"] / sec,
+                "eval_ratio_vs_plain_pi": rec["pi_from_v0"]["evals"] / max(1, sts["evals"]),
+                "held_out": accel != accels[0],
+            }
+            rec["nn_seeded"]["max_rel_diff_vs_reference"], rec["nn_seeded"]["nodes_over_1e-4"] = rel_diff(Vs, V, free)
+            ctx.set_search(inputs.SCAN_GOLDEN)
+            del Vs, as_, ts, seed
+            log(f"bench: large a={accel} seeded {rec['nn_seeded']}")
+        out["problems"].append(rec)
+        del V, a, t, free
+        ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +264,10 @@ def main():
     ap.add_argument("--no-converge", action="store_true", help="skip the time-to-converge run")
     ap.add_argument("--path", type=int, default=0, help="sweep kernel path: 0 auto, 1 direct, 2 factorised")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 16-problem measurement")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 96^3 x 64 solves and the network-seeded comparison")
+    ap.add_argument("--held-out", action="store_true",
+                    help="also solve the 96^3 x 64 problem with thrust 5e-4 using the network trained at 1e-3")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one plain 512 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -267,6 +377,11 @@ def main():
         }
         log(f"bench: converge {converge}")
 
+    large = None
+    if not args.no_large:
+        log("bench: 96^3 x 64 solves")
+        large = bench_large(accels=(1e-3, 5e-4) if args.held_out else (1e-3,))
+
     batched = None
     if not args.no_batched:
         log("bench: batched 16-problem solve")
@@ -331,6 +446,7 @@ def main():
             "naive_gather_frac": value * GATHER_BYTES_PER_EVAL / 1e9 / HBM_PEAK_GBS,
         },
         "time_to_converge": converge,
+        "large_96x96x96x64": large,
         "batched": batched,
         "cpu_baseline": cpu,
         "host": {"nproc": os.cpu_count(), "cpu": platform.processor()},

@@ -548,7 +548,11 @@ int64_t or_solve_vi(const or_problem *p, const uint8_t *kind, const or_search *s
 /* Modified policy iteration: greedy step (eq:p_impr together with T V);
  * stop if its residual is below tolerance; otherwise eval_sweeps frozen-policy
  * sweeps (eq:p_eval solved approximately); repeat.  eval_sweeps < 0 means
- * "evaluate until the frozen-policy sweep changes V by less than tol/10". */
+ * "evaluate until the frozen-policy sweep changes V by less than tol/10".
+ * From the second greedy step on, a node keeps its current control unless
+ * the search finds a strictly smaller Q (eq:p_impr with the search standing
+ * in for the exact argmin: the improvement step never returns a control worse
+ * than the current one). */
 int64_t or_solve_pi(const or_problem *p, const uint8_t *kind, const or_search *sr, real *V,
                     real *pol_ang, uint8_t *pol_thr, double tol_abs, double tol_rel,
                     int32_t eval_sweeps, int64_t max_outer, double *last_resid,
@@ -559,7 +563,27 @@ int64_t or_solve_pi(const or_problem *p, const uint8_t *kind, const or_search *s
   int64_t it, evals = 0;
   int done = 0;
   for (it = 1; it <= max_outer; it++) {
-    or_bellman_sweep(p, kind, sr, V, W, pol_ang, pol_thr, NULL);
+    if (it == 1) {
+      or_bellman_sweep(p, kind, sr, V, W, pol_ang, pol_thr, NULL);
+    } else {
+      /* policy improvement: the search result, unless the node's current
+       * control has a Q no larger (the incumbent is kept on ties) */
+      for (int64_t j = 0; j < N; j++) {
+        if (kind[j] != KIND_FREE) { W[j] = V[j]; continue; }
+        int i[4];
+        node_index(p, j, i);
+        qfun f = {p, V, i, NULL, (real)p->dt};
+        choice c = search(&f, sr);
+        real q_inc = q_node(p, V, i, pol_thr[j], pol_ang[j], (real)p->dt);
+        if (q_inc <= c.q) {
+          W[j] = q_inc;
+        } else {
+          W[j] = c.q;
+          pol_ang[j] = c.angle;
+          pol_thr[j] = (uint8_t)c.thr;
+        }
+      }
+    }
     or_residual(N, kind, V, W, res);
     memcpy(V, W, sizeof(real) * (size_t)N);
     if (tol_abs > 0 ? res[2] < tol_abs : res[0] < tol_rel) { done = 1; break; }

@@ -260,12 +260,16 @@ int64_t evals_per_full_search(const dpo_ctx* c) {
 bool use_fast(const dpo_ctx* c) { return c->path == 2 || (c->path == 0 && c->fast_ok); }
 
 int sweep_full(dpo_ctx* c, const float* Vin, float* Vout, float* ang, uint8_t* thr, hipStream_t s,
-               bool desc = false) {
+               bool desc = false, bool incumbent = false) {
   SweepArgs a = base_args(c);
   a.V_in = Vin;
   a.V_out = Vout;
   a.pol_ang = ang;
   a.pol_thr = thr;
+  if (incumbent) {
+    a.pol_ang_in = ang;
+    a.pol_thr_in = thr;
+  }
   if (desc) {
     a.desc_code = c->desc_code;
     a.desc_w = c->desc_w;
@@ -282,12 +286,16 @@ int sweep_full(dpo_ctx* c, const float* Vin, float* Vout, float* ang, uint8_t* t
 }
 
 int sweep_seeded(dpo_ctx* c, const float* Vin, float* Vout, float* ang, uint8_t* thr, const float* seed,
-                 hipStream_t s, bool desc = false) {
+                 hipStream_t s, bool desc = false, bool incumbent = false) {
   SweepArgs a = base_args(c);
   a.V_in = Vin;
   a.V_out = Vout;
   a.pol_ang = ang;
   a.pol_thr = thr;
+  if (incumbent) {
+    a.pol_ang_in = ang;
+    a.pol_thr_in = thr;
+  }
   a.seed = seed;
   if (desc) {
     a.desc_code = c->desc_code;
@@ -641,8 +649,8 @@ int dpo_solve_pi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, doubl
   while (it < max_outer) {
     // greedy step: policy improvement together with T V
     const bool use_seed = seeded && it > 0 && !verify;
-    if (use_seed) rc = sweep_seeded(c, cur, nxt, pol_angle, pol_thr, seed_angle, s, true);
-    else rc = sweep_full(c, cur, nxt, pol_angle, pol_thr, s, true);
+    if (use_seed) rc = sweep_seeded(c, cur, nxt, pol_angle, pol_thr, seed_angle, s, true, true);
+    else rc = sweep_full(c, cur, nxt, pol_angle, pol_thr, s, true, it > 0);
     if (rc != DPO_OK) return rc;
     it++;
     std::swap(cur, nxt);

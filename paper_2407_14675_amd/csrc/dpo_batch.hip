@@ -43,6 +43,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch_sweep(BatchArgs B, int pari
   a.rot_scan = B.rot_scan;
   a.desc_code = nullptr;
   a.seed = nullptr;
+  a.pol_ang_in = nullptr;
+  a.pol_thr_in = nullptr;
   const int t = (tile - B.tile_begin[k]) * blockDim.x + threadIdx.x;
   double rel = 0, sum = 0, mabs = 0, bad = 0;
   int fell_back = 0;

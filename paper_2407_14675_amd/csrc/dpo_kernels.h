@@ -17,8 +17,8 @@ struct SweepArgs {
   float* V_out;
   float* pol_ang;             // out, nullable
   uint8_t* pol_thr;           // out, nullable
-  const float* pol_ang_in;    // frozen policy (evaluation sweep)
-  const uint8_t* pol_thr_in;  // frozen policy (evaluation sweep)
+  const float* pol_ang_in;    // frozen policy (evaluation sweep); greedy sweeps: incumbent, nullable
+  const uint8_t* pol_thr_in;  // frozen policy (evaluation sweep); greedy sweeps: incumbent, nullable
   const float* seed;          // seeded search
   const uint32_t* free_node;  // packed coordinates (8 bits per axis, r lowest) of the free nodes
   int n_free;

@@ -146,6 +146,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_direct(SweepArgs a) {
     if (kMode == 0) table_search(qf, a, qc, ch);
     else if (kMode == 1) full_search(qf, a, qc, ch);
     else fell_back = seeded_search(qf, a, a.seed[j], qc, vin, ch);
+    keep_incumbent(qf, a, j, qc, ch);
     a.V_out[j] = ch.v;
     if (a.pol_ang) a.pol_ang[j] = ch.ang;
     if (a.pol_thr) a.pol_thr[j] = (uint8_t)ch.thr;

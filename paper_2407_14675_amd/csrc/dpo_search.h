@@ -201,6 +201,32 @@ __device__ inline int seeded_search(const QF& qf, const SweepArgs& a, float seed
   return 0;
 }
 
+// Policy iteration's greedy step also evaluates the node's current control
+// (pol_thr_in / pol_ang_in, read before the node's outputs are written) and
+// keeps it unless the search found a strictly smaller Q.  The scan + golden
+// search is only approximately the argmin; with the incumbent as a candidate
+// the greedy value never exceeds the current policy's, so policy iteration
+// from above decreases monotonically instead of alternating between two
+// nearly tied basins.
+template <class QF>
+__device__ inline void keep_incumbent(const QF& qf, const SweepArgs& a, int j, float qc, Choice& ch) {
+  if (!a.pol_thr_in) return;
+  const int thr0 = a.pol_thr_in[j] ? 1 : 0;
+  const float u0 = a.pol_ang_in[j];
+  float s0 = 0.0f, c0 = 1.0f, q0 = qc;
+  if (thr0) {
+    sincosf(u0, &s0, &c0);
+    q0 = qf(s0, c0);
+  }
+  if (q0 <= ch.v) {
+    ch.v = q0;
+    ch.ang = u0;
+    ch.sn = s0;
+    ch.cs = c0;
+    ch.thr = thr0;
+  }
+}
+
 // Foot descriptor of the chosen control (see SweepArgs::desc_code).
 __device__ inline void write_desc(const SweepArgs& a, int t, const NodeTerms& T, const Choice& ch) {
   float off[4];
@@ -396,6 +422,7 @@ __device__ inline void fast_node(const SweepArgs& a, int t, float4* lds, double&
   if (kMode == 0) table_search(qf, a, qc, ch);
   else if (kMode == 1) full_search(qf, a, qc, ch);
   else fell_back = seeded_search(qf, a, a.seed[j], qc, vin, ch);
+  keep_incumbent(qf, a, j, qc, ch);
   a.V_out[j] = ch.v;
   if (a.pol_ang) a.pol_ang[j] = ch.ang;
   if (a.pol_thr) a.pol_thr[j] = (uint8_t)ch.thr;

@@ -1,0 +1,134 @@
+"""Parity at the benchmark sizes, on sampled nodes: the greedy sweep and the
+frozen-policy sweep exactly as the benchmark launches them (automatic kernel
+path, default workgroup), checked node by node against the oracle's Bellman
+operator and Q at a few thousand sampled free nodes."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.core import KIND_FREE, Oracle
+from paper_2407_14675_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+ANGLE_ROUND = 1e-4
+
+
+@pytest.fixture(scope="module")
+def dpo():
+    from paper_2407_14675_amd import dpo as mod
+    mod.load()
+    return mod
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def corner_max(V, shape, nodes):
+    """max |V| over the 7^4 box of nodes around each sampled node (the cells a
+    foot can touch), for the float32 lerp rounding term of the tolerance."""
+    Vr = np.abs(V.reshape(shape))
+    out = np.empty(nodes.size)
+    idx = np.array(np.unravel_index(nodes, shape)).T
+    for c, (a, b, d, e) in enumerate(idx):
+        out[c] = Vr[max(a - 3, 0):a + 4, max(b - 3, 0):b + 4, max(d - 3, 0):d + 4, max(e - 3, 0):e + 4].max()
+    return out
+
+
+def check_sampled(o, V64, shape, nodes, Vg, tg, ag, Ve, n_scan=64):
+    """Greedy values at sampled nodes: agreement with the oracle's operator on
+    non-tie nodes (>= 99.9 %), attained at the device's own control, no worse
+    than coast and the scan samples; frozen-policy values equal the oracle's Q
+    of the device policy."""
+    Vo, ao, to, margin = o.bellman_nodes(V64, nodes)
+    tol = 1e-5 * np.maximum(1.0, np.abs(Vo)) + 1e-6 * corner_max(V64, shape, nodes)
+    vg = Vg.reshape(-1)[nodes].astype(np.float64)
+    thr = tg.reshape(-1)[nodes]
+    ang = ag.reshape(-1)[nodes].astype(np.float64)
+    clear = margin >= 1e-4 * np.maximum(1.0, np.abs(Vo))
+    ok = np.abs(vg[clear] - Vo[clear]) <= tol[clear]
+    assert ok.mean() >= 0.999, ok.mean()
+    attained = np.abs(vg - Vo) <= tol
+    for du in (0.0, -ANGLE_ROUND, ANGLE_ROUND):
+        attained |= np.abs(vg - o.q_many(V64, nodes, thr, ang + du)) <= tol
+    assert attained.all()
+    best = o.q_many(V64, nodes, np.zeros(nodes.size, np.uint8), np.zeros(nodes.size))
+    one = np.ones(nodes.size, np.uint8)
+    for s in range(n_scan):
+        best = np.minimum(best, o.q_many(V64, nodes, one, np.full(nodes.size, -math.pi + 2 * math.pi * s / n_scan)))
+    assert np.all(vg <= best + tol)
+    # frozen-policy sweep with the device policy (descriptors of the greedy sweep)
+    qe = o.q_many(V64, nodes, thr, ang)
+    ve = Ve.reshape(-1)[nodes].astype(np.float64)
+    assert np.all(np.abs(ve - qe) <= tol), np.max(np.abs(ve - qe) / tol)
+    return int(clear.sum())
+
+
+def sample_free(kind, count, seed, V=None, below=None):
+    """Sorted random free nodes; with V and below, half of them among the
+    nodes whose value is below `below` (where the controls differ)."""
+    free = kind.reshape(-1) == KIND_FREE
+    rng = np.random.default_rng(seed)
+    pools = [np.flatnonzero(free)]
+    if V is not None:
+        pools = [np.flatnonzero(free & (V.reshape(-1) >= below)), np.flatnonzero(free & (V.reshape(-1) < below))]
+    picks = [rng.choice(pool, size=min(count // len(pools), pool.size), replace=False) for pool in pools]
+    return np.sort(np.concatenate(picks)).astype(np.int64)
+
+
+def sweep_pair(ctx, V):
+    W = torch.empty_like(V)
+    E = torch.empty_like(V)
+    ang, thr = ctx.empty_policy()
+    ctx.bellman_sweep(V, W, ang, thr)
+    ctx.policy_eval_sweep_last(V, E)
+    return host(W), host(thr), host(ang), host(E)
+
+
+def test_policy_iteration_step_48x4_masked(dpo):
+    """The benchmark's 48^4 workload: mask from the 12^4 pre-solve, the value
+    after 10 policy-iteration steps, then one greedy and one evaluation sweep."""
+    print("48^4 masked, sampled", flush=True)
+    c0 = dpo.Context(inputs.CONFIG0)
+    Vc = c0.init_value()
+    a0, t0 = c0.empty_policy()
+    c0.solve_vi(Vc, a0, t0, tol_rel=1e-7, max_sweeps=20000, check_every=16)
+    p1 = inputs.CONFIG1
+    mask = c0.mask_from_coarse(Vc, p1, inputs.MASK_THRESHOLD_FRAC * p1["M"], inputs.MASK_DILATE)
+    ctx = dpo.Context(p1, mask=mask)
+    V = ctx.init_value()
+    ang, thr = ctx.empty_policy()
+    ctx.solve_pi(V, ang, thr, tol_rel=0.0, eval_sweeps=inputs.CONFIG1_EVAL_SWEEPS, max_outer=10)
+    W, tg, ag, E = sweep_pair(ctx, V)
+    o = Oracle(p1, mask=host(mask))
+    kind = host(ctx.kind())
+    np.testing.assert_array_equal(kind, o.kind)
+    nodes = sample_free(kind, 3000, seed=41)
+    V64 = host(V).astype(np.float64)
+    n_clear = check_sampled(o, V64, o.shape, nodes, W, tg, ag, E)
+    print("  sampled", nodes.size, "non-tie", n_clear, flush=True)
+
+
+@pytest.mark.parametrize("accel", [1e-3, 5e-4])
+def test_greedy_and_eval_sweeps_96x96x96x64(dpo, accel):
+    """The 96 x 96 x 96 x 64 grid (56.6M nodes) after 600 value-iteration
+    sweeps, one greedy and one evaluation sweep, 3000 sampled nodes (half of
+    them where V < 0.98 M)."""
+    print("96^3 x 64 sampled, a =", accel, flush=True)
+    p = inputs.config2(accel=accel)
+    ctx = dpo.Context(p)
+    V = ctx.init_value()
+    ang, thr = ctx.empty_policy()
+    ctx.solve_vi(V, ang, thr, tol_rel=0.0, max_sweeps=600, check_every=600)
+    W, tg, ag, E = sweep_pair(ctx, V)
+    kind = host(ctx.kind())
+    o = Oracle(p)
+    V64 = host(V).astype(np.float64)
+    nodes = sample_free(kind, 3000, seed=43, V=V64, below=inputs.MASK_THRESHOLD_FRAC * p["M"])
+    np.testing.assert_array_equal(kind.reshape(-1)[nodes], o.kind.reshape(-1)[nodes])
+    n_clear = check_sampled(o, V64, o.shape, nodes, W, tg, ag, E)
+    print("  sampled", nodes.size, "non-tie", n_clear, flush=True)

@@ -382,3 +382,20 @@ def test_float_build_precision_floor():
     r32 = o32.solve_vi(tol_abs=0.0, tol_rel=1e-7, max_sweeps=50000)
     err = np.abs(r32["V"].astype(np.float64) - v64) / np.maximum(np.abs(v64), 1.0)
     assert err.max() < 1e-4
+
+
+def test_policy_iteration_decreases_monotonically_from_above():
+    """With discounting (lambda = 0.7) V0 = M off target is a supersolution
+    (dt + exp(-lambda dt) M < M), and from there each policy-iteration step is
+    no larger than the previous at every node: the greedy step keeps the
+    current control unless the search is strictly better, and frozen-policy
+    sweeps of a policy whose Q is below V keep decreasing.  (Undiscounted,
+    exit feet cost dt + M > M, so M is not an upper bound.)"""
+    p = inputs.orbit_problem((6, 6, 6, 6), search=inputs.SCAN_GOLDEN, lam=0.7)
+    o = Oracle(p)
+    prev = None
+    for k in range(1, 7):
+        r = o.solve_pi(tol_abs=0.0, tol_rel=0.0, eval_sweeps=3, max_outer=k)
+        if prev is not None:
+            assert np.all(r["V"] <= prev + 1e-12 * np.maximum(1.0, np.abs(prev)))
+        prev = r["V"]
