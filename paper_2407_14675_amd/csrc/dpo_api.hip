@@ -47,6 +47,9 @@ struct dpo_ctx {
   int partial_blocks = 0;
   double* resid = nullptr;  // kPartial doubles
   float* work = nullptr;    // second value buffer of the solvers
+  float* work2 = nullptr;   // third value buffer (policy iteration keeps the greedy output while evaluating ahead)
+  double* resid_host = nullptr;  // pinned copy of the residual for the overlapped read-back
+  hipEvent_t resid_ready = nullptr;
   int* desc_code = nullptr;  // foot descriptors of the greedy step's controls (policy iteration)
   float2* desc_w = nullptr;
   bool desc_valid = false;    // a sweep has written them
@@ -122,6 +125,9 @@ int validate_search(dpo_ctx* c, const dpo_search* s) {
 hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 constexpr int kRot = 2 + 2 * 64;
+
+// MI355X Infinity Cache (last-level cache shared by the XCDs).
+constexpr double kLastLevelCacheBytes = 256.0 * 1024 * 1024;
 
 // Rotation constants of the golden section on [u0 - half, u0 + half]: sin/cos
 // of half*rho^3 (the two interior points), then of L0*rho^(k+4), L0 = 2*half,
@@ -238,6 +244,16 @@ int ensure_work(dpo_ctx* c) {
   return DPO_OK;
 }
 
+int ensure_pi_buffers(dpo_ctx* c) {
+  if (!c->work2 && hipMalloc(&c->work2, sizeof(float) * (size_t)c->N) != hipSuccess)
+    return fail(c, DPO_ENOMEM, "solver work buffer alloc");
+  if (!c->resid_host && hipHostMalloc(&c->resid_host, sizeof(double) * kPartial, hipHostMallocDefault) != hipSuccess)
+    return fail(c, DPO_ENOMEM, "pinned residual buffer alloc");
+  if (!c->resid_ready && hipEventCreateWithFlags(&c->resid_ready, hipEventDisableTiming) != hipSuccess)
+    return fail(c, DPO_EHIP, "residual event create");
+  return DPO_OK;
+}
+
 int ensure_desc(dpo_ctx* c) {
   if (c->desc_code) return DPO_OK;
   const size_t n = (size_t)(c->n_free > 0 ? c->n_free : 1);
@@ -331,7 +347,9 @@ int sweep_eval_desc(dpo_ctx* c, const float* Vin, float* Vout, hipStream_t s) {
   a.desc_code_in = c->desc_code;
   a.desc_w_in = c->desc_w;
   if (a.n_free == 0) return DPO_OK;
-  hipError_t e = launch_policy_eval_desc(a, s);
+  // streamed per sweep: coordinates + descriptor per free node, two value arrays
+  const double bytes = 16.0 * (double)c->n_free + 8.0 * (double)c->N;
+  hipError_t e = launch_policy_eval_desc(a, bytes > kLastLevelCacheBytes, s);
   if (e != hipSuccess) return hip_fail(c, e, "policy eval (descriptor) launch");
   return DPO_OK;
 }
@@ -460,6 +478,9 @@ void dpo_destroy(dpo_ctx* c) {
   if (c->partial) hipFree(c->partial);
   if (c->resid) hipFree(c->resid);
   if (c->work) hipFree(c->work);
+  if (c->work2) hipFree(c->work2);
+  if (c->resid_host) hipHostFree(c->resid_host);
+  if (c->resid_ready) hipEventDestroy(c->resid_ready);
   if (c->desc_code) hipFree(c->desc_code);
   if (c->desc_w) hipFree(c->desc_w);
   delete c;
@@ -629,13 +650,20 @@ int dpo_solve_pi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, doubl
   int rc = ensure_work(c);
   if (rc != DPO_OK) return rc;
   if ((rc = ensure_desc(c)) != DPO_OK) return rc;
+  if ((rc = ensure_pi_buffers(c)) != DPO_OK) return rc;
   hipStream_t s = S(stream);
   dpo_stats local;
   std::memset(&local, 0, sizeof(local));
   const double t0 = now_s();
-  HIP_TRY(c, hipMemcpyAsync(c->work, V, sizeof(float) * (size_t)c->N, hipMemcpyDeviceToDevice, s));
+  // Three value buffers: the greedy step writes G; the evaluation sweeps of
+  // the step alternate between the other two and are queued before the host
+  // reads the greedy residual (which travels back through pinned memory), so
+  // the round trip overlaps them.  If the step meets the stop rule, G holds
+  // T V and the sweeps queued after it are discarded.
+  float* buf[3] = {V, c->work, c->work2};
+  HIP_TRY(c, hipMemcpyAsync(buf[1], V, sizeof(float) * (size_t)c->N, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(c, hipMemcpyAsync(buf[2], V, sizeof(float) * (size_t)c->N, hipMemcpyDeviceToDevice, s));
   float* cur = V;
-  float* nxt = c->work;
   int code = DPO_ENOCONV;
   double h[kPartial] = {0, 0, 0, 0, 0};
   int64_t it = 0, evals = 0, fallback = 0;
@@ -647,15 +675,31 @@ int dpo_solve_pi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, doubl
   double seeded_best = INFINITY, full_best = INFINITY;
   int seeded_stall = 0, full_stall = 0;
   while (it < max_outer) {
+    float* G = cur == buf[0] ? buf[1] : buf[0];
     // greedy step: policy improvement together with T V
     const bool use_seed = seeded && it > 0 && !verify;
-    if (use_seed) rc = sweep_seeded(c, cur, nxt, pol_angle, pol_thr, seed_angle, s, true, true);
-    else rc = sweep_full(c, cur, nxt, pol_angle, pol_thr, s, true, it > 0);
+    if (use_seed) rc = sweep_seeded(c, cur, G, pol_angle, pol_thr, seed_angle, s, true, true);
+    else rc = sweep_full(c, cur, G, pol_angle, pol_thr, s, true, it > 0);
     if (rc != DPO_OK) return rc;
     it++;
-    std::swap(cur, nxt);
     if ((rc = finish_resid(c, c->resid, s)) != DPO_OK) return rc;
-    if ((rc = read_resid(c, h, s)) != DPO_OK) return rc;
+    HIP_TRY(c, hipMemcpyAsync(c->resid_host, c->resid, sizeof(double) * kPartial, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipEventRecord(c->resid_ready, s));
+    // evaluation sweeps of this step, queued ahead of the stop decision
+    float* src = G;
+    for (int e = 0; e < eval_sweeps; e++) {
+      float* dst = nullptr;
+      for (float* b : buf)
+        if (b != G && b != src) {
+          dst = b;
+          break;
+        }
+      if ((rc = sweep_eval_desc(c, src, dst, s)) != DPO_OK) return rc;
+      src = dst;
+    }
+    HIP_TRY(c, hipEventSynchronize(c->resid_ready));
+    std::memcpy(h, c->resid_host, sizeof(h));
+    cur = G;  // T V, the result if this step stops the solve
     if (use_seed) {
       fallback += (int64_t)h[4];
       evals += c->n_free * (1 + c->search.n_local) + (int64_t)h[4] * evals_per_full_search(c);
@@ -697,10 +741,7 @@ int dpo_solve_pi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, doubl
         break;
       }
     }
-    for (int e = 0; e < eval_sweeps; e++) {
-      if ((rc = sweep_eval_desc(c, cur, nxt, s)) != DPO_OK) return rc;
-      std::swap(cur, nxt);
-    }
+    cur = src;
     local.eval_sweeps += eval_sweeps;
     evals += (int64_t)eval_sweeps * c->n_free;
   }

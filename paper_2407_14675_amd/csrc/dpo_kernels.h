@@ -110,7 +110,7 @@ hipError_t launch_sweep_table(const SweepArgs& a, hipStream_t s);
 hipError_t launch_sweep_scan_golden(const SweepArgs& a, hipStream_t s);
 hipError_t launch_sweep_seeded(const SweepArgs& a, hipStream_t s);
 hipError_t launch_policy_eval(const SweepArgs& a, bool want_resid, hipStream_t s);
-hipError_t launch_policy_eval_desc(const SweepArgs& a, hipStream_t s);
+hipError_t launch_policy_eval_desc(const SweepArgs& a, bool streamed, hipStream_t s);
 hipError_t launch_sweep_fast(const SweepArgs& a, int mode, int block, hipStream_t s);
 hipError_t launch_resid_final(const double* partial, int nblocks, double* out, hipStream_t s);
 hipError_t launch_value_at(const float* V, const Grid& G, double M, const double x[4], double* out,

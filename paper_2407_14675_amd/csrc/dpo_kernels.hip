@@ -201,19 +201,35 @@ __global__ __launch_bounds__(kBlock) void k_policy_eval(SweepArgs a) {
 // thread handles kDescNpt of them so their loads are in flight together.
 constexpr int kDescNpt = 2;
 
+// kNt: bit 0 = non-temporal loads of the per-node stream (coordinates and
+// descriptor), bit 1 = non-temporal store of the value.  Used when a sweep's
+// data is larger than the last-level cache: the streamed bytes then no
+// longer evict the value rows that neighbouring nodes' gathers reuse.  When
+// everything fits, the temporal form lets the descriptors (reused by the 20
+// sweeps of a policy) and the values stay cached.
+template <int kNt>
 __global__ __launch_bounds__(kBlock) void k_policy_eval_desc(SweepArgs a) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int t0 = tile * (kDescNpt * kBlock) + threadIdx.x;
   uint32_t packed[kDescNpt];
   int code[kDescNpt];
   float2 w[kDescNpt];
+  typedef float nt_f2 __attribute__((ext_vector_type(2)));
 #pragma unroll
   for (int k = 0; k < kDescNpt; k++) {
     const int t = t0 + k * kBlock;
     if (t < a.n_free) {
-      packed[k] = a.free_node[t];
-      code[k] = a.desc_code_in[t];
-      w[k] = a.desc_w_in[t];
+      // streamed once per sweep: non-temporal, so they do not evict the value rows the gathers reuse
+      if (kNt & 1) {
+        packed[k] = __builtin_nontemporal_load(a.free_node + t);
+        code[k] = __builtin_nontemporal_load(a.desc_code_in + t);
+        const nt_f2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f2*>(a.desc_w_in) + t);
+        w[k] = make_float2(v.x, v.y);
+      } else {
+        packed[k] = a.free_node[t];
+        code[k] = a.desc_code_in[t];
+        w[k] = a.desc_w_in[t];
+      }
     }
   }
 #pragma unroll
@@ -235,7 +251,9 @@ __global__ __launch_bounds__(kBlock) void k_policy_eval_desc(SweepArgs a) {
       tt[2] = w[k].y;
       I = cell_value(a.V_in + (code[k] & 0x3fffffff), a.G, tt);
     }
-    a.V_out[j] = fmaf(a.P.gamma, I, thr ? a.P.q_thr : a.P.q_coast);
+    const float out = fmaf(a.P.gamma, I, thr ? a.P.q_thr : a.P.q_coast);
+    if (kNt & 2) __builtin_nontemporal_store(out, a.V_out + j);
+    else a.V_out[j] = out;
   }
 }
 
@@ -503,8 +521,9 @@ hipError_t launch_policy_eval(const SweepArgs& a, bool want_resid, hipStream_t s
   DPO_LAUNCH(k_policy_eval<false>, blocks_for(a.n_free), kBlock, s, a);
 }
 
-hipError_t launch_policy_eval_desc(const SweepArgs& a, hipStream_t s) {
-  DPO_LAUNCH(k_policy_eval_desc, blocks_for(a.n_free, kDescNpt * kBlock), kBlock, s, a);
+hipError_t launch_policy_eval_desc(const SweepArgs& a, bool streamed, hipStream_t s) {
+  if (streamed) DPO_LAUNCH(k_policy_eval_desc<3>, blocks_for(a.n_free, kDescNpt * kBlock), kBlock, s, a);
+  DPO_LAUNCH(k_policy_eval_desc<0>, blocks_for(a.n_free, kDescNpt * kBlock), kBlock, s, a);
 }
 
 hipError_t launch_resid_final(const double* partial, int nblocks, double* out, hipStream_t s) {
