@@ -12,7 +12,7 @@ namespace dpo {
 // problem, XCD-contiguous); the problem's record holds offsets into the
 // concatenated buffers, whose bases are kernel arguments.
 template <int kMode>
-__global__ __launch_bounds__(kMaxBlock) void k_batch_sweep(BatchArgs B, int parity) {
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_batch_sweep(BatchArgs B, int parity) {
   extern __shared__ float4 dyn_lds[];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   int k = 0;

@@ -159,7 +159,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_direct(SweepArgs a) {
 // Factorised-path sweep; the workgroup size is chosen at launch (64..512)
 // and the region pairs live in dynamic LDS (4 * blockDim.x float4).
 template <int kMode>
-__global__ __launch_bounds__(kMaxBlock) void k_sweep_fast(SweepArgs a) {
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_sweep_fast(SweepArgs a) {
   extern __shared__ float4 dyn_lds[];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int t = tile * blockDim.x + threadIdx.x;

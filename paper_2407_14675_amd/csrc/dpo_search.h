@@ -65,65 +65,53 @@ template <class QF>
 __device__ inline void golden(const QF& qf, float s0, float c0, float half, int steps, const float* __restrict__ rot,
                               GoldenState& g) {
   const float rho = 0.6180339887498949f;
-  float lo = -half, hi = half;
-  float x1 = hi - rho * (hi - lo), x2 = lo + rho * (hi - lo);
   const float sp = rot[0], cp = rot[1];
-  float s1 = fmaf(s0, cp, -c0 * sp), c1 = fmaf(c0, cp, s0 * sp);  // u0 - half*rho^3
-  float s2 = fmaf(s0, cp, c0 * sp), c2 = fmaf(c0, cp, -s0 * sp);  // u0 + half*rho^3
-  float f1 = qf(s1, c1);
-  if (f1 < g.best_q) {
-    g.best_q = f1;
-    g.best_d = x1;
-    g.best_s = s1;
-    g.best_c = c1;
+  // the two interior points u0 -+ half*rho^3 (rho^3 = 2 rho - 1)
+  const float x0 = half * 0.2360679774997897f;
+  float xN = -x0, sN = fmaf(s0, cp, -c0 * sp), cN = fmaf(c0, cp, s0 * sp);  // left point
+  float xK = x0, sK = fmaf(s0, cp, c0 * sp), cK = fmaf(c0, cp, -s0 * sp);   // right point
+  float fN = qf(sN, cN);
+  if (fN < g.best_q) {
+    g.best_q = fN;
+    g.best_d = xN;
+    g.best_s = sN;
+    g.best_c = cN;
   }
-  float f2 = qf(s2, c2);
-  if (f2 < g.best_q) {
-    g.best_q = f2;
-    g.best_d = x2;
-    g.best_s = s2;
-    g.best_c = c2;
+  float fK = qf(sK, cK);
+  if (fK < g.best_q) {
+    g.best_q = fK;
+    g.best_d = xK;
+    g.best_s = sK;
+    g.best_c = cK;
   }
+  // K: the interior point kept from the previous step; N: the point just
+  // evaluated, on the left of K when nl.  Each step keeps the lower interior
+  // point and places the new one symmetrically, at distance 2*half*rho^(k+4)
+  // from it, by rotating (sin, cos) of the kept point.
+  bool nl = true;
+  float delta = 2.0f * half * 0.1458980337503155f;  // 2*half*rho^4
   for (int it = 0; it < steps; it++) {
     const float sd = rot[2 + 2 * it], cd = rot[3 + 2 * it];
-    const bool left = f1 < f2;  // keep [lo, x2]; new point left of x1
-    float xn, sn, cn;
-    if (left) {
-      hi = x2;
-      x2 = x1;
-      f2 = f1;
-      xn = hi - rho * (hi - lo);
-      sn = fmaf(s1, cd, -c1 * sd);
-      cn = fmaf(c1, cd, s1 * sd);
-      s2 = s1;
-      c2 = c1;
-    } else {
-      lo = x1;
-      x1 = x2;
-      f1 = f2;
-      xn = lo + rho * (hi - lo);
-      sn = fmaf(s2, cd, c2 * sd);
-      cn = fmaf(c2, cd, -s2 * sd);
-      s1 = s2;
-      c1 = c2;
-    }
-    const float fn = qf(sn, cn);
-    if (left) {
-      x1 = xn;
-      s1 = sn;
-      c1 = cn;
-      f1 = fn;
-    } else {
-      x2 = xn;
-      s2 = sn;
-      c2 = cn;
-      f2 = fn;
-    }
-    if (fn < g.best_q) {
-      g.best_q = fn;
-      g.best_d = xn;
-      g.best_s = sn;
-      g.best_c = cn;
+    const float f_left = nl ? fN : fK, f_right = nl ? fK : fN;
+    const bool left = f_left < f_right;  // the left point is the lower one
+    const bool keepN = left == nl;
+    const float xk = keepN ? xN : xK, sk = keepN ? sN : sK, ck = keepN ? cN : cK, fk = keepN ? fN : fK;
+    const float sdd = left ? -sd : sd;
+    sN = fmaf(sk, cd, ck * sdd);
+    cN = fmaf(ck, cd, -sk * sdd);
+    xN = left ? xk - delta : xk + delta;
+    delta *= rho;
+    xK = xk;
+    sK = sk;
+    cK = ck;
+    fK = fk;
+    nl = left;
+    fN = qf(sN, cN);
+    if (fN < g.best_q) {
+      g.best_q = fN;
+      g.best_d = xN;
+      g.best_s = sN;
+      g.best_c = cN;
     }
   }
 }
@@ -133,6 +121,7 @@ template <class QF>
 __device__ inline void scan_table(const QF& qf, const SweepArgs& a, float& bq, int& bk) {
   bq = INFINITY;
   bk = 0;
+#pragma unroll 8
   for (int k = 0; k < a.n_ang; k++) {
     const float q = qf(a.tab_sin[k], a.tab_cos[k]);
     if (q < bq) {
@@ -304,14 +293,14 @@ struct FastNode {
   float g1, g2;  // thrust displacement per unit sin u (v_r) and cos u (v_t), cells
   float d1, d2;  // coast displacements along v_r and v_t
   float bv, bt;  // region 1 <=> offset >= threshold (the same float test as foot_cell)
-  const float4* coef;  // this thread's first region pair in LDS
-  int cs;              // LDS stride between region pairs (the workgroup size)
+  const char* coef;  // this thread's first region pair in LDS
+  int offv, offt;    // byte offsets of the region pairs with v_r region 1 / v_t region 1
 };
 
 __device__ inline float fast_q(const FastNode& F, float sn, float cs) {
   const float ov = fmaf(F.g1, sn, F.d1), ot = fmaf(F.g2, cs, F.d2);
-  const int idx = (ov >= F.bv ? 2 * F.cs : 0) + (ot >= F.bt ? F.cs : 0);
-  const float4 c = F.coef[idx];
+  const int off = (ov >= F.bv ? F.offv : 0) + (ot >= F.bt ? F.offt : 0);
+  const float4 c = *reinterpret_cast<const float4*>(F.coef + off);
   const float dv = ov - F.d1, dt = ot - F.d2;
   return fmaf(fmaf(c.w, dt, c.y), dv, fmaf(c.z, dt, c.x));
 }
@@ -331,8 +320,9 @@ __device__ inline float fast_setup(const SweepArgs& a, const NodeTerms& T, float
   F.g2 = T.g2;
   F.d1 = T.drift[1];
   F.d2 = T.drift[2];
-  F.cs = blockDim.x;
-  F.coef = lds + threadIdx.x;
+  F.offv = 2 * (int)blockDim.x * (int)sizeof(float4);
+  F.offt = (int)blockDim.x * (int)sizeof(float4);
+  F.coef = reinterpret_cast<const char*>(lds + threadIdx.x);
   // r cell, shared by every control
   int br = 0, bm = 0;
   float tr = 0.0f, tm = 0.0f;
