@@ -26,11 +26,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published peaks and the derived VALU peak (256 CUs x 4 SIMD x 16
-# lanes x 2.4 GHz = 3.93e13 lane-instructions/s; FMA counted as 2 flops gives
-# the 78.6 TFLOP/s non-packed FP32 rate).
+# MI355X published peaks.  FP32 vector: 256 CUs x 2.4 GHz x 256 flops per
+# clock = 157.3 TFLOP/s, i.e. one wave64 FP32 instruction per SIMD every two
+# clocks (1.23e12 wave instructions/s over the chip); the sweep kernels use no
+# packed FP32 instructions.
 HBM_PEAK_GBS = 8000.0
-VALU_PEAK_TFLOPS = 78.6
+VALU_PEAK_TFLOPS = 157.3
 
 # Algorithmic HBM bytes per active node of one frozen-policy evaluation sweep:
 # packed node coordinates (4), foot cell code (4), foot weights in v_r and v_t

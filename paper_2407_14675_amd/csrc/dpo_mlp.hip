@@ -171,9 +171,17 @@ __global__ __launch_bounds__(256) void k_mlp_grad(MlpArgs a) {
   __shared__ __attribute__((aligned(16))) uint16_t h1t[kHid * kLdT];
   __shared__ __attribute__((aligned(16))) uint16_t d2t[kHid * kLdT];
   __shared__ float red[4][kRed];
+  __shared__ __attribute__((aligned(16))) uint16_t w2s[kHid * kLdA];   // W2 [out][in]
+  __shared__ __attribute__((aligned(16))) uint16_t w2ts[kHid * kLdA];  // W2 [in][out]
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
   const int s0 = blockIdx.x * kMlpTile;
   float* part = a.partial + (size_t)blockIdx.x * kPStride;
+  // both bf16 copies of W2 staged once: 128 rows of 16 chunks of 8 bf16 each
+  for (int c = tid; c < kHid * 16; c += 256) {
+    const int row = c >> 4, col = (c & 15) * 8;
+    *reinterpret_cast<uint4*>(w2s + row * kLdA + col) = *reinterpret_cast<const uint4*>(a.w2 + row * kHid + col);
+    *reinterpret_cast<uint4*>(w2ts + row * kLdA + col) = *reinterpret_cast<const uint4*>(a.w2t + row * kHid + col);
+  }
   if (tid < kMlpTile) {
     float4 xv = make_float4(0.0f, 0.0f, 0.0f, 0.0f), tv = xv;
     if (s0 + tid < a.n) {
@@ -191,7 +199,7 @@ __global__ __launch_bounds__(256) void k_mlp_grad(MlpArgs a) {
   // ---- forward of the wave's 16 samples
   f32x4 z2[8], h2[8];
   float y[4][3];
-  wave_gemm<kHid>(act + 16 * w * kLdA, kLdA, a.w2, kHid, z2);
+  wave_gemm<kHid>(act + 16 * w * kLdA, kLdA, w2s, kLdA, z2);
   layer3(a.theta, z2, h2, y);
 
   // ---- loss and its derivative with respect to (c, s, logit)
@@ -290,7 +298,7 @@ __global__ __launch_bounds__(256) void k_mlp_grad(MlpArgs a) {
   // ---- back through W2: dh1 = d2 W2, then delta of layer 1 and the W1, b1 sums
   {
     f32x4 dh[8];
-    wave_gemm<kHid>(act + 16 * w * kLdA, kLdA, a.w2t, kHid, dh);
+    wave_gemm<kHid>(act + 16 * w * kLdA, kLdA, w2ts, kLdA, dh);
     float q[8 * 5];
 #pragma unroll
     for (int nt = 0; nt < 8; nt++) {
@@ -339,8 +347,17 @@ __global__ __launch_bounds__(256) void k_mlp_grad(MlpArgs a) {
 __global__ __launch_bounds__(256) void k_mlp_reduce(ReduceArgs a) {
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (p > kNParam) return;
+  // tile sums in a fixed order; eight loads in flight per thread
   float s = 0.0f;
-  for (int t = 0; t < a.tiles; t++) s += a.partial[(size_t)t * kPStride + p];
+  int t = 0;
+  for (; t + 8 <= a.tiles; t += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) v[u] = a.partial[(size_t)(t + u) * kPStride + p];
+#pragma unroll
+    for (int u = 0; u < 8; u++) s += v[u];
+  }
+  for (; t < a.tiles; t++) s += a.partial[(size_t)t * kPStride + p];
   if (p == kNParam) {
     if (a.loss) *a.loss = s * a.inv_n;
     return;
