@@ -49,6 +49,8 @@ struct dpo_ctx {
   float* work = nullptr;    // second value buffer of the solvers
   float* work2 = nullptr;   // third value buffer (policy iteration keeps the greedy output while evaluating ahead)
   double* resid_host = nullptr;  // pinned copy of the residual for the overlapped read-back
+  int* fb_list = nullptr;         // seeded sweeps: nodes whose full search is deferred to a second pass
+  int* fb_count = nullptr;
   hipEvent_t resid_ready = nullptr;
   int* desc_code = nullptr;  // foot descriptors of the greedy step's controls (policy iteration)
   float2* desc_w = nullptr;
@@ -125,6 +127,10 @@ int validate_search(dpo_ctx* c, const dpo_search* s) {
 hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 constexpr int kRot = 2 + 2 * 64;
+
+// Workgroups of the second (fallback) pass of a seeded sweep; the residual
+// partial buffer has room for them after the first pass's.
+constexpr int kFallbackBlocks = 2048;
 
 // MI355X Infinity Cache (last-level cache shared by the XCDs).
 constexpr double kLastLevelCacheBytes = 256.0 * 1024 * 1024;
@@ -319,8 +325,31 @@ int sweep_seeded(dpo_ctx* c, const float* Vin, float* Vout, float* ang, uint8_t*
     c->desc_valid = true;
   }
   if (a.n_free == 0) return DPO_OK;
-  hipError_t e = use_fast(c) ? launch_sweep_fast(a, 2, c->block, s) : launch_sweep_seeded(a, s);
-  c->last_blocks = blocks_for(c->n_free, use_fast(c) ? c->block : kBlock);
+  if (!use_fast(c)) {
+    hipError_t e = launch_sweep_seeded(a, s);
+    c->last_blocks = blocks_for(c->n_free, kBlock);
+    if (e != hipSuccess) return hip_fail(c, e, "seeded sweep launch");
+    return DPO_OK;
+  }
+  // factorised path: the local searches first, then the full search at the
+  // nodes that fall back, as a second launch over the list the first built
+  if (!c->fb_list) {
+    if (hipMalloc(&c->fb_list, sizeof(int) * (size_t)c->n_free) != hipSuccess ||
+        hipMalloc(&c->fb_count, sizeof(int)) != hipSuccess)
+      return fail(c, DPO_ENOMEM, "fallback list alloc");
+  }
+  a.fb_list = c->fb_list;
+  a.fb_count = c->fb_count;
+  const int nb1 = blocks_for(c->n_free, c->block);
+  const int nb2 = std::min(kFallbackBlocks, nb1);
+  hipError_t e = launch_zero_count(c->fb_count, s);
+  if (e == hipSuccess) e = launch_sweep_fast(a, 2, c->block, s);
+  if (e == hipSuccess) {
+    SweepArgs b = a;
+    b.partial = c->partial + (size_t)kPartial * nb1;
+    e = launch_sweep_fallback(b, c->block, nb2, s);
+  }
+  c->last_blocks = nb1 + nb2;
   if (e != hipSuccess) return hip_fail(c, e, "seeded sweep launch");
   return DPO_OK;
 }
@@ -457,7 +486,7 @@ int dpo_create(const dpo_grid* grid, const dpo_problem* prob, const dpo_search* 
     return cleanup(DPO_EHIP);
   }
   c->n_free = total;
-  c->partial_blocks = blocks_for(total > 0 ? total : 1, 64);
+  c->partial_blocks = blocks_for(total > 0 ? total : 1, 64) + kFallbackBlocks;
   if (hipMalloc(&c->partial, sizeof(double) * kPartial * c->partial_blocks) != hipSuccess) {
     c->err = "device allocation failed in dpo_create";
     return cleanup(DPO_ENOMEM);
@@ -479,6 +508,8 @@ void dpo_destroy(dpo_ctx* c) {
   if (c->resid) hipFree(c->resid);
   if (c->work) hipFree(c->work);
   if (c->work2) hipFree(c->work2);
+  if (c->fb_list) hipFree(c->fb_list);
+  if (c->fb_count) hipFree(c->fb_count);
   if (c->resid_host) hipHostFree(c->resid_host);
   if (c->resid_ready) hipEventDestroy(c->resid_ready);
   if (c->desc_code) hipFree(c->desc_code);

@@ -45,10 +45,12 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(8))) 
   a.seed = nullptr;
   a.pol_ang_in = nullptr;
   a.pol_thr_in = nullptr;
+  a.fb_list = nullptr;
+  a.fb_count = nullptr;
   const int t = (tile - B.tile_begin[k]) * blockDim.x + threadIdx.x;
   double rel = 0, sum = 0, mabs = 0, bad = 0;
-  int fell_back = 0;
-  if (t < a.n_free) fast_node<kMode>(a, t, dyn_lds, rel, sum, mabs, bad, fell_back);
+  int fell_back = 0, deferred = 0;
+  if (t < a.n_free) fast_node<kMode>(a, t, dyn_lds, rel, sum, mabs, bad, fell_back, deferred);
   block_residual(rel, sum, mabs, bad, (double)fell_back, B.partial, tile);
 }
 

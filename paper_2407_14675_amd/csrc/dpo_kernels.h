@@ -20,6 +20,8 @@ struct SweepArgs {
   const float* pol_ang_in;    // frozen policy (evaluation sweep); greedy sweeps: incumbent, nullable
   const uint8_t* pol_thr_in;  // frozen policy (evaluation sweep); greedy sweeps: incumbent, nullable
   const float* seed;          // seeded search
+  int* fb_list;               // seeded search on the factorised path: nodes whose full search is deferred, nullable
+  int* fb_count;              // their count (zeroed before the sweep)
   const uint32_t* free_node;  // packed coordinates (8 bits per axis, r lowest) of the free nodes
   int n_free;
   // per-axis / per-plane tables (FP64 1/r; thrust displacement per unit sin/cos per mass plane)
@@ -111,6 +113,8 @@ hipError_t launch_sweep_scan_golden(const SweepArgs& a, hipStream_t s);
 hipError_t launch_sweep_seeded(const SweepArgs& a, hipStream_t s);
 hipError_t launch_policy_eval(const SweepArgs& a, bool want_resid, hipStream_t s);
 hipError_t launch_policy_eval_desc(const SweepArgs& a, bool streamed, hipStream_t s);
+hipError_t launch_zero_count(int* count, hipStream_t s);
+hipError_t launch_sweep_fallback(const SweepArgs& a, int block, int blocks, hipStream_t s);
 hipError_t launch_sweep_fast(const SweepArgs& a, int mode, int block, hipStream_t s);
 hipError_t launch_resid_final(const double* partial, int nblocks, double* out, hipStream_t s);
 hipError_t launch_value_at(const float* V, const Grid& G, double M, const double x[4], double* out,

@@ -164,10 +164,37 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(8))) 
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int t = tile * blockDim.x + threadIdx.x;
   double rel = 0, sum = 0, mabs = 0, bad = 0;
-  int fell_back = 0;
-  if (t < a.n_free) fast_node<kMode>(a, t, dyn_lds, rel, sum, mabs, bad, fell_back);
+  int fell_back = 0, deferred = 0;
+  if (t < a.n_free) fast_node<kMode>(a, t, dyn_lds, rel, sum, mabs, bad, fell_back, deferred);
+  if (kMode == 2 && a.fb_list) {
+    // append the wave's deferred nodes with one atomic per wave
+    const unsigned long long bal = __ballot(deferred);
+    if (bal) {
+      const int lane = threadIdx.x & 63;
+      int base = 0;
+      if (lane == 0) base = atomicAdd(a.fb_count, __popcll(bal));
+      base = __shfl(base, 0, 64);
+      if (deferred) a.fb_list[base + __popcll(bal & ((1ull << lane) - 1ull))] = t;
+    }
+  }
   block_residual(rel, sum, mabs, bad, (double)fell_back, a.partial, blockIdx.x);
 }
+
+// Second pass of the seeded sweep: the full search at the nodes the first
+// pass listed, so that a wave's full searches run together instead of
+// stalling the lanes whose local search sufficed.  Persistent grid over the
+// list; the residual partials of this pass follow those of the first.
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_sweep_fallback(SweepArgs a) {
+  extern __shared__ float4 dyn_lds[];
+  const int count = *a.fb_count;
+  double rel = 0, sum = 0, mabs = 0, bad = 0;
+  int unused = 0, unused2 = 0;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < count; k += gridDim.x * blockDim.x)
+    fast_node<1>(a, a.fb_list[k], dyn_lds, rel, sum, mabs, bad, unused, unused2);
+  block_residual(rel, sum, mabs, bad, 0.0, a.partial, blockIdx.x);
+}
+
+__global__ void k_zero_count(int* count) { *count = 0; }
 
 // Frozen-policy sweep (eq:p_eval applied once).  The residual reduction is
 // only compiled in when a caller asks for it; the policy-iteration loop does
@@ -513,6 +540,14 @@ hipError_t launch_sweep_fast(const SweepArgs& a, int mode, int block, hipStream_
   if (mode == 0) hipLaunchKernelGGL(k_sweep_fast<0>, dim3(nb), dim3(block), lds, s, a);
   else if (mode == 1) hipLaunchKernelGGL(k_sweep_fast<1>, dim3(nb), dim3(block), lds, s, a);
   else hipLaunchKernelGGL(k_sweep_fast<2>, dim3(nb), dim3(block), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_count(int* count, hipStream_t s) { DPO_LAUNCH(k_zero_count, 1, 1, s, count); }
+
+hipError_t launch_sweep_fallback(const SweepArgs& a, int block, int blocks, hipStream_t s) {
+  const size_t lds = 4 * (size_t)block * sizeof(float4);
+  hipLaunchKernelGGL(k_sweep_fallback, dim3(blocks), dim3(block), lds, s, a);
   return hipGetLastError();
 }
 

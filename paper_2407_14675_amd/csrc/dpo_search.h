@@ -169,11 +169,11 @@ __device__ inline void table_search(const QF& qf, const SweepArgs& a, float qc, 
 }
 
 // Seeded local search: the seed angle, then a golden section with n_local - 3
-// steps on [seed - w, seed + w] (n_local thrust evaluations), then coast.  A
-// node whose result differs from its current value by more than
-// fallback_tol * max(1, |V|) repeats the full search.
+// steps on [seed - w, seed + w] (n_local thrust evaluations), then coast.
+// Returns true when the result differs from the node's current value by more
+// than fallback_tol * max(1, |V|): the node must repeat the full search.
 template <class QF>
-__device__ inline int seeded_search(const QF& qf, const SweepArgs& a, float seed, float qc, float vin, Choice& ch) {
+__device__ inline bool seeded_local(const QF& qf, const SweepArgs& a, float seed, float qc, float vin, Choice& ch) {
   float s0, c0;
   sincosf(seed, &s0, &c0);
   GoldenState g{qf(s0, c0), 0.0f, s0, c0};
@@ -183,7 +183,16 @@ __device__ inline int seeded_search(const QF& qf, const SweepArgs& a, float seed
   ch.ang = wrap_pi(seed + g.best_d);
   ch.sn = g.best_s;
   ch.cs = g.best_c;
-  if (fabsf(ch.v - vin) > a.fallback_tol * fmaxf(1.0f, fabsf(vin))) {
+  return fabsf(ch.v - vin) > a.fallback_tol * fmaxf(1.0f, fabsf(vin));
+}
+
+// At most this many fallback lanes of a wave are deferred to the second pass.
+constexpr int kDeferLanes = 16;
+
+// Seeded search with the fallback done in place.
+template <class QF>
+__device__ inline int seeded_search(const QF& qf, const SweepArgs& a, float seed, float qc, float vin, Choice& ch) {
+  if (seeded_local(qf, a, seed, qc, vin, ch)) {
     full_search(qf, a, qc, ch);
     return 1;
   }
@@ -401,7 +410,7 @@ __device__ inline float fast_setup(const SweepArgs& a, const NodeTerms& T, float
 // residual contributions.  kMode: 0 tabulated, 1 scan + golden, 2 seeded.
 template <int kMode>
 __device__ inline void fast_node(const SweepArgs& a, int t, float4* lds, double& rel, double& sum, double& mabs,
-                                 double& bad, int& fell_back) {
+                                 double& bad, int& fell_back, int& deferred) {
   NodeTerms T;
   const int j = node_terms_tab(a, a.free_node[t], T);
   FastNode F;
@@ -411,7 +420,21 @@ __device__ inline void fast_node(const SweepArgs& a, int t, float4* lds, double&
   Choice ch;
   if (kMode == 0) table_search(qf, a, qc, ch);
   else if (kMode == 1) full_search(qf, a, qc, ch);
-  else fell_back = seeded_search(qf, a, a.seed[j], qc, vin, ch);
+  else {
+    const bool need = seeded_local(qf, a, a.seed[j], qc, vin, ch);
+    // A wave where only a few lanes fall back would leave the others idle
+    // through a full search: those lanes are listed for a second pass.
+    // Where many lanes fall back, the wave does the full search in place.
+    const bool few = __popcll(__ballot(need)) <= kDeferLanes;
+    if (need) {
+      fell_back = 1;
+      if (a.fb_list && few) {
+        deferred = 1;
+        return;
+      }
+      full_search(qf, a, qc, ch);
+    }
+  }
   keep_incumbent(qf, a, j, qc, ch);
   a.V_out[j] = ch.v;
   if (a.pol_ang) a.pol_ang[j] = ch.ang;
