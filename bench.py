@@ -45,7 +45,7 @@ GATHER_BYTES_PER_EVAL = 64
 
 # HBM traffic of the evaluation sweep measured with rocprofv3 counters, with
 # the hash of the kernel sources it was measured on.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_policy_eval_desc_cfg1_48x4_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_policy_eval_desc_pi_48x4_masked_traffic.json")
 KERNEL_SOURCES = ["dpo_kernels.hip", "dpo_device.h", "dpo_kernels.h", "dpo_search.h"]
 
 
@@ -117,7 +117,7 @@ def bench_batched(max_sweeps=20000, tol=1e-6):
 
     from paper_2407_14675_amd import autotune, dpo, inputs
 
-    probs = inputs.config3_problems()
+    probs = inputs.batch_problems()
     b = dpo.Batch(probs)
     t0 = time.perf_counter()
     block, S = autotune.tune(b, replays=2)
@@ -172,7 +172,7 @@ def bench_large(accels=(1e-3,), with_seeded=True):
     out = {"grid": [96, 96, 96, 64], "problems": []}
     net = None
     for accel in accels:
-        p = inputs.config2(accel=accel)
+        p = inputs.large_problem(accel=accel)
         ctx = dpo.Context(p)
         free = ctx.kind() == 0
         V = ctx.init_value()
@@ -273,8 +273,8 @@ def main():
                     help="first run one plain 512 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding along the "
-              f"mass axis is a design note, not part of this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); sharding the grid along the mass "
+              f"axis over several GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -294,11 +294,11 @@ def main():
 
     # ---- reduced grid from the 12^4 pre-solve (setup, not timed)
     t_setup = time.perf_counter()
-    c0 = dpo.Context(inputs.CONFIG0)
+    c0 = dpo.Context(inputs.VI12)
     Vc = c0.init_value()
     a0, t0_ = c0.empty_policy()
     c0.solve_vi(Vc, a0, t0_, tol_rel=1e-7, max_sweeps=20000, check_every=16)
-    p1 = inputs.CONFIG1
+    p1 = inputs.PI48
     mask = c0.mask_from_coarse(Vc, p1, inputs.MASK_THRESHOLD_FRAC * p1["M"], inputs.MASK_DILATE)
     ctx = dpo.Context(p1, mask=mask)
     ctx.set_kernel_path(args.path)
@@ -309,7 +309,7 @@ def main():
 
     V = ctx.init_value()
     ang, thr = ctx.empty_policy()
-    E = inputs.CONFIG1_EVAL_SWEEPS
+    E = inputs.EVAL_SWEEPS
 
     # ---- warmup
     if args.warmup > 0:
@@ -409,7 +409,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "cfg1: policy iteration, 48^4 grid, reachability-masked active set, scan 64 + golden 12, "
+            "workload": "policy iteration, 48^4 grid, reachability-masked active set, scan 64 + golden 12, "
                         "20 evaluation sweeps per update",
             "grid": list(p1["n"]),
             "active_free_nodes": int(n_free),

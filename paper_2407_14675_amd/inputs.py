@@ -89,12 +89,12 @@ def eikonal_problem(n_side=17, *, half=1.0, speed=1.0, n_angles=16, M=1e3, lam=0
 SCAN_GOLDEN = dict(mode="scan_golden", n_scan=64, n_golden=12)
 
 # Plain value iteration, discrete table of 16 angles plus coast, 12^4 grid.
-CONFIG0 = orbit_problem((12, 12, 12, 12), name="cfg0_vi_12^4")
-CONFIG0_TOL_ABS = 1e-8
+VI12 = orbit_problem((12, 12, 12, 12), name="vi_12^4")
+VI12_TOL_ABS = 1e-8
 
 # Modified policy iteration on 48^4 with the reachability-masked active set.
-CONFIG1 = orbit_problem((48, 48, 48, 48), search=SCAN_GOLDEN, name="cfg1_pi_48^4_masked")
-CONFIG1_EVAL_SWEEPS = 20
+PI48 = orbit_problem((48, 48, 48, 48), search=SCAN_GOLDEN, name="pi_48^4_masked")
+EVAL_SWEEPS = 20
 # Reduced grid of the 48^4 workload: a fine node is active where the 12^4
 # value, interpolated at the node, is below MASK_THRESHOLD_FRAC * M (the
 # target is reached with positive weight), dilated by MASK_DILATE cells.
@@ -102,12 +102,12 @@ MASK_THRESHOLD_FRAC = 0.98
 MASK_DILATE = (1, 1, 1, 1)
 
 # Large single problem, 96 x 96 x 96 x 64, dt = 0.02, cost 1 + 0.1*throttle.
-def config2(accel=1e-3, n=(96, 96, 96, 64)):
+def large_problem(accel=1e-3, n=(96, 96, 96, 64)):
     return orbit_problem(n, accel=accel, dt=0.02, w_fuel=0.1, search=SCAN_GOLDEN,
-                         name=f"cfg2_{'x'.join(map(str, n))}_a{accel:g}")
+                         name=f"orbit_{'x'.join(map(str, n))}_a{accel:g}")
 
 
-def config3_draws(n_prob=16, seed=3):
+def batch_draws(n_prob=16, seed=3):
     """Sixteen transfer problems: target radius, thrust level and grid side.
 
     Problem 0 is forced to the smallest side (24) and the last to the largest (64).
@@ -122,12 +122,12 @@ def config3_draws(n_prob=16, seed=3):
             for i in range(n_prob)]
 
 
-def config3_problems(n_prob=16, seed=3, side_scale=1.0):
+def batch_problems(n_prob=16, seed=3, side_scale=1.0):
     out = []
-    for i, d in enumerate(config3_draws(n_prob, seed)):
+    for i, d in enumerate(batch_draws(n_prob, seed)):
         side = max(4, int(round(d["side"] * side_scale)))
         out.append(orbit_problem((side,) * 4, target_radius=d["target_radius"],
-                                 accel=d["accel"], name=f"cfg3_p{i}_{side}^4"))
+                                 accel=d["accel"], name=f"batch_p{i}_{side}^4"))
     return out
 
 

@@ -5,7 +5,7 @@ is read from the device library.  Run from the repository root:
 
     python tests/golden/make_golden.py
 
-cfg0_vi.npz   12^4 orbit problem, table of 16 angles + coast, value iteration
+vi12_table16.npz   12^4 orbit problem, table of 16 angles + coast, value iteration
               in double precision until the largest change is below 1e-8:
               V, best thrust angle, throttle, sweep count.
 """
@@ -22,14 +22,14 @@ from oracle.core import Oracle  # noqa: E402
 from paper_2407_14675_amd import inputs  # noqa: E402
 
 
-def make_cfg0():
-    o = Oracle(inputs.CONFIG0)
-    res = o.solve_vi(tol_abs=inputs.CONFIG0_TOL_ABS, max_sweeps=100000)
+def make_vi12():
+    o = Oracle(inputs.VI12)
+    res = o.solve_vi(tol_abs=inputs.VI12_TOL_ABS, max_sweeps=100000)
     assert res["converged"], res
-    np.savez_compressed(os.path.join(HERE, "cfg0_vi.npz"), V=res["V"], angle=res["angle"],
+    np.savez_compressed(os.path.join(HERE, "vi12_table16.npz"), V=res["V"], angle=res["angle"],
                         thr=res["thr"], sweeps=np.int64(res["sweeps"]))
-    print("cfg0: sweeps", res["sweeps"], "V(x0)", o.value_at(res["V"], inputs.X0))
+    print("12^4 value iteration: sweeps", res["sweeps"], "V(x0)", o.value_at(res["V"], inputs.X0))
 
 
 if __name__ == "__main__":
-    make_cfg0()
+    make_vi12()

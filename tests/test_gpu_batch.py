@@ -20,7 +20,7 @@ def dpo():
 
 def small_batch(sides):
     """Config-3 style draws (target radius, thrust level) on small grids."""
-    draws = inputs.config3_draws(len(sides), seed=3)
+    draws = inputs.batch_draws(len(sides), seed=3)
     return [inputs.orbit_problem((s,) * 4, target_radius=d["target_radius"], accel=d["accel"],
                                  name=f"batch_p{i}_{s}") for i, (d, s) in enumerate(zip(draws, sides))]
 

@@ -93,16 +93,16 @@ def test_policy_iteration_step_48x4_masked(dpo):
     """The benchmark's 48^4 workload: mask from the 12^4 pre-solve, the value
     after 10 policy-iteration steps, then one greedy and one evaluation sweep."""
     print("48^4 masked, sampled", flush=True)
-    c0 = dpo.Context(inputs.CONFIG0)
+    c0 = dpo.Context(inputs.VI12)
     Vc = c0.init_value()
     a0, t0 = c0.empty_policy()
     c0.solve_vi(Vc, a0, t0, tol_rel=1e-7, max_sweeps=20000, check_every=16)
-    p1 = inputs.CONFIG1
+    p1 = inputs.PI48
     mask = c0.mask_from_coarse(Vc, p1, inputs.MASK_THRESHOLD_FRAC * p1["M"], inputs.MASK_DILATE)
     ctx = dpo.Context(p1, mask=mask)
     V = ctx.init_value()
     ang, thr = ctx.empty_policy()
-    ctx.solve_pi(V, ang, thr, tol_rel=0.0, eval_sweeps=inputs.CONFIG1_EVAL_SWEEPS, max_outer=10)
+    ctx.solve_pi(V, ang, thr, tol_rel=0.0, eval_sweeps=inputs.EVAL_SWEEPS, max_outer=10)
     W, tg, ag, E = sweep_pair(ctx, V)
     o = Oracle(p1, mask=host(mask))
     kind = host(ctx.kind())
@@ -119,7 +119,7 @@ def test_greedy_and_eval_sweeps_96x96x96x64(dpo, accel):
     sweeps, one greedy and one evaluation sweep, 3000 sampled nodes (half of
     them where V < 0.98 M)."""
     print("96^3 x 64 sampled, a =", accel, flush=True)
-    p = inputs.config2(accel=accel)
+    p = inputs.large_problem(accel=accel)
     ctx = dpo.Context(p)
     V = ctx.init_value()
     ang, thr = ctx.empty_policy()

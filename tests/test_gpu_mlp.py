@@ -208,7 +208,7 @@ def test_nn_seeded_pi_matches_plain(dpo, accel):
     full search as fallback.  The seeded solve reaches the plain value within
     1e-4 relative; a = 5e-4 is held out of training."""
     print("nn-seeded PI, a =", accel, flush=True)
-    base = inputs.config2(accel=1e-3, n=(24, 24, 24, 16))
+    base = inputs.large_problem(accel=1e-3, n=(24, 24, 24, 16))
     cb = dpo.Context(base)
     Vb = cb.init_value()
     ab, tb = cb.empty_policy()
@@ -222,7 +222,7 @@ def test_nn_seeded_pi_matches_plain(dpo, accel):
     print("  pairs", npairs, "loss", hist[0], "->", hist[-1], flush=True)
     assert hist[-1] < hist[0]
 
-    p = inputs.config2(accel=accel, n=(24, 24, 24, 16))
+    p = inputs.large_problem(accel=accel, n=(24, 24, 24, 16))
     ctx = dpo.Context(p)
     V = ctx.init_value()
     a, t = ctx.empty_policy()

@@ -150,7 +150,7 @@ def check_search_values(o, V, free, Vg, tg, ag, Vo, margin, n_scan=64):
 # ------------------------------------------------------------- a1 kinds
 @pytest.mark.parametrize("n", [(12, 12, 12, 12), (7, 9, 5, 6)])
 def test_classification_and_compaction(dpo, n):
-    p = inputs.with_grid(inputs.CONFIG0, n)
+    p = inputs.with_grid(inputs.VI12, n)
     _say("classify", n)
     rng = np.random.default_rng(5)
     mask = (rng.random(tuple(reversed(n))) < 0.6).astype(np.uint8)
@@ -183,7 +183,7 @@ def test_probe_interp_multilinear(dpo):
 
 
 def test_probe_foot_matches_oracle(dpo):
-    p = inputs.CONFIG0
+    p = inputs.VI12
     _say("probe_foot")
     o = Oracle(p)
     nodes = inputs.random_nodes(p, 3000, seed=7)
@@ -226,7 +226,7 @@ def test_feet_on_faces_match_oracle(dpo):
 
 
 def test_probe_q_matches_oracle(dpo):
-    p = inputs.CONFIG0
+    p = inputs.VI12
     _say("probe_q")
     o = Oracle(p)
     V = inputs.random_value(p, seed=3, frac_M=0.05).astype(np.float32)
@@ -259,12 +259,12 @@ def _sweep_both(dpo, p, V, mask=None, search=None, path=0):
 @pytest.mark.parametrize("path", [1, 2])
 @pytest.mark.parametrize("which", ["random", "converged"])
 def test_table_sweep_parity(dpo, which, path):
-    p = inputs.CONFIG0
+    p = inputs.VI12
     _say("table sweep", which, "path", path)
     if which == "random":
         V = inputs.random_value(p, seed=21, frac_M=0.1)
     else:
-        V = np.load("tests/golden/cfg0_vi.npz")["V"]
+        V = np.load("tests/golden/vi12_table16.npz")["V"]
     V32 = V.astype(np.float32)
     o, ctx, Vg, ag, tg, res, Vo, ao, to, margin = _sweep_both(dpo, p, V32, path=path)
     free = o.kind == KIND_FREE
@@ -282,7 +282,7 @@ def test_table_sweep_parity(dpo, which, path):
 
 @pytest.mark.parametrize("path", [1, 2])
 def test_scan_golden_sweep_parity(dpo, path):
-    p = inputs.with_grid(inputs.CONFIG1, (10, 10, 10, 10))
+    p = inputs.with_grid(inputs.PI48, (10, 10, 10, 10))
     _say("scan-golden sweep, path", path)
     V = inputs.random_value(p, seed=23, low=0, high=30)
     # smooth it so that Q(u) is unimodal enough for the search to be meaningful
@@ -305,7 +305,7 @@ def test_scan_golden_random_masked_ragged(dpo, path):
     """Random values with M patches, a random reduced grid and a ragged grid
     whose node count is not a multiple of the workgroup size: values only
     (random fields make Q(u) multimodal, so the argmin is not unique)."""
-    p = inputs.with_grid(inputs.CONFIG1, (13, 9, 11, 7))
+    p = inputs.with_grid(inputs.PI48, (13, 9, 11, 7))
     _say("scan-golden random masked, path", path)
     rng = np.random.default_rng(29)
     mask = (rng.random((7, 11, 9, 13)) < 0.7).astype(np.uint8)
@@ -319,7 +319,7 @@ def test_scan_golden_random_masked_ragged(dpo, path):
 
 
 def test_policy_eval_parity(dpo):
-    p = inputs.CONFIG0
+    p = inputs.VI12
     _say("policy eval")
     o = Oracle(p)
     V = inputs.random_value(p, seed=31, frac_M=0.1).astype(np.float32)
@@ -340,7 +340,7 @@ def test_policy_eval_parity(dpo):
 def test_policy_eval_of_last_sweep(dpo, path):
     """The descriptor-driven evaluation sweep equals the oracle's frozen-policy
     sweep for the policy the Bellman sweep just chose."""
-    p = inputs.with_grid(inputs.CONFIG1, (10, 10, 10, 10))
+    p = inputs.with_grid(inputs.PI48, (10, 10, 10, 10))
     _say("policy eval of last sweep, path", path)
     V32 = inputs.random_value(p, seed=33, low=0, high=40).astype(np.float32)
     o = Oracle(p)
@@ -362,11 +362,11 @@ def test_policy_eval_of_last_sweep(dpo, path):
 
 
 # ------------------------------------------------------------- solvers
-def test_cfg0_value_iteration_parity(dpo):
+def test_vi12_value_iteration_parity(dpo):
     """12^4, 16 angles + coast, VI to convergence vs the stored oracle solution."""
-    p = inputs.CONFIG0
-    _say("cfg0 VI")
-    gold = np.load("tests/golden/cfg0_vi.npz")
+    p = inputs.VI12
+    _say("12^4 VI")
+    gold = np.load("tests/golden/vi12_table16.npz")
     o = Oracle(p)
     ctx = dpo.Context(p)
     V = ctx.init_value()
@@ -389,8 +389,8 @@ def test_cfg0_value_iteration_parity(dpo):
 
 def test_pi_matches_vi_on_device(dpo):
     """Value and policy iteration on the device reach the same fixed point."""
-    p = inputs.CONFIG0
-    _say("cfg0 PI vs VI")
+    p = inputs.VI12
+    _say("12^4 PI vs VI")
     ctx = dpo.Context(p)
     V1 = ctx.init_value()
     a1, t1 = ctx.empty_policy()
@@ -405,7 +405,7 @@ def test_pi_matches_vi_on_device(dpo):
 
 @pytest.fixture(scope="module")
 def small_pi_ref():
-    p = inputs.with_grid(inputs.CONFIG1, (10, 10, 10, 10))
+    p = inputs.with_grid(inputs.PI48, (10, 10, 10, 10))
     o = Oracle(p)
     ref = o.solve_pi(tol_abs=1e-8, eval_sweeps=20)
     assert ref["converged"]
@@ -452,9 +452,9 @@ def test_eikonal_on_device(dpo):
 
 # ---------------------------------------------------- a9 read-out, feedback
 def test_value_at_and_feedback_parity(dpo):
-    p = inputs.CONFIG0
+    p = inputs.VI12
     _say("value_at / feedback")
-    gold = np.load("tests/golden/cfg0_vi.npz")
+    gold = np.load("tests/golden/vi12_table16.npz")
     o = Oracle(p)
     ctx = dpo.Context(p)
     Vd = dev(gold["V"])
@@ -473,12 +473,12 @@ def test_value_at_and_feedback_parity(dpo):
 # ----------------------------------------------------------- a1 mask
 def test_mask_from_coarse_parity(dpo):
     _say("mask")
-    gold = np.load("tests/golden/cfg0_vi.npz")
+    gold = np.load("tests/golden/vi12_table16.npz")
     Vc32 = gold["V"].astype(np.float32)
-    fine = inputs.with_grid(inputs.CONFIG1, (24, 24, 24, 24))
-    thresh = inputs.MASK_THRESHOLD_FRAC * inputs.CONFIG0["M"]
-    want = mask_from_coarse(inputs.CONFIG0, Vc32.astype(np.float64), fine, inputs.MASK_DILATE, thresh)
-    ctx = dpo.Context(inputs.CONFIG0)
+    fine = inputs.with_grid(inputs.PI48, (24, 24, 24, 24))
+    thresh = inputs.MASK_THRESHOLD_FRAC * inputs.VI12["M"]
+    want = mask_from_coarse(inputs.VI12, Vc32.astype(np.float64), fine, inputs.MASK_DILATE, thresh)
+    ctx = dpo.Context(inputs.VI12)
     got = host(ctx.mask_from_coarse(dev(Vc32), fine, thresh, inputs.MASK_DILATE))
     np.testing.assert_array_equal(got, want)
 
@@ -487,7 +487,7 @@ def test_mask_from_coarse_parity(dpo):
 def test_abi_error_paths(dpo):
     _say("abi errors")
     import copy
-    p = copy.deepcopy(inputs.CONFIG0)
+    p = copy.deepcopy(inputs.VI12)
     bad = inputs.with_grid(p, (1, 12, 12, 12))
     with pytest.raises(dpo.DpoError) as e:
         dpo.Context(bad)

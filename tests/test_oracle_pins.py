@@ -153,7 +153,7 @@ def test_coast_step_conservation_defects():
         dE = dt^2 (A^2 + B^2)/2 - dt^2 v_r^2 / (r^2 (r + dt v_r)),
     A = v_t^2/r - 1/r^2, B = -v_r v_t/r (mu = 1).  A wrong sign of the
     centrifugal term leaves a first-order drift in E and fails this."""
-    p = inputs.CONFIG0
+    p = inputs.VI12
     o = Oracle(p)
     dt = p["dt"]
     for x in inputs.random_states(p, 300, seed=21):
@@ -174,7 +174,7 @@ def test_thrust_step_torque_and_power():
     adds to the coast step exactly: h gains (r + dt v_r) dt F_t (torque), E
     gains dt F_r (v_r + dt A) + dt F_t (v_t + dt B) + dt^2 |F|^2/2 (work),
     and mass drops by c dt."""
-    p = inputs.CONFIG0
+    p = inputs.VI12
     o = Oracle(p)
     dt, a, c = p["dt"], p["accel"], p["mdot"]
     rng = np.random.default_rng(22)
@@ -202,7 +202,7 @@ def test_target_node_counts(n, count):
     the centre.  By hand: at 12^4 two nodes in each of r, v_r, v_t (r: 1.04364,
     1.05273; v_r: +-0.004545; v_t: 0.97091, 0.97909) times 12 mass planes = 96;
     at 48^4, 5 x 4 x 5 x 48 = 4800."""
-    o = Oracle(inputs.with_grid(inputs.CONFIG0, (n,) * 4)) if n != 12 else Oracle(inputs.CONFIG0)
+    o = Oracle(inputs.with_grid(inputs.VI12, (n,) * 4)) if n != 12 else Oracle(inputs.VI12)
     assert int((o.kind == KIND_TARGET).sum()) == count
 
 
@@ -228,7 +228,7 @@ def test_operator_monotone_and_contraction():
 def test_vi_and_pi_reach_the_same_fixed_point():
     """Value iteration and policy iteration solve the same fixed-point problem
     (the scheme is a contraction / monotone SSP), so they agree."""
-    p = inputs.with_grid(inputs.CONFIG0, (6, 6, 6, 6))
+    p = inputs.with_grid(inputs.VI12, (6, 6, 6, 6))
     o = Oracle(p)
     vi = o.solve_vi(tol_abs=1e-11, max_sweeps=200000)
     pi20 = o.solve_pi(tol_abs=1e-11, eval_sweeps=20)
@@ -329,7 +329,7 @@ def test_seeded_search_reduces_to_scan_golden():
 def test_table_search_is_exhaustive_first_minimum():
     """Discrete table: the result is the first minimum over (coast, u_0..u_K-1),
     coast winning exact ties."""
-    p = inputs.with_grid(inputs.CONFIG0, (5, 5, 5, 5))
+    p = inputs.with_grid(inputs.VI12, (5, 5, 5, 5))
     o = Oracle(p)
     V = inputs.random_value(p, seed=41)
     Vs, ang, thr, margin = o.bellman_sweep(V)
@@ -343,7 +343,7 @@ def test_table_search_is_exhaustive_first_minimum():
 
 # ------------------------------------------------------------- residual
 def test_residual_known_values():
-    p = inputs.with_grid(inputs.CONFIG0, (4, 4, 4, 4))
+    p = inputs.with_grid(inputs.VI12, (4, 4, 4, 4))
     o = Oracle(p)
     Vo = np.full(o.shape, 10.0)
     Vn = Vo.copy()
@@ -359,7 +359,7 @@ def test_residual_known_values():
 def test_mask_dilation_box_counts():
     """A single reachable coarse node on an identical fine grid dilates to a
     (2d+1)^4 box clipped at the borders."""
-    p = inputs.with_grid(inputs.CONFIG0, (7, 7, 7, 7))
+    p = inputs.with_grid(inputs.VI12, (7, 7, 7, 7))
     Vc = np.full((7, 7, 7, 7), p["M"])
     Vc[3, 3, 3, 3] = 0.0
     m = mask_from_coarse(p, Vc, p, (1, 1, 1, 1))
@@ -375,7 +375,7 @@ def test_mask_dilation_box_counts():
 def test_float_build_precision_floor():
     """The same scheme run in single precision stays within the 1e-4 relative
     budget of the double result, so a float device path can meet it."""
-    p = inputs.with_grid(inputs.CONFIG0, (6, 6, 6, 6))
+    p = inputs.with_grid(inputs.VI12, (6, 6, 6, 6))
     o64 = Oracle(p)
     o32 = Oracle(p, precision="f32")
     v64 = o64.solve_vi(tol_abs=1e-9, max_sweeps=50000)["V"]
