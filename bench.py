@@ -109,15 +109,16 @@ def cpu_baseline(problem, seconds=12.0, seed=17):
     }
 
 
-def bench_batched(max_sweeps=20000, tol=1e-6):
+def bench_batched(max_sweeps=20000, tol=1e-6, side_scale=1.0):
     """16 transfer problems (target radius, thrust level and grid side drawn
-    with seed 3; sides 24..64) solved by value iteration, batched (one launch
-    per sweep, hipGraph replays, autotuned) and one after another."""
+    with seed 3; sides 24..64, times side_scale) solved by value iteration,
+    batched (one launch per sweep, hipGraph replays, autotuned) and one after
+    another."""
     import torch
 
     from paper_2407_14675_amd import autotune, dpo, inputs
 
-    probs = inputs.batch_problems()
+    probs = inputs.batch_problems(side_scale=side_scale)
     b = dpo.Batch(probs)
     t0 = time.perf_counter()
     block, S = autotune.tune(b, replays=2)
@@ -388,6 +389,10 @@ def main():
         log("bench: batched 16-problem solve")
         batched = bench_batched()
         log(f"bench: batched {batched}")
+        # the same draws on grids a quarter of the side (6..16): sweeps of a
+        # few microseconds, where launches and stop checks weigh
+        batched["small_grids"] = bench_batched(side_scale=0.25)
+        log(f"bench: batched small {batched['small_grids']}")
 
     cpu = None
     if not args.no_cpu:

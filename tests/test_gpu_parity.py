@@ -403,6 +403,32 @@ def test_pi_matches_vi_on_device(dpo):
     assert np.max(rel_err(host(V2), host(V1))) <= 1e-4
 
 
+def test_pi_edge_cases(dpo):
+    """Policy iteration with no evaluation sweeps is value iteration with the
+    incumbent rule and reaches the same fixed point; a solve cut by max_outer
+    reports its steps and sweeps."""
+    p = inputs.VI12
+    _say("PI edge cases")
+    ctx = dpo.Context(p)
+    V1 = ctx.init_value()
+    a1, t1 = ctx.empty_policy()
+    rc, st = ctx.solve_vi(V1, a1, t1, tol_rel=1e-6, max_sweeps=20000, check_every=1)
+    assert rc == dpo.DPO_OK
+    V2 = ctx.init_value()
+    a2, t2 = ctx.empty_policy()
+    rc, st = ctx.solve_pi(V2, a2, t2, tol_rel=1e-6, eval_sweeps=0, max_outer=20000)
+    assert rc == dpo.DPO_OK and st["eval_sweeps"] == 0
+    assert np.max(rel_err(host(V2), host(V1))) <= 1e-4
+    # a solve cut by max_outer: every greedy step counted, each followed by
+    # its evaluation sweeps, and the result finite and no larger than V0
+    V3 = ctx.init_value()
+    a3, t3 = ctx.empty_policy()
+    rc, st = ctx.solve_pi(V3, a3, t3, tol_rel=0.0, eval_sweeps=5, max_outer=3)
+    assert rc == dpo.DPO_ENOCONV and st["sweeps"] == 3 and st["eval_sweeps"] == 15
+    v3 = host(V3)
+    assert np.isfinite(v3).all() and np.all(v3 <= host(ctx.init_value()) + 3 * 6 * p["dt"])
+
+
 @pytest.fixture(scope="module")
 def small_pi_ref():
     p = inputs.with_grid(inputs.PI48, (10, 10, 10, 10))
