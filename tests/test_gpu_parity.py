@@ -569,17 +569,19 @@ def check_seeded_sweep(o, V, free, Vg, tg, ag, Vo, margin, fb, sr):
     return int(keep.sum())
 
 
-@pytest.mark.parametrize("path", [1, 2])
-def test_seeded_sweep_parity(dpo, small_pi_ref, path):
+@pytest.mark.parametrize("path,near_frac", [(1, 2 / 3), (2, 2 / 3), (2, 0.97)])
+def test_seeded_sweep_parity(dpo, small_pi_ref, path, near_frac):
     """Seeded greedy step at the converged 10^4 value function: seeds near the
-    optimal angles on two thirds of the nodes, random elsewhere (those fall
-    back to the full search)."""
+    optimal angles on a fraction of the nodes, random elsewhere (those fall
+    back to the full search).  With 3 % random seeds most waves have only a
+    few falling-back lanes, which the factorised path defers to its second
+    pass; with a third, most waves do the full search in place."""
     p, o, ref = small_pi_ref
-    _say("seeded sweep, path", path)
+    _say("seeded sweep, path", path, "near", near_frac)
     sr = inputs.SEEDED
     V32 = ref["V"].astype(np.float32)
     rng = np.random.default_rng(31)
-    near = rng.random(o.shape) < 2 / 3
+    near = rng.random(o.shape) < near_frac
     seed = np.where(near, ref["angle"] + rng.normal(0.0, 0.02, o.shape),
                     rng.uniform(-math.pi, math.pi, o.shape)).astype(np.float32)
     ctx = dpo.Context(p)
