@@ -175,7 +175,10 @@ int dpo_bellman_sweep(dpo_ctx* ctx, const float* V_in, float* V_out, float* pol_
 
 /* SEEDED sweep: seed_angle is a device float[N] of proposed thrust angles.
  * Nodes failing the fallback test repeat the SCAN_GOLDEN search; their count
- * is resid[4]. */
+ * is resid[4].  On the factorised path the full searches of sparse fallback
+ * nodes run in a second launch over a list built with atomics, so resid[1]
+ * (the FP64 sum) may differ between runs in its last bits; values, policy
+ * and the other residual entries are deterministic. */
 int dpo_bellman_sweep_seeded(dpo_ctx* ctx, const float* V_in, float* V_out, float* pol_angle,
                              uint8_t* pol_thr, const float* seed_angle, double* resid,
                              void* stream);
@@ -206,7 +209,12 @@ int dpo_solve_vi(dpo_ctx* ctx, float* V, float* pol_angle, uint8_t* pol_thr, dou
 
 /* Modified policy iteration (eq:p_impr then eq:p_eval by eval_sweeps
  * frozen-policy sweeps): stops when the residual of the greedy step is below
- * tol_rel; V then holds T V and the policy its argmin.  seed_angle (device,
+ * tol_rel; V then holds T V and the policy its argmin.  From the second
+ * greedy step on, a node keeps its current control unless the search finds a
+ * strictly smaller Q (the search is only approximately the argmin; this keeps
+ * the iterates from alternating between nearly tied controls).  A step's
+ * evaluation sweeps are queued before its residual is read back, and are
+ * discarded if the step meets the stop rule.  seed_angle (device,
  * nullable) enables the SEEDED greedy step for every outer iteration after the
  * first, until a seeded step meets tol_rel or 8 seeded steps in a row bring
  * no new lowest residual; from then on the greedy steps
