@@ -33,13 +33,18 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TFLOPS = 157.3
 
-# Algorithmic HBM bytes per active node of one frozen-policy evaluation sweep:
-# packed node coordinates (4), foot cell code (4), foot weights in v_r and v_t
-# (8), the node's share of the value array read once (4), value written (4).
-EVAL_BYTES_PER_NODE = 24
+# Algorithmic HBM bytes of one frozen-policy evaluation sweep: reported by
+# the library (dpo_eval_sweep_bytes): per free node the value written (4),
+# its share of the value array read once (4) and the foot descriptor stream
+# (packed coordinates 4 + 16-bit cell code 2 + weights in v_r and v_t 8 on
+# the 48^4 masked grid).
 # Greedy sweep: packed coordinates (4) + value read (4) + value, angle and
-# throttle written (4 + 4 + 1) + the foot descriptor written (12).
-GREEDY_BYTES_PER_NODE = 29
+# throttle written (4 + 4 + 1) + the compact foot descriptor written (2 + 8).
+GREEDY_BYTES_PER_NODE = 27
+# the evaluation-sweep kernel that runs for each descriptor form (bytes per
+# free node, the per-node form: 18 + 2 per fixed node)
+EVAL_KERNEL_BY_BYTES = {24: "k_policy_eval_desc<0>", 22: "k_policy_eval_d16<false, 0>",
+                        18: "k_policy_eval_d16<true, 0>"}
 # Gather bytes of one evaluation done naively: 16 float32 corners.
 GATHER_BYTES_PER_EVAL = 64
 
@@ -353,10 +358,10 @@ def main():
     torch.cuda.synchronize()
     eval_ms = ev0.elapsed_time(ev1) / reps
     log(f"bench: greedy sweep {greedy_ms:.4f} ms ({greedy_evals_s:.3e} evals/s), eval sweep {eval_ms:.4f} ms")
-    eval_bytes = EVAL_BYTES_PER_NODE * n_free
+    eval_bytes = ctx.eval_sweep_bytes()
     eval_gbs = eval_bytes / (eval_ms * 1e-3) / 1e9
     traffic = measured_traffic()
-    step_bytes = (GREEDY_BYTES_PER_NODE + E * EVAL_BYTES_PER_NODE) * n_free
+    step_bytes = GREEDY_BYTES_PER_NODE * n_free + E * eval_bytes
     step_gbs = step_bytes / (elapsed / args.steps) / 1e9
 
     # ---- time to a converged value function from V0 (separate run)
@@ -423,14 +428,14 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_policy_eval_desc",
+            "kernel": EVAL_KERNEL_BY_BYTES.get(round(eval_bytes / n_free), "k_policy_eval_d16"),
             "achieved": eval_gbs,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": eval_gbs / HBM_PEAK_GBS,
             "traffic": traffic,
             "algorithmic_bytes": eval_bytes,
-            "bytes_per_node": EVAL_BYTES_PER_NODE,
+            "bytes_per_node": eval_bytes / n_free,
             "nodes_per_launch": int(n_free),
             "avg_launch_ms": eval_ms,
             "launches_per_step": E,

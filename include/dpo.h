@@ -152,6 +152,16 @@ int dpo_set_block(dpo_ctx* ctx, int32_t block);
 /* The path the sweeps take now: 1 direct, 2 factorised (negative on error). */
 int dpo_kernel_path(const dpo_ctx* ctx);
 
+/* Algorithmic bytes of one dpo_policy_eval_sweep_last on ctx (*bytes, host):
+ * per free node the value written and its share of the value array read
+ * (4 + 4), plus the per-node stream of the foot descriptors: 16 bytes per free
+ * node (packed coordinates, 32-bit cell code, two cell coordinates); 14 with
+ * the compact 16-bit code, used when every foot stays within 31 cells of its
+ * node along v_r and v_t; or, when at least half of the nodes are free, 10
+ * per free node and 2 per fixed node (codes stored per node, no coordinate
+ * list). */
+int dpo_eval_sweep_bytes(const dpo_ctx* ctx, int64_t* bytes);
+
 /* Replace the search settings (same rules as in dpo_create). */
 int dpo_set_search(dpo_ctx* ctx, const dpo_search* search);
 

@@ -53,6 +53,8 @@ struct dpo_ctx {
   int* fb_count = nullptr;
   hipEvent_t resid_ready = nullptr;
   int* desc_code = nullptr;  // foot descriptors of the greedy step's controls (policy iteration)
+  uint16_t* desc16 = nullptr;  // compact codes (desc_format 1 and 2)
+  int desc_format = -1;        // 0 flat 32-bit codes, 1 compact by free node, 2 compact by node
   float2* desc_w = nullptr;
   bool desc_valid = false;    // a sweep has written them
   std::string err;
@@ -260,12 +262,63 @@ int ensure_pi_buffers(dpo_ctx* c) {
   return DPO_OK;
 }
 
+// Descriptor form: the compact 16-bit code needs every foot within
+// kDescReach cells of its node along v_r and v_t.  The bound is taken over the
+// grid's r nodes and the extreme v_r, v_t values (the drift along v_r is
+// linear in v_t^2, the one along v_t in v_r*v_t), plus the thrust step, plus
+// one cell for the cell base and one of margin.  With at least half of the
+// nodes free, the codes are stored per node and the sweep needs no free list.
+int desc_format_for(const dpo_ctx* c) {
+  const dpo_grid& g = c->grid;
+  const dpo_problem& p = c->prob;
+  const double h1 = c->G.h[1], h2 = c->G.h[2];
+  double mv = 0, mt = 0;
+  if (p.model == DPO_MODEL_ORBIT) {
+    if (!(g.lo[3] > 0)) return 0;
+    const double a2 = g.lo[2] * g.lo[2], b2 = g.hi[2] * g.hi[2];
+    const double vt2_max = std::max(a2, b2), vt2_min = (g.lo[2] <= 0 && g.hi[2] >= 0) ? 0.0 : std::min(a2, b2);
+    const double vrvt = std::max(std::fabs(g.lo[1]), std::fabs(g.hi[1])) * std::max(std::fabs(g.lo[2]), std::fabs(g.hi[2]));
+    for (int i = 0; i < g.n[0]; i++) {
+      const double r = g.lo[0] + i * c->G.h[0];
+      if (!(r > 0)) return 0;
+      const double ri = 1.0 / r;
+      mv = std::max(mv, std::max(std::fabs(vt2_max * ri - p.mu * ri * ri), std::fabs(vt2_min * ri - p.mu * ri * ri)));
+      mt = std::max(mt, vrvt * ri);
+    }
+    const double thrust = p.accel / g.lo[3];
+    mv = p.dt * (mv + thrust) / h1;
+    mt = p.dt * (mt + thrust) / h2;
+  } else {
+    mv = p.dt * std::fabs(p.speed) / h1;
+    mt = p.dt * std::fabs(p.speed) / h2;
+  }
+  if (!std::isfinite(mv) || !std::isfinite(mt) || mv + 2 > kDescReach || mt + 2 > kDescReach) return 0;
+  return 2 * c->n_free >= c->N ? 2 : 1;
+}
+
 int ensure_desc(dpo_ctx* c) {
-  if (c->desc_code) return DPO_OK;
-  const size_t n = (size_t)(c->n_free > 0 ? c->n_free : 1);
-  if (hipMalloc(&c->desc_code, sizeof(int) * n) != hipSuccess || hipMalloc(&c->desc_w, sizeof(float2) * n) != hipSuccess)
-    return fail(c, DPO_ENOMEM, "descriptor alloc");
+  if (c->desc_format >= 0) return DPO_OK;
+  const int format = desc_format_for(c);
+  const size_t n = (size_t)std::max<int64_t>(1, format == 2 ? c->N : c->n_free);
+  bool ok = hipMalloc(&c->desc_w, sizeof(float2) * n) == hipSuccess;
+  if (format == 0) ok = ok && hipMalloc(&c->desc_code, sizeof(int) * n) == hipSuccess;
+  else ok = ok && hipMalloc(&c->desc16, sizeof(uint16_t) * n) == hipSuccess;
+  // dense form: every code starts as kDescSkip; greedy sweeps overwrite the free nodes'
+  if (ok && format == 2) ok = hipMemset(c->desc16, 0xff, sizeof(uint16_t) * n) == hipSuccess;
+  if (!ok) return fail(c, DPO_ENOMEM, "descriptor alloc");
+  c->desc_format = format;
   return DPO_OK;
+}
+
+void set_desc_out(dpo_ctx* c, SweepArgs& a) {
+  a.desc_w = c->desc_w;
+  if (c->desc_format == 0) {
+    a.desc_code = c->desc_code;
+  } else {
+    a.desc16 = c->desc16;
+    a.desc_dense = c->desc_format == 2;
+  }
+  c->desc_valid = true;
 }
 
 int read_resid(dpo_ctx* c, double h[kPartial], hipStream_t s) {
@@ -292,11 +345,7 @@ int sweep_full(dpo_ctx* c, const float* Vin, float* Vout, float* ang, uint8_t* t
     a.pol_ang_in = ang;
     a.pol_thr_in = thr;
   }
-  if (desc) {
-    a.desc_code = c->desc_code;
-    a.desc_w = c->desc_w;
-    c->desc_valid = true;
-  }
+  if (desc) set_desc_out(c, a);
   if (a.n_free == 0) return DPO_OK;
   const int mode = c->search.mode == DPO_SEARCH_TABLE ? 0 : 1;
   hipError_t e;
@@ -319,11 +368,7 @@ int sweep_seeded(dpo_ctx* c, const float* Vin, float* Vout, float* ang, uint8_t*
     a.pol_thr_in = thr;
   }
   a.seed = seed;
-  if (desc) {
-    a.desc_code = c->desc_code;
-    a.desc_w = c->desc_w;
-    c->desc_valid = true;
-  }
+  if (desc) set_desc_out(c, a);
   if (a.n_free == 0) return DPO_OK;
   if (!use_fast(c)) {
     hipError_t e = launch_sweep_seeded(a, s);
@@ -368,17 +413,29 @@ int sweep_eval(dpo_ctx* c, const float* Vin, float* Vout, const float* ang, cons
   return DPO_OK;
 }
 
+// Bytes of the per-node stream of one descriptor sweep (coordinates, codes,
+// weights), not counting the values.
+int64_t eval_stream_bytes(const dpo_ctx* c) {
+  const int format = c->desc_format >= 0 ? c->desc_format : desc_format_for(c);
+  if (format == 0) return 16 * c->n_free;
+  if (format == 1) return 14 * c->n_free;
+  return 10 * c->n_free + 2 * (c->N - c->n_free);
+}
+
 // Frozen-policy sweep driven by the descriptors of the last greedy sweep.
 int sweep_eval_desc(dpo_ctx* c, const float* Vin, float* Vout, hipStream_t s) {
   SweepArgs a = base_args(c);
   a.V_in = Vin;
   a.V_out = Vout;
   a.desc_code_in = c->desc_code;
+  a.desc16_in = c->desc16;
   a.desc_w_in = c->desc_w;
   if (a.n_free == 0) return DPO_OK;
-  // streamed per sweep: coordinates + descriptor per free node, two value arrays
-  const double bytes = 16.0 * (double)c->n_free + 8.0 * (double)c->N;
-  hipError_t e = launch_policy_eval_desc(a, bytes > kLastLevelCacheBytes, s);
+  // streamed per sweep: the per-node stream and two value arrays
+  const double bytes = (double)eval_stream_bytes(c) + 8.0 * (double)c->N;
+  const bool streamed = bytes > kLastLevelCacheBytes;
+  hipError_t e = c->desc_format == 0 ? launch_policy_eval_desc(a, streamed, s)
+                                     : launch_policy_eval_desc16(a, c->desc_format, streamed, s);
   if (e != hipSuccess) return hip_fail(c, e, "policy eval (descriptor) launch");
   return DPO_OK;
 }
@@ -513,6 +570,7 @@ void dpo_destroy(dpo_ctx* c) {
   if (c->resid_host) hipHostFree(c->resid_host);
   if (c->resid_ready) hipEventDestroy(c->resid_ready);
   if (c->desc_code) hipFree(c->desc_code);
+  if (c->desc16) hipFree(c->desc16);
   if (c->desc_w) hipFree(c->desc_w);
   delete c;
 }
@@ -549,6 +607,13 @@ int dpo_set_block(dpo_ctx* c, int32_t block) {
 int dpo_kernel_path(const dpo_ctx* c) {
   if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
   return use_fast(c) ? 2 : 1;
+}
+
+int dpo_eval_sweep_bytes(const dpo_ctx* c, int64_t* bytes) {
+  if (!c || !bytes) return fail(const_cast<dpo_ctx*>(c), DPO_EINVAL, "NULL argument");
+  // the stream plus one value read (the gather's share) and one value write per free node
+  *bytes = eval_stream_bytes(c) + 8 * c->n_free;
+  return DPO_OK;
 }
 
 int dpo_set_search(dpo_ctx* c, const dpo_search* search) {
@@ -606,7 +671,7 @@ int dpo_policy_eval_sweep_last(dpo_ctx* c, const float* V_in, float* V_out, void
   if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
   if (!V_in || !V_out) return fail(c, DPO_EINVAL, "V_in / V_out is NULL");
   if (V_in == V_out) return fail(c, DPO_EINVAL, "V_in and V_out must differ (Jacobi sweep)");
-  if (!c->desc_code || !c->desc_valid) return fail(c, DPO_EINVAL, "no Bellman sweep has chosen a policy yet");
+  if (!c->desc_valid) return fail(c, DPO_EINVAL, "no Bellman sweep has chosen a policy yet");
   return sweep_eval_desc(c, V_in, V_out, S(stream));
 }
 

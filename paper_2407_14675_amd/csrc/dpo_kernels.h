@@ -52,11 +52,24 @@ struct SweepArgs {
   float2* desc_w;
   const int* desc_code_in;
   const float2* desc_w_in;
+  // Compact form used when every foot lies within 31 cells of its node along
+  // v_r and v_t: a 16-bit code with the cell's offset from the node along v_r
+  // (bits 0-5) and v_t (bits 6-11), each plus 32, bit 12 foot outside, bit
+  // 13 throttle.  Indexed by free-list position, or by node (desc_dense: the
+  // sweep then runs over every node and skips the code kDescSkip).
+  uint16_t* desc16;
+  const uint16_t* desc16_in;
+  int desc_dense;
   int mode;         // search mode (feedback)
   double w_time, w_fuel, lambda;
 };
 
 inline int blocks_for(long long n, int per = kBlock) { return (int)((n + per - 1) / per); }
+
+constexpr uint16_t kDescOut = 1u << 12;
+constexpr uint16_t kDescThr = 1u << 13;
+constexpr uint16_t kDescSkip = 0xffffu;  // not a free node (dense form)
+constexpr int kDescReach = 31;           // largest cell offset the compact code holds
 
 // Per-problem record of the batched sweep (device table).  It holds no
 // pointers: every array of the batch is one concatenated allocation passed
@@ -113,6 +126,8 @@ hipError_t launch_sweep_scan_golden(const SweepArgs& a, hipStream_t s);
 hipError_t launch_sweep_seeded(const SweepArgs& a, hipStream_t s);
 hipError_t launch_policy_eval(const SweepArgs& a, bool want_resid, hipStream_t s);
 hipError_t launch_policy_eval_desc(const SweepArgs& a, bool streamed, hipStream_t s);
+// format 1: compact codes by free-list position; 2: compact codes by node
+hipError_t launch_policy_eval_desc16(const SweepArgs& a, int format, bool streamed, hipStream_t s);
 hipError_t launch_zero_count(int* count, hipStream_t s);
 hipError_t launch_sweep_fallback(const SweepArgs& a, int block, int blocks, hipStream_t s);
 hipError_t launch_sweep_fast(const SweepArgs& a, int mode, int block, hipStream_t s);

@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_direct(SweepArgs a) {
     a.V_out[j] = ch.v;
     if (a.pol_ang) a.pol_ang[j] = ch.ang;
     if (a.pol_thr) a.pol_thr[j] = (uint8_t)ch.thr;
-    if (a.desc_code) write_desc(a, t, T, ch);
+    if (a.desc_code || a.desc16) write_desc(a, t, j, T, ch);
     node_residual(vin, ch.v, rel, sum, mabs, bad);
   }
   block_residual(rel, sum, mabs, bad, (double)fell_back, a.partial, blockIdx.x);
@@ -277,6 +277,68 @@ __global__ __launch_bounds__(kBlock) void k_policy_eval_desc(SweepArgs a) {
       tt[1] = w[k].x;
       tt[2] = w[k].y;
       I = cell_value(a.V_in + (code[k] & 0x3fffffff), a.G, tt);
+    }
+    const float out = fmaf(a.P.gamma, I, thr ? a.P.q_thr : a.P.q_coast);
+    if (kNt & 2) __builtin_nontemporal_store(out, a.V_out + j);
+    else a.V_out[j] = out;
+  }
+}
+
+// The same sweep from compact descriptors (SweepArgs::desc16): 14 bytes per
+// free node with the free list (coordinates 4, code 2, weights 8), 10 bytes
+// per node without it (kDense: every node is visited in order, fixed ones
+// carry kDescSkip and are left alone, and the node index is the thread's).
+template <bool kDense, int kNt>
+__global__ __launch_bounds__(kBlock) void k_policy_eval_d16(SweepArgs a) {
+  typedef float nt_f2 __attribute__((ext_vector_type(2)));
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int t0 = tile * (kDescNpt * kBlock) + threadIdx.x;
+  const int count = kDense ? a.G.n[0] * a.G.n[1] * a.G.n[2] * a.G.n[3] : a.n_free;
+  uint32_t packed[kDescNpt];
+  uint16_t code[kDescNpt];
+  float2 w[kDescNpt];
+#pragma unroll
+  for (int k = 0; k < kDescNpt; k++) {
+    const int t = t0 + k * kBlock;
+    if (t < count) {
+      if (kNt & 1) {
+        if (!kDense) packed[k] = __builtin_nontemporal_load(a.free_node + t);
+        code[k] = __builtin_nontemporal_load(a.desc16_in + t);
+        const nt_f2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f2*>(a.desc_w_in) + t);
+        w[k] = make_float2(v.x, v.y);
+      } else {
+        if (!kDense) packed[k] = a.free_node[t];
+        code[k] = a.desc16_in[t];
+        w[k] = a.desc_w_in[t];
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kDescNpt; k++) {
+    const int t = t0 + k * kBlock;
+    if (t >= count) continue;
+    if (kDense && code[k] == kDescSkip) continue;
+    int i[4];
+    int j;
+    if (kDense) {
+      j = t;
+      decode_node(a.G, t, i);
+    } else {
+      j = unpack_node(a.G, packed[k], i);
+    }
+    const bool thr = (code[k] & kDescThr) != 0;
+    float I = a.P.M;
+    if (!(code[k] & kDescOut)) {
+      // r and m cell coordinates, exactly as the greedy sweep formed them
+      const float o0 = drift_r(a, i[1]);
+      int b0, b3;
+      float tt[4];
+      axis_cell(i[0], a.G.n[0], o0, b0, tt[0]);
+      axis_cell(i[3], a.G.n[3], thr ? a.gm : 0.0f, b3, tt[3]);
+      tt[1] = w[k].x;
+      tt[2] = w[k].y;
+      const int dv = (int)(code[k] & 63u) - 32, dt = (int)((code[k] >> 6) & 63u) - 32;
+      I = cell_value(a.V_in + b0 + (i[1] + dv) * a.G.st[1] + (i[2] + dt) * a.G.st[2] + b3 * a.G.st[3], a.G, tt);
     }
     const float out = fmaf(a.P.gamma, I, thr ? a.P.q_thr : a.P.q_coast);
     if (kNt & 2) __builtin_nontemporal_store(out, a.V_out + j);
@@ -559,6 +621,16 @@ hipError_t launch_policy_eval(const SweepArgs& a, bool want_resid, hipStream_t s
 hipError_t launch_policy_eval_desc(const SweepArgs& a, bool streamed, hipStream_t s) {
   if (streamed) DPO_LAUNCH(k_policy_eval_desc<3>, blocks_for(a.n_free, kDescNpt * kBlock), kBlock, s, a);
   DPO_LAUNCH(k_policy_eval_desc<0>, blocks_for(a.n_free, kDescNpt * kBlock), kBlock, s, a);
+}
+
+hipError_t launch_policy_eval_desc16(const SweepArgs& a, int format, bool streamed, hipStream_t s) {
+  if (format == 2) {
+    const long long N = (long long)a.G.n[0] * a.G.n[1] * a.G.n[2] * a.G.n[3];
+    if (streamed) DPO_LAUNCH((k_policy_eval_d16<true, 3>), blocks_for(N, kDescNpt * kBlock), kBlock, s, a);
+    DPO_LAUNCH((k_policy_eval_d16<true, 0>), blocks_for(N, kDescNpt * kBlock), kBlock, s, a);
+  }
+  if (streamed) DPO_LAUNCH((k_policy_eval_d16<false, 3>), blocks_for(a.n_free, kDescNpt * kBlock), kBlock, s, a);
+  DPO_LAUNCH((k_policy_eval_d16<false, 0>), blocks_for(a.n_free, kDescNpt * kBlock), kBlock, s, a);
 }
 
 hipError_t launch_resid_final(const double* partial, int nblocks, double* out, hipStream_t s) {

@@ -226,7 +226,7 @@ __device__ inline void keep_incumbent(const QF& qf, const SweepArgs& a, int j, f
 }
 
 // Foot descriptor of the chosen control (see SweepArgs::desc_code).
-__device__ inline void write_desc(const SweepArgs& a, int t, const NodeTerms& T, const Choice& ch) {
+__device__ inline void write_desc(const SweepArgs& a, int t, int j, const NodeTerms& T, const Choice& ch) {
   float off[4];
   off[0] = T.drift[0];
   off[1] = ch.thr ? fmaf(T.g1, ch.sn, T.drift[1]) : T.drift[1];
@@ -235,10 +235,20 @@ __device__ inline void write_desc(const SweepArgs& a, int t, const NodeTerms& T,
   int base[4];
   float w[4];
   const bool inside = foot_cell(a.G, T.i, off, base, w);
+  const float2 wv = inside ? make_float2(w[1], w[2]) : make_float2(0.0f, 0.0f);
+  if (a.desc16) {
+    const int k = a.desc_dense ? j : t;
+    uint16_t code = ch.thr ? kDescThr : 0;
+    if (inside) code |= (uint16_t)((base[1] - T.i[1] + 32) | ((base[2] - T.i[2] + 32) << 6));
+    else code |= kDescOut;
+    a.desc16[k] = code;
+    a.desc_w[k] = wv;
+    return;
+  }
   const unsigned flat = inside ? (unsigned)(base[0] + base[1] * a.G.st[1] + base[2] * a.G.st[2] + base[3] * a.G.st[3])
                                : (1u << 30);
   a.desc_code[t] = (int)(flat | ((unsigned)ch.thr << 31));
-  a.desc_w[t] = inside ? make_float2(w[1], w[2]) : make_float2(0.0f, 0.0f);
+  a.desc_w[t] = wv;
 }
 
 // ---- fast path for thrust controls.
@@ -439,7 +449,7 @@ __device__ inline void fast_node(const SweepArgs& a, int t, float4* lds, double&
   a.V_out[j] = ch.v;
   if (a.pol_ang) a.pol_ang[j] = ch.ang;
   if (a.pol_thr) a.pol_thr[j] = (uint8_t)ch.thr;
-  if (a.desc_code) write_desc(a, t, T, ch);
+  if (a.desc_code || a.desc16) write_desc(a, t, j, T, ch);
   node_residual(vin, ch.v, rel, sum, mabs, bad);
 }
 

@@ -83,6 +83,7 @@ def load():
         "dpo_set_search": [vp, C.POINTER(Search)],
         "dpo_set_kernel_path": [vp, i32],
         "dpo_kernel_path": [vp],
+        "dpo_eval_sweep_bytes": [vp, C.POINTER(i64)],
         "dpo_init_value": [vp, vp, vp],
         "dpo_bellman_sweep": [vp, vp, vp, vp, vp, vp, vp],
         "dpo_bellman_sweep_seeded": [vp, vp, vp, vp, vp, vp, vp, vp],
@@ -234,6 +235,12 @@ class Context:
         if rc < 0:
             raise DpoError(rc, self.lib.dpo_last_error(self.h).decode())
         return rc
+
+    def eval_sweep_bytes(self):
+        """Algorithmic bytes of one frozen-policy sweep from foot descriptors."""
+        b = C.c_int64()
+        self._check(self.lib.dpo_eval_sweep_bytes(self.h, C.byref(b)))
+        return b.value
 
     def set_block(self, block):
         """Workgroup size of the factorised sweeps (64..512, multiple of 64)."""

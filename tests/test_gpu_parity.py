@@ -618,3 +618,49 @@ def test_walk_seeded_pi_matches_plain(dpo, small_pi_ref):
     free = o.kind == KIND_FREE
     _say("  outer", st["sweeps"], "fallback nodes", st["fallback_nodes"], "evals", st["evals"])
     assert rel_err(host(V), ref["V"])[free].max() <= 1e-4
+
+
+# ----------------------------------------------- foot-descriptor formats
+@pytest.mark.parametrize("case", ["per_node", "per_free_node", "flat_code"])
+def test_descriptor_formats(dpo, case):
+    """The evaluation sweep from descriptors in each storage form equals the
+    oracle's Q of the greedy step's policy: codes stored per node (most nodes
+    free), per free node (a sparse reduced grid), and 32-bit flat codes (feet
+    farther than the compact code reaches: dt = 2 on a 12^4 grid, the direct
+    kernel path)."""
+    _say("descriptor format", case)
+    mask = None
+    if case == "flat_code":
+        p = dict(inputs.with_grid(inputs.PI48, (12, 12, 12, 12)), dt=2.0)
+    else:
+        p = inputs.with_grid(inputs.PI48, (11, 10, 9, 8))
+        if case == "per_free_node":
+            rng = np.random.default_rng(71)
+            mask = (rng.random((8, 9, 10, 11)) < 0.35).astype(np.uint8)
+    o = Oracle(p, mask=mask)
+    ctx = dpo.Context(p, mask=None if mask is None else dev(mask, torch.uint8))
+    free = o.kind == KIND_FREE
+    nf = int(free.sum())
+    want = {"per_node": 18 * nf + 2 * (o.N - nf), "per_free_node": 22 * nf, "flat_code": 24 * nf}[case]
+    assert ctx.eval_sweep_bytes() == want
+    V = inputs.random_value(p, seed=73, frac_M=0.1).astype(np.float32)
+    Vin = dev(V)
+    W = Vin.clone()
+    ang, thr = ctx.empty_policy()
+    ctx.bellman_sweep(Vin, W, ang, thr)
+    E = Vin.clone()
+    ctx.policy_eval_sweep_last(Vin, E)
+    nodes = np.flatnonzero(free.reshape(-1))
+    from scipy.ndimage import maximum_filter
+    corner = maximum_filter(np.abs(V.astype(np.float64)), size=7, mode="nearest").reshape(-1)[nodes]
+    ve = host(E).reshape(-1)[nodes].astype(np.float64)
+    # the sweep reproduces the greedy step's own Q of the chosen control
+    vg = host(W).reshape(-1)[nodes].astype(np.float64)
+    assert np.all(np.abs(ve - vg) <= 1e-5 * np.maximum(1.0, np.abs(vg)) + 1e-6 * corner)
+    np.testing.assert_array_equal(host(E)[~free], V[~free])
+    if case != "flat_code":
+        # and the oracle's (with 35-cell feet, float32 and FP64 feet straddle
+        # the domain faces differently, so the flat-code case stops above)
+        q = o.q_many(V.astype(np.float64), nodes, host(thr).reshape(-1)[nodes],
+                     host(ang).reshape(-1)[nodes].astype(np.float64))
+        assert np.all(np.abs(ve - q) <= 1e-5 * np.maximum(1.0, np.abs(q)) + 1e-6 * corner)
