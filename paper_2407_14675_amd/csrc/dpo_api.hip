@@ -335,8 +335,9 @@ int64_t evals_per_full_search(const dpo_ctx* c) {
 bool use_fast(const dpo_ctx* c) { return c->path == 2 || (c->path == 0 && c->fast_ok); }
 
 int sweep_full(dpo_ctx* c, const float* Vin, float* Vout, float* ang, uint8_t* thr, hipStream_t s,
-               bool desc = false, bool incumbent = false) {
+               bool desc = false, bool incumbent = false, bool want_resid = true) {
   SweepArgs a = base_args(c);
+  if (!want_resid) a.partial = nullptr;
   a.V_in = Vin;
   a.V_out = Vout;
   a.pol_ang = ang;
@@ -696,7 +697,9 @@ int dpo_solve_vi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, doubl
   double h[kPartial] = {0, 0, 0, 0, 0};
   int64_t k = 0;
   while (k < max_sweeps) {
-    rc = sweep_full(c, cur, nxt, pol_angle, pol_thr, s);
+    // only the sweeps that end a check interval compute the residual
+    const bool check = (k + 1) % check_every == 0 || k + 1 == max_sweeps;
+    rc = sweep_full(c, cur, nxt, pol_angle, pol_thr, s, false, false, check);
     if (rc != DPO_OK) return rc;
     k++;
     std::swap(cur, nxt);
@@ -1114,7 +1117,7 @@ int batch_graph(dpo_batch* b, const BatchArgs& a, int block, int S, hipGraphExec
   hipGraph_t g = nullptr;
   BHIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
-  for (int s = 0; s < S && e == hipSuccess; s++) e = launch_batch_sweep(a, b->mode, block, s & 1, b->stream);
+  for (int s = 0; s < S && e == hipSuccess; s++) e = launch_batch_sweep(a, b->mode, block, s & 1, s == S - 1, b->stream);
   if (e == hipSuccess) e = launch_batch_reduce(a, b->stream);
   hipError_t e2 = hipStreamEndCapture(b->stream, &g);
   if (e != hipSuccess || e2 != hipSuccess) {

@@ -12,7 +12,7 @@ namespace dpo {
 // problem, XCD-contiguous); the problem's record holds offsets into the
 // concatenated buffers, whose bases are kernel arguments.
 template <int kMode>
-__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_batch_sweep(BatchArgs B, int parity) {
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_batch_sweep(BatchArgs B, int parity, int want_resid) {
   extern __shared__ float4 dyn_lds[];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   int k = 0;
@@ -53,7 +53,8 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(8))) 
   double rel = 0, sum = 0, mabs = 0, bad = 0;
   int fell_back = 0, deferred = 0;
   if (t < a.n_free) fast_node<kMode>(a, t, dyn_lds, rel, sum, mabs, bad, fell_back, deferred);
-  block_residual(rel, sum, mabs, bad, (double)fell_back, B.partial, tile);
+  // only the last sweep of a graph replay feeds the stop decision
+  if (want_resid) block_residual(rel, sum, mabs, bad, (double)fell_back, B.partial, tile);
 }
 
 // One workgroup per running problem: FP64 reduction of its tiles' partials
@@ -90,10 +91,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_reduce(BatchArgs B) {
   }
 }
 
-hipError_t launch_batch_sweep(const BatchArgs& b, int mode, int block, int parity, hipStream_t s) {
+hipError_t launch_batch_sweep(const BatchArgs& b, int mode, int block, int parity, int want_resid, hipStream_t s) {
   const size_t lds = sizeof(float4) * 4 * block;
-  if (mode == 0) hipLaunchKernelGGL(k_batch_sweep<0>, dim3(b.n_tiles), dim3(block), lds, s, b, parity);
-  else hipLaunchKernelGGL(k_batch_sweep<1>, dim3(b.n_tiles), dim3(block), lds, s, b, parity);
+  if (mode == 0) hipLaunchKernelGGL(k_batch_sweep<0>, dim3(b.n_tiles), dim3(block), lds, s, b, parity, want_resid);
+  else hipLaunchKernelGGL(k_batch_sweep<1>, dim3(b.n_tiles), dim3(block), lds, s, b, parity, want_resid);
   return hipGetLastError();
 }
 

@@ -111,7 +111,7 @@ struct BatchArgs {
   double tol;
 };
 
-hipError_t launch_batch_sweep(const BatchArgs& b, int mode, int block, int parity, hipStream_t s);
+hipError_t launch_batch_sweep(const BatchArgs& b, int mode, int block, int parity, int want_resid, hipStream_t s);
 hipError_t launch_batch_reduce(const BatchArgs& b, hipStream_t s);
 
 // Launch wrappers (asynchronous on `stream`); each returns the launch status.

@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_direct(SweepArgs a) {
     if (a.desc_code || a.desc16) write_desc(a, t, j, T, ch);
     node_residual(vin, ch.v, rel, sum, mabs, bad);
   }
-  block_residual(rel, sum, mabs, bad, (double)fell_back, a.partial, blockIdx.x);
+  if (a.partial) block_residual(rel, sum, mabs, bad, (double)fell_back, a.partial, blockIdx.x);
 }
 
 // Factorised-path sweep; the workgroup size is chosen at launch (64..512)
@@ -177,7 +177,8 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(8))) 
       if (deferred) a.fb_list[base + __popcll(bal & ((1ull << lane) - 1ull))] = t;
     }
   }
-  block_residual(rel, sum, mabs, bad, (double)fell_back, a.partial, blockIdx.x);
+  // a null partial buffer (value-iteration sweeps between checks) skips the residual
+  if (a.partial) block_residual(rel, sum, mabs, bad, (double)fell_back, a.partial, blockIdx.x);
 }
 
 // Second pass of the seeded sweep: the full search at the nodes the first
