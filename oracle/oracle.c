@@ -22,8 +22,16 @@
  *   - policy iteration, eq:p_eval then eq:p_impr, with the evaluation done by
  *     a fixed number of frozen-policy sweeps (modified policy iteration);
  *   - the minimisation by tabulation and golden-section refinement
- *     (paragraph "Efficient computation of the minimum");
+ *     (paragraph "Efficient computation of the minimum"), and a seeded local
+ *     golden search with the full search as fallback (the warm-started
+ *     minimisation of the same paragraph, with the seed given per node);
  *   - the approximate feedback eq:feed.
+ *
+ * Pins (tests): exact multilinear reproduction, Euler defects in closed
+ * form, the eikonal closed form, monotonicity and contraction, VI = PI,
+ * brute-force enumeration of the control.  Parity unpinned: the converged
+ * value function of the orbit problems has no closed form and is pinned only
+ * through those parts.
  *
  * Problem instance (nondimensional, mu = 1): state x = (r, v_r, v_t, m),
  *   r'   = v_r

@@ -41,7 +41,7 @@ struct SweepArgs {
   int n_local;
   float local_half_width;
   float fallback_tol;
-  double* partial;  // kPartial doubles per workgroup
+  double* partial;  // kPartial doubles per workgroup; null: the sweep skips the residual
   // Foot descriptor of each free node's chosen control (free-list order),
   // written by the greedy sweep when desc_code is set and read by the
   // frozen-policy sweep.  desc_code: bits 0-29 flat index of the cell's lowest
