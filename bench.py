@@ -55,12 +55,18 @@ KERNEL_SOURCES = ["dpo_kernels.hip", "dpo_device.h", "dpo_kernels.h", "dpo_searc
 
 
 def kernel_source_hash():
+    """Hash of the kernel sources with comments and blank space removed, so
+    that only code changes invalidate a counter measurement."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2407_14675_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2407_14675_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
