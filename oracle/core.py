@@ -11,7 +11,8 @@ from . import build as _build
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 MODELS = {"orbit": 0, "eikonal": 1}
-SEARCH_MODES = {"table": 0, "scan_golden": 1, "seeded": 2}
+SEARCH_MODES = {"table": 0, "scan_golden": 1, "seeded": 2, "table_walk": 3}
+INTEGRATORS = {"euler": 0, "heun": 1}
 KIND_FREE, KIND_TARGET, KIND_INACTIVE = 0, 1, 2
 
 
@@ -32,6 +33,7 @@ class ProblemStruct(C.Structure):
         ("speed", C.c_double),
         ("tgt_c", C.c_double * 4),
         ("tgt_w", C.c_double * 4),
+        ("integrator", C.c_int32),
     ]
 
 
@@ -51,6 +53,7 @@ def problem_struct(p):
         setattr(s, f, float(p[f]))
     s.tgt_c[:] = [float(v) for v in p["tgt_c"]]
     s.tgt_w[:] = [float(v) for v in p["tgt_w"]]
+    s.integrator = INTEGRATORS[p.get("integrator", "euler")]
     return s
 
 
@@ -100,6 +103,7 @@ def load(precision="f64"):
     lib.or_bellman_sweep.argtypes = [P, vp, S, vp, vp, vp, vp, vp]
     lib.or_bellman_nodes.argtypes = [P, vp, S, vp, vp, i64, vp, vp, vp, vp]
     lib.or_bellman_sweep_seeded.argtypes = [P, vp, S, vp, vp, vp, vp, vp, vp, vp]
+    lib.or_bellman_sweep_walk.argtypes = [P, vp, S, vp, vp, vp, vp, vp, vp, vp]
     lib.or_policy_eval_sweep.argtypes = [P, vp, vp, vp, vp, vp]
     lib.or_solve_vi.argtypes = [P, vp, S, vp, vp, vp, C.c_double, C.c_double, i64, vp]
     lib.or_solve_vi.restype = i64
@@ -216,6 +220,21 @@ class Oracle:
         self.lib.or_bellman_sweep_seeded(C.byref(self.ps), _ptr(self.kind), C.byref(ss), _ptr(Vin), _ptr(sd),
                                          _ptr(Vout), _ptr(ang), _ptr(thr), _ptr(margin), _ptr(fb))
         return Vout, ang, thr, margin, fb
+
+    def bellman_sweep_walk(self, V, ang_prev, search=None):
+        """Sweep with the table walk from the angles ang_prev (None: the full
+        table); returns V, angle, throttle, margin and the thrust evaluations."""
+        Vin = self._arr(V)
+        prev = None if ang_prev is None else self._arr(ang_prev)
+        ss = self.ss if search is None else search_struct(search)
+        Vout = np.empty_like(Vin)
+        ang = np.empty_like(Vin)
+        thr = np.empty(self.shape, dtype=np.uint8)
+        margin = np.empty_like(Vin)
+        ev = np.zeros(1, dtype=np.int64)
+        self.lib.or_bellman_sweep_walk(C.byref(self.ps), _ptr(self.kind), C.byref(ss), _ptr(Vin), _ptr(prev),
+                                       _ptr(Vout), _ptr(ang), _ptr(thr), _ptr(margin), _ptr(ev))
+        return Vout, ang, thr, margin, int(ev[0])
 
     def bellman_nodes(self, V, nodes, search=None):
         Vin = self._arr(V)

@@ -28,8 +28,11 @@
  *   - the approximate feedback eq:feed.
  *
  * Pins (tests): exact multilinear reproduction, Euler defects in closed
- * form, the eikonal closed form, monotonicity and contraction, VI = PI,
- * brute-force enumeration of the control.  Parity unpinned: the converged
+ * form, the Heun step's third-order local error against an accurate ODE
+ * integration, the eikonal closed form, monotonicity and contraction,
+ * VI = PI, brute-force enumeration of the control, and the walk's result a
+ * local minimiser of the full table that equals its global minimiser where
+ * the table is unimodal.  Parity unpinned: the converged
  * value function of the orbit problems has no closed form and is pinned only
  * through those parts.
  *
@@ -41,7 +44,8 @@
  * (the polar system of Section 3 with the angle measured from the tangential
  * direction, the cyclic angle theta dropped and mass added; the centrifugal
  * term carries a plus sign, which is the physically correct one).  The foot
- * point is one explicit Euler step.  A second model, a 2-D minimum-time
+ * point is one explicit Euler step, or one Heun (second-order Runge-Kutta)
+ * step, the scheme the paper itself uses.  A second model, a 2-D minimum-time
  * eikonal x' = s*(sin u, cos u) in axes (v_r, v_t), exists to pin the scheme
  * against a closed form.
  *
@@ -69,13 +73,16 @@ typedef struct {
   int32_t model; /* 0 = planar orbit, 1 = 2-D eikonal in axes (v_r, v_t) */
   double mu, accel, mdot, dt, lambda, w_time, w_fuel, M, speed;
   double tgt_c[4], tgt_w[4];
+  int32_t integrator; /* foot point: 0 = one explicit Euler step, 1 = Heun (RK2) */
 } or_problem;
 
 typedef struct {
   int32_t mode; /* 0 = discrete table of n_angles thrust angles plus coast,
                    1 = scan of n_scan angles, golden-section refinement,
                    2 = seeded: golden section around a given angle, with the
-                       mode-1 search as fallback */
+                       mode-1 search as fallback,
+                   3 = the mode-0 table searched by a walk from the previous
+                       optimum (mode 0 where no previous optimum exists) */
   int32_t n_angles, n_scan, n_golden;
   int32_t n_local;         /* mode 2: thrust evaluations of the local search */
   double local_half_width; /* mode 2: half-width of its bracket (rad) */
@@ -152,19 +159,37 @@ static void rhs(const or_problem *p, const real x[4], int thr, real u, real b[4]
   b[3] = -(real)p->mdot * (real)thr;
 }
 
-/* One explicit Euler step of length tau from an arbitrary state x. */
-void or_step(const or_problem *p, const real x[4], int thr, real u, real tau, real z[4]) {
+/* Mean slope of the one-step approximation of the trajectory from x over a
+ * step tau with the control held fixed (Section 3: the foot point
+ * x + tau*Phi(x, f) of eq:schema).  Euler: Phi = b(x).  Heun, the
+ * second-order Runge-Kutta method the paper names: Phi = (b(x) + b(x~))/2
+ * with the Euler predictor x~ = x + tau*b(x). */
+static void step_slope(const or_problem *p, const real x[4], int thr, real u, real tau, real phi[4]) {
   real b[4];
   rhs(p, x, thr, u, b);
-  for (int k = 0; k < 4; k++) z[k] = x[k] + tau * b[k];
+  if (p->integrator != 1) {
+    for (int k = 0; k < 4; k++) phi[k] = b[k];
+    return;
+  }
+  real xt[4], b2[4];
+  for (int k = 0; k < 4; k++) xt[k] = x[k] + tau * b[k];
+  rhs(p, xt, thr, u, b2);
+  for (int k = 0; k < 4; k++) phi[k] = (real)0.5 * (b[k] + b2[k]);
 }
 
-/* Foot of node i in grid coordinates: s_k = i_k + tau*b_k/h_k. */
+/* One step of length tau from an arbitrary state x: z = x + tau*Phi. */
+void or_step(const or_problem *p, const real x[4], int thr, real u, real tau, real z[4]) {
+  real phi[4];
+  step_slope(p, x, thr, u, tau, phi);
+  for (int k = 0; k < 4; k++) z[k] = x[k] + tau * phi[k];
+}
+
+/* Foot of node i in grid coordinates: s_k = i_k + tau*Phi_k/h_k. */
 static void foot_grid(const or_problem *p, const int i[4], int thr, real u, real tau, real s[4]) {
-  real x[4], b[4];
+  real x[4], phi[4];
   node_coords(p, i, x);
-  rhs(p, x, thr, u, b);
-  for (int k = 0; k < 4; k++) s[k] = (real)i[k] + tau * b[k] / (real)step(p, k);
+  step_slope(p, x, thr, u, tau, phi);
+  for (int k = 0; k < 4; k++) s[k] = (real)i[k] + tau * phi[k] / (real)step(p, k);
 }
 
 /* --------------------------------------------------------- interpolation */
@@ -395,9 +420,76 @@ static choice search_scan_golden(const qfun *f, int n_scan, int n_golden) {
   return c;
 }
 
+/* Mode 3 without a previous optimum is the mode-0 table. */
 static choice search(const qfun *f, const or_search *sr) {
-  if (sr->mode == 0) return search_table(f, sr->n_angles);
+  if (sr->mode == 0 || sr->mode == 3) return search_table(f, sr->n_angles);
   return search_scan_golden(f, sr->n_scan, sr->n_golden);
+}
+
+static real table_angle(int k, int K) { return (real)(-OR_PI + 2.0 * OR_PI * (double)k / (double)K); }
+
+/* Index of the table angle nearest to u on the circle (halves round up);
+ * 0 for a non-finite u. */
+static int table_index(real u, int K) {
+  if (!isfinite((double)u)) return 0;
+  double k = floor(((double)u + OR_PI) * (double)K / (2.0 * OR_PI) + 0.5);
+  k -= (double)K * floor(k / (double)K);
+  int ki = (int)k;
+  return (ki >= 0 && ki < K) ? ki : 0;
+}
+
+static void keep_smaller(real *m, real gap) {
+  gap = (real)fabs((double)gap);
+  if (gap < *m) *m = gap;
+}
+
+/* Walk over the mode-0 table from the previous optimum (Section 3,
+ * "Efficient computation of the minimum": after the first iteration the
+ * search starts at the previous optimal control and moves one step at a time
+ * towards lower Q until it stands on a local minimiser).  Start at the table
+ * angle nearest to u_prev; look at both cyclic neighbours; move to the lower
+ * one if it is strictly below the current Q (the k-1 side when the two are
+ * equal); from then on keep moving the same way while the next angle is
+ * strictly lower (the angle just left is higher, so it never needs a second
+ * look).  Thrust iff the walk's Q is strictly below the coast Q.  The margin
+ * is the smallest gap of any comparison the walk decided (tie indicator).
+ * *evals (nullable) accumulates the thrust evaluations. */
+static choice search_walk(const qfun *f, int K, real u_prev, int64_t *evals) {
+  int k = table_index(u_prev, K);
+  const int km = (k + K - 1) % K, kp = (k + 1) % K;
+  real qk = qeval(f, 1, table_angle(k, K));
+  const real qm = qeval(f, 1, table_angle(km, K));
+  const real qp = qeval(f, 1, table_angle(kp, K));
+  int64_t n = 3;
+  real margin = INFINITY;
+  keep_smaller(&margin, qm - qk);
+  keep_smaller(&margin, qp - qk);
+  int d = 0;
+  if (qm < qk && qm <= qp) d = -1;
+  else if (qp < qk) d = 1;
+  if (qm < qk && qp < qk) keep_smaller(&margin, qm - qp);
+  if (d != 0) {
+    k = d < 0 ? km : kp;
+    qk = d < 0 ? qm : qp;
+    for (int step_no = 0; step_no < K; step_no++) {
+      const int kn = (k + d + K) % K;
+      const real qn = qeval(f, 1, table_angle(kn, K));
+      n++;
+      keep_smaller(&margin, qn - qk);
+      if (!(qn < qk)) break;
+      k = kn;
+      qk = qn;
+    }
+  }
+  const real q_coast = qeval(f, 0, 0);
+  keep_smaller(&margin, qk - q_coast);
+  choice c;
+  c.angle = wrap_angle(table_angle(k, K));
+  c.thr = qk < q_coast;
+  c.q = c.thr ? qk : q_coast;
+  c.margin = margin;
+  if (evals) *evals += n;
+  return c;
 }
 
 /* Seeded search (the warm-started minimisation of Section 3, "Efficient
@@ -458,6 +550,39 @@ void or_bellman_sweep(const or_problem *p, const uint8_t *kind, const or_search 
     node_index(p, j, i);
     qfun f = {p, Vin, i, NULL, (real)p->dt};
     choice c = search(&f, sr);
+    Vout[j] = c.q;
+    if (pol_ang) pol_ang[j] = c.angle;
+    if (pol_thr) pol_thr[j] = (uint8_t)c.thr;
+    if (margin) margin[j] = c.margin;
+  }
+}
+
+/* One Jacobi Bellman sweep with the table walk (mode 3) started at each
+ * node's previous angle ang_prev[j] (may alias pol_ang); with ang_prev NULL,
+ * the full mode-0 table.  *evals (nullable) accumulates the thrust
+ * evaluations.  Fixed nodes are copied. */
+void or_bellman_sweep_walk(const or_problem *p, const uint8_t *kind, const or_search *sr, const real *Vin,
+                           const real *ang_prev, real *Vout, real *pol_ang, uint8_t *pol_thr, real *margin,
+                           int64_t *evals) {
+  int64_t N = n_total(p);
+  for (int64_t j = 0; j < N; j++) {
+    if (kind[j] != KIND_FREE) {
+      Vout[j] = Vin[j];
+      if (pol_ang) pol_ang[j] = 0;
+      if (pol_thr) pol_thr[j] = 0;
+      if (margin) margin[j] = INFINITY;
+      continue;
+    }
+    int i[4];
+    node_index(p, j, i);
+    qfun f = {p, Vin, i, NULL, (real)p->dt};
+    choice c;
+    if (ang_prev) {
+      c = search_walk(&f, sr->n_angles, ang_prev[j], evals);
+    } else {
+      c = search_table(&f, sr->n_angles);
+      if (evals) *evals += sr->n_angles;
+    }
     Vout[j] = c.q;
     if (pol_ang) pol_ang[j] = c.angle;
     if (pol_thr) pol_thr[j] = (uint8_t)c.thr;
@@ -543,7 +668,9 @@ int64_t or_solve_vi(const or_problem *p, const uint8_t *kind, const or_search *s
   double res[3] = {0, 0, 0};
   int done = 0;
   for (k = 1; k <= max_sweeps; k++) {
-    or_bellman_sweep(p, kind, sr, V, W, pol_ang, pol_thr, NULL);
+    /* the walk (mode 3) starts from the previous sweep's angles */
+    if (sr->mode == 3) or_bellman_sweep_walk(p, kind, sr, V, k > 1 ? pol_ang : NULL, W, pol_ang, pol_thr, NULL, NULL);
+    else or_bellman_sweep(p, kind, sr, V, W, pol_ang, pol_thr, NULL);
     or_residual(N, kind, V, W, res);
     memcpy(V, W, sizeof(real) * (size_t)N);
     if (tol_abs > 0 ? res[2] < tol_abs : res[0] < tol_rel) { done = 1; break; }
@@ -581,7 +708,8 @@ int64_t or_solve_pi(const or_problem *p, const uint8_t *kind, const or_search *s
         int i[4];
         node_index(p, j, i);
         qfun f = {p, V, i, NULL, (real)p->dt};
-        choice c = search(&f, sr);
+        /* mode 3: the walk starts at the current policy's angle */
+        choice c = sr->mode == 3 ? search_walk(&f, sr->n_angles, pol_ang[j], NULL) : search(&f, sr);
         real q_inc = q_node(p, V, i, pol_thr[j], pol_ang[j], (real)p->dt);
         if (q_inc <= c.q) {
           W[j] = q_inc;
