@@ -268,6 +268,54 @@ def bench_large(accels=(1e-3,), with_seeded=True):
     return out
 
 
+def bench_variants(mask, V_euler):
+    """The paper's own step and search variants on the headline's 48^4 masked
+    grid, each solved by policy iteration to 1e-6 from V0:
+      * table walk: the 73 controls (coast + 72 angles) searched in full on
+        the first greedy step and by the walk from the previous optimum after
+        it, against the exhaustive search of the same table;
+      * Heun foot: scan 64 + golden 12 with the second-order Runge-Kutta foot
+        (direct path; evaluation sweeps recompute the foot from the angle),
+        against the Euler solve of the headline (V_euler)."""
+    import numpy as np
+    import torch
+
+    from paper_2407_14675_amd import dpo, inputs
+
+    def solve(problem):
+        ctx = dpo.Context(problem, mask=mask)
+        V = ctx.init_value()
+        ang, thr = ctx.empty_policy()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rc, st = ctx.solve_pi(V, ang, thr, tol_rel=1e-6, eval_sweeps=inputs.EVAL_SWEEPS, max_outer=3000)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t
+        return ctx, V, {"seconds": sec, "outer_iterations": st["sweeps"], "converged": bool(st["converged"]),
+                        "evals": st["evals"], "evals_per_s": st["evals"] / sec,
+                        "V_x0": ctx.value_at(V, inputs.X0), "kernel_path": ctx.kernel_path()}
+
+    out = {}
+    table = dict(inputs.PI48, search=dict(mode="table", n_angles=72))
+    ct, Vt, rt = solve(table)
+    cw, Vw, rw = solve(dict(table, search=dict(mode="table_walk", n_angles=72)))
+    free = torch.from_numpy(np.ascontiguousarray(ct.kind().cpu().numpy() == 0)).cuda()
+    d = ((Vw - Vt).abs() / Vt.abs().clamp(min=1.0))[free]
+    rw.update({"max_rel_diff_vs_table": float(d.max()), "frac_within_1e-4": float((d <= 1e-4).float().mean()),
+               "min_diff_vs_table": float((Vw - Vt)[free].min()), "speedup_vs_table": rt["seconds"] / rw["seconds"],
+               "evals_ratio_table_over_walk": rt["evals"] / rw["evals"]})
+    out["table72_exhaustive"] = rt
+    out["table72_walk"] = rw
+    log(f"bench: table 72 {rt}")
+    log(f"bench: walk 72 {rw}")
+    ch, Vh, rh = solve(dict(inputs.PI48, integrator="heun"))
+    dh = ((Vh - V_euler).abs() / V_euler.abs().clamp(min=1.0))[free]
+    rh.update({"max_rel_diff_vs_euler": float(dh.max()), "median_rel_diff_vs_euler": float(dh.median())})
+    out["heun_scan_golden"] = rh
+    log(f"bench: heun {rh}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -279,6 +327,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 16-problem measurement")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 96^3 x 64 solves and the network-seeded comparison")
+    ap.add_argument("--no-variants", action="store_true", help="skip the table-walk and Heun-foot solves")
     ap.add_argument("--held-out", action="store_true",
                     help="also solve the 96^3 x 64 problem with thrust 5e-4 using the network trained at 1e-3")
     ap.add_argument("--calib-copy", action="store_true",
@@ -390,6 +439,11 @@ def main():
         }
         log(f"bench: converge {converge}")
 
+    variants = None
+    if not args.no_variants and converge is not None:
+        log("bench: paper variants (table walk, Heun foot)")
+        variants = bench_variants(mask, Vc1)
+
     large = None
     if not args.no_large:
         log("bench: 96^3 x 64 solves")
@@ -463,6 +517,7 @@ def main():
             "naive_gather_frac": value * GATHER_BYTES_PER_EVAL / 1e9 / HBM_PEAK_GBS,
         },
         "time_to_converge": converge,
+        "paper_variants": variants,
         "large_96x96x96x64": large,
         "batched": batched,
         "cpu_baseline": cpu,

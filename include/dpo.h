@@ -47,10 +47,14 @@ enum {
 
 enum { DPO_MODEL_ORBIT = 0, DPO_MODEL_EIKONAL = 1 };
 
+/* One-step approximation of the trajectory from a node (the foot point). */
+enum { DPO_STEP_EULER = 0, DPO_STEP_HEUN = 1 };
+
 enum {
   DPO_SEARCH_TABLE = 0,       /* coast + n_angles tabulated thrust angles (exhaustive) */
   DPO_SEARCH_SCAN_GOLDEN = 1, /* scan of n_scan angles, n_golden golden-section steps */
-  DPO_SEARCH_SEEDED = 2       /* local golden search around a per-node seed angle */
+  DPO_SEARCH_SEEDED = 2,      /* local golden search around a per-node seed angle */
+  DPO_SEARCH_TABLE_WALK = 3   /* the TABLE controls, searched by a walk from the previous optimum */
 };
 
 /* Node kinds reported by dpo_get_kind(). */
@@ -69,7 +73,14 @@ typedef struct {
  *  model ORBIT:   r' = v_r, v_r' = v_t^2/r - mu/r^2 + thr*(accel/m)*sin u,
  *                 v_t' = -v_r*v_t/r + thr*(accel/m)*cos u, m' = -mdot*thr;
  *  model EIKONAL: v_r' = thr*speed*sin u, v_t' = thr*speed*cos u (r, m fixed).
- *  Foot point: one explicit Euler step of length dt.
+ *  Foot point x + dt*Phi(x, f) (eq:schema), the control held over the step:
+ *  integrator DPO_STEP_EULER: Phi = b(x), one explicit Euler step;
+ *  DPO_STEP_HEUN: Phi = (b(x) + b(x + dt*b(x)))/2, Heun's second-order
+ *  Runge-Kutta step (the paper's choice, Section 3).  Under Heun the r and m
+ *  cells of a thrust foot depend on the angle, so the factorised sweep and
+ *  the foot descriptors do not apply: sweeps take the direct path, policy
+ *  evaluation recomputes the foot from the stored angle, and the batched
+ *  solver rejects the problem.
  *  Running cost l = w_time + w_fuel*thr; discount exp(-lambda*dt) (eq:cost).
  *  M: value of I[V] outside the domain and at inactive nodes.
  *  Target: nodes with |x_k - tgt_c[k]| <= tgt_w[k] + h_k/2 on every axis get
@@ -78,6 +89,7 @@ typedef struct {
   int32_t model;
   double mu, accel, mdot, dt, lambda, w_time, w_fuel, M, speed;
   double tgt_c[4], tgt_w[4];
+  int32_t integrator; /* DPO_STEP_EULER or DPO_STEP_HEUN */
 } dpo_problem;
 
 /* Minimisation over the control set (paper Section 3, "Efficient computation
@@ -93,6 +105,16 @@ typedef struct {
  *               with n_local evaluations in total, then coast; a node whose best
  *               Q differs from its current value by more than
  *               fallback_tol*max(1,|V|) repeats the SCAN_GOLDEN search.
+ *  TABLE_WALK:  the TABLE controls, searched as in Section 3 ("Efficient
+ *               computation of the minimum") after the first iteration: start
+ *               at the table angle nearest to the node's previous optimum,
+ *               look at both cyclic neighbours, move to the lower one if it is
+ *               strictly below (the lower-index side on a tie between them),
+ *               then keep moving the same way while the next angle is strictly
+ *               lower; thrust iff the walk's Q is strictly below coast.  The
+ *               walk stops on any local minimiser of the table, including a
+ *               plateau of equal values.  Where no previous optimum exists
+ *               (the first sweep of a solve) the full table is searched.
  *  Limits: 1 <= n_angles <= 1024; 8 <= n_scan <= 1024; 0 <= n_golden <= 64. */
 typedef struct {
   int32_t mode, n_angles, n_scan, n_golden, n_local;
@@ -103,7 +125,7 @@ typedef struct {
 typedef struct {
   int64_t sweeps;         /* Bellman sweeps with full search (VI sweeps or PI greedy steps) */
   int64_t eval_sweeps;    /* frozen-policy sweeps */
-  int64_t evals;          /* node-control Q evaluations */
+  int64_t evals;          /* node-control Q evaluations (TABLE_WALK: counted by the sweeps) */
   int64_t fallback_nodes; /* SEEDED: nodes that repeated the full search */
   int64_t verify_steps;   /* seeded policy iteration: full-search greedy steps after the first */
   double resid_max_rel;   /* last max |dV|/max(1,|V|) over free nodes (FP64) */
@@ -177,9 +199,13 @@ int dpo_init_value(dpo_ctx* ctx, float* V, void* stream);
  * written: V_out must already hold their fixed values (dpo_init_value or a
  * copy of V_in).  V_in and V_out must not overlap.  If resid is not NULL it
  * receives (device double[5]) max|dV|/max(1,|V_out|), sum|dV|, max|dV|, the
- * count of non-finite outputs and the count of seeded-search fallbacks,
+ * count of non-finite outputs and the count of seeded-search fallbacks (for
+ * TABLE_WALK: the walks' thrust evaluations),
  * accumulated over the free nodes in FP64 in a fixed order.  pol_angle /
- * pol_thr may be NULL.  SEEDED mode needs dpo_bellman_sweep_seeded instead. */
+ * pol_thr may be NULL.  SEEDED mode needs dpo_bellman_sweep_seeded instead.
+ * TABLE_WALK: pol_angle is required and read on entry: each node's walk
+ * starts at the table angle nearest to its entry (a non-finite entry starts
+ * at index 0), and the entry is then overwritten with the walk's result. */
 int dpo_bellman_sweep(dpo_ctx* ctx, const float* V_in, float* V_out, float* pol_angle,
                       uint8_t* pol_thr, double* resid, void* stream);
 
@@ -204,7 +230,8 @@ int dpo_policy_eval_sweep(dpo_ctx* ctx, const float* V_in, float* V_out, const f
  * control's foot, so this sweep is one descriptor load, 16 gathers and 15
  * lerps per node (the evaluation sweep of policy iteration, eq:p_eval).
  * Same fixed-node rule as dpo_bellman_sweep; no residual.  DPO_EINVAL if no
- * Bellman sweep has run on ctx. */
+ * Bellman sweep has run on ctx, or for the Heun foot (descriptors need the
+ * Euler step). */
 int dpo_policy_eval_sweep_last(dpo_ctx* ctx, const float* V_in, float* V_out, void* stream);
 
 /* --------------------------------------------------------------- solvers */
@@ -213,7 +240,9 @@ int dpo_policy_eval_sweep_last(dpo_ctx* ctx, const float* V_in, float* V_out, vo
  * V <- T V from the given V (initialise with dpo_init_value) until the
  * relative residual max|dV|/max(1,|V|) < tol_rel, checked every check_every
  * sweeps, or until it has not decreased for 64 checks (stalled).  Returns
- * DPO_ENOCONV after max_sweeps.  V, pol_angle, pol_thr: device, N entries. */
+ * DPO_ENOCONV after max_sweeps.  V, pol_angle, pol_thr: device, N entries.
+ * TABLE_WALK: the first sweep searches the full table, every later sweep
+ * walks from the previous sweep's angles. */
 int dpo_solve_vi(dpo_ctx* ctx, float* V, float* pol_angle, uint8_t* pol_thr, double tol_rel,
                  int64_t max_sweeps, int32_t check_every, dpo_stats* stats, void* stream);
 
@@ -234,6 +263,8 @@ int dpo_solve_vi(dpo_ctx* ctx, float* V, float* pol_angle, uint8_t* pol_thr, dou
  * be pol_angle itself (each node reads its seed before its angle is
  * overwritten), which warm-starts every node from its previous optimum as in
  * paper Section 3, "Efficient computation of the minimum".
+ * TABLE_WALK: the first greedy step searches the full table, later ones walk
+ * from the current policy's angles (the incumbent rule applies as above).
  * Returns DPO_ENOCONV after max_outer greedy steps, or when 32 full-search
  * greedy steps in a row bring no new lowest residual (stats->stalled). */
 int dpo_solve_pi(dpo_ctx* ctx, float* V, float* pol_angle, uint8_t* pol_thr, double tol_rel,
@@ -248,7 +279,8 @@ int dpo_value_at(dpo_ctx* ctx, const float* V, const double* x, double* out, voi
 
 /* Approximate optimal feedback eq:feed at n arbitrary states (device
  * double[n*4]) with time step tau, using the context's search (TABLE or
- * SCAN_GOLDEN): best thrust angle, throttle, and the minimal Q (q_out nullable). */
+ * SCAN_GOLDEN; TABLE_WALK searches its full table) and integrator: best
+ * thrust angle, throttle, and the minimal Q (q_out nullable). */
 int dpo_extract_feedback(dpo_ctx* ctx, const float* V, const double* states, int64_t n,
                          double tau, float* angle_out, uint8_t* thr_out, float* q_out,
                          void* stream);
@@ -289,7 +321,7 @@ int dpo_probe_foot(dpo_ctx* ctx, const int32_t* nodes, const uint8_t* thr, const
  * problem stops, the graph is re-captured over the remaining ones.  Sweep
  * counts are therefore multiples of S.  Each problem gets its own grid and physics; the search
  * (TABLE or SCAN_GOLDEN) is shared, and the factorised sweep must apply to
- * every problem. */
+ * every problem (so the Euler foot only). */
 typedef struct dpo_batch dpo_batch;
 
 typedef struct {

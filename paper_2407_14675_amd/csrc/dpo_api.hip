@@ -57,6 +57,8 @@ struct dpo_ctx {
   int desc_format = -1;        // 0 flat 32-bit codes, 1 compact by free node, 2 compact by node
   float2* desc_w = nullptr;
   bool desc_valid = false;    // a sweep has written them
+  unsigned long long* eval_acc = nullptr;  // table walk: per-workgroup thrust-evaluation counts
+  unsigned long long* eval_sum = nullptr;
   std::string err;
 };
 
@@ -104,12 +106,14 @@ int validate_problem(dpo_ctx* c, const dpo_problem* p) {
   if (!std::isfinite(p->M)) return fail(c, DPO_EINVAL, "problem: M must be finite");
   if (p->model == DPO_MODEL_ORBIT && !(p->accel >= 0 && p->mdot >= 0))
     return fail(c, DPO_EINVAL, "problem: accel and mdot must be >= 0");
+  if (p->integrator != DPO_STEP_EULER && p->integrator != DPO_STEP_HEUN)
+    return fail(c, DPO_EINVAL, "problem: unknown integrator");
   return DPO_OK;
 }
 
 int validate_search(dpo_ctx* c, const dpo_search* s) {
   if (!s) return fail(c, DPO_EINVAL, "search is NULL");
-  if (s->mode == DPO_SEARCH_TABLE) {
+  if (s->mode == DPO_SEARCH_TABLE || s->mode == DPO_SEARCH_TABLE_WALK) {
     if (s->n_angles < 1 || s->n_angles > 1024) return fail(c, DPO_EINVAL, "search: n_angles in [1, 1024]");
   } else if (s->mode == DPO_SEARCH_SCAN_GOLDEN || s->mode == DPO_SEARCH_SEEDED) {
     if (s->n_scan < 8 || s->n_scan > 1024) return fail(c, DPO_EINVAL, "search: n_scan in [8, 1024]");
@@ -163,7 +167,8 @@ int upload_table(dpo_ctx* c) {
     golden_rotations(c->search.local_half_width > 0 ? c->search.local_half_width : 0.1, r.data() + kRot);
     HIP_TRY(c, hipMemcpy(c->rot, r.data(), sizeof(float) * 2 * kRot, hipMemcpyHostToDevice));
   }
-  const int K = c->search.mode == DPO_SEARCH_TABLE ? c->search.n_angles : c->search.n_scan;
+  const bool table = c->search.mode == DPO_SEARCH_TABLE || c->search.mode == DPO_SEARCH_TABLE_WALK;
+  const int K = table ? c->search.n_angles : c->search.n_scan;
   if (K > c->tab_cap) {
     if (c->tab) hipFree(c->tab);
     c->tab = nullptr;
@@ -328,14 +333,49 @@ int read_resid(dpo_ctx* c, double h[kPartial], hipStream_t s) {
 }
 
 int64_t evals_per_full_search(const dpo_ctx* c) {
-  if (c->search.mode == DPO_SEARCH_TABLE) return 1 + c->search.n_angles;
+  if (c->search.mode == DPO_SEARCH_TABLE || c->search.mode == DPO_SEARCH_TABLE_WALK) return 1 + c->search.n_angles;
   return 1 + c->search.n_scan + (c->search.n_golden > 0 ? 2 + c->search.n_golden : 0);
 }
 
 bool use_fast(const dpo_ctx* c) { return c->path == 2 || (c->path == 0 && c->fast_ok); }
 
+// Foot descriptors record the r and m cells as functions of the node and the
+// throttle alone, which holds for the Euler foot only.
+bool desc_ok(const dpo_ctx* c) { return !c->P.heun; }
+
+// Table walk evaluation counters: one entry per workgroup of the largest grid
+// any sweep launches (workgroups of 64 threads and up).
+int ensure_walk(dpo_ctx* c) {
+  if (c->eval_acc) return DPO_OK;
+  const size_t n = (size_t)blocks_for(std::max<int64_t>(1, c->n_free), 64);
+  if (hipMalloc(&c->eval_acc, sizeof(unsigned long long) * n) != hipSuccess ||
+      hipMalloc(&c->eval_sum, sizeof(unsigned long long)) != hipSuccess)
+    return fail(c, DPO_ENOMEM, "walk counter alloc");
+  return DPO_OK;
+}
+
+int walk_counts_zero(dpo_ctx* c, hipStream_t s) {
+  const size_t n = (size_t)blocks_for(std::max<int64_t>(1, c->n_free), 64);
+  HIP_TRY(c, hipMemsetAsync(c->eval_acc, 0, sizeof(unsigned long long) * n, s));
+  return DPO_OK;
+}
+
+// Sum of the walk's thrust evaluations since walk_counts_zero (synchronises s).
+int walk_counts_read(dpo_ctx* c, hipStream_t s, int64_t* out) {
+  const int n = blocks_for(std::max<int64_t>(1, c->n_free), 64);
+  unsigned long long h = 0;
+  HIP_TRY(c, launch_sum_counts(c->eval_acc, n, c->eval_sum, s));
+  HIP_TRY(c, hipMemcpyAsync(&h, c->eval_sum, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  *out = (int64_t)h;
+  return DPO_OK;
+}
+
+// walk_from: TABLE_WALK sweeps walk from these angles (null: the full table);
+// count: add the walk's thrust evaluations to the context's counters.
 int sweep_full(dpo_ctx* c, const float* Vin, float* Vout, float* ang, uint8_t* thr, hipStream_t s,
-               bool desc = false, bool incumbent = false, bool want_resid = true) {
+               bool desc = false, bool incumbent = false, bool want_resid = true, const float* walk_from = nullptr,
+               bool count = false) {
   SweepArgs a = base_args(c);
   if (!want_resid) a.partial = nullptr;
   a.V_in = Vin;
@@ -346,12 +386,17 @@ int sweep_full(dpo_ctx* c, const float* Vin, float* Vout, float* ang, uint8_t* t
     a.pol_ang_in = ang;
     a.pol_thr_in = thr;
   }
-  if (desc) set_desc_out(c, a);
+  if (desc && desc_ok(c)) set_desc_out(c, a);
   if (a.n_free == 0) return DPO_OK;
-  const int mode = c->search.mode == DPO_SEARCH_TABLE ? 0 : 1;
+  int mode = c->search.mode == DPO_SEARCH_SCAN_GOLDEN ? 1 : 0;
+  if (c->search.mode == DPO_SEARCH_TABLE_WALK && walk_from) {
+    mode = 3;
+    a.walk_from = walk_from;
+    if (count) a.eval_acc = c->eval_acc;
+  }
   hipError_t e;
   if (use_fast(c)) e = launch_sweep_fast(a, mode, c->block, s);
-  else e = mode == 0 ? launch_sweep_table(a, s) : launch_sweep_scan_golden(a, s);
+  else e = launch_sweep_direct(a, mode, s);
   c->last_blocks = blocks_for(c->n_free, use_fast(c) ? c->block : kBlock);
   if (e != hipSuccess) return hip_fail(c, e, "bellman sweep launch");
   return DPO_OK;
@@ -369,10 +414,10 @@ int sweep_seeded(dpo_ctx* c, const float* Vin, float* Vout, float* ang, uint8_t*
     a.pol_thr_in = thr;
   }
   a.seed = seed;
-  if (desc) set_desc_out(c, a);
+  if (desc && desc_ok(c)) set_desc_out(c, a);
   if (a.n_free == 0) return DPO_OK;
   if (!use_fast(c)) {
-    hipError_t e = launch_sweep_seeded(a, s);
+    hipError_t e = launch_sweep_direct(a, 2, s);
     c->last_blocks = blocks_for(c->n_free, kBlock);
     if (e != hipSuccess) return hip_fail(c, e, "seeded sweep launch");
     return DPO_OK;
@@ -467,6 +512,7 @@ int dpo_create(const dpo_grid* grid, const dpo_problem* prob, const dpo_search* 
   c->search = *search;
   c->G = make_grid(*grid);
   c->P.model = prob->model;
+  c->P.heun = prob->integrator == DPO_STEP_HEUN ? 1 : 0;
   c->P.mu = prob->mu;
   c->P.accel = prob->accel;
   c->P.mdot = prob->mdot;
@@ -527,7 +573,7 @@ int dpo_create(const dpo_grid* grid, const dpo_problem* prob, const dpo_search* 
     c->gm = (float)gm;
     // the factorised thrust kernel needs every thrust foot of a node within two
     // cells per moving axis and within one m cell
-    c->fast_ok = gmax < 0.45 && gm > -1.0 && gm <= 0.0;
+    c->fast_ok = gmax < 0.45 && gm > -1.0 && gm <= 0.0 && prob->integrator == DPO_STEP_EULER;
     hipError_t e1 = hipMemcpy(c->rinv, rinv.data(), sizeof(double) * rinv.size(), hipMemcpyHostToDevice);
     hipError_t e2 = hipMemcpy(c->gtab, gt.data(), sizeof(float) * gt.size(), hipMemcpyHostToDevice);
     if (e1 != hipSuccess || e2 != hipSuccess) {
@@ -573,6 +619,8 @@ void dpo_destroy(dpo_ctx* c) {
   if (c->desc_code) hipFree(c->desc_code);
   if (c->desc16) hipFree(c->desc16);
   if (c->desc_w) hipFree(c->desc_w);
+  if (c->eval_acc) hipFree(c->eval_acc);
+  if (c->eval_sum) hipFree(c->eval_sum);
   delete c;
 }
 
@@ -612,6 +660,11 @@ int dpo_kernel_path(const dpo_ctx* c) {
 
 int dpo_eval_sweep_bytes(const dpo_ctx* c, int64_t* bytes) {
   if (!c || !bytes) return fail(const_cast<dpo_ctx*>(c), DPO_EINVAL, "NULL argument");
+  if (!desc_ok(c)) {
+    // Heun: the frozen-policy sweep reads coordinates, angle and throttle
+    *bytes = (4 + 4 + 1 + 8) * c->n_free;
+    return DPO_OK;
+  }
   // the stream plus one value read (the gather's share) and one value write per free node
   *bytes = eval_stream_bytes(c) + 8 * c->n_free;
   return DPO_OK;
@@ -638,9 +691,11 @@ int dpo_bellman_sweep(dpo_ctx* c, const float* V_in, float* V_out, float* pol_an
   if (!V_in || !V_out) return fail(c, DPO_EINVAL, "V_in / V_out is NULL");
   if (V_in == V_out) return fail(c, DPO_EINVAL, "V_in and V_out must differ (Jacobi sweep)");
   if (c->search.mode == DPO_SEARCH_SEEDED) return fail(c, DPO_EINVAL, "SEEDED mode: use dpo_bellman_sweep_seeded");
-  int rc = ensure_desc(c);
+  const bool walk = c->search.mode == DPO_SEARCH_TABLE_WALK;
+  if (walk && !pol_angle) return fail(c, DPO_EINVAL, "TABLE_WALK: pol_angle holds the walk's start and is required");
+  int rc = desc_ok(c) ? ensure_desc(c) : DPO_OK;
   if (rc != DPO_OK) return rc;
-  rc = sweep_full(c, V_in, V_out, pol_angle, pol_thr, S(stream), true);
+  rc = sweep_full(c, V_in, V_out, pol_angle, pol_thr, S(stream), true, false, true, walk ? pol_angle : nullptr);
   if (rc != DPO_OK) return rc;
   return finish_resid(c, resid, S(stream));
 }
@@ -651,7 +706,7 @@ int dpo_bellman_sweep_seeded(dpo_ctx* c, const float* V_in, float* V_out, float*
   if (!V_in || !V_out || !seed_angle) return fail(c, DPO_EINVAL, "V_in / V_out / seed_angle is NULL");
   if (V_in == V_out) return fail(c, DPO_EINVAL, "V_in and V_out must differ (Jacobi sweep)");
   if (c->search.mode != DPO_SEARCH_SEEDED) return fail(c, DPO_EINVAL, "search mode is not SEEDED");
-  int rc = ensure_desc(c);
+  int rc = desc_ok(c) ? ensure_desc(c) : DPO_OK;
   if (rc != DPO_OK) return rc;
   rc = sweep_seeded(c, V_in, V_out, pol_angle, pol_thr, seed_angle, S(stream), true);
   if (rc != DPO_OK) return rc;
@@ -672,6 +727,7 @@ int dpo_policy_eval_sweep_last(dpo_ctx* c, const float* V_in, float* V_out, void
   if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
   if (!V_in || !V_out) return fail(c, DPO_EINVAL, "V_in / V_out is NULL");
   if (V_in == V_out) return fail(c, DPO_EINVAL, "V_in and V_out must differ (Jacobi sweep)");
+  if (!desc_ok(c)) return fail(c, DPO_EINVAL, "foot descriptors need the Euler foot; use dpo_policy_eval_sweep");
   if (!c->desc_valid) return fail(c, DPO_EINVAL, "no Bellman sweep has chosen a policy yet");
   return sweep_eval_desc(c, V_in, V_out, S(stream));
 }
@@ -685,6 +741,8 @@ int dpo_solve_vi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, doubl
   int rc = ensure_work(c);
   if (rc != DPO_OK) return rc;
   hipStream_t s = S(stream);
+  const bool walk = c->search.mode == DPO_SEARCH_TABLE_WALK;
+  if (walk && ((rc = ensure_walk(c)) != DPO_OK || (rc = walk_counts_zero(c, s)) != DPO_OK)) return rc;
   dpo_stats local;
   std::memset(&local, 0, sizeof(local));
   const double t0 = now_s();
@@ -699,7 +757,9 @@ int dpo_solve_vi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, doubl
   while (k < max_sweeps) {
     // only the sweeps that end a check interval compute the residual
     const bool check = (k + 1) % check_every == 0 || k + 1 == max_sweeps;
-    rc = sweep_full(c, cur, nxt, pol_angle, pol_thr, s, false, false, check);
+    // TABLE_WALK: the first sweep searches the full table, later ones walk from the previous angles
+    rc = sweep_full(c, cur, nxt, pol_angle, pol_thr, s, false, false, check, walk && k > 0 ? pol_angle : nullptr,
+                    true);
     if (rc != DPO_OK) return rc;
     k++;
     std::swap(cur, nxt);
@@ -729,6 +789,11 @@ int dpo_solve_vi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, doubl
   HIP_TRY(c, hipStreamSynchronize(s));
   local.sweeps = k;
   local.evals = k * c->n_free * evals_per_full_search(c);
+  if (walk) {
+    int64_t w = 0;
+    if ((rc = walk_counts_read(c, s, &w)) != DPO_OK) return rc;
+    local.evals = k * c->n_free + (k > 0 ? c->n_free * c->search.n_angles : 0) + w;
+  }
   local.resid_max_rel = h[0];
   local.resid_sum_abs = h[1];
   local.resid_max_abs = h[2];
@@ -748,9 +813,11 @@ int dpo_solve_pi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, doubl
   if (!seeded && c->search.mode == DPO_SEARCH_SEEDED) return fail(c, DPO_EINVAL, "SEEDED mode needs seed_angle");
   int rc = ensure_work(c);
   if (rc != DPO_OK) return rc;
-  if ((rc = ensure_desc(c)) != DPO_OK) return rc;
+  if (desc_ok(c) && (rc = ensure_desc(c)) != DPO_OK) return rc;
   if ((rc = ensure_pi_buffers(c)) != DPO_OK) return rc;
   hipStream_t s = S(stream);
+  const bool walk = c->search.mode == DPO_SEARCH_TABLE_WALK;
+  if (walk && ((rc = ensure_walk(c)) != DPO_OK || (rc = walk_counts_zero(c, s)) != DPO_OK)) return rc;
   dpo_stats local;
   std::memset(&local, 0, sizeof(local));
   const double t0 = now_s();
@@ -778,7 +845,7 @@ int dpo_solve_pi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, doubl
     // greedy step: policy improvement together with T V
     const bool use_seed = seeded && it > 0 && !verify;
     if (use_seed) rc = sweep_seeded(c, cur, G, pol_angle, pol_thr, seed_angle, s, true, true);
-    else rc = sweep_full(c, cur, G, pol_angle, pol_thr, s, true, it > 0);
+    else rc = sweep_full(c, cur, G, pol_angle, pol_thr, s, true, it > 0, true, walk && it > 0 ? pol_angle : nullptr, true);
     if (rc != DPO_OK) return rc;
     it++;
     if ((rc = finish_resid(c, c->resid, s)) != DPO_OK) return rc;
@@ -793,7 +860,8 @@ int dpo_solve_pi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, doubl
           dst = b;
           break;
         }
-      if ((rc = sweep_eval_desc(c, src, dst, s)) != DPO_OK) return rc;
+      rc = desc_ok(c) ? sweep_eval_desc(c, src, dst, s) : sweep_eval(c, src, dst, pol_angle, pol_thr, false, s);
+      if (rc != DPO_OK) return rc;
       src = dst;
     }
     HIP_TRY(c, hipEventSynchronize(c->resid_ready));
@@ -803,7 +871,8 @@ int dpo_solve_pi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, doubl
       fallback += (int64_t)h[4];
       evals += c->n_free * (1 + c->search.n_local) + (int64_t)h[4] * evals_per_full_search(c);
     } else {
-      evals += c->n_free * evals_per_full_search(c);
+      // walk steps: coast here, the walk's thrust evaluations from the counters at the end
+      evals += c->n_free * (walk && it > 1 ? 1 : evals_per_full_search(c));
       if (seeded && it > 1) local.verify_steps++;
     }
     if (h[3] > 0) {
@@ -846,6 +915,11 @@ int dpo_solve_pi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, doubl
   }
   if (cur != V) HIP_TRY(c, hipMemcpyAsync(V, cur, sizeof(float) * (size_t)c->N, hipMemcpyDeviceToDevice, s));
   HIP_TRY(c, hipStreamSynchronize(s));
+  if (walk) {
+    int64_t w = 0;
+    if ((rc = walk_counts_read(c, s, &w)) != DPO_OK) return rc;
+    evals += w;
+  }
   local.sweeps = it;
   local.evals = evals;
   local.fallback_nodes = fallback;
@@ -874,7 +948,7 @@ int dpo_extract_feedback(dpo_ctx* c, const float* V, const double* states, int64
   if (!V || !states || !angle_out || !thr_out) return fail(c, DPO_EINVAL, "null array argument");
   if (n < 0 || n > 0x7fffffff) return fail(c, DPO_EINVAL, "bad n");
   if (!(tau > 0)) return fail(c, DPO_EINVAL, "tau must be > 0");
-  if (c->search.mode == DPO_SEARCH_SEEDED) return fail(c, DPO_EINVAL, "feedback needs TABLE or SCAN_GOLDEN");
+  if (c->search.mode == DPO_SEARCH_SEEDED) return fail(c, DPO_EINVAL, "feedback needs TABLE, SCAN_GOLDEN or TABLE_WALK");
   if (n == 0) return DPO_OK;
   SweepArgs a = base_args(c);
   a.V_in = V;

@@ -49,10 +49,12 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(8))) 
   a.pol_thr_in = nullptr;
   a.fb_list = nullptr;
   a.fb_count = nullptr;
+  a.walk_from = nullptr;
+  a.eval_acc = nullptr;
   const int t = (tile - B.tile_begin[k]) * blockDim.x + threadIdx.x;
   double rel = 0, sum = 0, mabs = 0, bad = 0;
-  int fell_back = 0, deferred = 0;
-  if (t < a.n_free) fast_node<kMode>(a, t, dyn_lds, rel, sum, mabs, bad, fell_back, deferred);
+  int fell_back = 0, deferred = 0, evals = 0;
+  if (t < a.n_free) fast_node<kMode>(a, t, dyn_lds, rel, sum, mabs, bad, fell_back, deferred, evals);
   // only the last sweep of a graph replay feeds the stop decision
   if (want_resid) block_residual(rel, sum, mabs, bad, (double)fell_back, B.partial, tile);
 }

@@ -26,6 +26,7 @@ struct Grid {
 
 struct Phys {
   int model;  // 0 orbit, 1 eikonal
+  int heun;   // 1: Heun (second-order Runge-Kutta) foot point, 0: Euler
   double mu, accel, mdot, dt, speed;
   float q_coast;  // dt * w_time
   float q_thr;    // dt * (w_time + w_fuel)
@@ -173,22 +174,99 @@ __device__ inline float interp_off(const float* __restrict__ V, const Grid& G, c
   return cell_value(V + (base[0] + base[1] * G.st[1] + base[2] * G.st[2] + base[3] * G.st[3]), G, t);
 }
 
-// Q of one control at a node: dt*l + gamma * I[V](foot).
-template <bool kSnap = false>
-__device__ inline float q_thrust(const float* __restrict__ V, const Grid& G, const Phys& P,
-                                 const NodeTerms& T, float sn, float cs) {
-  float off[4];
-  off[0] = T.drift[0];
-  off[1] = fmaf(T.g1, sn, T.drift[1]);
-  off[2] = fmaf(T.g2, cs, T.drift[2]);
-  off[3] = T.drift[3] + T.gm;
-  return fmaf(P.gamma, interp_off<kSnap>(V, G, T.i, off, P.M), P.q_thr);
+// ---- Heun foot point (paper Section 3 names a second-order Runge-Kutta
+// step): foot = x + tau*(b(x) + b(x~))/2 with x~ = x + tau*b(x), i.e. the
+// Euler displacement tau*b(x) plus (tau/2)*(b(x~) - b(x)).  The Euler part
+// comes from NodeTerms as on the Euler path; the correction is formed in
+// float from the predictor's increments, with every difference of nearly
+// equal terms (1/r~ - 1/r, v_t~^2/r~ - v_t^2/r, ...) written as a product of
+// increments, so it carries float's relative error on its own size
+// (~1e-2 cell) instead of on the slopes.  The eikonal field does not depend
+// on the state: there the correction is zero.
+struct HeunTerms {
+  float r, vr, vt, m;  // the state the step starts from
+  float d1, d2;        // control-free slopes along v_r and v_t (rounded from FP64)
+  float acc;           // accel / m
+  float tau, mdot, mu, accel;
+  float sc[3];         // (tau/2) / h_k for r, v_r, v_t
+  int orbit;
+};
+
+__device__ inline void heun_terms(const Grid& G, const Phys& P, const double x[4], double tau, HeunTerms& H) {
+#pragma clang fp contract(off)
+  H.orbit = P.model == 0;
+  const double r = x[0], vr = x[1], vt = x[2], m = x[3];
+  H.r = (float)r;
+  H.vr = (float)vr;
+  H.vt = (float)vt;
+  H.m = (float)m;
+  if (H.orbit) {
+    const double inv_r = 1.0 / r;
+    H.d1 = (float)(vt * vt * inv_r - P.mu * inv_r * inv_r);
+    H.d2 = (float)(-vr * vt * inv_r);
+    H.acc = (float)(P.accel / m);
+  } else {
+    H.d1 = H.d2 = H.acc = 0.0f;
+  }
+  H.tau = (float)tau;
+  H.mdot = (float)P.mdot;
+  H.mu = (float)P.mu;
+  H.accel = (float)P.accel;
+  for (int k = 0; k < 3; k++) H.sc[k] = (float)(0.5 * tau * G.inv_h[k]);
 }
 
-template <bool kSnap = false>
-__device__ inline float q_coast(const float* __restrict__ V, const Grid& G, const Phys& P,
-                                const NodeTerms& T) {
-  return fmaf(P.gamma, interp_off<kSnap>(V, G, T.i, T.drift, P.M), P.q_coast);
+// (tau/2)*(b(x~) - b(x)) in cells along r, v_r, v_t (m: zero, its rate is constant).
+__device__ inline void heun_corr(const HeunTerms& H, int thr, float sn, float cs, float c[3]) {
+  if (!H.orbit) {
+    c[0] = c[1] = c[2] = 0.0f;
+    return;
+  }
+  const float k1v = thr ? fmaf(H.acc, sn, H.d1) : H.d1;
+  const float k1t = thr ? fmaf(H.acc, cs, H.d2) : H.d2;
+  const float dr = H.tau * H.vr, dv = H.tau * k1v, dw = H.tau * k1t;
+  const float rt = H.r + dr;
+  const float inv = 1.0f / (H.r * rt);
+  // v_t~^2/r~ - v_t^2/r and -mu (1/r~^2 - 1/r^2)
+  const float cent = (dw * (2.0f * H.vt + dw) * H.r - H.vt * H.vt * dr) * inv;
+  const float grav = H.mu * dr * (2.0f * H.r + dr) * inv * inv;
+  // -(v_r~ v_t~/r~ - v_r v_t/r)
+  const float cor = -((dv * H.vt + H.vr * dw + dv * dw) * H.r - H.vr * H.vt * dr) * inv;
+  float tv = 0.0f, tt = 0.0f;
+  if (thr) {
+    const float dm = -H.tau * H.mdot;
+    const float dinv_m = -dm / (H.m * (H.m + dm));  // 1/m~ - 1/m
+    tv = H.accel * sn * dinv_m;
+    tt = H.accel * cs * dinv_m;
+  }
+  c[0] = H.sc[0] * dv;
+  c[1] = H.sc[1] * (cent + grav + tv);
+  c[2] = H.sc[2] * (cor + tt);
+}
+
+// Foot displacement (cells) of a control under the node's integrator.
+template <bool kHeun>
+__device__ inline void foot_off(const NodeTerms& T, const HeunTerms& H, int thr, float sn, float cs, float off[4]) {
+  off[0] = T.drift[0];
+  off[1] = thr ? fmaf(T.g1, sn, T.drift[1]) : T.drift[1];
+  off[2] = thr ? fmaf(T.g2, cs, T.drift[2]) : T.drift[2];
+  off[3] = T.drift[3] + (thr ? T.gm : 0.0f);
+  if (kHeun) {
+    float c[3];
+    heun_corr(H, thr, sn, cs, c);
+    off[0] += c[0];
+    off[1] += c[1];
+    off[2] += c[2];
+  }
+}
+
+// Q of one control at a node, dt*l + gamma * I[V](foot), for thr (angle given
+// by its sin/cos) under either integrator.
+template <bool kHeun, bool kSnap = false>
+__device__ inline float q_step(const float* __restrict__ V, const Grid& G, const Phys& P, const NodeTerms& T,
+                               const HeunTerms& H, int thr, float sn, float cs) {
+  float off[4];
+  foot_off<kHeun>(T, H, thr, sn, cs, off);
+  return fmaf(P.gamma, interp_off<kSnap>(V, G, T.i, off, P.M), thr ? P.q_thr : P.q_coast);
 }
 
 __device__ inline float wrap_pi(float u) {

@@ -20,6 +20,8 @@ struct SweepArgs {
   const float* pol_ang_in;    // frozen policy (evaluation sweep); greedy sweeps: incumbent, nullable
   const uint8_t* pol_thr_in;  // frozen policy (evaluation sweep); greedy sweeps: incumbent, nullable
   const float* seed;          // seeded search
+  const float* walk_from;     // table walk: each node's previous angle (may alias pol_ang)
+  unsigned long long* eval_acc;  // table walk: per-workgroup running count of thrust evaluations, nullable
   int* fb_list;               // seeded search on the factorised path: nodes whose full search is deferred, nullable
   int* fb_count;              // their count (zeroed before the sweep)
   const uint32_t* free_node;  // packed coordinates (8 bits per axis, r lowest) of the free nodes
@@ -121,10 +123,12 @@ int compact_chunks(int N);
 hipError_t launch_compact(const Grid& G, const uint8_t* kind, int N, int* counts, int* offsets,
                           uint32_t* free_node, hipStream_t s);
 hipError_t launch_init_value(const uint8_t* kind, float M, float* V, int N, hipStream_t s);
-hipError_t launch_sweep_table(const SweepArgs& a, hipStream_t s);
-hipError_t launch_sweep_scan_golden(const SweepArgs& a, hipStream_t s);
-hipError_t launch_sweep_seeded(const SweepArgs& a, hipStream_t s);
+// Direct-path sweep; mode 0 table, 1 scan + golden, 2 seeded, 3 table walk
+// (the integrator comes from a.P.heun).
+hipError_t launch_sweep_direct(const SweepArgs& a, int mode, hipStream_t s);
 hipError_t launch_policy_eval(const SweepArgs& a, bool want_resid, hipStream_t s);
+// out[0] = sum of acc[0..n) (fixed order, one workgroup)
+hipError_t launch_sum_counts(const unsigned long long* acc, int n, unsigned long long* out, hipStream_t s);
 hipError_t launch_policy_eval_desc(const SweepArgs& a, bool streamed, hipStream_t s);
 // format 1: compact codes by free-list position; 2: compact codes by node
 hipError_t launch_policy_eval_desc16(const SweepArgs& a, int format, bool streamed, hipStream_t s);

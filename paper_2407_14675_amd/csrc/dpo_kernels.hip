@@ -127,33 +127,48 @@ __global__ __launch_bounds__(kBlock) void k_init_value(const uint8_t* __restrict
 }
 
 // --------------------------------------------------------------- a2..a8
+// Heun terms of a free node from its packed coordinates (grid coordinates
+// formed as lo + i*h, the product rounded before the sum).
+__device__ inline void node_heun(const SweepArgs& a, const int i[4], HeunTerms& H) {
+#pragma clang fp contract(off)
+  double x[4];
+  for (int k = 0; k < 4; k++) x[k] = a.G.lo[k] + (double)i[k] * a.G.h[k];
+  heun_terms(a.G, a.P, x, a.P.dt, H);
+}
+
 // ---- direct path: every evaluation gathers its 16 corners from V.
-// Used for any problem; the fast path below covers the orbit workloads.
-template <int kMode>
+// Used for any problem and for the Heun foot; the fast path below covers
+// the orbit workloads with the Euler foot.
+template <int kMode, bool kHeun>
 __global__ __launch_bounds__(kBlock) void k_sweep_direct(SweepArgs a) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int t = tile * kBlock + threadIdx.x;
   double rel = 0, sum = 0, mabs = 0, bad = 0;
-  int fell_back = 0;
+  int fell_back = 0, evals = 0;
   if (t < a.n_free) {
     NodeTerms T;
     const int j = node_terms_tab(a, a.free_node[t], T);
+    HeunTerms H;
+    if (kHeun) node_heun(a, T.i, H);
     const float* __restrict__ V = a.V_in;
-    auto qf = [&](float sn, float cs) { return q_thrust(V, a.G, a.P, T, sn, cs); };
-    const float qc = q_coast(V, a.G, a.P, T);
+    auto qf = [&](float sn, float cs) { return q_step<kHeun>(V, a.G, a.P, T, H, 1, sn, cs); };
+    const float qc = q_step<kHeun>(V, a.G, a.P, T, H, 0, 0.0f, 1.0f);
     const float vin = V[j];
     Choice ch;
     if (kMode == 0) table_search(qf, a, qc, ch);
     else if (kMode == 1) full_search(qf, a, qc, ch);
+    else if (kMode == 3) evals = walk_search(qf, a, a.walk_from[j], qc, ch);
     else fell_back = seeded_search(qf, a, a.seed[j], qc, vin, ch);
     keep_incumbent(qf, a, j, qc, ch);
     a.V_out[j] = ch.v;
     if (a.pol_ang) a.pol_ang[j] = ch.ang;
     if (a.pol_thr) a.pol_thr[j] = (uint8_t)ch.thr;
-    if (a.desc_code || a.desc16) write_desc(a, t, j, T, ch);
+    if (!kHeun && (a.desc_code || a.desc16)) write_desc(a, t, j, T, ch);
     node_residual(vin, ch.v, rel, sum, mabs, bad);
   }
-  if (a.partial) block_residual(rel, sum, mabs, bad, (double)fell_back, a.partial, blockIdx.x);
+  if (kMode == 3 && a.eval_acc) block_add_count(evals, a.eval_acc);
+  // the fifth residual entry: seeded fallbacks, or the walk's thrust evaluations
+  if (a.partial) block_residual(rel, sum, mabs, bad, (double)(kMode == 3 ? evals : fell_back), a.partial, blockIdx.x);
 }
 
 // Factorised-path sweep; the workgroup size is chosen at launch (64..512)
@@ -164,8 +179,9 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(8))) 
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int t = tile * blockDim.x + threadIdx.x;
   double rel = 0, sum = 0, mabs = 0, bad = 0;
-  int fell_back = 0, deferred = 0;
-  if (t < a.n_free) fast_node<kMode>(a, t, dyn_lds, rel, sum, mabs, bad, fell_back, deferred);
+  int fell_back = 0, deferred = 0, evals = 0;
+  if (t < a.n_free) fast_node<kMode>(a, t, dyn_lds, rel, sum, mabs, bad, fell_back, deferred, evals);
+  if (kMode == 3 && a.eval_acc) block_add_count(evals, a.eval_acc);
   if (kMode == 2 && a.fb_list) {
     // append the wave's deferred nodes with one atomic per wave
     const unsigned long long bal = __ballot(deferred);
@@ -177,8 +193,9 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(8))) 
       if (deferred) a.fb_list[base + __popcll(bal & ((1ull << lane) - 1ull))] = t;
     }
   }
-  // a null partial buffer (value-iteration sweeps between checks) skips the residual
-  if (a.partial) block_residual(rel, sum, mabs, bad, (double)fell_back, a.partial, blockIdx.x);
+  // a null partial buffer (value-iteration sweeps between checks) skips the residual;
+  // the fifth entry: seeded fallbacks, or the walk's thrust evaluations
+  if (a.partial) block_residual(rel, sum, mabs, bad, (double)(kMode == 3 ? evals : fell_back), a.partial, blockIdx.x);
 }
 
 // Second pass of the seeded sweep: the full search at the nodes the first
@@ -189,9 +206,9 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(8))) 
   extern __shared__ float4 dyn_lds[];
   const int count = *a.fb_count;
   double rel = 0, sum = 0, mabs = 0, bad = 0;
-  int unused = 0, unused2 = 0;
+  int unused = 0, unused2 = 0, unused3 = 0;
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < count; k += gridDim.x * blockDim.x)
-    fast_node<1>(a, a.fb_list[k], dyn_lds, rel, sum, mabs, bad, unused, unused2);
+    fast_node<1>(a, a.fb_list[k], dyn_lds, rel, sum, mabs, bad, unused, unused2, unused3);
   block_residual(rel, sum, mabs, bad, 0.0, a.partial, blockIdx.x);
 }
 
@@ -200,7 +217,7 @@ __global__ void k_zero_count(int* count) { *count = 0; }
 // Frozen-policy sweep (eq:p_eval applied once).  The residual reduction is
 // only compiled in when a caller asks for it; the policy-iteration loop does
 // not, since it stops on the residual of the greedy step.
-template <bool kResid>
+template <bool kResid, bool kHeun>
 __global__ __launch_bounds__(kBlock) void k_policy_eval(SweepArgs a) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int t = tile * kBlock + threadIdx.x;
@@ -208,14 +225,12 @@ __global__ __launch_bounds__(kBlock) void k_policy_eval(SweepArgs a) {
   if (t < a.n_free) {
     NodeTerms T;
     const int j = node_terms_tab(a, a.free_node[t], T);
-    float v;
-    if (a.pol_thr_in[j]) {
-      float sn, cs;
-      __sincosf(a.pol_ang_in[j], &sn, &cs);
-      v = q_thrust(a.V_in, a.G, a.P, T, sn, cs);
-    } else {
-      v = q_coast(a.V_in, a.G, a.P, T);
-    }
+    HeunTerms H;
+    if (kHeun) node_heun(a, T.i, H);
+    const int thr = a.pol_thr_in[j] ? 1 : 0;
+    float sn = 0.0f, cs = 1.0f;
+    if (thr) __sincosf(a.pol_ang_in[j], &sn, &cs);
+    const float v = q_step<kHeun>(a.V_in, a.G, a.P, T, H, thr, sn, cs);
     a.V_out[j] = v;
     if (kResid) node_residual(a.V_in[j], v, rel, sum, mabs, bad);
   }
@@ -443,14 +458,22 @@ __global__ __launch_bounds__(kBlock) void k_feedback(SweepArgs a, const double* 
   }
   state_terms(a.G, a.P, y, tau, T.drift, T.g1, T.g2, T.gm);
   for (int k = 0; k < 4; k++) T.drift[k] += frac[k];
+  HeunTerms H;
+  heun_terms(a.G, a.P, y, tau, H);
   SweepArgs b = a;
   b.P.q_coast = (float)(tau * (double)a.w_time);
   b.P.q_thr = (float)(tau * ((double)a.w_time + (double)a.w_fuel));
   b.P.gamma = (float)exp(-a.lambda * tau);
-  auto qf = [&](float sn, float cs) { return q_thrust<true>(b.V_in, b.G, b.P, T, sn, cs); };
-  const float qc = q_coast<true>(b.V_in, b.G, b.P, T);
+  const bool heun = a.P.heun != 0;
+  auto qf = [&](float sn, float cs) {
+    return heun ? q_step<true, true>(b.V_in, b.G, b.P, T, H, 1, sn, cs)
+                : q_step<false, true>(b.V_in, b.G, b.P, T, H, 1, sn, cs);
+  };
+  const float qc = heun ? q_step<true, true>(b.V_in, b.G, b.P, T, H, 0, 0.0f, 1.0f)
+                        : q_step<false, true>(b.V_in, b.G, b.P, T, H, 0, 0.0f, 1.0f);
   Choice ch;
-  if (a.mode == 0) table_search(qf, b, qc, ch);
+  // the walk's table (mode 3) is searched in full: a state has no previous optimum
+  if (a.mode == 0 || a.mode == 3) table_search(qf, b, qc, ch);
   else full_search(qf, b, qc, ch);
   ang_out[c] = ch.ang;
   thr_out[c] = (uint8_t)ch.thr;
@@ -539,15 +562,35 @@ __global__ __launch_bounds__(kBlock) void k_probe_q(SweepArgs a, const int* __re
   if (c >= n) return;
   NodeTerms T;
   node_terms(a.G, a.P, nodes[c], a.P.dt, T);
-  float sn = 0.0f, cs = 0.0f;
-  if (thr[c]) sincosf(ang[c], &sn, &cs);
-  if (q_out) q_out[c] = thr[c] ? q_thrust(a.V_in, a.G, a.P, T, sn, cs) : q_coast(a.V_in, a.G, a.P, T);
+  HeunTerms H;
+  node_heun(a, T.i, H);
+  const int th = thr[c] ? 1 : 0;
+  float sn = 0.0f, cs = 1.0f;
+  if (th) sincosf(ang[c], &sn, &cs);
+  const bool heun = a.P.heun != 0;
+  if (q_out)
+    q_out[c] = heun ? q_step<true>(a.V_in, a.G, a.P, T, H, th, sn, cs) : q_step<false>(a.V_in, a.G, a.P, T, H, th, sn, cs);
   if (off_out) {
-    off_out[4 * c + 0] = T.drift[0];
-    off_out[4 * c + 1] = thr[c] ? fmaf(T.g1, sn, T.drift[1]) : T.drift[1];
-    off_out[4 * c + 2] = thr[c] ? fmaf(T.g2, cs, T.drift[2]) : T.drift[2];
-    off_out[4 * c + 3] = T.drift[3] + (thr[c] ? T.gm : 0.0f);
+    float off[4];
+    if (heun) foot_off<true>(T, H, th, sn, cs, off);
+    else foot_off<false>(T, H, th, sn, cs, off);
+    for (int k = 0; k < 4; k++) off_out[4 * c + k] = off[k];
   }
+}
+
+// Fixed-order sum of the per-workgroup evaluation counts of the table walk.
+__global__ __launch_bounds__(kBlock) void k_sum_counts(const unsigned long long* __restrict__ acc, int n,
+                                                       unsigned long long* __restrict__ out) {
+  __shared__ unsigned long long part[kBlock];
+  unsigned long long v = 0;
+  for (int i = threadIdx.x; i < n; i += kBlock) v += acc[i];
+  part[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = part[0];
 }
 
 }  // namespace dpo
@@ -585,16 +628,22 @@ hipError_t launch_init_value(const uint8_t* kind, float M, float* V, int N, hipS
   DPO_LAUNCH(k_init_value, blocks_for(N), kBlock, s, kind, M, V, N);
 }
 
-hipError_t launch_sweep_table(const SweepArgs& a, hipStream_t s) {
-  DPO_LAUNCH(k_sweep_direct<0>, blocks_for(a.n_free), kBlock, s, a);
+hipError_t launch_sweep_direct(const SweepArgs& a, int mode, hipStream_t s) {
+  const int nb = blocks_for(a.n_free);
+  if (a.P.heun) {
+    if (mode == 0) DPO_LAUNCH((k_sweep_direct<0, true>), nb, kBlock, s, a);
+    if (mode == 1) DPO_LAUNCH((k_sweep_direct<1, true>), nb, kBlock, s, a);
+    if (mode == 2) DPO_LAUNCH((k_sweep_direct<2, true>), nb, kBlock, s, a);
+    DPO_LAUNCH((k_sweep_direct<3, true>), nb, kBlock, s, a);
+  }
+  if (mode == 0) DPO_LAUNCH((k_sweep_direct<0, false>), nb, kBlock, s, a);
+  if (mode == 1) DPO_LAUNCH((k_sweep_direct<1, false>), nb, kBlock, s, a);
+  if (mode == 2) DPO_LAUNCH((k_sweep_direct<2, false>), nb, kBlock, s, a);
+  DPO_LAUNCH((k_sweep_direct<3, false>), nb, kBlock, s, a);
 }
 
-hipError_t launch_sweep_scan_golden(const SweepArgs& a, hipStream_t s) {
-  DPO_LAUNCH(k_sweep_direct<1>, blocks_for(a.n_free), kBlock, s, a);
-}
-
-hipError_t launch_sweep_seeded(const SweepArgs& a, hipStream_t s) {
-  DPO_LAUNCH(k_sweep_direct<2>, blocks_for(a.n_free), kBlock, s, a);
+hipError_t launch_sum_counts(const unsigned long long* acc, int n, unsigned long long* out, hipStream_t s) {
+  DPO_LAUNCH(k_sum_counts, 1, kBlock, s, acc, n, out);
 }
 
 hipError_t launch_sweep_fast(const SweepArgs& a, int mode, int block, hipStream_t s) {
@@ -602,7 +651,8 @@ hipError_t launch_sweep_fast(const SweepArgs& a, int mode, int block, hipStream_
   const size_t lds = sizeof(float4) * 4 * block;
   if (mode == 0) hipLaunchKernelGGL(k_sweep_fast<0>, dim3(nb), dim3(block), lds, s, a);
   else if (mode == 1) hipLaunchKernelGGL(k_sweep_fast<1>, dim3(nb), dim3(block), lds, s, a);
-  else hipLaunchKernelGGL(k_sweep_fast<2>, dim3(nb), dim3(block), lds, s, a);
+  else if (mode == 2) hipLaunchKernelGGL(k_sweep_fast<2>, dim3(nb), dim3(block), lds, s, a);
+  else hipLaunchKernelGGL(k_sweep_fast<3>, dim3(nb), dim3(block), lds, s, a);
   return hipGetLastError();
 }
 
@@ -615,8 +665,13 @@ hipError_t launch_sweep_fallback(const SweepArgs& a, int block, int blocks, hipS
 }
 
 hipError_t launch_policy_eval(const SweepArgs& a, bool want_resid, hipStream_t s) {
-  if (want_resid) DPO_LAUNCH(k_policy_eval<true>, blocks_for(a.n_free), kBlock, s, a);
-  DPO_LAUNCH(k_policy_eval<false>, blocks_for(a.n_free), kBlock, s, a);
+  const int nb = blocks_for(a.n_free);
+  if (a.P.heun) {
+    if (want_resid) DPO_LAUNCH((k_policy_eval<true, true>), nb, kBlock, s, a);
+    DPO_LAUNCH((k_policy_eval<false, true>), nb, kBlock, s, a);
+  }
+  if (want_resid) DPO_LAUNCH((k_policy_eval<true, false>), nb, kBlock, s, a);
+  DPO_LAUNCH((k_policy_eval<false, false>), nb, kBlock, s, a);
 }
 
 hipError_t launch_policy_eval_desc(const SweepArgs& a, bool streamed, hipStream_t s) {

@@ -186,6 +186,74 @@ __device__ inline bool seeded_local(const QF& qf, const SweepArgs& a, float seed
   return fabsf(ch.v - vin) > a.fallback_tol * fmaxf(1.0f, fabsf(vin));
 }
 
+// Table index nearest to the angle u on the circle (halves round up); 0 for
+// a non-finite u.  Exact for the table's own angles, whose distance to an
+// index is ~1e-6 of a step.
+__device__ inline int table_index(float u, int K) {
+  if (!(fabsf(u) <= 1.0e30f)) return 0;
+  const float t = floorf((u + 3.14159265358979f) * ((float)K * 0.159154943091895f) + 0.5f);
+  const int k = (int)(t - (float)K * floorf(t / (float)K));
+  return (k >= 0 && k < K) ? k : 0;
+}
+
+// Walk over the tabulated angles from the previous optimum (paper Section 3,
+// "Efficient computation of the minimum"): start at the table angle nearest
+// to u_prev, look at both cyclic neighbours, move to the lower one if it is
+// strictly below (the k-1 side when the two are equal), then keep moving the
+// same way while the next angle is strictly lower (the angle just left is
+// higher, so it never needs another look).  Thrust iff the walk's Q is
+// strictly below the coast value.  At most K + 2 evaluations; returns their
+// number.
+template <class QF>
+__device__ inline int walk_search(const QF& qf, const SweepArgs& a, float u_prev, float qc, Choice& ch) {
+  const int K = a.n_ang;
+  int k = table_index(u_prev, K);
+  const int km = k == 0 ? K - 1 : k - 1, kp = k == K - 1 ? 0 : k + 1;
+  float qk = qf(a.tab_sin[k], a.tab_cos[k]);
+  const float qm = qf(a.tab_sin[km], a.tab_cos[km]);
+  const float qp = qf(a.tab_sin[kp], a.tab_cos[kp]);
+  int n = 3;
+  int d = 0;
+  if (qm < qk && qm <= qp) d = -1;
+  else if (qp < qk) d = 1;
+  if (d != 0) {
+    k = d < 0 ? km : kp;
+    qk = d < 0 ? qm : qp;
+    for (int it = 0; it < K; it++) {
+      int kn = k + d;
+      kn = kn < 0 ? K - 1 : (kn >= K ? 0 : kn);
+      const float qn = qf(a.tab_sin[kn], a.tab_cos[kn]);
+      n++;
+      if (!(qn < qk)) break;
+      k = kn;
+      qk = qn;
+    }
+  }
+  ch.thr = qk < qc ? 1 : 0;
+  ch.v = ch.thr ? qk : qc;
+  ch.ang = a.tab_ang[k];
+  ch.sn = a.tab_sin[k];
+  ch.cs = a.tab_cos[k];
+  return n;
+}
+
+// Adds the workgroup's sum of v to acc[blockIdx.x] (each workgroup owns its
+// entry, so successive sweeps on one stream accumulate without atomics).
+// Every thread of the workgroup must call it.
+__device__ inline void block_add_count(int v, unsigned long long* acc) {
+  __shared__ int wsum[kMaxBlock / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) wsum[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long s = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); i++) s += wsum[i];
+    acc[blockIdx.x] += (unsigned long long)s;
+  }
+}
+
 // At most this many fallback lanes of a wave are deferred to the second pass.
 constexpr int kDeferLanes = 16;
 
@@ -420,7 +488,7 @@ __device__ inline float fast_setup(const SweepArgs& a, const NodeTerms& T, float
 // residual contributions.  kMode: 0 tabulated, 1 scan + golden, 2 seeded.
 template <int kMode>
 __device__ inline void fast_node(const SweepArgs& a, int t, float4* lds, double& rel, double& sum, double& mabs,
-                                 double& bad, int& fell_back, int& deferred) {
+                                 double& bad, int& fell_back, int& deferred, int& evals) {
   NodeTerms T;
   const int j = node_terms_tab(a, a.free_node[t], T);
   FastNode F;
@@ -430,6 +498,7 @@ __device__ inline void fast_node(const SweepArgs& a, int t, float4* lds, double&
   Choice ch;
   if (kMode == 0) table_search(qf, a, qc, ch);
   else if (kMode == 1) full_search(qf, a, qc, ch);
+  else if (kMode == 3) evals = walk_search(qf, a, a.walk_from[j], qc, ch);
   else {
     const bool need = seeded_local(qf, a, a.seed[j], qc, vin, ch);
     // A wave where only a few lanes fall back would leave the others idle

@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(HERE, "libdpo.so")
 
 DPO_OK, DPO_ENOCONV, DPO_EINVAL, DPO_ENOMEM, DPO_EHIP, DPO_ENUMERIC = 0, 1, -1, -2, -3, -4
 MODELS = {"orbit": 0, "eikonal": 1}
-SEARCH = {"table": 0, "scan_golden": 1, "seeded": 2}
+SEARCH = {"table": 0, "scan_golden": 1, "seeded": 2, "table_walk": 3}
+INTEGRATORS = {"euler": 0, "heun": 1}
 KIND_FREE, KIND_TARGET, KIND_INACTIVE = 0, 1, 2
 
 
@@ -35,7 +36,7 @@ class Problem(C.Structure):
     _fields_ = [("model", C.c_int32), ("mu", C.c_double), ("accel", C.c_double), ("mdot", C.c_double),
                 ("dt", C.c_double), ("lam", C.c_double), ("w_time", C.c_double), ("w_fuel", C.c_double),
                 ("M", C.c_double), ("speed", C.c_double), ("tgt_c", C.c_double * 4),
-                ("tgt_w", C.c_double * 4)]
+                ("tgt_w", C.c_double * 4), ("integrator", C.c_int32)]
 
 
 class Search(C.Structure):
@@ -151,6 +152,7 @@ def problem_struct(problem):
         setattr(p, f, float(problem[f]))
     p.tgt_c[:] = [float(v) for v in problem["tgt_c"]]
     p.tgt_w[:] = [float(v) for v in problem["tgt_w"]]
+    p.integrator = INTEGRATORS[problem.get("integrator", "euler")]
     return p
 
 

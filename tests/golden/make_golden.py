@@ -8,6 +8,11 @@ is read from the device library.  Run from the repository root:
 vi12_table16.npz   12^4 orbit problem, table of 16 angles + coast, value iteration
               in double precision until the largest change is below 1e-8:
               V, best thrust angle, throttle, sweep count.
+vi12_table16_heun.npz   the same problem with the Heun (second-order
+              Runge-Kutta) foot point, same stop rule.
+vi12_walk16.npz   the Euler problem with the table searched by the walk from
+              the previous sweep's angles (full table on the first sweep),
+              same stop rule.
 """
 import os
 import sys
@@ -31,5 +36,31 @@ def make_vi12():
     print("12^4 value iteration: sweeps", res["sweeps"], "V(x0)", o.value_at(res["V"], inputs.X0))
 
 
+def make_vi12_heun():
+    p = dict(inputs.VI12, integrator="heun")
+    o = Oracle(p)
+    res = o.solve_vi(tol_abs=inputs.VI12_TOL_ABS, max_sweeps=100000)
+    assert res["converged"], res
+    np.savez_compressed(os.path.join(HERE, "vi12_table16_heun.npz"), V=res["V"], angle=res["angle"],
+                        thr=res["thr"], sweeps=np.int64(res["sweeps"]))
+    print("12^4 value iteration, Heun foot: sweeps", res["sweeps"], "V(x0)", o.value_at(res["V"], inputs.X0))
+
+
+def make_vi12_walk():
+    p = dict(inputs.VI12, search=dict(mode="table_walk", n_angles=16))
+    o = Oracle(p)
+    res = o.solve_vi(tol_abs=inputs.VI12_TOL_ABS, max_sweeps=100000)
+    assert res["converged"], res
+    np.savez_compressed(os.path.join(HERE, "vi12_walk16.npz"), V=res["V"], angle=res["angle"],
+                        thr=res["thr"], sweeps=np.int64(res["sweeps"]))
+    print("12^4 value iteration, table walk: sweeps", res["sweeps"], "V(x0)", o.value_at(res["V"], inputs.X0))
+
+
 if __name__ == "__main__":
-    make_vi12()
+    which = sys.argv[1:] or ["vi12", "vi12_heun", "vi12_walk"]
+    if "vi12" in which:
+        make_vi12()
+    if "vi12_heun" in which:
+        make_vi12_heun()
+    if "vi12_walk" in which:
+        make_vi12_walk()
