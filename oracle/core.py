@@ -10,7 +10,7 @@ from . import build as _build
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
-MODELS = {"orbit": 0, "eikonal": 1}
+MODELS = {"orbit": 0, "eikonal": 1, "crown": 2}
 SEARCH_MODES = {"table": 0, "scan_golden": 1, "seeded": 2, "table_walk": 3}
 INTEGRATORS = {"euler": 0, "heun": 1}
 KIND_FREE, KIND_TARGET, KIND_INACTIVE = 0, 1, 2
@@ -34,6 +34,11 @@ class ProblemStruct(C.Structure):
         ("tgt_c", C.c_double * 4),
         ("tgt_w", C.c_double * 4),
         ("integrator", C.c_int32),
+        ("el_beta", C.c_double),
+        ("el_gamma", C.c_double),
+        ("el_a", C.c_double),
+        ("el_e", C.c_double),
+        ("el_omega", C.c_double),
     ]
 
 
@@ -54,6 +59,8 @@ def problem_struct(p):
     s.tgt_c[:] = [float(v) for v in p["tgt_c"]]
     s.tgt_w[:] = [float(v) for v in p["tgt_w"]]
     s.integrator = INTEGRATORS[p.get("integrator", "euler")]
+    for f in ("el_beta", "el_gamma", "el_a", "el_e", "el_omega"):
+        setattr(s, f, float(p.get(f, 0.0)))
     return s
 
 
@@ -114,6 +121,9 @@ def load(precision="f64"):
     lib.or_brute_thrust_min.argtypes = [P, vp, i64, i64, vp]
     lib.or_brute_thrust_min.restype = real
     lib.or_mask_from_coarse.argtypes = [P, vp, P, C.c_double, vp, vp]
+    lib.or_running_cost.argtypes = [P, vp, C.c_int]
+    lib.or_running_cost.restype = real
+    lib.or_elements.argtypes = [P, vp, vp]
     lib.or_real_size.restype = C.c_int32
     lib._real = real
     lib._np_real = np.float64 if precision == "f64" else np.float32
@@ -158,6 +168,17 @@ class Oracle:
         tau = self.problem["dt"] if tau is None else tau
         self.lib.or_step(C.byref(self.ps), _ptr(x), int(thr), u, tau, _ptr(z))
         return z
+
+    def running_cost(self, x, thr):
+        x = np.ascontiguousarray(np.asarray(x, dtype=self.dtype))
+        return float(self.lib.or_running_cost(C.byref(self.ps), _ptr(x), int(thr)))
+
+    def elements(self, x):
+        """(a, e cos omega, e sin omega) of a crown-problem state."""
+        x = np.ascontiguousarray(np.asarray(x, dtype=self.dtype))
+        out = np.zeros(3, dtype=self.dtype)
+        self.lib.or_elements(C.byref(self.ps), _ptr(x), _ptr(out))
+        return out
 
     def interp(self, V, s):
         V = self._arr(V)
@@ -307,14 +328,17 @@ class Oracle:
         return float(q), float(u[0])
 
     def node_coords(self, j):
-        """Physical coordinates of flat node j (plain grid definition)."""
+        """Physical coordinates of flat node j (plain grid definition; the
+        crown problem's theta axis has h = (hi - lo)/n)."""
         n = self.problem["n"]
         i = []
         for k in range(4):
             i.append(j % n[k])
             j //= n[k]
         lo, hi = self.problem["lo"], self.problem["hi"]
-        return np.array([lo[k] + i[k] * ((hi[k] - lo[k]) / (n[k] - 1)) for k in range(4)])
+        per = self.problem["model"] == "crown"
+        h = [(hi[k] - lo[k]) / (n[k] if (per and k == 3) else n[k] - 1) for k in range(4)]
+        return np.array([lo[k] + i[k] * h[k] for k in range(4)])
 
 
 def mask_from_coarse(coarse_problem, Vc, fine_problem, dilate, thresh=None):

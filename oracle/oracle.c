@@ -51,6 +51,10 @@
  *
  * Grid: closed uniform tensor grid, node i_k at lo_k + i_k*h_k with
  * h_k = (hi_k - lo_k)/(n_k - 1); storage is C order [m][v_t][v_r][r].
+ * The crown problem (model 2, the paper's Example 1: polar grid "closed with
+ * periodic conditions", Section 3) has theta as axis 3 instead of the mass:
+ * node i at lo + i*h with h = (hi - lo)/n (hi is lo's periodic image), and
+ * interpolation wraps around along that axis, which never leaves the domain.
  * The foot is expressed in grid coordinates, s_k = i_k + dt*b_k/h_k, which
  * is the same point as (z_k - lo_k)/h_k but exact for a zero displacement.
  */
@@ -70,10 +74,14 @@ typedef double real;
 typedef struct {
   int32_t n[4];
   double lo[4], hi[4];
-  int32_t model; /* 0 = planar orbit, 1 = 2-D eikonal in axes (v_r, v_t) */
+  int32_t model; /* 0 = planar orbit, 1 = 2-D eikonal in axes (v_r, v_t),
+                    2 = the crown problem: planar orbit in axes (r, v_r, v_t, theta)
+                        with theta periodic, constant thrust, orbital-element cost */
   double mu, accel, mdot, dt, lambda, w_time, w_fuel, M, speed;
   double tgt_c[4], tgt_w[4];
   int32_t integrator; /* foot point: 0 = one explicit Euler step, 1 = Heun (RK2) */
+  /* model 2 running cost: beta*(a - a_bar)^2 + gamma*|e_vec - e_bar_vec|^2 */
+  double el_beta, el_gamma, el_a, el_e, el_omega;
 } or_problem;
 
 typedef struct {
@@ -92,7 +100,10 @@ typedef struct {
 enum { KIND_FREE = 0, KIND_TARGET = 1, KIND_INACTIVE = 2 };
 
 /* ------------------------------------------------------------------ grid */
+static int periodic(const or_problem *p, int k) { return k == 3 && p->model == 2; }
+
 static double step(const or_problem *p, int k) {
+  if (periodic(p, k)) return (p->hi[k] - p->lo[k]) / (double)p->n[k];
   return (p->hi[k] - p->lo[k]) / (double)(p->n[k] - 1);
 }
 
@@ -143,6 +154,18 @@ void or_init_value(const or_problem *p, const uint8_t *kind, real *V) {
 /* ------------------------------------------------------------- dynamics */
 /* Right-hand side b(x, f) for throttle thr in {0,1} and thrust angle u. */
 static void rhs(const or_problem *p, const real x[4], int thr, real u, real b[4]) {
+  if (p->model == 2) {
+    /* the paper's polar system (Section 3) with the centrifugal term's sign
+     * corrected, thrust of constant acceleration `accel` split radial sin u,
+     * tangential cos u, and theta' = v_t / r */
+    real r = x[0], vr = x[1], vt = x[2];
+    real acc = thr ? (real)p->accel : (real)0;
+    b[0] = vr;
+    b[1] = vt * vt / r - (real)p->mu / (r * r) + acc * (real)sin(u);
+    b[2] = -vr * vt / r + acc * (real)cos(u);
+    b[3] = vt / r;
+    return;
+  }
   if (p->model == 1) {
     real s = thr ? (real)p->speed : (real)0;
     b[0] = 0;
@@ -201,6 +224,18 @@ static void foot_grid(const or_problem *p, const int i[4], int thr, real u, real
  * If idx/w are given, the 16 corner indices and weights are returned. */
 static int cell(const or_problem *p, const real s[4], int base[4], real t[4]) {
   for (int k = 0; k < 4; k++) {
+    if (periodic(p, k)) {
+      /* wrap into [0, n): the cell between node n-1 and node 0 is a cell too */
+      if (!isfinite((double)s[k])) return 0;
+      const real n = (real)p->n[k];
+      real w = s[k] - n * (real)floor((double)(s[k] / n));
+      int b = (int)floor((double)w);
+      if (b >= p->n[k]) b = p->n[k] - 1;
+      if (b < 0) b = 0;
+      base[k] = b;
+      t[k] = w - (real)b;
+      continue;
+    }
     if (!(s[k] >= 0 && s[k] <= (real)(p->n[k] - 1))) return 0;
     int b = (int)floor(s[k]);
     if (b > p->n[k] - 2) b = p->n[k] - 2;
@@ -222,6 +257,7 @@ static real interp(const or_problem *p, const real *V, const real s[4]) {
       int e = (c >> k) & 1;
       w *= e ? t[k] : (real)1 - t[k];
       corner[k] = base[k] + e;
+      if (periodic(p, k) && corner[k] == p->n[k]) corner[k] = 0;
     }
     acc += w * V[flat_index(p, corner)];
   }
@@ -243,6 +279,7 @@ int or_interp_weights(const or_problem *p, const real s[4], int64_t idx[16], rea
       int e = (c >> k) & 1;
       ww *= e ? t[k] : (real)1 - t[k];
       corner[k] = base[k] + e;
+      if (periodic(p, k) && corner[k] == p->n[k]) corner[k] = 0;
     }
     idx[c] = flat_index(p, corner);
     w[c] = ww;
@@ -257,6 +294,7 @@ int or_interp_weights(const or_problem *p, const real s[4], int64_t idx[16], rea
 #define FACE_EPS 1e-6
 static real to_grid(const or_problem *p, int k, double xk) {
   double s = (xk - p->lo[k]) / step(p, k);
+  if (periodic(p, k)) return (real)s;
   double top = (double)(p->n[k] - 1);
   if (s < 0 && s > -FACE_EPS) s = 0;
   if (s > top && s < top + FACE_EPS) s = top;
@@ -272,15 +310,65 @@ double or_value_at(const or_problem *p, const real *V, const double x[4]) {
 /* --------------------------------------------------- Bellman Q of a control */
 static real discount(const or_problem *p, real tau) { return (real)exp(-p->lambda * tau); }
 
-static real running_cost(const or_problem *p, int thr) {
-  return (real)p->w_time + (real)p->w_fuel * (real)thr;
+/* Orbital elements of the crown problem's state x = (r, v_r, v_t, theta),
+ * as the paper writes them (Section 3, polar running cost), except that the
+ * printed semi-major axis -mu/(v^2 r - 2 mu) lacks a factor r (it is
+ * dimensionless as printed): a = -mu r/(v^2 r - 2 mu), the vis-viva form;
+ * eccentricity e = sqrt(1 + 2 E h^2/mu^2) with the
+ * energy E = v^2/2 - mu/r and the angular momentum h = r v_t; argument of
+ * perigee omega = theta - theta*, the true anomaly theta* = 2 arctan(r v_r
+ * sqrt(p/mu) / (r (e - 1) + p)) with the semi-latus rectum p = a (1 - e^2).
+ * That half-angle tangent is (e sin theta*)/(e + e cos theta*) with
+ * e sin theta* = v_r sqrt(p/mu) and e cos theta* = p/r - 1; it is 0/0 at the
+ * apoapsis, so the angle is taken from those two components directly,
+ * theta* = atan2(v_r sqrt(p/mu), p/r - 1): the same angle wherever the
+ * half-angle form is defined. */
+void or_elements(const or_problem *p, const real x[4], real out[3]) {
+  const double mu = p->mu;
+  const double r = x[0], vr = x[1], vt = x[2], th = x[3];
+  const double v2 = vr * vr + vt * vt;
+  const double a = -mu * r / (v2 * r - 2.0 * mu);
+  const double E = 0.5 * v2 - mu / r;
+  const double h = r * vt;
+  double e2 = 1.0 + 2.0 * E * h * h / (mu * mu);
+  if (e2 < 0) e2 = 0;
+  const double e = sqrt(e2);
+  double ecw = 0, esw = 0;
+  if (e > 0) {
+    const double pp = a * (1.0 - e * e);
+    const double ts = atan2(vr * sqrt(pp / mu), pp / r - 1.0);
+    const double om = th - ts;
+    ecw = e * cos(om);
+    esw = e * sin(om);
+  }
+  out[0] = (real)a;
+  out[1] = (real)ecw;
+  out[2] = (real)esw;
+}
+
+/* Running cost l(x, f): w_time + w_fuel*thr, plus for the crown problem the
+ * paper's orbital-element terms (eq:runcost_polar) beta*(a - a_bar)^2 +
+ * gamma*((e cos w - e_bar cos w_bar)^2 + (e sin w - e_bar sin w_bar)^2); the
+ * fuel term alpha*u_bar*thr is w_fuel*thr. */
+real or_running_cost(const or_problem *p, const real x[4], int thr) {
+  double l = p->w_time + p->w_fuel * (double)thr;
+  if (p->model == 2) {
+    real el[3];
+    or_elements(p, x, el);
+    const double da = (double)el[0] - p->el_a;
+    const double dx = (double)el[1] - p->el_e * cos(p->el_omega);
+    const double dy = (double)el[2] - p->el_e * sin(p->el_omega);
+    l += p->el_beta * da * da + p->el_gamma * (dx * dx + dy * dy);
+  }
+  return (real)l;
 }
 
 /* Q(x_j, f) = dt*l + exp(-lambda*dt) * I[V](foot) at node i with step tau. */
 static real q_node(const or_problem *p, const real *V, const int i[4], int thr, real u, real tau) {
-  real s[4];
+  real s[4], x[4];
   foot_grid(p, i, thr, u, tau, s);
-  return tau * running_cost(p, thr) + discount(p, tau) * interp(p, V, s);
+  node_coords(p, i, x);
+  return tau * or_running_cost(p, x, thr) + discount(p, tau) * interp(p, V, s);
 }
 
 real or_q(const or_problem *p, const real *V, int64_t j, int thr, real u) {
@@ -300,7 +388,7 @@ static real q_state(const or_problem *p, const real *V, const real y[4], int thr
   real z[4], s[4];
   or_step(p, y, thr, u, tau, z);
   for (int k = 0; k < 4; k++) s[k] = to_grid(p, k, (double)z[k]);
-  return tau * running_cost(p, thr) + discount(p, tau) * interp(p, V, s);
+  return tau * or_running_cost(p, y, thr) + discount(p, tau) * interp(p, V, s);
 }
 
 /* ------------------------------------------------------------- search */

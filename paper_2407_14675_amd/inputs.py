@@ -5,9 +5,10 @@ numbers and random draws only: grid extents, physical constants, search sizes
 and seeded fields.  It contains none of the method's arithmetic (no dynamics,
 no interpolation, no target snapping, no Bellman operator).
 
-Every workload is the nondimensional planar orbit-transfer problem
-(mu = 1, r0 = 1) in the state (r, v_r, v_t, m); the paper's own Example 1
-(Section 4) uses a different instance and is not one of these workloads.
+The benchmark workloads are the nondimensional planar orbit-transfer
+problem (mu = 1, r0 = 1) in the state (r, v_r, v_t, m).  The paper's own
+Example 1 (Section 4) is the crown problem below, in kilometres and seconds,
+state (rho, v_rho, v_theta, theta) with theta periodic.
 """
 from __future__ import annotations
 
@@ -129,6 +130,54 @@ def batch_problems(n_prob=16, seed=3, side_scale=1.0):
         out.append(orbit_problem((side,) * 4, target_radius=d["target_radius"],
                                  accel=d["accel"], name=f"batch_p{i}_{side}^4"))
     return out
+
+
+# ---------------------------------------------------------------- Example 1
+# The paper's Example 1 (Section 4): target orbit a = 7000 km, e = 0.001,
+# argument of perigee 0; thrust acceleration 5e-7 km/s^2 (no mass change);
+# cost weights alpha = 2.04e-8 (on the thrust acceleration), beta = 2.31e-2,
+# gamma = 1.5; discount 1e-3 1/s; dt = 10 s; 73 controls (72 angles at 5
+# degrees and coast); rho in [6930, 7070] km, theta in [0, 2 pi), v_rho in
+# [-0.01, 0.01] km/s, v_theta in [7.526, 7.566] km/s on 110 x 30 x 30 x 30
+# nodes.  Axes here: (rho, v_rho, v_theta, theta), theta periodic (axis 3).
+# M, the value of a foot outside the crown, is 1e6: above the largest
+# running cost on the domain (~750) divided by the discount rate.
+EX1_MU = 398600.4
+EX1_ACCEL = 5e-7
+EX1_ALPHA = 2.04e-8
+
+
+def crown_problem(n=(110, 30, 30, 30), *, integrator="heun", n_angles=72, M=1e6, name="example1_crown"):
+    return dict(
+        name=name,
+        model="crown",
+        n=tuple(int(v) for v in n),
+        lo=(6930.0, -0.01, 7.526, 0.0),
+        hi=(7070.0, 0.01, 7.566, 2.0 * math.pi),
+        mu=EX1_MU,
+        accel=EX1_ACCEL,
+        mdot=0.0,
+        dt=10.0,
+        lam=1e-3,
+        w_time=0.0,
+        w_fuel=EX1_ALPHA * EX1_ACCEL,
+        M=float(M),
+        speed=0.0,
+        tgt_c=(0.0, 0.0, 0.0, 0.0),
+        tgt_w=(-1.0, -1.0, -1.0, -1.0),  # no target set: the cost steers towards the orbit
+        integrator=integrator,
+        el_beta=2.31e-2,
+        el_gamma=1.5,
+        el_a=7000.0,
+        el_e=0.001,
+        el_omega=0.0,
+        search=dict(mode="table", n_angles=int(n_angles)),
+    )
+
+
+EX1 = crown_problem()
+# Start of the paper's closed-loop orbit raise: circular orbit at 6978 km.
+EX1_START_RADIUS = 6978.0
 
 
 def with_grid(problem, n):
