@@ -45,7 +45,7 @@ enum {
   DPO_ENUMERIC = -4  /* a sweep produced a non-finite value */
 };
 
-enum { DPO_MODEL_ORBIT = 0, DPO_MODEL_EIKONAL = 1 };
+enum { DPO_MODEL_ORBIT = 0, DPO_MODEL_EIKONAL = 1, DPO_MODEL_CROWN = 2 };
 
 /* One-step approximation of the trajectory from a node (the foot point). */
 enum { DPO_STEP_EULER = 0, DPO_STEP_HEUN = 1 };
@@ -63,7 +63,11 @@ enum { DPO_KIND_FREE = 0, DPO_KIND_TARGET = 1, DPO_KIND_INACTIVE = 2 };
 /* Closed uniform grid (paper Section 3, "Grid and polar coordinates"):
  * node i_k of axis k sits at lo[k] + i_k*(hi[k]-lo[k])/(n[k]-1).  Axis order
  * (r, v_r, v_t, m).  Requires 2 <= n[k] <= 256, lo[k] < hi[k] and at most
- * 2^30 nodes in total. */
+ * 2^30 nodes in total.  For DPO_MODEL_CROWN axis 3 is the polar angle theta
+ * and is periodic ("closed with periodic conditions", Section 3): node i at
+ * lo[3] + i*(hi[3]-lo[3])/n[3], hi[3] being lo[3]'s periodic image (2 pi
+ * above it for an angle); feet wrap around along it and never leave the
+ * domain there. */
 typedef struct {
   int32_t n[4];
   double lo[4], hi[4];
@@ -73,6 +77,17 @@ typedef struct {
  *  model ORBIT:   r' = v_r, v_r' = v_t^2/r - mu/r^2 + thr*(accel/m)*sin u,
  *                 v_t' = -v_r*v_t/r + thr*(accel/m)*cos u, m' = -mdot*thr;
  *  model EIKONAL: v_r' = thr*speed*sin u, v_t' = thr*speed*cos u (r, m fixed).
+ *  model CROWN (the paper's Example 1, Section 4): state (r, v_r, v_t, theta)
+ *                 with the orbit dynamics above for a constant thrust
+ *                 acceleration accel (no mass), theta' = v_t/r, and the
+ *                 running cost of eq:runcost_polar added to l below:
+ *                 el_beta*(a - el_a)^2 + el_gamma*|e_vec - el_e*(cos el_omega,
+ *                 sin el_omega)|^2, with a the vis-viva semi-major axis and
+ *                 e_vec the eccentricity vector of the state (computed in FP64
+ *                 per node at dpo_create).  No target set is implied: give an
+ *                 empty target box (negative tgt_w).  Needs lo[0] > 0.
+ *  The factorised sweep, the foot descriptors, the reduced-grid mask helper
+ *  and the batched solver take the ORBIT and EIKONAL models only.
  *  Foot point x + dt*Phi(x, f) (eq:schema), the control held over the step:
  *  integrator DPO_STEP_EULER: Phi = b(x), one explicit Euler step;
  *  DPO_STEP_HEUN: Phi = (b(x) + b(x + dt*b(x)))/2, Heun's second-order
@@ -90,6 +105,7 @@ typedef struct {
   double mu, accel, mdot, dt, lambda, w_time, w_fuel, M, speed;
   double tgt_c[4], tgt_w[4];
   int32_t integrator; /* DPO_STEP_EULER or DPO_STEP_HEUN */
+  double el_beta, el_gamma, el_a, el_e, el_omega; /* DPO_MODEL_CROWN running cost (else unused) */
 } dpo_problem;
 
 /* Minimisation over the control set (paper Section 3, "Efficient computation

@@ -57,6 +57,7 @@ struct dpo_ctx {
   int desc_format = -1;        // 0 flat 32-bit codes, 1 compact by free node, 2 compact by node
   float2* desc_w = nullptr;
   bool desc_valid = false;    // a sweep has written them
+  float* qnode = nullptr;                  // crown problem: dt * running cost per node
   unsigned long long* eval_acc = nullptr;  // table walk: per-workgroup thrust-evaluation counts
   unsigned long long* eval_sum = nullptr;
   std::string err;
@@ -99,8 +100,10 @@ int validate_grid(dpo_ctx* c, const dpo_grid* g) {
 
 int validate_problem(dpo_ctx* c, const dpo_problem* p) {
   if (!p) return fail(c, DPO_EINVAL, "problem is NULL");
-  if (p->model != DPO_MODEL_ORBIT && p->model != DPO_MODEL_EIKONAL)
+  if (p->model != DPO_MODEL_ORBIT && p->model != DPO_MODEL_EIKONAL && p->model != DPO_MODEL_CROWN)
     return fail(c, DPO_EINVAL, "problem: unknown model");
+  if (p->model == DPO_MODEL_CROWN && !(p->mu > 0 && p->accel >= 0))
+    return fail(c, DPO_EINVAL, "problem: the crown model needs mu > 0 and accel >= 0");
   if (!(p->dt > 0) || !std::isfinite(p->dt)) return fail(c, DPO_EINVAL, "problem: dt must be > 0");
   if (!(p->lambda >= 0)) return fail(c, DPO_EINVAL, "problem: lambda must be >= 0");
   if (!std::isfinite(p->M)) return fail(c, DPO_EINVAL, "problem: M must be finite");
@@ -188,14 +191,16 @@ int upload_table(dpo_ctx* c) {
   return DPO_OK;
 }
 
-Grid make_grid(const dpo_grid& g) {
+// periodic3: axis 3 wraps, node i at lo + i*(hi - lo)/n (hi is lo's image).
+Grid make_grid(const dpo_grid& g, bool periodic3 = false) {
   Grid G;
   for (int k = 0; k < 4; k++) {
     G.n[k] = g.n[k];
     G.lo[k] = g.lo[k];
-    G.h[k] = (g.hi[k] - g.lo[k]) / (double)(g.n[k] - 1);
+    G.h[k] = (g.hi[k] - g.lo[k]) / (double)(k == 3 && periodic3 ? g.n[k] : g.n[k] - 1);
     G.inv_h[k] = 1.0 / G.h[k];
   }
+  G.periodic3 = periodic3 ? 1 : 0;
   G.st[0] = 1;
   G.st[1] = g.n[0];
   G.st[2] = g.n[0] * g.n[1];
@@ -216,6 +221,8 @@ SweepArgs base_args(const dpo_ctx* c) {
   a.c0 = c->c0;
   a.c1 = c->c1;
   a.c2 = c->c2;
+  a.c3 = c->prob.dt * c->G.inv_h[3];
+  a.qnode = c->qnode;
   a.gm = c->gm;
   a.tab_sin = c->tab;
   a.tab_cos = c->tab + c->n_ang;
@@ -341,7 +348,7 @@ bool use_fast(const dpo_ctx* c) { return c->path == 2 || (c->path == 0 && c->fas
 
 // Foot descriptors record the r and m cells as functions of the node and the
 // throttle alone, which holds for the Euler foot only.
-bool desc_ok(const dpo_ctx* c) { return !c->P.heun; }
+bool desc_ok(const dpo_ctx* c) { return !c->P.heun && c->P.model != DPO_MODEL_CROWN; }
 
 // Table walk evaluation counters: one entry per workgroup of the largest grid
 // any sweep launches (workgroups of 64 threads and up).
@@ -510,8 +517,19 @@ int dpo_create(const dpo_grid* grid, const dpo_problem* prob, const dpo_search* 
   c->grid = *grid;
   c->prob = *prob;
   c->search = *search;
-  c->G = make_grid(*grid);
+  const bool crown = prob->model == DPO_MODEL_CROWN;
+  if (crown && !(grid->lo[0] > 0)) {
+    g_err = "grid: the crown model needs r > 0";
+    delete c;
+    return DPO_EINVAL;
+  }
+  c->G = make_grid(*grid, crown);
   c->P.model = prob->model;
+  c->P.el_beta = prob->el_beta;
+  c->P.el_gamma = prob->el_gamma;
+  c->P.el_a = prob->el_a;
+  c->P.el_ex = prob->el_e * std::cos(prob->el_omega);
+  c->P.el_ey = prob->el_e * std::sin(prob->el_omega);
   c->P.heun = prob->integrator == DPO_STEP_HEUN ? 1 : 0;
   c->P.mu = prob->mu;
   c->P.accel = prob->accel;
@@ -553,14 +571,15 @@ int dpo_create(const dpo_grid* grid, const dpo_problem* prob, const dpo_search* 
     std::vector<double> rinv(grid->n[0]);
     for (int i = 0; i < grid->n[0]; i++) {
       const double r = grid->lo[0] + i * c->G.h[0];
-      rinv[i] = prob->model == DPO_MODEL_ORBIT ? 1.0 / r : 0.0;
+      rinv[i] = prob->model != DPO_MODEL_EIKONAL ? 1.0 / r : 0.0;
     }
     const int nm = grid->n[3];
     std::vector<float> gt(2 * nm);
     double gmax = 0;
     for (int i = 0; i < nm; i++) {
       const double m = grid->lo[3] + i * c->G.h[3];
-      const double acc = prob->model == DPO_MODEL_ORBIT ? prob->accel / m : prob->speed;
+      const double acc = prob->model == DPO_MODEL_ORBIT ? prob->accel / m
+                         : prob->model == DPO_MODEL_CROWN ? prob->accel : prob->speed;
       const double g1 = prob->dt * acc * c->G.inv_h[1], g2 = prob->dt * acc * c->G.inv_h[2];
       gt[i] = (float)g1;
       gt[nm + i] = (float)g2;
@@ -573,7 +592,7 @@ int dpo_create(const dpo_grid* grid, const dpo_problem* prob, const dpo_search* 
     c->gm = (float)gm;
     // the factorised thrust kernel needs every thrust foot of a node within two
     // cells per moving axis and within one m cell
-    c->fast_ok = gmax < 0.45 && gm > -1.0 && gm <= 0.0 && prob->integrator == DPO_STEP_EULER;
+    c->fast_ok = gmax < 0.45 && gm > -1.0 && gm <= 0.0 && prob->integrator == DPO_STEP_EULER && !crown;
     hipError_t e1 = hipMemcpy(c->rinv, rinv.data(), sizeof(double) * rinv.size(), hipMemcpyHostToDevice);
     hipError_t e2 = hipMemcpy(c->gtab, gt.data(), sizeof(float) * gt.size(), hipMemcpyHostToDevice);
     if (e1 != hipSuccess || e2 != hipSuccess) {
@@ -590,6 +609,18 @@ int dpo_create(const dpo_grid* grid, const dpo_problem* prob, const dpo_search* 
     return cleanup(DPO_EHIP);
   }
   c->n_free = total;
+  if (crown) {
+    if (hipMalloc(&c->qnode, sizeof(float) * (size_t)N) != hipSuccess) {
+      c->err = "device allocation failed in dpo_create";
+      return cleanup(DPO_ENOMEM);
+    }
+    e = launch_node_cost(c->G, c->P, c->qnode, N, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      c->err = std::string("dpo_create: ") + hipGetErrorString(e);
+      return cleanup(DPO_EHIP);
+    }
+  }
   c->partial_blocks = blocks_for(total > 0 ? total : 1, 64) + kFallbackBlocks;
   if (hipMalloc(&c->partial, sizeof(double) * kPartial * c->partial_blocks) != hipSuccess) {
     c->err = "device allocation failed in dpo_create";
@@ -620,6 +651,7 @@ void dpo_destroy(dpo_ctx* c) {
   if (c->desc16) hipFree(c->desc16);
   if (c->desc_w) hipFree(c->desc_w);
   if (c->eval_acc) hipFree(c->eval_acc);
+  if (c->qnode) hipFree(c->qnode);
   if (c->eval_sum) hipFree(c->eval_sum);
   delete c;
 }
@@ -661,8 +693,9 @@ int dpo_kernel_path(const dpo_ctx* c) {
 int dpo_eval_sweep_bytes(const dpo_ctx* c, int64_t* bytes) {
   if (!c || !bytes) return fail(const_cast<dpo_ctx*>(c), DPO_EINVAL, "NULL argument");
   if (!desc_ok(c)) {
-    // Heun: the frozen-policy sweep reads coordinates, angle and throttle
-    *bytes = (4 + 4 + 1 + 8) * c->n_free;
+    // no descriptors: the frozen-policy sweep reads coordinates, angle and
+    // throttle (and the crown problem's node cost)
+    *bytes = (4 + 4 + 1 + 8 + (c->qnode ? 4 : 0)) * c->n_free;
     return DPO_OK;
   }
   // the stream plus one value read (the gather's share) and one value write per free node
@@ -962,6 +995,7 @@ int dpo_mask_from_coarse(dpo_ctx* c, const float* Vc, const dpo_grid* fine, doub
   if (!Vc || !fine || !dilate || !mask) return fail(c, DPO_EINVAL, "null argument");
   int rc = validate_grid(c, fine);
   if (rc != DPO_OK) return rc;
+  if (c->P.model == DPO_MODEL_CROWN) return fail(c, DPO_EINVAL, "mask_from_coarse: not for the crown model");
   for (int k = 0; k < 4; k++) {
     if (fine->lo[k] != c->grid.lo[k] || fine->hi[k] != c->grid.hi[k])
       return fail(c, DPO_EINVAL, "fine grid must share the coarse domain box");

@@ -22,12 +22,15 @@ struct Grid {
   double lo[4];
   double h[4];
   double inv_h[4];
+  int periodic3;  // axis 3 is periodic (the crown problem's theta): h3 = (hi - lo)/n, feet wrap
 };
 
 struct Phys {
-  int model;  // 0 orbit, 1 eikonal
+  int model;  // 0 orbit, 1 eikonal, 2 crown (polar state with theta, orbital-element cost)
   int heun;   // 1: Heun (second-order Runge-Kutta) foot point, 0: Euler
   double mu, accel, mdot, dt, speed;
+  // crown running cost: el_beta*(a - el_a)^2 + el_gamma*|e_vec - (el_ex, el_ey)|^2
+  double el_beta, el_gamma, el_a, el_ex, el_ey;
   float q_coast;  // dt * w_time
   float q_thr;    // dt * (w_time + w_fuel)
   float gamma;    // exp(-lambda * dt)
@@ -57,11 +60,22 @@ __device__ inline void decode_node(const Grid& G, int j, int i[4]) {
 
 // Right-hand side of the planar dynamics at a physical state x, scaled by
 // tau and divided by the grid steps.  Orbit: (v_r, v_t^2/r - mu/r^2,
-// -v_r v_t / r, 0) + thr*(0, (a/m) sin u, (a/m) cos u, -c).
+// -v_r v_t / r, 0) + thr*(0, (a/m) sin u, (a/m) cos u, -c).  Crown: the same
+// with a constant thrust acceleration and theta' = v_t / r on axis 3.
 __device__ inline void state_terms(const Grid& G, const Phys& P, const double x[4], double tau,
                                    float drift[4], float& g1, float& g2, float& gm) {
 #pragma clang fp contract(off)
-  if (P.model == 0) {
+  if (P.model == 2) {
+    const double r = x[0], vr = x[1], vt = x[2];
+    const double inv_r = 1.0 / r;
+    drift[0] = (float)(tau * vr * G.inv_h[0]);
+    drift[1] = (float)(tau * (vt * vt * inv_r - P.mu * inv_r * inv_r) * G.inv_h[1]);
+    drift[2] = (float)(tau * (-vr * vt * inv_r) * G.inv_h[2]);
+    drift[3] = (float)(tau * vt * inv_r * G.inv_h[3]);
+    g1 = (float)(tau * P.accel * G.inv_h[1]);
+    g2 = (float)(tau * P.accel * G.inv_h[2]);
+    gm = 0.0f;
+  } else if (P.model == 0) {
     const double r = x[0], vr = x[1], vt = x[2], m = x[3];
     const double inv_r = 1.0 / r;
     drift[0] = (float)(tau * vr * G.inv_h[0]);
@@ -123,11 +137,36 @@ __device__ inline bool axis_cell(int i, int n, float o, int& b, float& t) {
   return true;
 }
 
+// Periodic axis: the foot wraps into [0, n); the cell between node n-1 and
+// node 0 is a cell like any other.  False only for a non-finite offset.
+__device__ inline bool periodic_cell(int i, int n, float o, int& b, float& t) {
+  if (!(fabsf(o) <= 1.0e30f)) return false;
+  const float nf = (float)n;
+  const float s = (float)i + o;
+  const float w = s - nf * floorf(s / nf);
+  const float fl = floorf(w);
+  b = (int)fl;
+  t = w - fl;
+  if (b >= n) {  // w rounded up to n: node 0
+    b = 0;
+    t = 0.0f;
+  }
+  if (b < 0) {
+    b = 0;
+    t = 0.0f;
+  }
+  return true;
+}
+
 template <bool kSnap = false>
 __device__ inline bool foot_cell(const Grid& G, const int i[4], const float off[4], int base[4], float t[4]) {
 #pragma unroll
   for (int k = 0; k < 4; k++) {
     float o = off[k];
+    if (k == 3 && G.periodic3) {
+      if (!periodic_cell(i[3], G.n[3], o, base[3], t[3])) return false;
+      continue;
+    }
     if (kSnap) {
       const float lo = (float)(-i[k]), hi = (float)(G.n[k] - 1 - i[k]);
       if (o < lo && o > lo - 1e-6f) o = lo;
@@ -144,9 +183,11 @@ struct __attribute__((aligned(4))) CornerPair {
 };
 
 // 16-corner Q1 value of the cell whose lowest corner is p: 15 lerps, r first
-// (the 8 r-adjacent corner pairs are 8 loads).
-__device__ inline float cell_value(const float* __restrict__ p, const Grid& G, const float t[4]) {
-  const int s1 = G.st[1], s2 = G.st[2], s3 = G.st[3];
+// (the 8 r-adjacent corner pairs are 8 loads).  s3: element step from the
+// cell's lower to its upper corner along axis 3 (G.st[3], or back to node 0
+// on a periodic axis).
+__device__ inline float cell_value(const float* __restrict__ p, const Grid& G, const float t[4], int s3) {
+  const int s1 = G.st[1], s2 = G.st[2];
   float c[8];
 #pragma unroll
   for (int e = 0; e < 8; e++) {
@@ -171,7 +212,8 @@ __device__ inline float interp_off(const float* __restrict__ V, const Grid& G, c
   int base[4];
   float t[4];
   if (!foot_cell<kSnap>(G, i, off, base, t)) return M;
-  return cell_value(V + (base[0] + base[1] * G.st[1] + base[2] * G.st[2] + base[3] * G.st[3]), G, t);
+  const int s3 = (G.periodic3 && base[3] == G.n[3] - 1) ? -base[3] * G.st[3] : G.st[3];
+  return cell_value(V + (base[0] + base[1] * G.st[1] + base[2] * G.st[2] + base[3] * G.st[3]), G, t, s3);
 }
 
 // ---- Heun foot point (paper Section 3 names a second-order Runge-Kutta
@@ -184,18 +226,20 @@ __device__ inline float interp_off(const float* __restrict__ V, const Grid& G, c
 // (~1e-2 cell) instead of on the slopes.  The eikonal field does not depend
 // on the state: there the correction is zero.
 struct HeunTerms {
-  float r, vr, vt, m;  // the state the step starts from
+  float r, vr, vt, m;  // the state the step starts from (m = 1 for the crown problem)
   float d1, d2;        // control-free slopes along v_r and v_t (rounded from FP64)
   float acc;           // accel / m
   float tau, mdot, mu, accel;
-  float sc[3];         // (tau/2) / h_k for r, v_r, v_t
-  int orbit;
+  float sc[4];         // (tau/2) / h_k
+  int orbit;           // orbit or crown dynamics (the eikonal field is constant)
+  int crown;           // axis 3 is theta, theta' = v_t / r
 };
 
 __device__ inline void heun_terms(const Grid& G, const Phys& P, const double x[4], double tau, HeunTerms& H) {
 #pragma clang fp contract(off)
-  H.orbit = P.model == 0;
-  const double r = x[0], vr = x[1], vt = x[2], m = x[3];
+  H.orbit = P.model == 0 || P.model == 2;
+  H.crown = P.model == 2;
+  const double r = x[0], vr = x[1], vt = x[2], m = H.crown ? 1.0 : x[3];
   H.r = (float)r;
   H.vr = (float)vr;
   H.vt = (float)vt;
@@ -209,16 +253,17 @@ __device__ inline void heun_terms(const Grid& G, const Phys& P, const double x[4
     H.d1 = H.d2 = H.acc = 0.0f;
   }
   H.tau = (float)tau;
-  H.mdot = (float)P.mdot;
+  H.mdot = H.crown ? 0.0f : (float)P.mdot;
   H.mu = (float)P.mu;
   H.accel = (float)P.accel;
-  for (int k = 0; k < 3; k++) H.sc[k] = (float)(0.5 * tau * G.inv_h[k]);
+  for (int k = 0; k < 4; k++) H.sc[k] = (float)(0.5 * tau * G.inv_h[k]);
 }
 
-// (tau/2)*(b(x~) - b(x)) in cells along r, v_r, v_t (m: zero, its rate is constant).
-__device__ inline void heun_corr(const HeunTerms& H, int thr, float sn, float cs, float c[3]) {
+// (tau/2)*(b(x~) - b(x)) in cells along r, v_r, v_t and axis 3 (the mass:
+// zero, its rate is constant; the crown's theta: v_t~/r~ - v_t/r).
+__device__ inline void heun_corr(const HeunTerms& H, int thr, float sn, float cs, float c[4]) {
   if (!H.orbit) {
-    c[0] = c[1] = c[2] = 0.0f;
+    c[0] = c[1] = c[2] = c[3] = 0.0f;
     return;
   }
   const float k1v = thr ? fmaf(H.acc, sn, H.d1) : H.d1;
@@ -241,6 +286,7 @@ __device__ inline void heun_corr(const HeunTerms& H, int thr, float sn, float cs
   c[0] = H.sc[0] * dv;
   c[1] = H.sc[1] * (cent + grav + tv);
   c[2] = H.sc[2] * (cor + tt);
+  c[3] = H.crown ? H.sc[3] * ((dw * H.r - H.vt * dr) * inv) : 0.0f;
 }
 
 // Foot displacement (cells) of a control under the node's integrator.
@@ -251,22 +297,42 @@ __device__ inline void foot_off(const NodeTerms& T, const HeunTerms& H, int thr,
   off[2] = thr ? fmaf(T.g2, cs, T.drift[2]) : T.drift[2];
   off[3] = T.drift[3] + (thr ? T.gm : 0.0f);
   if (kHeun) {
-    float c[3];
+    float c[4];
     heun_corr(H, thr, sn, cs, c);
     off[0] += c[0];
     off[1] += c[1];
     off[2] += c[2];
+    off[3] += c[3];
   }
 }
 
 // Q of one control at a node, dt*l + gamma * I[V](foot), for thr (angle given
-// by its sin/cos) under either integrator.
+// by its sin/cos) under either integrator.  qx: the state-dependent part of
+// dt*l at the node (the crown problem's orbital-element cost; 0 otherwise).
 template <bool kHeun, bool kSnap = false>
 __device__ inline float q_step(const float* __restrict__ V, const Grid& G, const Phys& P, const NodeTerms& T,
-                               const HeunTerms& H, int thr, float sn, float cs) {
+                               const HeunTerms& H, int thr, float sn, float cs, float qx = 0.0f) {
   float off[4];
   foot_off<kHeun>(T, H, thr, sn, cs, off);
-  return fmaf(P.gamma, interp_off<kSnap>(V, G, T.i, off, P.M), thr ? P.q_thr : P.q_coast);
+  return fmaf(P.gamma, interp_off<kSnap>(V, G, T.i, off, P.M), (thr ? P.q_thr : P.q_coast) + qx);
+}
+
+// The crown problem's orbital-element running cost at a physical state x =
+// (r, v_r, v_t, theta), in FP64: beta*(a - a_bar)^2 + gamma*|e - e_bar|^2,
+// a from vis-viva and the eccentricity vector in polar form,
+// e = ((h^2/(mu r) - 1) (cos th, sin th) + (v_r h/mu) (sin th, -cos th)), h = r v_t.
+__device__ inline double crown_cost(const Phys& P, const double x[4]) {
+#pragma clang fp contract(off)
+  const double r = x[0], vr = x[1], vt = x[2], th = x[3];
+  const double v2 = vr * vr + vt * vt;
+  const double a = -P.mu * r / (v2 * r - 2.0 * P.mu);
+  const double h = r * vt;
+  const double ec = h * h / (P.mu * r) - 1.0, es = vr * h / P.mu;
+  double sth, cth;
+  sincos(th, &sth, &cth);
+  const double ex = ec * cth + es * sth, ey = ec * sth - es * cth;
+  const double da = a - P.el_a, dx = ex - P.el_ex, dy = ey - P.el_ey;
+  return P.el_beta * da * da + P.el_gamma * (dx * dx + dy * dy);
 }
 
 __device__ inline float wrap_pi(float u) {

@@ -30,7 +30,8 @@ struct SweepArgs {
   const double* rinv;
   const float* g1tab;
   const float* g2tab;
-  double c0, c1, c2;  // dt / h_k for axes r, v_r, v_t
+  double c0, c1, c2, c3;  // dt / h_k for axes r, v_r, v_t and axis 3
+  const float* qnode;     // crown problem: dt times the orbital-element running cost per node, nullable
   float gm;           // thrust displacement along m (cells)
   const float* tab_sin;  // tabulated controls (TABLE) or scan samples (SCAN_GOLDEN)
   const float* tab_cos;
@@ -127,6 +128,8 @@ hipError_t launch_init_value(const uint8_t* kind, float M, float* V, int N, hipS
 // (the integrator comes from a.P.heun).
 hipError_t launch_sweep_direct(const SweepArgs& a, int mode, hipStream_t s);
 hipError_t launch_policy_eval(const SweepArgs& a, bool want_resid, hipStream_t s);
+// crown problem: qnode[j] = dt * running cost at node j (FP64, rounded)
+hipError_t launch_node_cost(const Grid& G, const Phys& P, float* qnode, int N, hipStream_t s);
 // out[0] = sum of acc[0..n) (fixed order, one workgroup)
 hipError_t launch_sum_counts(const unsigned long long* acc, int n, unsigned long long* out, hipStream_t s);
 hipError_t launch_policy_eval_desc(const SweepArgs& a, bool streamed, hipStream_t s);

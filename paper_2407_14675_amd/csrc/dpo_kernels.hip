@@ -151,8 +151,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep_direct(SweepArgs a) {
     HeunTerms H;
     if (kHeun) node_heun(a, T.i, H);
     const float* __restrict__ V = a.V_in;
-    auto qf = [&](float sn, float cs) { return q_step<kHeun>(V, a.G, a.P, T, H, 1, sn, cs); };
-    const float qc = q_step<kHeun>(V, a.G, a.P, T, H, 0, 0.0f, 1.0f);
+    const float qx = a.qnode ? a.qnode[j] : 0.0f;
+    auto qf = [&](float sn, float cs) { return q_step<kHeun>(V, a.G, a.P, T, H, 1, sn, cs, qx); };
+    const float qc = q_step<kHeun>(V, a.G, a.P, T, H, 0, 0.0f, 1.0f, qx);
     const float vin = V[j];
     Choice ch;
     if (kMode == 0) table_search(qf, a, qc, ch);
@@ -230,7 +231,7 @@ __global__ __launch_bounds__(kBlock) void k_policy_eval(SweepArgs a) {
     const int thr = a.pol_thr_in[j] ? 1 : 0;
     float sn = 0.0f, cs = 1.0f;
     if (thr) __sincosf(a.pol_ang_in[j], &sn, &cs);
-    const float v = q_step<kHeun>(a.V_in, a.G, a.P, T, H, thr, sn, cs);
+    const float v = q_step<kHeun>(a.V_in, a.G, a.P, T, H, thr, sn, cs, a.qnode ? a.qnode[j] : 0.0f);
     a.V_out[j] = v;
     if (kResid) node_residual(a.V_in[j], v, rel, sum, mabs, bad);
   }
@@ -292,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_policy_eval_desc(SweepArgs a) {
       axis_cell(i[3], a.G.n[3], thr ? a.gm : 0.0f, b3, tt[3]);
       tt[1] = w[k].x;
       tt[2] = w[k].y;
-      I = cell_value(a.V_in + (code[k] & 0x3fffffff), a.G, tt);
+      I = cell_value(a.V_in + (code[k] & 0x3fffffff), a.G, tt, a.G.st[3]);
     }
     const float out = fmaf(a.P.gamma, I, thr ? a.P.q_thr : a.P.q_coast);
     if (kNt & 2) __builtin_nontemporal_store(out, a.V_out + j);
@@ -354,7 +355,7 @@ __global__ __launch_bounds__(kBlock) void k_policy_eval_d16(SweepArgs a) {
       tt[1] = w[k].x;
       tt[2] = w[k].y;
       const int dv = (int)(code[k] & 63u) - 32, dt = (int)((code[k] >> 6) & 63u) - 32;
-      I = cell_value(a.V_in + b0 + (i[1] + dv) * a.G.st[1] + (i[2] + dt) * a.G.st[2] + b3 * a.G.st[3], a.G, tt);
+      I = cell_value(a.V_in + b0 + (i[1] + dv) * a.G.st[1] + (i[2] + dt) * a.G.st[2] + b3 * a.G.st[3], a.G, tt, a.G.st[3]);
     }
     const float out = fmaf(a.P.gamma, I, thr ? a.P.q_thr : a.P.q_coast);
     if (kNt & 2) __builtin_nontemporal_store(out, a.V_out + j);
@@ -409,6 +410,21 @@ __global__ void k_value_at(const float* __restrict__ V, Grid G, double M, double
   int base[4];
   double t[4];
   for (int k = 0; k < 4; k++) {
+    if (k == 3 && G.periodic3) {
+      // periodic axis: wrap into [0, n)
+      const double n = (double)G.n[3];
+      double w = (x[3] - G.lo[3]) * G.inv_h[3];
+      if (!(fabs(w) <= 1e30)) {
+        *out = M;
+        return;
+      }
+      w -= n * floor(w / n);
+      int b = (int)floor(w);
+      if (b >= G.n[3]) b = 0, w = 0.0;
+      base[3] = b;
+      t[3] = w - (double)b;
+      continue;
+    }
     const double s = to_grid(G, k, x[k]);
     if (!(s >= 0.0 && s <= (double)(G.n[k] - 1))) {
       *out = M;
@@ -420,13 +436,14 @@ __global__ void k_value_at(const float* __restrict__ V, Grid G, double M, double
     t[k] = s - (double)b;
   }
   const float* p = V + (base[0] + base[1] * G.st[1] + base[2] * G.st[2] + base[3] * G.st[3]);
+  const int s3 = (G.periodic3 && base[3] == G.n[3] - 1) ? -base[3] * G.st[3] : G.st[3];
   double acc3[2];
   for (int e3 = 0; e3 < 2; e3++) {
     double acc2[2];
     for (int e2 = 0; e2 < 2; e2++) {
       double acc1[2];
       for (int e1 = 0; e1 < 2; e1++) {
-        const float* q = p + e1 * G.st[1] + e2 * G.st[2] + e3 * G.st[3];
+        const float* q = p + e1 * G.st[1] + e2 * G.st[2] + e3 * s3;
         acc1[e1] = (double)q[0] + t[0] * ((double)q[1] - (double)q[0]);
       }
       acc2[e2] = acc1[0] + t[1] * (acc1[1] - acc1[0]);
@@ -449,7 +466,9 @@ __global__ __launch_bounds__(kBlock) void k_feedback(SweepArgs a, const double* 
   float frac[4];
   for (int k = 0; k < 4; k++) {
     y[k] = states[4 * c + k];
-    const double s = (y[k] - a.G.lo[k]) * a.G.inv_h[k];
+    double s = (y[k] - a.G.lo[k]) * a.G.inv_h[k];
+    // periodic axis: wrap the state into [0, n) first
+    if (k == 3 && a.G.periodic3 && fabs(s) <= 1e30) s -= (double)a.G.n[3] * floor(s / (double)a.G.n[3]);
     double fl = floor(s);
     if (!(fl >= 0.0)) fl = 0.0;  // outside (or NaN) states keep a valid node; the bounds test decides
     if (fl > (double)(a.G.n[k] - 1)) fl = (double)(a.G.n[k] - 1);
@@ -465,12 +484,14 @@ __global__ __launch_bounds__(kBlock) void k_feedback(SweepArgs a, const double* 
   b.P.q_thr = (float)(tau * ((double)a.w_time + (double)a.w_fuel));
   b.P.gamma = (float)exp(-a.lambda * tau);
   const bool heun = a.P.heun != 0;
+  // crown: the orbital-element cost at the state itself (eq:feed evaluates l at y)
+  const float qx = a.P.model == 2 ? (float)(tau * crown_cost(a.P, y)) : 0.0f;
   auto qf = [&](float sn, float cs) {
-    return heun ? q_step<true, true>(b.V_in, b.G, b.P, T, H, 1, sn, cs)
-                : q_step<false, true>(b.V_in, b.G, b.P, T, H, 1, sn, cs);
+    return heun ? q_step<true, true>(b.V_in, b.G, b.P, T, H, 1, sn, cs, qx)
+                : q_step<false, true>(b.V_in, b.G, b.P, T, H, 1, sn, cs, qx);
   };
-  const float qc = heun ? q_step<true, true>(b.V_in, b.G, b.P, T, H, 0, 0.0f, 1.0f)
-                        : q_step<false, true>(b.V_in, b.G, b.P, T, H, 0, 0.0f, 1.0f);
+  const float qc = heun ? q_step<true, true>(b.V_in, b.G, b.P, T, H, 0, 0.0f, 1.0f, qx)
+                        : q_step<false, true>(b.V_in, b.G, b.P, T, H, 0, 0.0f, 1.0f, qx);
   Choice ch;
   // the walk's table (mode 3) is searched in full: a state has no previous optimum
   if (a.mode == 0 || a.mode == 3) table_search(qf, b, qc, ch);
@@ -568,14 +589,29 @@ __global__ __launch_bounds__(kBlock) void k_probe_q(SweepArgs a, const int* __re
   float sn = 0.0f, cs = 1.0f;
   if (th) sincosf(ang[c], &sn, &cs);
   const bool heun = a.P.heun != 0;
+  const float qx = a.qnode ? a.qnode[nodes[c]] : 0.0f;
   if (q_out)
-    q_out[c] = heun ? q_step<true>(a.V_in, a.G, a.P, T, H, th, sn, cs) : q_step<false>(a.V_in, a.G, a.P, T, H, th, sn, cs);
+    q_out[c] = heun ? q_step<true>(a.V_in, a.G, a.P, T, H, th, sn, cs, qx)
+                    : q_step<false>(a.V_in, a.G, a.P, T, H, th, sn, cs, qx);
   if (off_out) {
     float off[4];
     if (heun) foot_off<true>(T, H, th, sn, cs, off);
     else foot_off<false>(T, H, th, sn, cs, off);
     for (int k = 0; k < 4; k++) off_out[4 * c + k] = off[k];
   }
+}
+
+// Crown problem: dt times the orbital-element running cost at every node, FP64
+// then rounded (node coordinates lo + i*h with the product rounded first).
+__global__ __launch_bounds__(kBlock) void k_node_cost(Grid G, Phys P, float* __restrict__ qnode, int N) {
+#pragma clang fp contract(off)
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= N) return;
+  int i[4];
+  decode_node(G, j, i);
+  double x[4];
+  for (int k = 0; k < 4; k++) x[k] = G.lo[k] + (double)i[k] * G.h[k];
+  qnode[j] = (float)(P.dt * crown_cost(P, x));
 }
 
 // Fixed-order sum of the per-workgroup evaluation counts of the table walk.
@@ -640,6 +676,10 @@ hipError_t launch_sweep_direct(const SweepArgs& a, int mode, hipStream_t s) {
   if (mode == 1) DPO_LAUNCH((k_sweep_direct<1, false>), nb, kBlock, s, a);
   if (mode == 2) DPO_LAUNCH((k_sweep_direct<2, false>), nb, kBlock, s, a);
   DPO_LAUNCH((k_sweep_direct<3, false>), nb, kBlock, s, a);
+}
+
+hipError_t launch_node_cost(const Grid& G, const Phys& P, float* qnode, int N, hipStream_t s) {
+  DPO_LAUNCH(k_node_cost, blocks_for(N), kBlock, s, G, P, qnode, N);
 }
 
 hipError_t launch_sum_counts(const unsigned long long* acc, int n, unsigned long long* out, hipStream_t s) {

@@ -21,7 +21,7 @@ namespace dpo {
 // The r displacement dt*v_r/h_r (cells) of nodes in v_r row i1.
 __device__ inline float drift_r(const SweepArgs& a, int i1) {
 #pragma clang fp contract(off)
-  if (a.P.model != 0) return 0.0f;
+  if (a.P.model == 1) return 0.0f;
   const double vr = a.G.lo[1] + (double)i1 * a.G.h[1];
   return (float)(a.c0 * vr);
 }
@@ -29,17 +29,19 @@ __device__ inline float drift_r(const SweepArgs& a, int i1) {
 __device__ inline int node_terms_tab(const SweepArgs& a, uint32_t packed, NodeTerms& T) {
 #pragma clang fp contract(off)
   const int j = unpack_node(a.G, packed, T.i);
-  if (a.P.model == 0) {
+  T.drift[3] = 0.0f;
+  if (a.P.model != 1) {
     const double ri = a.rinv[T.i[0]];
     const double vr = a.G.lo[1] + (double)T.i[1] * a.G.h[1];
     const double vt = a.G.lo[2] + (double)T.i[2] * a.G.h[2];
     T.drift[0] = drift_r(a, T.i[1]);
     T.drift[1] = (float)(a.c1 * (vt * vt * ri - a.P.mu * ri * ri));
     T.drift[2] = (float)(-a.c2 * vr * vt * ri);
+    // crown: theta' = v_t / r along axis 3
+    if (a.P.model == 2) T.drift[3] = (float)(a.c3 * vt * ri);
   } else {
     T.drift[0] = T.drift[1] = T.drift[2] = 0.0f;
   }
-  T.drift[3] = 0.0f;
   T.g1 = a.g1tab[T.i[3]];
   T.g2 = a.g2tab[T.i[3]];
   T.gm = a.gm;

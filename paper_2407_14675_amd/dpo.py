@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdpo.so")
 
 DPO_OK, DPO_ENOCONV, DPO_EINVAL, DPO_ENOMEM, DPO_EHIP, DPO_ENUMERIC = 0, 1, -1, -2, -3, -4
-MODELS = {"orbit": 0, "eikonal": 1}
+MODELS = {"orbit": 0, "eikonal": 1, "crown": 2}
 SEARCH = {"table": 0, "scan_golden": 1, "seeded": 2, "table_walk": 3}
 INTEGRATORS = {"euler": 0, "heun": 1}
 KIND_FREE, KIND_TARGET, KIND_INACTIVE = 0, 1, 2
@@ -36,7 +36,8 @@ class Problem(C.Structure):
     _fields_ = [("model", C.c_int32), ("mu", C.c_double), ("accel", C.c_double), ("mdot", C.c_double),
                 ("dt", C.c_double), ("lam", C.c_double), ("w_time", C.c_double), ("w_fuel", C.c_double),
                 ("M", C.c_double), ("speed", C.c_double), ("tgt_c", C.c_double * 4),
-                ("tgt_w", C.c_double * 4), ("integrator", C.c_int32)]
+                ("tgt_w", C.c_double * 4), ("integrator", C.c_int32), ("el_beta", C.c_double),
+                ("el_gamma", C.c_double), ("el_a", C.c_double), ("el_e", C.c_double), ("el_omega", C.c_double)]
 
 
 class Search(C.Structure):
@@ -153,6 +154,8 @@ def problem_struct(problem):
     p.tgt_c[:] = [float(v) for v in problem["tgt_c"]]
     p.tgt_w[:] = [float(v) for v in problem["tgt_w"]]
     p.integrator = INTEGRATORS[problem.get("integrator", "euler")]
+    for f in ("el_beta", "el_gamma", "el_a", "el_e", "el_omega"):
+        setattr(p, f, float(problem.get(f, 0.0)))
     return p
 
 

@@ -13,6 +13,10 @@ vi12_table16_heun.npz   the same problem with the Heun (second-order
 vi12_walk16.npz   the Euler problem with the table searched by the walk from
               the previous sweep's angles (full table on the first sweep),
               same stop rule.
+crown8_table72.npz   the paper's Example 1 problem (crown grid, theta
+              periodic, orbital-element cost, discount, Heun foot, 72 angles
+              + coast) on 8 x 6 x 6 x 8 nodes, value iteration until the
+              largest change is below 1e-6 (values up to ~1e6).
 """
 import os
 import sys
@@ -56,11 +60,23 @@ def make_vi12_walk():
     print("12^4 value iteration, table walk: sweeps", res["sweeps"], "V(x0)", o.value_at(res["V"], inputs.X0))
 
 
+def make_crown8():
+    p = inputs.crown_problem((8, 6, 6, 8))
+    o = Oracle(p)
+    res = o.solve_vi(tol_abs=1e-6, max_sweeps=100000)
+    assert res["converged"], res
+    np.savez_compressed(os.path.join(HERE, "crown8_table72.npz"), V=res["V"], angle=res["angle"],
+                        thr=res["thr"], sweeps=np.int64(res["sweeps"]))
+    print("crown 8x6x6x8 value iteration: sweeps", res["sweeps"])
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["vi12", "vi12_heun", "vi12_walk"]
+    which = sys.argv[1:] or ["vi12", "vi12_heun", "vi12_walk", "crown8"]
     if "vi12" in which:
         make_vi12()
     if "vi12_heun" in which:
         make_vi12_heun()
     if "vi12_walk" in which:
         make_vi12_walk()
+    if "crown8" in which:
+        make_crown8()

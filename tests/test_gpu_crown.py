@@ -1,0 +1,174 @@
+"""Parity of the crown problem (the paper's Example 1: polar state with theta
+periodic, orbital-element running cost, discount, Heun foot) on the device,
+through the C ABI, with the CPU oracle.  Tolerances as in the other parity
+tests: one evaluation or sweep within 1e-5*max(1,|V|) plus the float32
+rounding of the corners a foot touches; the converged value within
+1e-4*max(1,|V|)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.core import KIND_FREE, Oracle
+from paper_2407_14675_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dpo():
+    from paper_2407_14675_amd import dpo as mod
+    mod.load()
+    return mod
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dtype).contiguous()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel_err(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.abs(a - b) / np.maximum(1.0, np.abs(b))
+
+
+def sweep_tol(V, Vref):
+    from scipy.ndimage import maximum_filter
+    corner = maximum_filter(np.abs(np.asarray(V, dtype=np.float64)), size=7, mode="wrap")
+    return 1e-5 * np.maximum(1.0, np.abs(Vref)) + 1e-6 * corner
+
+
+def crown(n=(12, 8, 8, 10), integrator="heun"):
+    return inputs.crown_problem(n, integrator=integrator)
+
+
+def smooth_value(p, seed):
+    """A value field of the size the solution has (1e2..1e4), smooth in the
+    state and periodic in theta, plus a little noise."""
+    n = p["n"]
+    rng = np.random.default_rng(seed)
+    ax = [np.linspace(0, 1, n[k]) for k in range(3)]
+    th = 2 * math.pi * np.arange(n[3]) / n[3]
+    R, VR, VT, TH = np.meshgrid(ax[0], ax[1], ax[2], th, indexing="ij")
+    V = 2e3 + 4e3 * (R - 0.5) ** 2 + 3e3 * VR ** 2 + 2e3 * (VT - 0.4) ** 2 + 500 * np.cos(TH)
+    V = V.transpose(3, 2, 1, 0) + rng.uniform(0, 20, size=(n[3], n[2], n[1], n[0]))
+    return V
+
+
+@pytest.mark.parametrize("integrator", ["euler", "heun"])
+def test_crown_probe_foot_and_q(dpo, integrator):
+    p = crown(integrator=integrator)
+    _say("crown probe foot/q", integrator)
+    o = Oracle(p)
+    ctx = dpo.Context(p)
+    assert ctx.kernel_path() == 1
+    nodes = inputs.random_nodes(p, 2000, seed=101)
+    rng = np.random.default_rng(102)
+    thr = rng.integers(0, 2, size=nodes.size).astype(np.uint8)
+    ang = rng.uniform(-math.pi, math.pi, size=nodes.size).astype(np.float32)
+    off = host(ctx.probe_foot(nodes, thr, ang))
+    n = np.array(p["n"])
+    h = (np.array(p["hi"]) - np.array(p["lo"])) / np.array([n[0] - 1, n[1] - 1, n[2] - 1, n[3]])
+    for c in range(nodes.size):
+        x = o.node_coords(int(nodes[c]))
+        want = (o.step(x, int(thr[c]), float(ang[c])) - x) / h
+        np.testing.assert_allclose(off[c], want, atol=2e-6, rtol=0)
+    V = smooth_value(p, 103).astype(np.float32)
+    q = host(ctx.probe_q(dev(V), nodes, thr, ang))
+    want = o.q_many(V.astype(np.float64), nodes, thr, ang.astype(np.float64))
+    assert np.max(rel_err(q, want)) < 1e-5
+
+
+@pytest.mark.parametrize("integrator", ["euler", "heun"])
+def test_crown_sweep_parity(dpo, integrator):
+    """One Bellman sweep over the 72-angle table; feet at the last theta node
+    wrap to node 0.  The thrust moves a foot by ~2e-3 cell per step, so the
+    Q of different angles differ by far less than 1e-4*|V| and every node is
+    a tie by that measure: what is unique is the minimal value, which must
+    agree at every free node, and the device's value must be the oracle's Q
+    of the device's own control."""
+    p = crown(integrator=integrator)
+    _say("crown sweep", integrator)
+    o = Oracle(p)
+    V32 = smooth_value(p, 104).astype(np.float32)
+    V64 = V32.astype(np.float64)
+    ctx = dpo.Context(p)
+    Vin = dev(V32)
+    Vout = Vin.clone()
+    ang, thr = ctx.empty_policy()
+    ctx.bellman_sweep(Vin, Vout, ang, thr)
+    Vo, ao, to, margin = o.bellman_sweep(V64)
+    Vg, tg, ag = host(Vout), host(thr), host(ang)
+    free = o.kind == KIND_FREE
+    tol = sweep_tol(V32, Vo)
+    assert np.all((np.abs(Vg - Vo) <= tol)[free]), np.max((np.abs(Vg - Vo) / tol)[free])
+    nodes = np.flatnonzero(free.reshape(-1))
+    q_own = o.q_many(V64, nodes, tg.reshape(-1)[nodes], ag.reshape(-1)[nodes].astype(np.float64))
+    assert np.all(np.abs(q_own - Vg.reshape(-1)[nodes]) <= tol.reshape(-1)[nodes])
+    _say("  free", int(free.sum()), "thrust", int((tg[free] == 1).sum()), "oracle thrust", int((to[free] == 1).sum()))
+
+
+def test_crown_policy_iteration_parity(dpo):
+    """Policy iteration on 8 x 6 x 6 x 8 against the oracle's value iteration
+    (stored), and the FP64 read-out at states on and across the theta seam."""
+    p = inputs.crown_problem((8, 6, 6, 8))
+    _say("crown PI")
+    gold = np.load("tests/golden/crown8_table72.npz")
+    o = Oracle(p)
+    ctx = dpo.Context(p)
+    V = ctx.init_value()
+    a, t = ctx.empty_policy()
+    rc, st = ctx.solve_pi(V, a, t, tol_rel=1e-6, eval_sweeps=20, max_outer=2000)
+    _say("  PI steps", st["sweeps"], "eval sweeps", st["eval_sweeps"], "rc", rc)
+    assert st["converged"] or st["stalled"]
+    Vg = host(V)
+    assert rel_err(Vg, gold["V"]).max() <= 1e-4
+    rng = np.random.default_rng(105)
+    for th in (0.0, 2 * math.pi - 1e-3, 2 * math.pi + 0.3, -0.2, 6.1):
+        x = [rng.uniform(6940, 7060), rng.uniform(-0.009, 0.009), rng.uniform(7.53, 7.56), th]
+        assert ctx.value_at(V, x) == pytest.approx(o.value_at(Vg.astype(np.float64), x), rel=1e-9, abs=1e-6)
+
+
+def test_crown_feedback_parity(dpo):
+    p = inputs.crown_problem((8, 6, 6, 8))
+    _say("crown feedback")
+    gold = np.load("tests/golden/crown8_table72.npz")
+    o = Oracle(p)
+    ctx = dpo.Context(p)
+    V32 = gold["V"].astype(np.float32)
+    states = inputs.random_states(p, 400, seed=106, margin=0.02)
+    states[:, 3] = np.random.default_rng(107).uniform(-1, 7.5, size=len(states))  # across the seam
+    ang, thr, q = ctx.feedback(dev(V32), states)
+    ao, to, qo = o.feedback(V32.astype(np.float64), states)
+    tol = 1e-5 * np.maximum(1.0, np.abs(qo)) + 1e-6 * np.abs(V32).max()
+    assert np.all(np.abs(host(q) - qo) <= tol), np.max(np.abs(host(q) - qo) / tol)
+    assert (host(thr) == to).mean() >= 0.98
+
+
+def test_crown_refusals(dpo):
+    """The factorised sweep, the descriptors, the mask helper and the batched
+    solver take the orbit and eikonal models only."""
+    p = inputs.crown_problem((8, 6, 6, 8))
+    ctx = dpo.Context(p)
+    with pytest.raises(dpo.DpoError):
+        ctx.set_kernel_path(2)
+    V = ctx.init_value()
+    with pytest.raises(dpo.DpoError):
+        ctx.policy_eval_sweep_last(V, V.clone())
+    with pytest.raises(dpo.DpoError):
+        dpo.Batch([p, p])
+    bad = dict(p, lo=(0.0,) + tuple(p["lo"][1:]))
+    with pytest.raises(dpo.DpoError):
+        dpo.Context(bad)
