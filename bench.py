@@ -316,6 +316,58 @@ def bench_variants(mask, V_euler):
     return out
 
 
+def bench_example1():
+    """The paper's Example 1 at its own size (crown grid 110 x 30 x 30 x 30,
+    73 controls, Heun foot, dt = 10 s, discount 1e-3): policy iteration
+    (20 evaluation sweeps per step) with the full table at every greedy step
+    and with the walk from the previous optimum, and value iteration, each
+    from V0 = M to a relative residual of 1e-6; the read-out at the start of
+    the paper's orbit raise (circular orbit at 6978 km, theta = 0)."""
+    import math
+
+    import torch
+
+    from paper_2407_14675_amd import dpo, inputs
+
+    p = inputs.EX1
+    x_start = (inputs.EX1_START_RADIUS, 0.0, math.sqrt(inputs.EX1_MU / inputs.EX1_START_RADIUS), 0.0)
+    out = {"grid": list(p["n"]), "nodes": int(inputs.n_nodes(p)), "controls": p["search"]["n_angles"] + 1,
+           "integrator": p["integrator"], "tol_rel": 1e-6}
+
+    def run(problem, solver):
+        ctx = dpo.Context(problem)
+        V = ctx.init_value()
+        ang, thr = ctx.empty_policy()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        if solver == "pi":
+            rc, st = ctx.solve_pi(V, ang, thr, tol_rel=1e-6, eval_sweeps=inputs.EVAL_SWEEPS, max_outer=5000)
+        else:
+            rc, st = ctx.solve_vi(V, ang, thr, tol_rel=1e-6, max_sweeps=200000, check_every=16)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t
+        res = {"seconds": sec, "sweeps": st["sweeps"], "eval_sweeps": st["eval_sweeps"],
+               "converged": bool(st["converged"]), "stalled": bool(st["stalled"]),
+               "resid_max_rel": st["resid_max_rel"], "evals": st["evals"], "evals_per_s": st["evals"] / sec,
+               "V_start": ctx.value_at(V, x_start), "kernel_path": ctx.kernel_path()}
+        return V, res
+
+    Vt, out["pi_table"] = run(p, "pi")
+    log(f"bench: example 1 PI {out['pi_table']}")
+    Vw, out["pi_walk"] = run(dict(p, search=dict(mode="table_walk", n_angles=p["search"]["n_angles"])), "pi")
+    d = (Vw - Vt).abs() / Vt.abs().clamp(min=1.0)
+    out["pi_walk"]["max_rel_diff_vs_table"] = float(d.max())
+    out["pi_walk"]["frac_within_1e-4"] = float((d <= 1e-4).float().mean())
+    log(f"bench: example 1 PI walk {out['pi_walk']}")
+    Vv, out["vi"] = run(p, "vi")
+    out["vi"]["max_rel_diff_vs_pi"] = float(((Vv - Vt).abs() / Vt.abs().clamp(min=1.0)).max())
+    out["vi_over_pi_time"] = out["vi"]["seconds"] / out["pi_table"]["seconds"]
+    log(f"bench: example 1 VI {out['vi']}")
+    out["paper"] = {"pi_seconds": 18 * 60, "vi_seconds": 15 * 3600,
+                    "hardware": "MacBook Air laptop, Mex-compiled Matlab (paper Section 4)"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -328,6 +380,7 @@ def main():
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 96^3 x 64 solves and the network-seeded comparison")
     ap.add_argument("--no-variants", action="store_true", help="skip the table-walk and Heun-foot solves")
+    ap.add_argument("--no-example1", action="store_true", help="skip the paper's Example 1 solves")
     ap.add_argument("--held-out", action="store_true",
                     help="also solve the 96^3 x 64 problem with thrust 5e-4 using the network trained at 1e-3")
     ap.add_argument("--calib-copy", action="store_true",
@@ -444,6 +497,11 @@ def main():
         log("bench: paper variants (table walk, Heun foot)")
         variants = bench_variants(mask, Vc1)
 
+    example1 = None
+    if not args.no_example1:
+        log("bench: the paper's Example 1 (crown grid)")
+        example1 = bench_example1()
+
     large = None
     if not args.no_large:
         log("bench: 96^3 x 64 solves")
@@ -518,6 +576,7 @@ def main():
         },
         "time_to_converge": converge,
         "paper_variants": variants,
+        "paper_example1": example1,
         "large_96x96x96x64": large,
         "batched": batched,
         "cpu_baseline": cpu,
