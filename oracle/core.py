@@ -121,6 +121,8 @@ def load(precision="f64"):
     lib.or_brute_thrust_min.argtypes = [P, vp, i64, i64, vp]
     lib.or_brute_thrust_min.restype = real
     lib.or_mask_from_coarse.argtypes = [P, vp, P, C.c_double, vp, vp]
+    lib.or_rk4_step.argtypes = [P, vp, C.c_int, real, real]
+    lib.or_simulate.argtypes = [P, S, vp, vp, i64, C.c_double, C.c_int32, C.c_int32, vp, vp, vp]
     lib.or_running_cost.argtypes = [P, vp, C.c_int]
     lib.or_running_cost.restype = real
     lib.or_elements.argtypes = [P, vp, vp]
@@ -319,6 +321,25 @@ class Oracle:
         self.lib.or_feedback(C.byref(self.ps), C.byref(ss), _ptr(Vin), _ptr(st), cnt,
                              float(tau), _ptr(ang), _ptr(thr), _ptr(q))
         return ang, thr, q
+
+    def rk4_step(self, x, thr, u, h):
+        x = np.ascontiguousarray(np.asarray(x, dtype=self.dtype)).copy()
+        self.lib.or_rk4_step(C.byref(self.ps), _ptr(x), int(thr), u, h)
+        return x
+
+    def simulate(self, V, states, tau, steps, substeps=1, search=None, history=True):
+        """Closed loop from states (count x 4): returns final states and, with
+        history, the trajectory ((steps+1) x count x 4) and the controls."""
+        Vin = self._arr(V)
+        ss = self.ss if search is None else search_struct(search)
+        st = np.ascontiguousarray(np.asarray(states, dtype=np.float64).reshape(-1, 4)).copy()
+        cnt = st.shape[0]
+        traj = np.zeros((steps + 1, cnt, 4)) if history else None
+        thr = np.zeros((steps, cnt), dtype=np.uint8) if history else None
+        ang = np.zeros((steps, cnt), dtype=self.dtype) if history else None
+        self.lib.or_simulate(C.byref(self.ps), C.byref(ss), _ptr(Vin), _ptr(st), cnt, float(tau), int(steps),
+                             int(substeps), _ptr(traj), _ptr(thr), _ptr(ang))
+        return st, traj, thr, ang
 
     def brute_thrust_min(self, V, j, n_angles):
         Vin = self._arr(V)

@@ -25,7 +25,9 @@
  *     (paragraph "Efficient computation of the minimum"), and a seeded local
  *     golden search with the full search as fallback (the warm-started
  *     minimisation of the same paragraph, with the seed given per node);
- *   - the approximate feedback eq:feed.
+ *   - the approximate feedback eq:feed, and the closed loop that applies it
+ *     to the model integrated by the classical fourth-order Runge-Kutta
+ *     method (Section 4's simulations).
  *
  * Pins (tests): exact multilinear reproduction, Euler defects in closed
  * form, the Heun step's third-order local error against an accurate ODE
@@ -848,6 +850,51 @@ void or_feedback(const or_problem *p, const or_search *sr, const real *V, const 
     angle_out[c] = ch.angle;
     thr_out[c] = (uint8_t)ch.thr;
     if (q_out) q_out[c] = ch.q;
+  }
+}
+
+/* ------------------------------------------------- closed-loop simulation */
+/* One classical fourth-order Runge-Kutta step of length h of the model's
+ * dynamics (the "real system" of Section 3, computed by a fourth-order
+ * Runge-Kutta method) with the control (thr, u) held over the step. */
+void or_rk4_step(const or_problem *p, real x[4], int thr, real u, real h) {
+  real k1[4], k2[4], k3[4], k4[4], y[4];
+  rhs(p, x, thr, u, k1);
+  for (int k = 0; k < 4; k++) y[k] = x[k] + (real)0.5 * h * k1[k];
+  rhs(p, y, thr, u, k2);
+  for (int k = 0; k < 4; k++) y[k] = x[k] + (real)0.5 * h * k2[k];
+  rhs(p, y, thr, u, k3);
+  for (int k = 0; k < 4; k++) y[k] = x[k] + h * k3[k];
+  rhs(p, y, thr, u, k4);
+  for (int k = 0; k < 4; k++) x[k] += h / (real)6 * (k1[k] + (real)2 * k2[k] + (real)2 * k3[k] + k4[k]);
+}
+
+/* Closed loop (Section 3, feedback eq:feed, and the simulations of
+ * Section 4): from each of count states, `steps` times: the feedback control
+ * at the current state with time step tau (the context's search), then
+ * `substeps` fourth-order Runge-Kutta steps of length tau/substeps with that
+ * control held.  states (count x 4) is updated in place; traj (nullable)
+ * receives the states before every step and after the last, step-major
+ * ((steps+1) x count x 4); thr_hist / ang_hist (nullable) the controls,
+ * step-major (steps x count). */
+void or_simulate(const or_problem *p, const or_search *sr, const real *V, double *states, int64_t count,
+                 double tau, int32_t steps, int32_t substeps, double *traj, uint8_t *thr_hist, real *ang_hist) {
+  for (int64_t c = 0; c < count; c++) {
+    real y[4];
+    for (int k = 0; k < 4; k++) y[k] = (real)states[4 * c + k];
+    if (traj)
+      for (int k = 0; k < 4; k++) traj[4 * c + k] = (double)y[k];
+    for (int32_t s = 0; s < steps; s++) {
+      qfun f = {p, V, NULL, y, (real)tau};
+      choice ch = search(&f, sr);
+      const real h = (real)(tau / (double)substeps);
+      for (int32_t q = 0; q < substeps; q++) or_rk4_step(p, y, ch.thr, ch.angle, h);
+      if (thr_hist) thr_hist[(int64_t)s * count + c] = (uint8_t)ch.thr;
+      if (ang_hist) ang_hist[(int64_t)s * count + c] = ch.angle;
+      if (traj)
+        for (int k = 0; k < 4; k++) traj[((int64_t)(s + 1) * count + c) * 4 + k] = (double)y[k];
+    }
+    for (int k = 0; k < 4; k++) states[4 * c + k] = (double)y[k];
   }
 }
 
