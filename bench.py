@@ -365,6 +365,84 @@ def bench_example1():
     log(f"bench: example 1 VI {out['vi']}")
     out["paper"] = {"pi_seconds": 18 * 60, "vi_seconds": 15 * 3600,
                     "hardware": "MacBook Air laptop, Mex-compiled Matlab (paper Section 4)"}
+    out["orbit_raise"] = orbit_raise(p, Vt, x_start)
+    log(f"bench: example 1 orbit raise {out['orbit_raise']}")
+    return out
+
+
+def orbit_raise(p, V, x_start, horizon_s=5e5, batch=4096, cpu=True):
+    """The paper's closed-loop orbit raise on the Example 1 solution V: from
+    the circular orbit at 6978 km, the feedback eq:feed with tau = dt and the
+    model integrated by RK4, for horizon_s seconds.  Reports when the
+    semi-major axis first comes within 1 km of the target, when the thruster
+    fires for the last time, and the final errors (radius against the target
+    ellipse at the final angle, semi-major axis, eccentricity vector); the
+    same loop for `batch` perturbed starts at once (trajectory-steps/s); and
+    the CPU oracle's run of the single trajectory (time, final agreement)."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_2407_14675_amd import dpo, inputs
+
+    mu = p["mu"]
+    steps = int(round(horizon_s / p["dt"]))
+    ctx = dpo.Context(p)
+
+    def elements(x):
+        r, vr, vt, th = x
+        v2 = vr * vr + vt * vt
+        a = -mu * r / (v2 * r - 2 * mu)
+        h = r * vt
+        ec, es = h * h / (mu * r) - 1, vr * h / mu
+        return a, ec * math.cos(th) + es * math.sin(th), ec * math.sin(th) - es * math.cos(th)
+
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    final, traj, thr, _ = ctx.simulate(V, np.array([x_start]), tau=p["dt"], steps=steps)
+    torch.cuda.synchronize()
+    gpu_s = time.perf_counter() - t
+    traj = traj.cpu().numpy()[:, 0]
+    thr = thr.cpu().numpy()[:, 0]
+    a_err = np.array([abs(elements(x)[0] - p["el_a"]) for x in traj[::10]])
+    near = np.flatnonzero(a_err < 1.0)
+    fired = np.flatnonzero(thr)
+    xf = traj[-1]
+    a, ex, ey = elements(xf)
+    e_bar = (p["el_e"] * math.cos(p["el_omega"]), p["el_e"] * math.sin(p["el_omega"]))
+    pp = p["el_a"] * (1 - p["el_e"] ** 2)
+    r_target = pp / (1 + p["el_e"] * math.cos(xf[3] - p["el_omega"]))
+    out = {"horizon_s": horizon_s, "steps": steps, "tau_s": p["dt"], "gpu_seconds": gpu_s,
+           "t_within_1km_of_a_bar_s": float(near[0] * 10 * p["dt"]) if near.size else None,
+           "last_thrust_s": float((fired[-1] + 1) * p["dt"]) if fired.size else None,
+           "thrust_fraction": float(thr.mean()),
+           "final_radius_error_km": float(abs(xf[0] - r_target)), "final_a_error_km": float(a - p["el_a"]),
+           "final_e_error": float(math.hypot(ex - e_bar[0], ey - e_bar[1])),
+           "paper": "target neighbourhood after ~1e5 s, thruster off after ~5e5 s, radius error ~1e-2 km"}
+    # many perturbed starts at once
+    rng = np.random.default_rng(5)
+    starts = np.tile(np.array(x_start), (batch, 1))
+    starts[:, 0] += rng.uniform(-20, 20, size=batch)
+    starts[:, 3] = rng.uniform(0, 2 * math.pi, size=batch)
+    bsteps = 2000
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ctx.simulate(V, starts, tau=p["dt"], steps=bsteps, history=False)
+    torch.cuda.synchronize()
+    bt = time.perf_counter() - t
+    out["batch"] = {"trajectories": batch, "steps": bsteps, "seconds": bt,
+                    "trajectory_steps_per_s": batch * bsteps / bt}
+    if cpu:
+        from oracle.core import Oracle
+        o = Oracle(p)
+        t = time.perf_counter()
+        ofinal, otraj, othr, _ = o.simulate(V.cpu().numpy().astype(np.float64), np.array([x_start]), p["dt"], steps)
+        out["cpu_oracle_seconds"] = time.perf_counter() - t
+        same = (othr[:, 0] == thr)
+        out["steps_before_first_different_throttle"] = int(np.argmin(same)) if not same.all() else steps
+        out["cpu_final_radius_km"] = float(ofinal[0, 0])
+        out["cpu_last_thrust_s"] = float((np.flatnonzero(othr[:, 0])[-1] + 1) * p["dt"]) if othr.any() else None
     return out
 
 

@@ -84,8 +84,11 @@ typedef struct {
  *                 el_beta*(a - el_a)^2 + el_gamma*|e_vec - el_e*(cos el_omega,
  *                 sin el_omega)|^2, with a the vis-viva semi-major axis and
  *                 e_vec the eccentricity vector of the state (computed in FP64
- *                 per node at dpo_create).  No target set is implied: give an
- *                 empty target box (negative tgt_w).  Needs lo[0] > 0.
+ *                 per node at dpo_create).  The state constraint (I = M)
+ *                 holds on the two circular faces r = lo[0], hi[0] only; a
+ *                 foot beyond a v_r or v_t face is put on that face.  No
+ *                 target set is implied: give an empty target box (negative
+ *                 tgt_w).  Needs lo[0] > 0.
  *  The factorised sweep, the foot descriptors, the reduced-grid mask helper
  *  and the batched solver take the ORBIT and EIKONAL models only.
  *  Foot point x + dt*Phi(x, f) (eq:schema), the control held over the step:
@@ -300,6 +303,20 @@ int dpo_value_at(dpo_ctx* ctx, const float* V, const double* x, double* out, voi
 int dpo_extract_feedback(dpo_ctx* ctx, const float* V, const double* states, int64_t n,
                          double tau, float* angle_out, uint8_t* thr_out, float* q_out,
                          void* stream);
+
+/* Closed loop (paper Section 3, eq:feed, and the simulations of Section 4):
+ * from each of n states (device double[n*4], updated in place), `steps`
+ * times: the feedback of dpo_extract_feedback at the current state with time
+ * step tau, then `substeps` classical fourth-order Runge-Kutta steps of
+ * length tau/substeps of the model's own dynamics in FP64 with that control
+ * held.  One device thread follows each trajectory for all its steps.
+ * Histories (device, nullable), step-major so that a step's writes are
+ * contiguous: traj double[(steps+1)*n*4] (the states before every step and
+ * after the last), thr_hist u8[steps*n], ang_hist float[steps*n].
+ * Asynchronous on stream.  Limits: 0 <= n < 2^31 - 256, steps >= 0,
+ * 1 <= substeps <= 4096, tau > 0; SEEDED search is refused. */
+int dpo_simulate(dpo_ctx* ctx, const float* V, double* states, int64_t n, double tau, int32_t steps,
+                 int32_t substeps, double* traj, uint8_t* thr_hist, float* ang_hist, void* stream);
 
 /* Reachability mask for a reduced grid: for every node of `fine` (same
  * domain box as ctx), keep = (FP64 Q1 value of the coarse V at the node <

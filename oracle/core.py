@@ -122,6 +122,8 @@ def load(precision="f64"):
     lib.or_brute_thrust_min.restype = real
     lib.or_mask_from_coarse.argtypes = [P, vp, P, C.c_double, vp, vp]
     lib.or_rk4_step.argtypes = [P, vp, C.c_int, real, real]
+    lib.or_q_state.argtypes = [P, vp, vp, C.c_int, real, real]
+    lib.or_q_state.restype = real
     lib.or_simulate.argtypes = [P, S, vp, vp, i64, C.c_double, C.c_int32, C.c_int32, vp, vp, vp]
     lib.or_running_cost.argtypes = [P, vp, C.c_int]
     lib.or_running_cost.restype = real
@@ -321,6 +323,13 @@ class Oracle:
         self.lib.or_feedback(C.byref(self.ps), C.byref(ss), _ptr(Vin), _ptr(st), cnt,
                              float(tau), _ptr(ang), _ptr(thr), _ptr(q))
         return ang, thr, q
+
+    def q_state(self, V, y, thr, u, tau=None):
+        """Q of the control (thr, u) at an arbitrary state y (eq:feed's argument)."""
+        Vin = self._arr(V)
+        y = np.ascontiguousarray(np.asarray(y, dtype=self.dtype))
+        tau = self.problem["dt"] if tau is None else tau
+        return float(self.lib.or_q_state(C.byref(self.ps), _ptr(Vin), _ptr(y), int(thr), u, tau))
 
     def rk4_step(self, x, thr, u, h):
         x = np.ascontiguousarray(np.asarray(x, dtype=self.dtype)).copy()

@@ -238,11 +238,18 @@ static int cell(const or_problem *p, const real s[4], int base[4], real t[4]) {
       t[k] = w - (real)b;
       continue;
     }
-    if (!(s[k] >= 0 && s[k] <= (real)(p->n[k] - 1))) return 0;
-    int b = (int)floor(s[k]);
+    real sk = s[k];
+    /* crown problem: the state constraint (I = M) holds on the two circular
+     * faces r = r_min, r_max only; a foot beyond a velocity face is put on it */
+    if (p->model == 2 && (k == 1 || k == 2) && isfinite((double)sk)) {
+      if (sk < 0) sk = 0;
+      if (sk > (real)(p->n[k] - 1)) sk = (real)(p->n[k] - 1);
+    }
+    if (!(sk >= 0 && sk <= (real)(p->n[k] - 1))) return 0;
+    int b = (int)floor(sk);
     if (b > p->n[k] - 2) b = p->n[k] - 2;
     base[k] = b;
-    t[k] = s[k] - (real)b;
+    t[k] = sk - (real)b;
   }
   return 1;
 }
@@ -391,6 +398,11 @@ static real q_state(const or_problem *p, const real *V, const real y[4], int thr
   or_step(p, y, thr, u, tau, z);
   for (int k = 0; k < 4; k++) s[k] = to_grid(p, k, (double)z[k]);
   return tau * or_running_cost(p, y, thr) + discount(p, tau) * interp(p, V, s);
+}
+
+/* Exported: Q at an arbitrary state y with step tau (tests of the closed loop). */
+real or_q_state(const or_problem *p, const real *V, const real y[4], int thr, real u, real tau) {
+  return q_state(p, V, y, thr, u, tau);
 }
 
 /* ------------------------------------------------------------- search */

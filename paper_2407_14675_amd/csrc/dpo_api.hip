@@ -201,6 +201,7 @@ Grid make_grid(const dpo_grid& g, bool periodic3 = false) {
     G.inv_h[k] = 1.0 / G.h[k];
   }
   G.periodic3 = periodic3 ? 1 : 0;
+  G.clamp12 = periodic3 ? 1 : 0;  // the crown problem
   G.st[0] = 1;
   G.st[1] = g.n[0];
   G.st[2] = g.n[0] * g.n[1];
@@ -986,6 +987,22 @@ int dpo_extract_feedback(dpo_ctx* c, const float* V, const double* states, int64
   SweepArgs a = base_args(c);
   a.V_in = V;
   HIP_TRY(c, launch_feedback(a, states, (int)n, tau, angle_out, thr_out, q_out, S(stream)));
+  return DPO_OK;
+}
+
+int dpo_simulate(dpo_ctx* c, const float* V, double* states, int64_t n, double tau, int32_t steps, int32_t substeps,
+                 double* traj, uint8_t* thr_hist, float* ang_hist, void* stream) {
+  if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
+  if (!V) return fail(c, DPO_EINVAL, "V is NULL");
+  if (n < 0 || n > 0x7fffffff - kBlock) return fail(c, DPO_EINVAL, "bad n");
+  if (!(tau > 0) || !std::isfinite(tau)) return fail(c, DPO_EINVAL, "tau must be > 0");
+  if (steps < 0 || substeps < 1 || substeps > 4096) return fail(c, DPO_EINVAL, "steps >= 0, substeps in [1, 4096]");
+  if (c->search.mode == DPO_SEARCH_SEEDED) return fail(c, DPO_EINVAL, "the closed loop needs TABLE, SCAN_GOLDEN or TABLE_WALK");
+  if (n == 0) return DPO_OK;
+  if (!states) return fail(c, DPO_EINVAL, "states is NULL");
+  SweepArgs a = base_args(c);
+  a.V_in = V;
+  HIP_TRY(c, launch_simulate(a, states, (int)n, tau, steps, substeps, traj, thr_hist, ang_hist, S(stream)));
   return DPO_OK;
 }
 

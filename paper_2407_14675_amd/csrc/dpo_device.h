@@ -23,6 +23,8 @@ struct Grid {
   double h[4];
   double inv_h[4];
   int periodic3;  // axis 3 is periodic (the crown problem's theta): h3 = (hi - lo)/n, feet wrap
+  int clamp12;    // feet beyond the v_r / v_t faces are put on them (the crown problem's state
+                  // constraint holds on the two circular faces r = r_min, r_max only)
 };
 
 struct Phys {
@@ -167,6 +169,8 @@ __device__ inline bool foot_cell(const Grid& G, const int i[4], const float off[
       if (!periodic_cell(i[3], G.n[3], o, base[3], t[3])) return false;
       continue;
     }
+    if ((k == 1 || k == 2) && G.clamp12 && fabsf(o) <= 1.0e30f)
+      o = fminf(fmaxf(o, (float)(-i[k])), (float)(G.n[k] - 1 - i[k]));
     if (kSnap) {
       const float lo = (float)(-i[k]), hi = (float)(G.n[k] - 1 - i[k]);
       if (o < lo && o > lo - 1e-6f) o = lo;

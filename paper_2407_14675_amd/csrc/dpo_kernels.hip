@@ -425,7 +425,8 @@ __global__ void k_value_at(const float* __restrict__ V, Grid G, double M, double
       t[3] = w - (double)b;
       continue;
     }
-    const double s = to_grid(G, k, x[k]);
+    double s = to_grid(G, k, x[k]);
+    if ((k == 1 || k == 2) && G.clamp12 && fabs(s) <= 1e30) s = fmin(fmax(s, 0.0), (double)(G.n[k] - 1));
     if (!(s >= 0.0 && s <= (double)(G.n[k] - 1))) {
       *out = M;
       return;
@@ -453,19 +454,14 @@ __global__ void k_value_at(const float* __restrict__ V, Grid G, double M, double
   *out = acc3[0] + t[3] * (acc3[1] - acc3[0]);
 }
 
-// Feedback eq:feed at arbitrary states: the state is split into a grid node
-// and an in-cell offset, so the sweep's search runs unchanged on it.
-__global__ __launch_bounds__(kBlock) void k_feedback(SweepArgs a, const double* __restrict__ states,
-                                                     int n, double tau, float* __restrict__ ang_out,
-                                                     uint8_t* __restrict__ thr_out,
-                                                     float* __restrict__ q_out) {
-  const int c = blockIdx.x * kBlock + threadIdx.x;
-  if (c >= n) return;
+// Feedback eq:feed at an arbitrary state y: the state is split into a grid
+// node and an in-cell offset, so the sweep's search runs unchanged on it.
+__device__ inline void feedback_at(const SweepArgs& a, const double y_in[4], double tau, Choice& ch) {
   double y[4];
   NodeTerms T;
   float frac[4];
   for (int k = 0; k < 4; k++) {
-    y[k] = states[4 * c + k];
+    y[k] = y_in[k];
     double s = (y[k] - a.G.lo[k]) * a.G.inv_h[k];
     // periodic axis: wrap the state into [0, n) first
     if (k == 3 && a.G.periodic3 && fabs(s) <= 1e30) s -= (double)a.G.n[3] * floor(s / (double)a.G.n[3]);
@@ -492,13 +488,86 @@ __global__ __launch_bounds__(kBlock) void k_feedback(SweepArgs a, const double* 
   };
   const float qc = heun ? q_step<true, true>(b.V_in, b.G, b.P, T, H, 0, 0.0f, 1.0f, qx)
                         : q_step<false, true>(b.V_in, b.G, b.P, T, H, 0, 0.0f, 1.0f, qx);
-  Choice ch;
   // the walk's table (mode 3) is searched in full: a state has no previous optimum
   if (a.mode == 0 || a.mode == 3) table_search(qf, b, qc, ch);
   else full_search(qf, b, qc, ch);
+}
+
+__global__ __launch_bounds__(kBlock) void k_feedback(SweepArgs a, const double* __restrict__ states,
+                                                     int n, double tau, float* __restrict__ ang_out,
+                                                     uint8_t* __restrict__ thr_out,
+                                                     float* __restrict__ q_out) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= n) return;
+  double y[4];
+  for (int k = 0; k < 4; k++) y[k] = states[4 * c + k];
+  Choice ch;
+  feedback_at(a, y, tau, ch);
   ang_out[c] = ch.ang;
   thr_out[c] = (uint8_t)ch.thr;
   if (q_out) q_out[c] = ch.v;
+}
+
+// ---- closed loop: the model's own dynamics in FP64 (the real system of the
+// simulations of Section 4), integrated by the classical fourth-order
+// Runge-Kutta method with the control held over each step.
+__device__ inline void plant_rhs(const Phys& P, const double x[4], int thr, double sn, double cs, double b[4]) {
+#pragma clang fp contract(off)
+  if (P.model == 1) {
+    const double s = thr ? P.speed : 0.0;
+    b[0] = 0.0;
+    b[1] = s * sn;
+    b[2] = s * cs;
+    b[3] = 0.0;
+    return;
+  }
+  const double r = x[0], vr = x[1], vt = x[2];
+  const double acc = thr ? (P.model == 2 ? P.accel : P.accel / x[3]) : 0.0;
+  b[0] = vr;
+  b[1] = vt * vt / r - P.mu / (r * r) + acc * sn;
+  b[2] = -vr * vt / r + acc * cs;
+  b[3] = P.model == 2 ? vt / r : -P.mdot * (double)thr;
+}
+
+__device__ inline void rk4_step(const Phys& P, double x[4], int thr, double sn, double cs, double h) {
+#pragma clang fp contract(off)
+  double k1[4], k2[4], k3[4], k4[4], y[4];
+  plant_rhs(P, x, thr, sn, cs, k1);
+  for (int k = 0; k < 4; k++) y[k] = x[k] + 0.5 * h * k1[k];
+  plant_rhs(P, y, thr, sn, cs, k2);
+  for (int k = 0; k < 4; k++) y[k] = x[k] + 0.5 * h * k2[k];
+  plant_rhs(P, y, thr, sn, cs, k3);
+  for (int k = 0; k < 4; k++) y[k] = x[k] + h * k3[k];
+  plant_rhs(P, y, thr, sn, cs, k4);
+  for (int k = 0; k < 4; k++) x[k] += h / 6.0 * (k1[k] + 2.0 * k2[k] + 2.0 * k3[k] + k4[k]);
+}
+
+// One trajectory per thread: `steps` times the feedback at the current state
+// (time step tau), then `substeps` RK4 steps of tau/substeps with that
+// control.  Histories are step-major so that a step's writes are coalesced.
+__global__ __launch_bounds__(kBlock) void k_simulate(SweepArgs a, double* __restrict__ states, int n, double tau,
+                                                     int steps, int substeps, double* __restrict__ traj,
+                                                     uint8_t* __restrict__ thr_hist, float* __restrict__ ang_hist) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= n) return;
+  double y[4];
+  for (int k = 0; k < 4; k++) y[k] = states[4 * c + k];
+  if (traj)
+    for (int k = 0; k < 4; k++) traj[4 * (size_t)c + k] = y[k];
+  const double h = tau / (double)substeps;
+  for (int s = 0; s < steps; s++) {
+    Choice ch;
+    feedback_at(a, y, tau, ch);
+    double sn, cs;
+    sincos((double)ch.ang, &sn, &cs);
+    for (int q = 0; q < substeps; q++) rk4_step(a.P, y, ch.thr, sn, cs, h);
+    const size_t at = (size_t)s * (size_t)n + (size_t)c;
+    if (thr_hist) thr_hist[at] = (uint8_t)ch.thr;
+    if (ang_hist) ang_hist[at] = ch.ang;
+    if (traj)
+      for (int k = 0; k < 4; k++) traj[4 * (at + (size_t)n) + k] = y[k];
+  }
+  for (int k = 0; k < 4; k++) states[4 * c + k] = y[k];
 }
 
 // Reachability seed: FP64 Q1 value of the coarse V at every fine node.
@@ -741,6 +810,11 @@ hipError_t launch_value_at(const float* V, const Grid& G, double M, const double
 hipError_t launch_feedback(const SweepArgs& a, const double* states, int n, double tau, float* ang,
                            uint8_t* thr, float* q, hipStream_t s) {
   DPO_LAUNCH(k_feedback, blocks_for(n), kBlock, s, a, states, n, tau, ang, thr, q);
+}
+
+hipError_t launch_simulate(const SweepArgs& a, double* states, int n, double tau, int steps, int substeps,
+                           double* traj, uint8_t* thr_hist, float* ang_hist, hipStream_t s) {
+  DPO_LAUNCH(k_simulate, blocks_for(n), kBlock, s, a, states, n, tau, steps, substeps, traj, thr_hist, ang_hist);
 }
 
 hipError_t launch_mask_seed(const float* Vc, const Grid& Gc, double M, const Grid& Gf, double thresh,

@@ -140,8 +140,10 @@ def batch_problems(n_prob=16, seed=3, side_scale=1.0):
 # degrees and coast); rho in [6930, 7070] km, theta in [0, 2 pi), v_rho in
 # [-0.01, 0.01] km/s, v_theta in [7.526, 7.566] km/s on 110 x 30 x 30 x 30
 # nodes.  Axes here: (rho, v_rho, v_theta, theta), theta periodic (axis 3).
-# M, the value of a foot outside the crown, is 1e6: above the largest
-# running cost on the domain (~750) divided by the discount rate.
+# M, the value of a foot beyond the circular faces rho = 6930 and 7070 km
+# (the state constraint; feet beyond a velocity face are put on it), is 1e6:
+# above the largest running cost on the domain (~750) divided by the
+# discount rate.
 EX1_MU = 398600.4
 EX1_ACCEL = 5e-7
 EX1_ALPHA = 2.04e-8

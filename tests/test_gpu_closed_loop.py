@@ -1,0 +1,125 @@
+"""The closed loop on the device (feedback eq:feed, then the model's own
+dynamics by classical fourth-order Runge-Kutta in FP64) against the CPU
+oracle's closed loop.
+
+Trajectories are compared step by step up to the first step at which the
+device and the oracle choose different controls (a float32 search and an
+FP64 search may part at a near-tie; after that the two trajectories are both
+valid and drift apart).  Before it, the states agree to the float32
+rounding of the stored angle acting over the steps taken."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.core import Oracle
+from paper_2407_14675_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dpo():
+    from paper_2407_14675_amd import dpo as mod
+    mod.load()
+    return mod
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dtype).contiguous()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def test_eikonal_closed_loop_goes_straight_home(dpo):
+    p = inputs.eikonal_problem(17)
+    o = Oracle(p)
+    res = o.solve_vi(tol_abs=1e-13, max_sweeps=2000)
+    h = 2.0 / 16
+    ctx = dpo.Context(p)
+    starts = np.array([[0.0, 0.0, 6 * h, 0.0], [0.0, -5 * h, 0.0, 0.0], [0.0, 7 * h, 0.0, 0.0]])
+    final, traj, thr, ang = ctx.simulate(dev(res["V"]), starts, tau=h / p["speed"], steps=4)
+    traj = host(traj)
+    for c, x0 in enumerate(starts):
+        direction = -np.sign(x0) * (np.abs(x0) > 0)
+        for k in range(5):
+            # the stored float32 angle leaves ~4e-8 of the speed across the axis
+            np.testing.assert_allclose(traj[k, c], x0 + k * h * direction, atol=1e-6)
+    assert np.all(host(thr) == 1)
+    np.testing.assert_array_equal(host(final), traj[-1])
+
+
+def compare(o, ctx, V32, starts, tau, steps, name):
+    """Device and oracle loops from the same starts: identical states (to the
+    float32 angle's rounding) up to the first step with different controls,
+    and at that step the device's control is a near-tie at the shared state:
+    its oracle Q is within the one-evaluation tolerance of the oracle's
+    optimum."""
+    V64 = V32.astype(np.float64)
+    final, traj, thr, ang = ctx.simulate(dev(V32), starts, tau=tau, steps=steps)
+    ofinal, otraj, othr, oang = o.simulate(V64, starts, tau, steps)
+    traj, thr, ang = host(traj), host(thr), host(ang)
+    same = (thr == othr) & ((othr == 0) | (np.abs(ang - oang) < 1e-5))
+    n = starts.shape[0]
+    first = np.array([np.argmin(same[:, c]) if not same[:, c].all() else steps for c in range(n)])
+    scale = np.maximum(np.abs(otraj), 1.0)
+    worst = 0.0
+    vmax = float(np.abs(V32).max())
+    parted = 0
+    for c in range(n):
+        k = first[c]
+        d = np.abs(traj[:k + 1, c] - otraj[:k + 1, c]) / scale[:k + 1, c]
+        worst = max(worst, float(d.max()))
+        if k < steps:
+            parted += 1
+            y = otraj[k, c]
+            q_opt = o.q_state(V64, y, othr[k, c], float(oang[k, c]), tau)
+            q_dev = o.q_state(V64, y, thr[k, c], float(ang[k, c]), tau)
+            assert q_dev - q_opt <= 1e-5 * max(1.0, abs(q_opt)) + 1e-6 * vmax, (c, k, q_dev, q_opt)
+    _say(f"  {name}: {parted} of {n} loops part at a near-tie (median step {np.median(first)} of {steps}),"
+         f" worst state difference before that {worst:.2e}")
+    assert worst <= 1e-8
+    np.testing.assert_array_equal(host(final), traj[-1])
+
+
+def test_orbit_closed_loop_parity(dpo):
+    p = inputs.VI12
+    _say("orbit closed loop")
+    gold = np.load("tests/golden/vi12_table16.npz")
+    V32 = gold["V"].astype(np.float32)
+    o = Oracle(p)
+    ctx = dpo.Context(p)
+    starts = inputs.random_states(p, 64, seed=121, margin=0.1)
+    compare(o, ctx, V32, starts, p["dt"], 200, "12^4 orbit")
+
+
+def test_crown_closed_loop_parity(dpo):
+    p = inputs.crown_problem((8, 6, 6, 8))
+    _say("crown closed loop")
+    gold = np.load("tests/golden/crown8_table72.npz")
+    V32 = gold["V"].astype(np.float32)
+    o = Oracle(p)
+    ctx = dpo.Context(p)
+    starts = inputs.random_states(p, 64, seed=122, margin=0.1)
+    compare(o, ctx, V32, starts, p["dt"], 300, "crown 8x6x6x8")
+
+
+def test_simulate_arguments(dpo):
+    ctx = dpo.Context(inputs.VI12)
+    V = ctx.init_value()
+    with pytest.raises(dpo.DpoError):
+        ctx.simulate(V, np.zeros((2, 4)), tau=-1.0, steps=2)
+    with pytest.raises(dpo.DpoError):
+        ctx.simulate(V, np.zeros((2, 4)), tau=0.1, steps=2, substeps=0)
+    final, traj, thr, ang = ctx.simulate(V, np.zeros((0, 4)), tau=0.1, steps=3)
+    assert final.shape == (0, 4)
