@@ -122,6 +122,7 @@ def load(precision="f64"):
     lib.or_brute_thrust_min.restype = real
     lib.or_mask_from_coarse.argtypes = [P, vp, P, C.c_double, vp, vp]
     lib.or_rk4_step.argtypes = [P, vp, C.c_int, real, real]
+    lib.or_policy_system.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.or_q_state.argtypes = [P, vp, vp, C.c_int, real, real]
     lib.or_q_state.restype = real
     lib.or_simulate.argtypes = [P, S, vp, vp, i64, C.c_double, C.c_int32, C.c_int32, vp, vp, vp]
@@ -330,6 +331,33 @@ class Oracle:
         y = np.ascontiguousarray(np.asarray(y, dtype=self.dtype))
         tau = self.problem["dt"] if tau is None else tau
         return float(self.lib.or_q_state(C.byref(self.ps), _ptr(Vin), _ptr(y), int(thr), u, tau))
+
+    def policy_evaluate_exact(self, V, ang, thr):
+        """Exact policy evaluation (eq:p_eval as a linear system, Section 3):
+        the sparse system assembled from the Q1 weights and solved by a
+        direct sparse factorisation; fixed nodes keep V's values."""
+        import scipy.sparse as sp
+        import scipy.sparse.linalg as spl
+        Vf = self._arr(V)
+        a = self._arr(ang)
+        t = np.ascontiguousarray(np.asarray(thr, dtype=np.uint8).reshape(self.shape))
+        free = (self.kind.reshape(-1) == KIND_FREE)
+        nf = int(free.sum())
+        unknown = np.full(self.N, -1, dtype=np.int64)
+        unknown[free] = np.arange(nf)
+        rows = np.zeros(17 * max(nf, 1), dtype=np.int64)
+        cols = np.zeros_like(rows)
+        vals = np.zeros(17 * max(nf, 1))
+        rhs = np.zeros(max(nf, 1))
+        nnz = np.zeros(1, dtype=np.int64)
+        self.lib.or_policy_system(C.byref(self.ps), _ptr(self.kind), _ptr(Vf), _ptr(a), _ptr(t), _ptr(unknown),
+                                  _ptr(rows), _ptr(cols), _ptr(vals), _ptr(rhs), _ptr(nnz))
+        k = int(nnz[0])
+        A = sp.csr_matrix((vals[:k], (rows[:k], cols[:k])), shape=(nf, nf))
+        v = spl.spsolve(A.tocsc(), rhs[:nf])
+        out = np.array(Vf, dtype=np.float64).reshape(-1)
+        out[free] = v
+        return out.reshape(self.shape)
 
     def rk4_step(self, x, thr, u, h):
         x = np.ascontiguousarray(np.asarray(x, dtype=self.dtype)).copy()

@@ -757,6 +757,56 @@ void or_policy_eval_sweep(const or_problem *p, const uint8_t *kind, const real *
   }
 }
 
+/* The linear system of eq:p_eval for the frozen policy (pol_ang, pol_thr),
+ * written out as the paper describes (Section 3): at every free node j,
+ *   v_j - exp(-lambda dt) sum_i w_ji v_i = dt l(x_j, f_j)
+ *            + exp(-lambda dt) (sum over fixed corners of w_ji V_i, or M
+ *              when the foot leaves the domain),
+ * with w_ji the Q1 weights of the foot's 16 corners.  Free unknowns are
+ * numbered by node order (unknown[j], -1 at fixed nodes, caller-provided).
+ * Triplets (row, col, val) of the matrix I - exp(-lambda dt) P_ff are
+ * written to rows/cols/vals (at most 17 per free node; *nnz receives the
+ * count) and the right-hand side to rhs (one per free node). */
+void or_policy_system(const or_problem *p, const uint8_t *kind, const real *Vfixed, const real *pol_ang,
+                      const uint8_t *pol_thr, const int64_t *unknown, int64_t *rows, int64_t *cols, double *vals,
+                      double *rhs, int64_t *nnz) {
+  const int64_t N = n_total(p);
+  const double g = (double)discount(p, (real)p->dt);
+  int64_t k = 0;
+  for (int64_t j = 0; j < N; j++) {
+    if (kind[j] != KIND_FREE) continue;
+    const int64_t row = unknown[j];
+    int i[4];
+    node_index(p, j, i);
+    real s[4], x[4];
+    foot_grid(p, i, pol_thr[j], pol_ang[j], (real)p->dt, s);
+    node_coords(p, i, x);
+    double b = (double)p->dt * (double)or_running_cost(p, x, pol_thr[j]);
+    rows[k] = row;
+    cols[k] = row;
+    vals[k] = 1.0;
+    k++;
+    int64_t idx[16];
+    real w[16];
+    if (!or_interp_weights(p, s, idx, w)) {
+      b += g * p->M;
+    } else {
+      for (int c = 0; c < 16; c++) {
+        if (kind[idx[c]] == KIND_FREE) {
+          rows[k] = row;
+          cols[k] = unknown[idx[c]];
+          vals[k] = -g * (double)w[c];
+          k++;
+        } else {
+          b += g * (double)w[c] * (double)Vfixed[idx[c]];
+        }
+      }
+    }
+    rhs[row] = b;
+  }
+  *nnz = k;
+}
+
 /* ------------------------------------------------------------- solvers */
 /* Value iteration: V <- T V until max_j |dV_j| < tol_abs (FP64 rule) or, if
  * tol_abs <= 0, until the relative residual is below tol_rel.
