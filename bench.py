@@ -320,9 +320,10 @@ def bench_example1():
     """The paper's Example 1 at its own size (crown grid 110 x 30 x 30 x 30,
     73 controls, Heun foot, dt = 10 s, discount 1e-3): policy iteration
     (20 evaluation sweeps per step) with the full table at every greedy step
-    and with the walk from the previous optimum, and value iteration, each
-    from V0 = M to a relative residual of 1e-6; the read-out at the start of
-    the paper's orbit raise (circular orbit at 6978 km, theta = 0)."""
+    and with the walk from the previous optimum, policy iteration with the
+    evaluation solved exactly by GMRES, and value iteration, each from V0 = M
+    to a relative residual of 1e-6; the read-out at the start of the paper's
+    orbit raise (circular orbit at 6978 km, theta = 0)."""
     import math
 
     import torch
@@ -342,6 +343,8 @@ def bench_example1():
         t = time.perf_counter()
         if solver == "pi":
             rc, st = ctx.solve_pi(V, ang, thr, tol_rel=1e-6, eval_sweeps=inputs.EVAL_SWEEPS, max_outer=5000)
+        elif solver == "pi_exact":
+            rc, st = ctx.solve_pi(V, ang, thr, tol_rel=1e-6, eval_sweeps=-1, max_outer=500)
         else:
             rc, st = ctx.solve_vi(V, ang, thr, tol_rel=1e-6, max_sweeps=200000, check_every=16)
         torch.cuda.synchronize()
@@ -359,6 +362,9 @@ def bench_example1():
     out["pi_walk"]["max_rel_diff_vs_table"] = float(d.max())
     out["pi_walk"]["frac_within_1e-4"] = float((d <= 1e-4).float().mean())
     log(f"bench: example 1 PI walk {out['pi_walk']}")
+    Ve, out["pi_exact_gmres"] = run(p, "pi_exact")
+    out["pi_exact_gmres"]["max_rel_diff_vs_modified_pi"] = float(((Ve - Vt).abs() / Vt.abs().clamp(min=1.0)).max())
+    log(f"bench: example 1 PI exact {out['pi_exact_gmres']}")
     Vv, out["vi"] = run(p, "vi")
     out["vi"]["max_rel_diff_vs_pi"] = float(((Vv - Vt).abs() / Vt.abs().clamp(min=1.0)).max())
     out["vi_over_pi_time"] = out["vi"]["seconds"] / out["pi_table"]["seconds"]

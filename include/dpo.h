@@ -284,8 +284,32 @@ int dpo_solve_vi(dpo_ctx* ctx, float* V, float* pol_angle, uint8_t* pol_thr, dou
  * paper Section 3, "Efficient computation of the minimum".
  * TABLE_WALK: the first greedy step searches the full table, later ones walk
  * from the current policy's angles (the incumbent rule applies as above).
+ * eval_sweeps < 0: the policy iteration of Section 3 with eq:p_eval solved
+ * exactly: after every greedy step that does not stop the solve, the new
+ * policy is evaluated by dpo_policy_evaluate to a node-wise relative
+ * residual of 5e-7 (at most 300 operator applications), starting from the
+ * greedy values;
+ * stats->eval_sweeps counts the operator applications.  Needs lambda > 0
+ * and the TABLE or SCAN_GOLDEN search; no seed_angle.
  * Returns DPO_ENOCONV after max_outer greedy steps, or when 32 full-search
  * greedy steps in a row bring no new lowest residual (stats->stalled). */
+/* Exact policy evaluation (eq:p_eval solved as the sparse linear system
+ * (I - exp(-lambda dt) P) v = b of Section 3, by restarted GMRES(32), the
+ * solver the paper names): V (device, N) holds the fixed nodes' values and,
+ * at free nodes, the initial guess on entry and the solution on exit; the
+ * frozen policy is pol_angle / pol_thr.  The operator is applied matrix-free
+ * by the frozen-policy sweep without its affine part; vectors are float32,
+ * dot products FP64 in a fixed order.  Stops when the node-wise relative
+ * residual max_j |b - A v|_j / max(1, |v_j|) <= tol_rel (checked between
+ * restart cycles; a cycle ends after 32 steps or once its 2-norm residual
+ * has fallen 100-fold) or after max_iter operator applications
+ * (DPO_ENOCONV, V holds the last iterate).  *matvecs and
+ * *resid_rel (host, nullable): operator applications and the final
+ * relative residual.  Needs lambda > 0 (undiscounted, a policy whose chains
+ * never leave the free set makes the system singular).  Synchronises. */
+int dpo_policy_evaluate(dpo_ctx* ctx, float* V, const float* pol_angle, const uint8_t* pol_thr, double tol_rel,
+                        int32_t max_iter, int64_t* matvecs, double* resid_rel, void* stream);
+
 int dpo_solve_pi(dpo_ctx* ctx, float* V, float* pol_angle, uint8_t* pol_thr, double tol_rel,
                  int32_t eval_sweeps, int64_t max_outer, const float* seed_angle,
                  dpo_stats* stats, void* stream);

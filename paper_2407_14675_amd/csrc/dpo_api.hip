@@ -18,6 +18,7 @@
 #include "../../include/dpo.h"
 #include "dpo_kernels.h"
 #include "dpo_mlp.h"
+#include "dpo_krylov.h"
 
 using namespace dpo;
 
@@ -58,6 +59,12 @@ struct dpo_ctx {
   float2* desc_w = nullptr;
   bool desc_valid = false;    // a sweep has written them
   float* qnode = nullptr;                  // crown problem: dt * running cost per node
+  float* kry = nullptr;      // exact policy evaluation: Krylov basis, (kry_m + 1) x N
+  float* kbuf = nullptr;     // its b, x, y vectors (3 x N)
+  double* kpart = nullptr;   // dot-product partials
+  double* kdots = nullptr;   // dot products (kMaxBasis)
+  double* kcoef = nullptr;   // update coefficients (kMaxBasis)
+  int kry_m = 0;
   unsigned long long* eval_acc = nullptr;  // table walk: per-workgroup thrust-evaluation counts
   unsigned long long* eval_sum = nullptr;
   std::string err;
@@ -494,6 +501,145 @@ int sweep_eval_desc(dpo_ctx* c, const float* Vin, float* Vout, hipStream_t s) {
   return DPO_OK;
 }
 
+// ---- exact policy evaluation: restarted GMRES(m) on (I - gamma P) v = b
+// over the free nodes (paper Section 3: eq:p_eval is a sparse linear system;
+// GMRES is the solver the paper names).  b is the frozen-policy sweep of V
+// with its free entries zeroed (running cost plus the fixed corners and M);
+// the operator is the sweep without that affine part.  Classical
+// Gram-Schmidt with one reorthogonalisation; Hessenberg and Givens rotations
+// on the host in FP64.  Stop measure: the node-wise relative residual
+// max_j |b - A v|_j / max(1, |v_j|), checked between cycles; a cycle ends
+// after m steps or once its 2-norm residual has fallen by kCycleDrop.
+
+constexpr int kGmresRestart = 32;
+constexpr double kCycleDrop = 1e-2;
+constexpr double kExactEvalTol = 5e-7;  // node-wise residual of the evaluations inside policy iteration
+
+int ensure_krylov(dpo_ctx* c, int m) {
+  const size_t N = (size_t)c->N;
+  if (c->kry && c->kry_m >= m) return DPO_OK;
+  if (c->kry) hipFree(c->kry);
+  c->kry = nullptr;
+  if (hipMalloc(&c->kry, sizeof(float) * N * (size_t)(m + 1)) != hipSuccess) return fail(c, DPO_ENOMEM, "Krylov basis alloc");
+  c->kry_m = m;
+  if (!c->kbuf && hipMalloc(&c->kbuf, sizeof(float) * N * 3) != hipSuccess) return fail(c, DPO_ENOMEM, "Krylov vectors alloc");
+  if (!c->kpart && hipMalloc(&c->kpart, sizeof(double) * kStreamBlocks * kDotGroup) != hipSuccess)
+    return fail(c, DPO_ENOMEM, "Krylov partials alloc");
+  if (!c->kdots && hipMalloc(&c->kdots, sizeof(double) * kMaxBasis) != hipSuccess) return fail(c, DPO_ENOMEM, "alloc");
+  if (!c->kcoef && hipMalloc(&c->kcoef, sizeof(double) * kMaxBasis) != hipSuccess) return fail(c, DPO_ENOMEM, "alloc");
+  return DPO_OK;
+}
+
+// h[0..k) = <basis_i, w> on the host (synchronises s)
+int host_dots(dpo_ctx* c, const float* basis, int k, const float* w, double* h, hipStream_t s) {
+  HIP_TRY(c, launch_dots(basis, k, (size_t)c->N, w, (int)c->N, c->kpart, c->kdots, s));
+  HIP_TRY(c, hipMemcpyAsync(h, c->kdots, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  return DPO_OK;
+}
+
+int gmres_eval(dpo_ctx* c, float* V, const float* ang, const uint8_t* thr, double tol, int max_iter, int64_t* matvecs,
+               double* rel_out, hipStream_t s) {
+  const int m = kGmresRestart;
+  int rc = ensure_krylov(c, m);
+  if (rc != DPO_OK) return rc;
+  const int N = (int)c->N;
+  const size_t ld = (size_t)N;
+  float* B = c->kbuf;
+  float* X = c->kbuf + ld;
+  float* Y = c->kbuf + 2 * ld;
+  float* basis = c->kry;
+  SweepArgs a = base_args(c);
+  a.pol_ang_in = ang;
+  a.pol_thr_in = thr;
+  int64_t mv = 0;
+  // b: the sweep of V with its free entries zeroed (Y as scratch)
+  HIP_TRY(c, hipMemcpyAsync(Y, V, sizeof(float) * ld, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(c, launch_free_zero(a, Y, s));
+  HIP_TRY(c, hipMemsetAsync(B, 0, sizeof(float) * ld, s));
+  {
+    SweepArgs e = a;
+    e.V_in = Y;
+    e.V_out = B;
+    e.partial = nullptr;
+    if (a.n_free > 0) HIP_TRY(c, launch_policy_eval(e, false, s));
+  }
+  // x: the current V at free nodes, zero elsewhere
+  HIP_TRY(c, hipMemsetAsync(X, 0, sizeof(float) * ld, s));
+  HIP_TRY(c, launch_free_copy(a, V, X, s));
+  std::vector<double> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), y(m), h1(m + 1), h2(m + 1);
+  double rel = 0;
+  int it = 0;
+  while (true) {
+    // r = b - A x into basis row 0
+    HIP_TRY(c, launch_eval_hom(a, X, Y, s));
+    mv++;
+    HIP_TRY(c, launch_residual(B, X, Y, basis, N, s));
+    HIP_TRY(c, launch_relmax(basis, X, N, c->kpart, c->kdots, s));
+    HIP_TRY(c, hipMemcpyAsync(&rel, c->kdots, sizeof(double), hipMemcpyDeviceToHost, s));
+    double rr = 0;
+    if ((rc = host_dots(c, basis, 1, basis, &rr, s)) != DPO_OK) return rc;
+    const double beta = std::sqrt(rr);
+    if (!(rel > tol) || !(beta > 0) || it >= max_iter) break;
+    HIP_TRY(c, launch_scale(basis, 1.0 / beta, basis, N, s));
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    while (k < m && it < max_iter) {
+      float* vk = basis + (size_t)k * ld;
+      float* w = basis + (size_t)(k + 1) * ld;
+      HIP_TRY(c, launch_eval_hom(a, vk, Y, s));
+      mv++;
+      it++;
+      HIP_TRY(c, launch_sub(vk, Y, w, N, s));
+      // two classical Gram-Schmidt passes against v_0..v_k
+      if ((rc = host_dots(c, basis, k + 1, w, h1.data(), s)) != DPO_OK) return rc;
+      HIP_TRY(c, hipMemcpyAsync(c->kcoef, h1.data(), sizeof(double) * (k + 1), hipMemcpyHostToDevice, s));
+      HIP_TRY(c, launch_axpys(w, basis, k + 1, ld, c->kcoef, N, s));
+      if ((rc = host_dots(c, basis, k + 1, w, h2.data(), s)) != DPO_OK) return rc;
+      HIP_TRY(c, hipMemcpyAsync(c->kcoef, h2.data(), sizeof(double) * (k + 1), hipMemcpyHostToDevice, s));
+      HIP_TRY(c, launch_axpys(w, basis, k + 1, ld, c->kcoef, N, s));
+      double ww = 0;
+      if ((rc = host_dots(c, w, 1, w, &ww, s)) != DPO_OK) return rc;
+      const double hn = std::sqrt(ww);
+      for (int i = 0; i <= k; i++) H[(size_t)i * m + k] = h1[i] + h2[i];
+      H[(size_t)(k + 1) * m + k] = hn;
+      // previous rotations, then a new one that zeroes H[k+1][k]
+      for (int i = 0; i < k; i++) {
+        const double t0 = H[(size_t)i * m + k], t1 = H[(size_t)(i + 1) * m + k];
+        H[(size_t)i * m + k] = cs[i] * t0 + sn[i] * t1;
+        H[(size_t)(i + 1) * m + k] = -sn[i] * t0 + cs[i] * t1;
+      }
+      const double d0 = H[(size_t)k * m + k], d1 = H[(size_t)(k + 1) * m + k];
+      const double den = std::hypot(d0, d1);
+      cs[k] = den > 0 ? d0 / den : 1.0;
+      sn[k] = den > 0 ? d1 / den : 0.0;
+      H[(size_t)k * m + k] = den;
+      H[(size_t)(k + 1) * m + k] = 0.0;
+      g[k + 1] = -sn[k] * g[k];
+      g[k] = cs[k] * g[k];
+      k++;
+      if (hn > 0) HIP_TRY(c, launch_scale(w, 1.0 / hn, w, N, s));
+      if (!(std::fabs(g[k]) > kCycleDrop * beta) || !(hn > 0)) break;
+    }
+    // x += V_k y with H y = g (upper triangular k x k)
+    for (int i = k - 1; i >= 0; i--) {
+      double t = g[i];
+      for (int q = i + 1; q < k; q++) t -= H[(size_t)i * m + q] * y[q];
+      y[i] = H[(size_t)i * m + i] != 0 ? t / H[(size_t)i * m + i] : 0.0;
+    }
+    for (int i = 0; i < k; i++) y[i] = -y[i];
+    HIP_TRY(c, hipMemcpyAsync(c->kcoef, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+    HIP_TRY(c, launch_axpys(X, basis, k, ld, c->kcoef, N, s));
+  }
+  HIP_TRY(c, launch_free_copy(a, X, V, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  if (matvecs) *matvecs = mv;
+  if (rel_out) *rel_out = rel;
+  return DPO_OK;
+}
+
 double now_s() {
   using namespace std::chrono;
   return duration<double>(steady_clock::now().time_since_epoch()).count();
@@ -653,6 +799,11 @@ void dpo_destroy(dpo_ctx* c) {
   if (c->desc_w) hipFree(c->desc_w);
   if (c->eval_acc) hipFree(c->eval_acc);
   if (c->qnode) hipFree(c->qnode);
+  if (c->kry) hipFree(c->kry);
+  if (c->kbuf) hipFree(c->kbuf);
+  if (c->kpart) hipFree(c->kpart);
+  if (c->kdots) hipFree(c->kdots);
+  if (c->kcoef) hipFree(c->kcoef);
   if (c->eval_sum) hipFree(c->eval_sum);
   delete c;
 }
@@ -837,11 +988,100 @@ int dpo_solve_vi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, doubl
   return code;
 }
 
+int dpo_policy_evaluate(dpo_ctx* c, float* V, const float* pol_angle, const uint8_t* pol_thr, double tol_rel,
+                        int32_t max_iter, int64_t* matvecs, double* resid_rel, void* stream) {
+  if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
+  if (!V || !pol_angle || !pol_thr) return fail(c, DPO_EINVAL, "null array argument");
+  if (!(c->prob.lambda > 0)) return fail(c, DPO_EINVAL, "exact policy evaluation needs lambda > 0");
+  if (!(tol_rel > 0) || max_iter < 1) return fail(c, DPO_EINVAL, "tol_rel > 0 and max_iter >= 1");
+  double rel = 0;
+  int rc = gmres_eval(c, V, pol_angle, pol_thr, tol_rel, max_iter, matvecs, &rel, S(stream));
+  if (rc != DPO_OK) return rc;
+  if (resid_rel) *resid_rel = rel;
+  if (!(rel <= tol_rel)) return fail(c, DPO_ENOCONV, "GMRES did not reach tol_rel within max_iter");
+  return DPO_OK;
+}
+
+namespace {
+
+// Policy iteration with the evaluation solved exactly (eq:p_eval by GMRES):
+// greedy step, stop if its residual is below tol_rel, else evaluate the new
+// policy to a node-wise relative residual of kExactEvalTol (at most 300
+// operator applications) starting from the greedy values.  float32 floors
+// that residual at ~3e-7 where values next to the exit faces carry M.
+int solve_pi_exact(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, double tol_rel, int64_t max_outer,
+                   dpo_stats* st, hipStream_t s) {
+  int rc = ensure_work(c);
+  if (rc != DPO_OK) return rc;
+  dpo_stats local;
+  std::memset(&local, 0, sizeof(local));
+  const double t0 = now_s();
+  HIP_TRY(c, hipMemcpyAsync(c->work, V, sizeof(float) * (size_t)c->N, hipMemcpyDeviceToDevice, s));
+  float* cur = V;
+  float* nxt = c->work;
+  double h[kPartial] = {0, 0, 0, 0, 0};
+  int code = DPO_ENOCONV;
+  int64_t it = 0, evals = 0, mv_total = 0;
+  double full_best = INFINITY;
+  int full_stall = 0;
+  while (it < max_outer) {
+    if ((rc = sweep_full(c, cur, nxt, pol_angle, pol_thr, s, false, it > 0)) != DPO_OK) return rc;
+    it++;
+    if ((rc = finish_resid(c, c->resid, s)) != DPO_OK) return rc;
+    if ((rc = read_resid(c, h, s)) != DPO_OK) return rc;
+    evals += c->n_free * evals_per_full_search(c);
+    std::swap(cur, nxt);
+    if (h[3] > 0) {
+      code = DPO_ENUMERIC;
+      fail(c, DPO_ENUMERIC, "policy iteration produced non-finite values");
+      break;
+    }
+    if (h[0] < tol_rel) {
+      code = DPO_OK;
+      local.converged = 1;
+      break;
+    }
+    if (h[0] < full_best) {
+      full_best = h[0];
+      full_stall = 0;
+    } else if (++full_stall >= 32) {
+      local.stalled = 1;
+      break;
+    }
+    int64_t mv = 0;
+    double rel = 0;
+    if ((rc = gmres_eval(c, cur, pol_angle, pol_thr, kExactEvalTol, 300, &mv, &rel, s)) != DPO_OK) return rc;
+    mv_total += mv;
+    evals += mv * c->n_free;
+  }
+  if (cur != V) HIP_TRY(c, hipMemcpyAsync(V, cur, sizeof(float) * (size_t)c->N, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  local.sweeps = it;
+  local.eval_sweeps = mv_total;
+  local.evals = evals;
+  local.resid_max_rel = h[0];
+  local.resid_sum_abs = h[1];
+  local.resid_max_abs = h[2];
+  local.seconds = now_s() - t0;
+  if (st) *st = local;
+  if (code == DPO_ENOCONV) fail(c, DPO_ENOCONV, local.stalled ? "policy iteration stalled" : "max_outer reached");
+  return code;
+}
+
+}  // namespace
+
 int dpo_solve_pi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, double tol_rel, int32_t eval_sweeps,
                  int64_t max_outer, const float* seed_angle, dpo_stats* st, void* stream) {
   if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
   if (!V || !pol_angle || !pol_thr) return fail(c, DPO_EINVAL, "null array argument");
-  if (max_outer < 1 || eval_sweeps < 0 || !(tol_rel >= 0)) return fail(c, DPO_EINVAL, "bad max_outer / eval_sweeps / tol");
+  if (max_outer < 1 || !(tol_rel >= 0)) return fail(c, DPO_EINVAL, "bad max_outer / tol");
+  if (eval_sweeps < 0) {
+    if (seed_angle) return fail(c, DPO_EINVAL, "exact evaluation (eval_sweeps < 0) takes no seed_angle");
+    if (c->search.mode == DPO_SEARCH_SEEDED || c->search.mode == DPO_SEARCH_TABLE_WALK)
+      return fail(c, DPO_EINVAL, "exact evaluation needs the TABLE or SCAN_GOLDEN search");
+    if (!(c->prob.lambda > 0)) return fail(c, DPO_EINVAL, "exact policy evaluation needs lambda > 0");
+    return solve_pi_exact(c, V, pol_angle, pol_thr, tol_rel, max_outer, st, S(stream));
+  }
   const bool seeded = seed_angle != nullptr;
   if (seeded && c->search.mode != DPO_SEARCH_SEEDED) return fail(c, DPO_EINVAL, "seed_angle given but search mode is not SEEDED");
   if (!seeded && c->search.mode == DPO_SEARCH_SEEDED) return fail(c, DPO_EINVAL, "SEEDED mode needs seed_angle");

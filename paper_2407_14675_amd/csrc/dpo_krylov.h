@@ -1,0 +1,35 @@
+// Internal interface of the exact policy evaluation kernels (GMRES on
+// eq:p_eval, paper Section 3).
+#pragma once
+
+#include <algorithm>
+
+#include "dpo_kernels.h"
+
+namespace dpo {
+
+constexpr int kDotGroup = 8;        // basis vectors per pass of the dot-product kernel
+constexpr int kMaxBasis = 64;       // largest Krylov basis (restart length + 1)
+constexpr int kStreamBlocks = 1024; // workgroups of the vector kernels (grid-stride loops)
+
+// y = exp(-lambda dt) P x at free nodes (frozen policy a.pol_ang_in / a.pol_thr_in)
+hipError_t launch_eval_hom(const SweepArgs& a, const float* x, float* y, hipStream_t s);
+// r = b - x + y
+hipError_t launch_residual(const float* b, const float* x, const float* y, float* r, int N, hipStream_t s);
+// w = v - y
+hipError_t launch_sub(const float* v, const float* y, float* w, int N, hipStream_t s);
+// out[i] = <basis_i, w> in FP64 for i < k (partial: kStreamBlocks * kDotGroup doubles)
+hipError_t launch_dots(const float* basis, int k, size_t ld, const float* w, int N, double* partial, double* out,
+                       hipStream_t s);
+// out[0] = max_j |r_j| / max(1, |x_j|) (partial: kStreamBlocks doubles)
+hipError_t launch_relmax(const float* r, const float* x, int N, double* partial, double* out, hipStream_t s);
+// w -= sum_i coef[i] basis_i, i < k <= kMaxBasis
+hipError_t launch_axpys(float* w, const float* basis, int k, size_t ld, const double* coef, int N, hipStream_t s);
+// dst = s * src
+hipError_t launch_scale(const float* src, double s, float* dst, int N, hipStream_t st);
+// dst[j] = src[j] at the free nodes j
+hipError_t launch_free_copy(const SweepArgs& a, const float* src, float* dst, hipStream_t s);
+// dst[j] = 0 at the free nodes j
+hipError_t launch_free_zero(const SweepArgs& a, float* dst, hipStream_t s);
+
+}  // namespace dpo

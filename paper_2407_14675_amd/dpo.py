@@ -93,6 +93,7 @@ def load():
         "dpo_policy_eval_sweep_last": [vp, vp, vp, vp],
         "dpo_solve_vi": [vp, vp, vp, vp, dbl, i64, i32, C.POINTER(Stats), vp],
         "dpo_solve_pi": [vp, vp, vp, vp, dbl, i32, i64, vp, C.POINTER(Stats), vp],
+        "dpo_policy_evaluate": [vp, vp, vp, vp, dbl, i32, C.POINTER(i64), C.POINTER(dbl), vp],
         "dpo_value_at": [vp, vp, vp, vp, vp],
         "dpo_extract_feedback": [vp, vp, vp, i64, dbl, vp, vp, vp, vp],
         "dpo_simulate": [vp, vp, vp, i64, dbl, i32, i32, vp, vp, vp, vp],
@@ -297,6 +298,16 @@ class Context:
                                    int(max_outer), _p(seed), C.byref(st), _stream())
         self._check(rc, allow=(DPO_OK, DPO_ENOCONV))
         return rc, st.as_dict()
+
+    def policy_evaluate(self, V, pol_ang, pol_thr, tol_rel=1e-7, max_iter=500):
+        """Exact policy evaluation by GMRES (V in/out); returns (rc, operator
+        applications, final relative residual)."""
+        mv = C.c_int64()
+        rel = C.c_double()
+        rc = self.lib.dpo_policy_evaluate(self.h, _p(V), _p(pol_ang), _p(pol_thr), float(tol_rel), int(max_iter),
+                                          C.byref(mv), C.byref(rel), _stream())
+        self._check(rc, allow=(DPO_OK, DPO_ENOCONV))
+        return rc, mv.value, rel.value
 
     # ------------------------------------------------- read-out / feedback
     def value_at(self, V, x):
