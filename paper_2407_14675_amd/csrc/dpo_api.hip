@@ -507,7 +507,9 @@ int sweep_eval_desc(dpo_ctx* c, const float* Vin, float* Vout, hipStream_t s) {
 // with its free entries zeroed (running cost plus the fixed corners and M);
 // the operator is the sweep without that affine part.  Classical
 // Gram-Schmidt with one reorthogonalisation; Hessenberg and Givens rotations
-// on the host in FP64.  Stop measure: the node-wise relative residual
+// on the host in FP64; the second pass only where the first lost more than a
+// factor 1/sqrt(2) of the vector's norm (the criterion of Daniel, Gragg,
+// Kaufman and Stewart).  Stop measure: the node-wise relative residual
 // max_j |b - A v|_j / max(1, |v_j|), checked between cycles; a cycle ends
 // after m steps or once its 2-norm residual has fallen by kCycleDrop.
 
@@ -567,7 +569,7 @@ int gmres_eval(dpo_ctx* c, float* V, const float* ang, const uint8_t* thr, doubl
   // x: the current V at free nodes, zero elsewhere
   HIP_TRY(c, hipMemsetAsync(X, 0, sizeof(float) * ld, s));
   HIP_TRY(c, launch_free_copy(a, V, X, s));
-  std::vector<double> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), y(m), h1(m + 1), h2(m + 1);
+  std::vector<double> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), y(m), h1(m + 2), h2(m + 1);
   double rel = 0;
   int it = 0;
   while (true) {
@@ -593,15 +595,21 @@ int gmres_eval(dpo_ctx* c, float* V, const float* ang, const uint8_t* thr, doubl
       mv++;
       it++;
       HIP_TRY(c, launch_sub(vk, Y, w, N, s));
-      // two classical Gram-Schmidt passes against v_0..v_k
-      if ((rc = host_dots(c, basis, k + 1, w, h1.data(), s)) != DPO_OK) return rc;
+      // classical Gram-Schmidt against v_0..v_k; w is basis row k+1, so the
+      // same pass also gives |w|^2 (h1[k+1])
+      if ((rc = host_dots(c, basis, k + 2, w, h1.data(), s)) != DPO_OK) return rc;
+      const double before = std::sqrt(std::max(h1[k + 1], 0.0));
       HIP_TRY(c, hipMemcpyAsync(c->kcoef, h1.data(), sizeof(double) * (k + 1), hipMemcpyHostToDevice, s));
-      HIP_TRY(c, launch_axpys(w, basis, k + 1, ld, c->kcoef, N, s));
-      if ((rc = host_dots(c, basis, k + 1, w, h2.data(), s)) != DPO_OK) return rc;
-      HIP_TRY(c, hipMemcpyAsync(c->kcoef, h2.data(), sizeof(double) * (k + 1), hipMemcpyHostToDevice, s));
       HIP_TRY(c, launch_axpys(w, basis, k + 1, ld, c->kcoef, N, s));
       double ww = 0;
       if ((rc = host_dots(c, w, 1, w, &ww, s)) != DPO_OK) return rc;
+      std::fill(h2.begin(), h2.end(), 0.0);
+      if (std::sqrt(ww) < 0.7071067811865476 * before) {
+        if ((rc = host_dots(c, basis, k + 1, w, h2.data(), s)) != DPO_OK) return rc;
+        HIP_TRY(c, hipMemcpyAsync(c->kcoef, h2.data(), sizeof(double) * (k + 1), hipMemcpyHostToDevice, s));
+        HIP_TRY(c, launch_axpys(w, basis, k + 1, ld, c->kcoef, N, s));
+        if ((rc = host_dots(c, w, 1, w, &ww, s)) != DPO_OK) return rc;
+      }
       const double hn = std::sqrt(ww);
       for (int i = 0; i <= k; i++) H[(size_t)i * m + k] = h1[i] + h2[i];
       H[(size_t)(k + 1) * m + k] = hn;

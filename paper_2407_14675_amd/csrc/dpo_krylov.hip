@@ -113,22 +113,21 @@ __global__ void k_relmax_final(const double* __restrict__ partial, int nblocks, 
   out[0] = s;
 }
 
-// out[i] = sum over blocks of partial[b * kDotGroup + i], fixed order.
-__global__ __launch_bounds__(kBlock) void k_dots_final(const double* __restrict__ partial, int nblocks, int k,
+// out[i] = sum over blocks of partial[b * kDotGroup + i], fixed order; one
+// workgroup per output.
+__global__ __launch_bounds__(kBlock) void k_dots_final(const double* __restrict__ partial, int nblocks,
                                                        double* __restrict__ out) {
   __shared__ double red[kBlock];
-  for (int i = 0; i < k; i++) {
-    double s = 0.0;
-    for (int q = threadIdx.x; q < nblocks; q += kBlock) s += partial[(size_t)q * kDotGroup + i];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) out[i] = red[0];
+  const int i = blockIdx.x;
+  double s = 0.0;
+  for (int q = threadIdx.x; q < nblocks; q += kBlock) s += partial[(size_t)q * kDotGroup + i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
+  if (threadIdx.x == 0) out[i] = red[0];
 }
 
 // w -= sum_i coef[i] * basis_i  (k <= kMaxBasis terms, FP64 sum per element)
@@ -198,7 +197,7 @@ hipError_t launch_dots(const float* basis, int k, size_t ld, const float* w, int
     hipLaunchKernelGGL(k_dots, dim3(kStreamBlocks), dim3(kBlock), 0, s, basis + (size_t)g * ld, kg, ld, w, N, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(kBlock), 0, s, partial, kStreamBlocks, kg, out + g);
+    hipLaunchKernelGGL(k_dots_final, dim3(kg), dim3(kBlock), 0, s, partial, kStreamBlocks, out + g);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
