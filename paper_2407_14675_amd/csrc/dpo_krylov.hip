@@ -106,11 +106,21 @@ __global__ __launch_bounds__(kBlock) void k_relmax(const float* __restrict__ r, 
   }
 }
 
-__global__ void k_relmax_final(const double* __restrict__ partial, int nblocks, double* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double s = 0.0;
-  for (int q = 0; q < nblocks; q++) s = (partial[q] > s || partial[q] != partial[q]) ? partial[q] : s;
-  out[0] = s;
+__global__ __launch_bounds__(kBlock) void k_relmax_final(const double* __restrict__ partial, int nblocks,
+                                                         double* __restrict__ out) {
+  __shared__ double red[kBlock];
+  double m = 0.0;
+  for (int q = threadIdx.x; q < nblocks; q += kBlock) m = (partial[q] > m || partial[q] != partial[q]) ? partial[q] : m;
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      const double u = red[threadIdx.x + w];
+      if (u > red[threadIdx.x] || u != u) red[threadIdx.x] = u;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
 }
 
 // out[i] = sum over blocks of partial[b * kDotGroup + i], fixed order; one
@@ -208,7 +218,7 @@ hipError_t launch_relmax(const float* r, const float* x, int N, double* partial,
   hipLaunchKernelGGL(k_relmax, dim3(kStreamBlocks), dim3(kBlock), 0, s, r, x, N, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_relmax_final, dim3(1), dim3(64), 0, s, partial, kStreamBlocks, out);
+  hipLaunchKernelGGL(k_relmax_final, dim3(1), dim3(kBlock), 0, s, partial, kStreamBlocks, out);
   return hipGetLastError();
 }
 
