@@ -261,7 +261,7 @@ int finish_resid(dpo_ctx* c, double* out, hipStream_t s) {
     HIP_TRY(c, hipMemsetAsync(out, 0, sizeof(double) * kPartial, s));
     return DPO_OK;
   }
-  HIP_TRY(c, launch_resid_final(c->partial, nb, out, s));
+  HIP_TRY(c, launch_resid_final(c->partial, nb, c->partial + (size_t)kPartial * c->partial_blocks, out, s));
   return DPO_OK;
 }
 
@@ -777,7 +777,8 @@ int dpo_create(const dpo_grid* grid, const dpo_problem* prob, const dpo_search* 
     }
   }
   c->partial_blocks = blocks_for(total > 0 ? total : 1, 64) + kFallbackBlocks;
-  if (hipMalloc(&c->partial, sizeof(double) * kPartial * c->partial_blocks) != hipSuccess) {
+  // the partials, then the first stage of their reduction
+  if (hipMalloc(&c->partial, sizeof(double) * kPartial * (c->partial_blocks + kResidStage)) != hipSuccess) {
     c->err = "device allocation failed in dpo_create";
     return cleanup(DPO_ENOMEM);
   }

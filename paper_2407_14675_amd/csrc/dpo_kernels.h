@@ -72,6 +72,7 @@ inline int blocks_for(long long n, int per = kBlock) { return (int)((n + per - 1
 constexpr uint16_t kDescOut = 1u << 12;
 constexpr uint16_t kDescThr = 1u << 13;
 constexpr uint16_t kDescSkip = 0xffffu;  // not a free node (dense form)
+constexpr int kResidStage = 256;          // workgroups of the first stage of the residual reduction
 constexpr int kDescReach = 31;           // largest cell offset the compact code holds
 
 // Per-problem record of the batched sweep (device table).  It holds no
@@ -138,7 +139,9 @@ hipError_t launch_policy_eval_desc16(const SweepArgs& a, int format, bool stream
 hipError_t launch_zero_count(int* count, hipStream_t s);
 hipError_t launch_sweep_fallback(const SweepArgs& a, int block, int blocks, hipStream_t s);
 hipError_t launch_sweep_fast(const SweepArgs& a, int mode, int block, hipStream_t s);
-hipError_t launch_resid_final(const double* partial, int nblocks, double* out, hipStream_t s);
+// Final FP64 reduction of nblocks residual partials into out[kPartial];
+// `stage` holds kResidStage * kPartial doubles for the first of two stages.
+hipError_t launch_resid_final(const double* partial, int nblocks, double* stage, double* out, hipStream_t s);
 hipError_t launch_value_at(const float* V, const Grid& G, double M, const double x[4], double* out,
                            hipStream_t s);
 hipError_t launch_feedback(const SweepArgs& a, const double* states, int n, double tau, float* ang,

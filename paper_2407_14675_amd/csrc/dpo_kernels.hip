@@ -5,6 +5,8 @@
 //
 // Paper: arXiv 2407.14675, Section 3 (eq:schema, value and policy iteration,
 // minimisation by tabulation and golden section, feedback eq:feed).
+#include <algorithm>
+
 #include "dpo_search.h"
 
 namespace dpo {
@@ -363,12 +365,15 @@ __global__ __launch_bounds__(kBlock) void k_policy_eval_d16(SweepArgs a) {
   }
 }
 
-// Final FP64 reduction of the workgroup partials in a fixed order.
+// FP64 reduction of workgroup partials in a fixed order: workgroup b folds
+// the partials b*kBlock + t + k*gridDim.x*kBlock and writes its result to
+// out[kPartial*b ...]; one workgroup gives the final value, several give the
+// first stage of a two-stage reduction.
 __global__ __launch_bounds__(kBlock) void k_resid_final(const double* __restrict__ partial, int nblocks,
                                                         double* __restrict__ out) {
   __shared__ double red[kPartial][kBlock];
   double acc[kPartial] = {0, 0, 0, 0, 0};
-  for (int i = threadIdx.x; i < nblocks; i += kBlock) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < nblocks; i += gridDim.x * kBlock) {
     acc[0] = fmax(acc[0], partial[kPartial * i + 0]);
     acc[1] += partial[kPartial * i + 1];
     acc[2] = fmax(acc[2], partial[kPartial * i + 2]);
@@ -388,7 +393,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_final(const double* __restrict
     __syncthreads();
   }
   if (threadIdx.x == 0)
-    for (int q = 0; q < kPartial; q++) out[q] = red[q][0];
+    for (int q = 0; q < kPartial; q++) out[kPartial * blockIdx.x + q] = red[q][0];
 }
 
 // ------------------------------------------------------------------ a9
@@ -798,8 +803,16 @@ hipError_t launch_policy_eval_desc16(const SweepArgs& a, int format, bool stream
   DPO_LAUNCH((k_policy_eval_d16<false, 0>), blocks_for(a.n_free, kDescNpt * kBlock), kBlock, s, a);
 }
 
-hipError_t launch_resid_final(const double* partial, int nblocks, double* out, hipStream_t s) {
-  DPO_LAUNCH(k_resid_final, 1, kBlock, s, partial, nblocks, out);
+hipError_t launch_resid_final(const double* partial, int nblocks, double* stage, double* out, hipStream_t s) {
+  // One workgroup reads a few thousand partials quickly; beyond that (a
+  // large grid leaves one partial per workgroup of its sweep) the first
+  // stage spreads the read over up to kResidStage workgroups.
+  const int g = std::min(kResidStage, (nblocks + 4 * kBlock - 1) / (4 * kBlock));
+  if (g <= 1) DPO_LAUNCH(k_resid_final, 1, kBlock, s, partial, nblocks, out);
+  hipLaunchKernelGGL(k_resid_final, dim3(g), dim3(kBlock), 0, s, partial, nblocks, stage);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  DPO_LAUNCH(k_resid_final, 1, kBlock, s, stage, g, out);
 }
 
 hipError_t launch_value_at(const float* V, const Grid& G, double M, const double x[4], double* out,
