@@ -332,15 +332,22 @@ int dpo_extract_feedback(dpo_ctx* ctx, const float* V, const double* states, int
  * from each of n states (device double[n*4], updated in place), `steps`
  * times: the feedback of dpo_extract_feedback at the current state with time
  * step tau, then `substeps` classical fourth-order Runge-Kutta steps of
- * length tau/substeps of the model's own dynamics in FP64 with that control
- * held.  One device thread follows each trajectory for all its steps.
+ * length tau/substeps of the simulated system in FP64 with that control
+ * held.  The simulated system is the model's own dynamics plus, when drag >
+ * 0, the aerodynamic drag of Section 4's Example 2: an acceleration of
+ * magnitude drag * |v|^2 opposite to the velocity (v_r, v_t), drag in 1 /
+ * (the grid's length unit); V and the feedback stay those of the model
+ * without it.  drag must be 0 for DPO_MODEL_EIKONAL.  One device thread
+ * follows each trajectory for all its steps.
  * Histories (device, nullable), step-major so that a step's writes are
  * contiguous: traj double[(steps+1)*n*4] (the states before every step and
  * after the last), thr_hist u8[steps*n], ang_hist float[steps*n].
  * Asynchronous on stream.  Limits: 0 <= n < 2^31 - 256, steps >= 0,
- * 1 <= substeps <= 4096, tau > 0; SEEDED search is refused. */
+ * 1 <= substeps <= 4096, tau > 0, drag >= 0 and finite; SEEDED search is
+ * refused. */
 int dpo_simulate(dpo_ctx* ctx, const float* V, double* states, int64_t n, double tau, int32_t steps,
-                 int32_t substeps, double* traj, uint8_t* thr_hist, float* ang_hist, void* stream);
+                 int32_t substeps, double drag, double* traj, uint8_t* thr_hist, float* ang_hist,
+                 void* stream);
 
 /* Reachability mask for a reduced grid: for every node of `fine` (same
  * domain box as ctx), keep = (FP64 Q1 value of the coarse V at the node <

@@ -121,11 +121,11 @@ def load(precision="f64"):
     lib.or_brute_thrust_min.argtypes = [P, vp, i64, i64, vp]
     lib.or_brute_thrust_min.restype = real
     lib.or_mask_from_coarse.argtypes = [P, vp, P, C.c_double, vp, vp]
-    lib.or_rk4_step.argtypes = [P, vp, C.c_int, real, real]
+    lib.or_rk4_step.argtypes = [P, vp, C.c_int, real, real, real]
     lib.or_policy_system.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.or_q_state.argtypes = [P, vp, vp, C.c_int, real, real]
     lib.or_q_state.restype = real
-    lib.or_simulate.argtypes = [P, S, vp, vp, i64, C.c_double, C.c_int32, C.c_int32, vp, vp, vp]
+    lib.or_simulate.argtypes = [P, S, vp, vp, i64, C.c_double, C.c_int32, C.c_int32, C.c_double, vp, vp, vp]
     lib.or_running_cost.argtypes = [P, vp, C.c_int]
     lib.or_running_cost.restype = real
     lib.or_elements.argtypes = [P, vp, vp]
@@ -359,14 +359,15 @@ class Oracle:
         out[free] = v
         return out.reshape(self.shape)
 
-    def rk4_step(self, x, thr, u, h):
+    def rk4_step(self, x, thr, u, h, drag=0.0):
         x = np.ascontiguousarray(np.asarray(x, dtype=self.dtype)).copy()
-        self.lib.or_rk4_step(C.byref(self.ps), _ptr(x), int(thr), u, h)
+        self.lib.or_rk4_step(C.byref(self.ps), _ptr(x), int(thr), u, h, drag)
         return x
 
-    def simulate(self, V, states, tau, steps, substeps=1, search=None, history=True):
+    def simulate(self, V, states, tau, steps, substeps=1, search=None, history=True, drag=0.0):
         """Closed loop from states (count x 4): returns final states and, with
-        history, the trajectory ((steps+1) x count x 4) and the controls."""
+        history, the trajectory ((steps+1) x count x 4) and the controls.
+        drag: Example 2's drag coefficient on the simulated system only."""
         Vin = self._arr(V)
         ss = self.ss if search is None else search_struct(search)
         st = np.ascontiguousarray(np.asarray(states, dtype=np.float64).reshape(-1, 4)).copy()
@@ -375,7 +376,7 @@ class Oracle:
         thr = np.zeros((steps, cnt), dtype=np.uint8) if history else None
         ang = np.zeros((steps, cnt), dtype=self.dtype) if history else None
         self.lib.or_simulate(C.byref(self.ps), C.byref(ss), _ptr(Vin), _ptr(st), cnt, float(tau), int(steps),
-                             int(substeps), _ptr(traj), _ptr(thr), _ptr(ang))
+                             int(substeps), float(drag), _ptr(traj), _ptr(thr), _ptr(ang))
         return st, traj, thr, ang
 
     def brute_thrust_min(self, V, j, n_angles):

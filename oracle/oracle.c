@@ -916,18 +916,30 @@ void or_feedback(const or_problem *p, const or_search *sr, const real *V, const 
 }
 
 /* ------------------------------------------------- closed-loop simulation */
-/* One classical fourth-order Runge-Kutta step of length h of the model's
- * dynamics (the "real system" of Section 3, computed by a fourth-order
- * Runge-Kutta method) with the control (thr, u) held over the step. */
-void or_rk4_step(const or_problem *p, real x[4], int thr, real u, real h) {
+/* The "real system" of the simulations: the model's dynamics plus, for the
+ * orbit models, the aerodynamic drag of Section 4's Example 2, an
+ * acceleration of magnitude drag * |v|^2 against the velocity (v_r, v_t)
+ * (the air at rest); drag = 0 leaves the model's own dynamics. */
+static void plant_rhs(const or_problem *p, const real x[4], int thr, real u, real drag, real b[4]) {
+  rhs(p, x, thr, u, b);
+  if (drag != 0 && p->model != 1) {
+    real speed = (real)sqrt((double)(x[1] * x[1] + x[2] * x[2]));
+    b[1] -= drag * speed * x[1];
+    b[2] -= drag * speed * x[2];
+  }
+}
+
+/* One classical fourth-order Runge-Kutta step of length h of the real
+ * system with the control (thr, u) held over the step. */
+void or_rk4_step(const or_problem *p, real x[4], int thr, real u, real h, real drag) {
   real k1[4], k2[4], k3[4], k4[4], y[4];
-  rhs(p, x, thr, u, k1);
+  plant_rhs(p, x, thr, u, drag, k1);
   for (int k = 0; k < 4; k++) y[k] = x[k] + (real)0.5 * h * k1[k];
-  rhs(p, y, thr, u, k2);
+  plant_rhs(p, y, thr, u, drag, k2);
   for (int k = 0; k < 4; k++) y[k] = x[k] + (real)0.5 * h * k2[k];
-  rhs(p, y, thr, u, k3);
+  plant_rhs(p, y, thr, u, drag, k3);
   for (int k = 0; k < 4; k++) y[k] = x[k] + h * k3[k];
-  rhs(p, y, thr, u, k4);
+  plant_rhs(p, y, thr, u, drag, k4);
   for (int k = 0; k < 4; k++) x[k] += h / (real)6 * (k1[k] + (real)2 * k2[k] + (real)2 * k3[k] + k4[k]);
 }
 
@@ -938,9 +950,11 @@ void or_rk4_step(const or_problem *p, real x[4], int thr, real u, real h) {
  * control held.  states (count x 4) is updated in place; traj (nullable)
  * receives the states before every step and after the last, step-major
  * ((steps+1) x count x 4); thr_hist / ang_hist (nullable) the controls,
- * step-major (steps x count). */
+ * step-major (steps x count).  drag: the Example 2 drag coefficient of the
+ * real system (0: none); the feedback still uses V of the model without it. */
 void or_simulate(const or_problem *p, const or_search *sr, const real *V, double *states, int64_t count,
-                 double tau, int32_t steps, int32_t substeps, double *traj, uint8_t *thr_hist, real *ang_hist) {
+                 double tau, int32_t steps, int32_t substeps, double drag, double *traj, uint8_t *thr_hist,
+                 real *ang_hist) {
   for (int64_t c = 0; c < count; c++) {
     real y[4];
     for (int k = 0; k < 4; k++) y[k] = (real)states[4 * c + k];
@@ -950,7 +964,7 @@ void or_simulate(const or_problem *p, const or_search *sr, const real *V, double
       qfun f = {p, V, NULL, y, (real)tau};
       choice ch = search(&f, sr);
       const real h = (real)(tau / (double)substeps);
-      for (int32_t q = 0; q < substeps; q++) or_rk4_step(p, y, ch.thr, ch.angle, h);
+      for (int32_t q = 0; q < substeps; q++) or_rk4_step(p, y, ch.thr, ch.angle, h, (real)drag);
       if (thr_hist) thr_hist[(int64_t)s * count + c] = (uint8_t)ch.thr;
       if (ang_hist) ang_hist[(int64_t)s * count + c] = ch.angle;
       if (traj)

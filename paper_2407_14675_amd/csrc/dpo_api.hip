@@ -1240,18 +1240,20 @@ int dpo_extract_feedback(dpo_ctx* c, const float* V, const double* states, int64
 }
 
 int dpo_simulate(dpo_ctx* c, const float* V, double* states, int64_t n, double tau, int32_t steps, int32_t substeps,
-                 double* traj, uint8_t* thr_hist, float* ang_hist, void* stream) {
+                 double drag, double* traj, uint8_t* thr_hist, float* ang_hist, void* stream) {
   if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
   if (!V) return fail(c, DPO_EINVAL, "V is NULL");
   if (n < 0 || n > 0x7fffffff - kBlock) return fail(c, DPO_EINVAL, "bad n");
   if (!(tau > 0) || !std::isfinite(tau)) return fail(c, DPO_EINVAL, "tau must be > 0");
   if (steps < 0 || substeps < 1 || substeps > 4096) return fail(c, DPO_EINVAL, "steps >= 0, substeps in [1, 4096]");
   if (c->search.mode == DPO_SEARCH_SEEDED) return fail(c, DPO_EINVAL, "the closed loop needs TABLE, SCAN_GOLDEN or TABLE_WALK");
+  if (!(drag >= 0) || !std::isfinite(drag)) return fail(c, DPO_EINVAL, "drag must be finite and >= 0");
+  if (drag != 0 && c->prob.model == DPO_MODEL_EIKONAL) return fail(c, DPO_EINVAL, "drag: orbit models only");
   if (n == 0) return DPO_OK;
   if (!states) return fail(c, DPO_EINVAL, "states is NULL");
   SweepArgs a = base_args(c);
   a.V_in = V;
-  HIP_TRY(c, launch_simulate(a, states, (int)n, tau, steps, substeps, traj, thr_hist, ang_hist, S(stream)));
+  HIP_TRY(c, launch_simulate(a, states, (int)n, tau, steps, substeps, drag, traj, thr_hist, ang_hist, S(stream)));
   return DPO_OK;
 }
 

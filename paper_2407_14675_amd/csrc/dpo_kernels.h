@@ -147,7 +147,7 @@ hipError_t launch_value_at(const float* V, const Grid& G, double M, const double
 hipError_t launch_feedback(const SweepArgs& a, const double* states, int n, double tau, float* ang,
                            uint8_t* thr, float* q, hipStream_t s);
 hipError_t launch_simulate(const SweepArgs& a, double* states, int n, double tau, int steps, int substeps,
-                           double* traj, uint8_t* thr_hist, float* ang_hist, hipStream_t s);
+                           double drag, double* traj, uint8_t* thr_hist, float* ang_hist, hipStream_t s);
 hipError_t launch_mask_seed(const float* Vc, const Grid& Gc, double M, const Grid& Gf, double thresh,
                             uint8_t* seed, int Nf, hipStream_t s);
 hipError_t launch_dilate_axis(const uint8_t* in, uint8_t* out, const Grid& G, int axis, int d, int N,

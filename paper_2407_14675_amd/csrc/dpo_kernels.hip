@@ -513,10 +513,13 @@ __global__ __launch_bounds__(kBlock) void k_feedback(SweepArgs a, const double* 
   if (q_out) q_out[c] = ch.v;
 }
 
-// ---- closed loop: the model's own dynamics in FP64 (the real system of the
-// simulations of Section 4), integrated by the classical fourth-order
-// Runge-Kutta method with the control held over each step.
-__device__ inline void plant_rhs(const Phys& P, const double x[4], int thr, double sn, double cs, double b[4]) {
+// ---- closed loop: the simulated system of Section 4 in FP64, the model's
+// own dynamics plus (orbit models, drag != 0) Example 2's aerodynamic drag,
+// an acceleration drag * |v|^2 against the velocity (v_r, v_t); integrated
+// by the classical fourth-order Runge-Kutta method with the control held
+// over each step.
+__device__ inline void plant_rhs(const Phys& P, const double x[4], int thr, double sn, double cs, double drag,
+                                 double b[4]) {
 #pragma clang fp contract(off)
   if (P.model == 1) {
     const double s = thr ? P.speed : 0.0;
@@ -528,22 +531,23 @@ __device__ inline void plant_rhs(const Phys& P, const double x[4], int thr, doub
   }
   const double r = x[0], vr = x[1], vt = x[2];
   const double acc = thr ? (P.model == 2 ? P.accel : P.accel / x[3]) : 0.0;
+  const double dv = drag * sqrt(vr * vr + vt * vt);
   b[0] = vr;
-  b[1] = vt * vt / r - P.mu / (r * r) + acc * sn;
-  b[2] = -vr * vt / r + acc * cs;
+  b[1] = (vt * vt / r - P.mu / (r * r) + acc * sn) - dv * vr;
+  b[2] = (-vr * vt / r + acc * cs) - dv * vt;
   b[3] = P.model == 2 ? vt / r : -P.mdot * (double)thr;
 }
 
-__device__ inline void rk4_step(const Phys& P, double x[4], int thr, double sn, double cs, double h) {
+__device__ inline void rk4_step(const Phys& P, double x[4], int thr, double sn, double cs, double drag, double h) {
 #pragma clang fp contract(off)
   double k1[4], k2[4], k3[4], k4[4], y[4];
-  plant_rhs(P, x, thr, sn, cs, k1);
+  plant_rhs(P, x, thr, sn, cs, drag, k1);
   for (int k = 0; k < 4; k++) y[k] = x[k] + 0.5 * h * k1[k];
-  plant_rhs(P, y, thr, sn, cs, k2);
+  plant_rhs(P, y, thr, sn, cs, drag, k2);
   for (int k = 0; k < 4; k++) y[k] = x[k] + 0.5 * h * k2[k];
-  plant_rhs(P, y, thr, sn, cs, k3);
+  plant_rhs(P, y, thr, sn, cs, drag, k3);
   for (int k = 0; k < 4; k++) y[k] = x[k] + h * k3[k];
-  plant_rhs(P, y, thr, sn, cs, k4);
+  plant_rhs(P, y, thr, sn, cs, drag, k4);
   for (int k = 0; k < 4; k++) x[k] += h / 6.0 * (k1[k] + 2.0 * k2[k] + 2.0 * k3[k] + k4[k]);
 }
 
@@ -551,7 +555,7 @@ __device__ inline void rk4_step(const Phys& P, double x[4], int thr, double sn, 
 // (time step tau), then `substeps` RK4 steps of tau/substeps with that
 // control.  Histories are step-major so that a step's writes are coalesced.
 __global__ __launch_bounds__(kBlock) void k_simulate(SweepArgs a, double* __restrict__ states, int n, double tau,
-                                                     int steps, int substeps, double* __restrict__ traj,
+                                                     int steps, int substeps, double drag, double* __restrict__ traj,
                                                      uint8_t* __restrict__ thr_hist, float* __restrict__ ang_hist) {
   const int c = blockIdx.x * kBlock + threadIdx.x;
   if (c >= n) return;
@@ -565,7 +569,7 @@ __global__ __launch_bounds__(kBlock) void k_simulate(SweepArgs a, double* __rest
     feedback_at(a, y, tau, ch);
     double sn, cs;
     sincos((double)ch.ang, &sn, &cs);
-    for (int q = 0; q < substeps; q++) rk4_step(a.P, y, ch.thr, sn, cs, h);
+    for (int q = 0; q < substeps; q++) rk4_step(a.P, y, ch.thr, sn, cs, drag, h);
     const size_t at = (size_t)s * (size_t)n + (size_t)c;
     if (thr_hist) thr_hist[at] = (uint8_t)ch.thr;
     if (ang_hist) ang_hist[at] = ch.ang;
@@ -826,8 +830,9 @@ hipError_t launch_feedback(const SweepArgs& a, const double* states, int n, doub
 }
 
 hipError_t launch_simulate(const SweepArgs& a, double* states, int n, double tau, int steps, int substeps,
-                           double* traj, uint8_t* thr_hist, float* ang_hist, hipStream_t s) {
-  DPO_LAUNCH(k_simulate, blocks_for(n), kBlock, s, a, states, n, tau, steps, substeps, traj, thr_hist, ang_hist);
+                           double drag, double* traj, uint8_t* thr_hist, float* ang_hist, hipStream_t s) {
+  DPO_LAUNCH(k_simulate, blocks_for(n), kBlock, s, a, states, n, tau, steps, substeps, drag, traj, thr_hist,
+             ang_hist);
 }
 
 hipError_t launch_mask_seed(const float* Vc, const Grid& Gc, double M, const Grid& Gf, double thresh,

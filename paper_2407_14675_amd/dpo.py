@@ -96,7 +96,7 @@ def load():
         "dpo_policy_evaluate": [vp, vp, vp, vp, dbl, i32, C.POINTER(i64), C.POINTER(dbl), vp],
         "dpo_value_at": [vp, vp, vp, vp, vp],
         "dpo_extract_feedback": [vp, vp, vp, i64, dbl, vp, vp, vp, vp],
-        "dpo_simulate": [vp, vp, vp, i64, dbl, i32, i32, vp, vp, vp, vp],
+        "dpo_simulate": [vp, vp, vp, i64, dbl, i32, i32, dbl, vp, vp, vp, vp],
         "dpo_mask_from_coarse": [vp, vp, C.POINTER(Grid), dbl, vp, vp, vp],
         "dpo_probe_interp": [vp, vp, vp, i64, vp, vp],
         "dpo_probe_q": [vp, vp, vp, vp, vp, i64, vp, vp],
@@ -327,10 +327,11 @@ class Context:
                                                   _p(q), _stream()))
         return ang, thr, q
 
-    def simulate(self, V, states, tau=None, steps=1, substeps=1, history=True):
+    def simulate(self, V, states, tau=None, steps=1, substeps=1, history=True, drag=0.0):
         """Closed loop from states (n x 4): feedback, then RK4 with the control
-        held, `steps` times.  Returns the final states (device, float64) and,
-        with history, the trajectory ((steps+1) x n x 4) and the controls
+        held, `steps` times; drag > 0 adds Example 2's drag to the simulated
+        system only.  Returns the final states (device, float64) and, with
+        history, the trajectory ((steps+1) x n x 4) and the controls
         (steps x n)."""
         st = torch.as_tensor(states, dtype=torch.float64).to(self.device).contiguous().reshape(-1, 4).clone()
         n = st.shape[0]
@@ -341,7 +342,7 @@ class Context:
             ang = torch.empty((steps, n), dtype=torch.float32, device=self.device)
         tau = self.problem["dt"] if tau is None else tau
         self._check(self.lib.dpo_simulate(self.h, _p(V), _p(st), n, float(tau), int(steps), int(substeps),
-                                          _p(traj), _p(thr), _p(ang), _stream()))
+                                          float(drag), _p(traj), _p(thr), _p(ang), _stream()))
         return st, traj, thr, ang
 
     def mask_from_coarse(self, Vc, fine_problem, thresh, dilate):

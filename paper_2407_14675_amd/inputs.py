@@ -181,6 +181,12 @@ EX1 = crown_problem()
 # Start of the paper's closed-loop orbit raise: circular orbit at 6978 km.
 EX1_START_RADIUS = 6978.0
 
+# Example 2's drag on the simulated system (Section 4): acceleration
+# C |v|^2 against the velocity with C = C_D S rho_D / (2 m); C_D = 2.2,
+# S = 2.25 m^2, rho_D = 8.09e-14 kg/m^3, m = 350 kg give C in 1/m, times 1000
+# for the crown grid's km (a = C v^2 with v in km/s then comes out in km/s^2).
+EX2_DRAG = 2.2 * 2.25 * 8.09e-14 / (2.0 * 350.0) * 1000.0
+
 
 def with_grid(problem, n):
     """Same physics on another grid."""

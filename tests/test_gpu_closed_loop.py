@@ -59,15 +59,15 @@ def test_eikonal_closed_loop_goes_straight_home(dpo):
     np.testing.assert_array_equal(host(final), traj[-1])
 
 
-def compare(o, ctx, V32, starts, tau, steps, name):
+def compare(o, ctx, V32, starts, tau, steps, name, drag=0.0):
     """Device and oracle loops from the same starts: identical states (to the
     float32 angle's rounding) up to the first step with different controls,
     and at that step the device's control is a near-tie at the shared state:
     its oracle Q is within the one-evaluation tolerance of the oracle's
     optimum."""
     V64 = V32.astype(np.float64)
-    final, traj, thr, ang = ctx.simulate(dev(V32), starts, tau=tau, steps=steps)
-    ofinal, otraj, othr, oang = o.simulate(V64, starts, tau, steps)
+    final, traj, thr, ang = ctx.simulate(dev(V32), starts, tau=tau, steps=steps, drag=drag)
+    ofinal, otraj, othr, oang = o.simulate(V64, starts, tau, steps, drag=drag)
     traj, thr, ang = host(traj), host(thr), host(ang)
     same = (thr == othr) & ((othr == 0) | (np.abs(ang - oang) < 1e-5))
     n = starts.shape[0]
@@ -114,6 +114,27 @@ def test_crown_closed_loop_parity(dpo):
     compare(o, ctx, V32, starts, p["dt"], 300, "crown 8x6x6x8")
 
 
+@pytest.mark.parametrize("which", ["orbit", "crown"])
+def test_closed_loop_with_drag_parity(dpo, which):
+    """Example 2: the feedback of the model without drag drives a system
+    with drag; the drag coefficients give ~30 % (orbit, nondimensional) and
+    ~10 % (crown) of the thrust acceleration, so that the controls respond."""
+    if which == "orbit":
+        p, gold, drag, steps = inputs.VI12, "tests/golden/vi12_table16.npz", 3e-4, 200
+    else:
+        p, gold, drag, steps = inputs.crown_problem((8, 6, 6, 8)), "tests/golden/crown8_table72.npz", 1e-9, 300
+    _say("closed loop with drag", which)
+    V32 = np.load(gold)["V"].astype(np.float32)
+    o = Oracle(p)
+    ctx = dpo.Context(p)
+    starts = inputs.random_states(p, 64, seed=123, margin=0.1)
+    compare(o, ctx, V32, starts, p["dt"], steps, which + " with drag", drag=drag)
+    # the drag changes the device's trajectories
+    plain = host(ctx.simulate(dev(V32), starts, tau=p["dt"], steps=steps, history=False)[0])
+    dragged = host(ctx.simulate(dev(V32), starts, tau=p["dt"], steps=steps, history=False, drag=drag)[0])
+    assert np.any(plain != dragged)
+
+
 def test_simulate_arguments(dpo):
     ctx = dpo.Context(inputs.VI12)
     V = ctx.init_value()
@@ -121,5 +142,12 @@ def test_simulate_arguments(dpo):
         ctx.simulate(V, np.zeros((2, 4)), tau=-1.0, steps=2)
     with pytest.raises(dpo.DpoError):
         ctx.simulate(V, np.zeros((2, 4)), tau=0.1, steps=2, substeps=0)
+    with pytest.raises(dpo.DpoError):
+        ctx.simulate(V, np.zeros((2, 4)), tau=0.1, steps=2, drag=-1.0)
+    with pytest.raises(dpo.DpoError):
+        ctx.simulate(V, np.zeros((2, 4)), tau=0.1, steps=2, drag=float("nan"))
+    eik = dpo.Context(inputs.eikonal_problem(17))
+    with pytest.raises(dpo.DpoError):
+        eik.simulate(eik.init_value(), np.zeros((2, 4)), tau=0.1, steps=2, drag=0.1)
     final, traj, thr, ang = ctx.simulate(V, np.zeros((0, 4)), tau=0.1, steps=3)
     assert final.shape == (0, 4)
