@@ -72,6 +72,9 @@ inline int blocks_for(long long n, int per = kBlock) { return (int)((n + per - 1
 constexpr uint16_t kDescOut = 1u << 12;
 constexpr uint16_t kDescThr = 1u << 13;
 constexpr uint16_t kDescSkip = 0xffffu;  // not a free node (dense form)
+// Feedback and closed loop: up to this many states one wave per state (the
+// lanes split the table), beyond it one thread per state.
+constexpr int kWaveStates = 8192;
 constexpr int kResidStage = 256;          // workgroups of the first stage of the residual reduction
 constexpr int kDescReach = 31;           // largest cell offset the compact code holds
 

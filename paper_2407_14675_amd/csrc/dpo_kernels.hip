@@ -461,6 +461,9 @@ __global__ void k_value_at(const float* __restrict__ V, Grid G, double M, double
 
 // Feedback eq:feed at an arbitrary state y: the state is split into a grid
 // node and an in-cell offset, so the sweep's search runs unchanged on it.
+// kWave: the lanes of a wave share the state and split the table (every
+// lane computes the same set-up and ends with the same choice).
+template <bool kWave>
 __device__ inline void feedback_at(const SweepArgs& a, const double y_in[4], double tau, Choice& ch) {
   double y[4];
   NodeTerms T;
@@ -494,20 +497,25 @@ __device__ inline void feedback_at(const SweepArgs& a, const double y_in[4], dou
   const float qc = heun ? q_step<true, true>(b.V_in, b.G, b.P, T, H, 0, 0.0f, 1.0f, qx)
                         : q_step<false, true>(b.V_in, b.G, b.P, T, H, 0, 0.0f, 1.0f, qx);
   // the walk's table (mode 3) is searched in full: a state has no previous optimum
-  if (a.mode == 0 || a.mode == 3) table_search(qf, b, qc, ch);
-  else full_search(qf, b, qc, ch);
+  if (a.mode == 0 || a.mode == 3) table_search<kWave>(qf, b, qc, ch);
+  else full_search<kWave>(qf, b, qc, ch);
 }
 
+// kWave: one wave per state (few states: the table is split over the lanes,
+// and the chip holds 64 times as many independent waves); else one thread
+// per state.
+template <bool kWave>
 __global__ __launch_bounds__(kBlock) void k_feedback(SweepArgs a, const double* __restrict__ states,
                                                      int n, double tau, float* __restrict__ ang_out,
                                                      uint8_t* __restrict__ thr_out,
                                                      float* __restrict__ q_out) {
-  const int c = blockIdx.x * kBlock + threadIdx.x;
-  if (c >= n) return;
+  const int c = kWave ? (int)(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) : (int)(blockIdx.x * kBlock + threadIdx.x);
+  if (c >= n) return;  // wave-uniform in the wave mode
   double y[4];
   for (int k = 0; k < 4; k++) y[k] = states[4 * c + k];
   Choice ch;
-  feedback_at(a, y, tau, ch);
+  feedback_at<kWave>(a, y, tau, ch);
+  if (kWave && (threadIdx.x & 63) != 0) return;
   ang_out[c] = ch.ang;
   thr_out[c] = (uint8_t)ch.thr;
   if (q_out) q_out[c] = ch.v;
@@ -551,32 +559,38 @@ __device__ inline void rk4_step(const Phys& P, double x[4], int thr, double sn, 
   for (int k = 0; k < 4; k++) x[k] += h / 6.0 * (k1[k] + 2.0 * k2[k] + 2.0 * k3[k] + k4[k]);
 }
 
-// One trajectory per thread: `steps` times the feedback at the current state
-// (time step tau), then `substeps` RK4 steps of tau/substeps with that
-// control.  Histories are step-major so that a step's writes are coalesced.
+// One trajectory per thread (or, kWave, per wave: the lanes split the
+// feedback's table and all integrate the same state): `steps` times the
+// feedback at the current state (time step tau), then `substeps` RK4 steps of
+// tau/substeps with that control.  Histories are step-major so that a step's
+// writes are coalesced.
+template <bool kWave>
 __global__ __launch_bounds__(kBlock) void k_simulate(SweepArgs a, double* __restrict__ states, int n, double tau,
                                                      int steps, int substeps, double drag, double* __restrict__ traj,
                                                      uint8_t* __restrict__ thr_hist, float* __restrict__ ang_hist) {
-  const int c = blockIdx.x * kBlock + threadIdx.x;
-  if (c >= n) return;
+  const int c = kWave ? (int)(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) : (int)(blockIdx.x * kBlock + threadIdx.x);
+  if (c >= n) return;  // wave-uniform in the wave mode
+  const bool lead = !kWave || (threadIdx.x & 63) == 0;
   double y[4];
   for (int k = 0; k < 4; k++) y[k] = states[4 * c + k];
-  if (traj)
+  if (traj && lead)
     for (int k = 0; k < 4; k++) traj[4 * (size_t)c + k] = y[k];
   const double h = tau / (double)substeps;
   for (int s = 0; s < steps; s++) {
     Choice ch;
-    feedback_at(a, y, tau, ch);
+    feedback_at<kWave>(a, y, tau, ch);
     double sn, cs;
     sincos((double)ch.ang, &sn, &cs);
     for (int q = 0; q < substeps; q++) rk4_step(a.P, y, ch.thr, sn, cs, drag, h);
+    if (!lead) continue;
     const size_t at = (size_t)s * (size_t)n + (size_t)c;
     if (thr_hist) thr_hist[at] = (uint8_t)ch.thr;
     if (ang_hist) ang_hist[at] = ch.ang;
     if (traj)
       for (int k = 0; k < 4; k++) traj[4 * (at + (size_t)n) + k] = y[k];
   }
-  for (int k = 0; k < 4; k++) states[4 * c + k] = y[k];
+  if (lead)
+    for (int k = 0; k < 4; k++) states[4 * c + k] = y[k];
 }
 
 // Reachability seed: FP64 Q1 value of the coarse V at every fine node.
@@ -826,12 +840,16 @@ hipError_t launch_value_at(const float* V, const Grid& G, double M, const double
 
 hipError_t launch_feedback(const SweepArgs& a, const double* states, int n, double tau, float* ang,
                            uint8_t* thr, float* q, hipStream_t s) {
-  DPO_LAUNCH(k_feedback, blocks_for(n), kBlock, s, a, states, n, tau, ang, thr, q);
+  if (n <= kWaveStates) DPO_LAUNCH(k_feedback<true>, (n + kBlock / 64 - 1) / (kBlock / 64), kBlock, s, a, states, n, tau, ang, thr, q);
+  DPO_LAUNCH(k_feedback<false>, blocks_for(n), kBlock, s, a, states, n, tau, ang, thr, q);
 }
 
 hipError_t launch_simulate(const SweepArgs& a, double* states, int n, double tau, int steps, int substeps,
                            double drag, double* traj, uint8_t* thr_hist, float* ang_hist, hipStream_t s) {
-  DPO_LAUNCH(k_simulate, blocks_for(n), kBlock, s, a, states, n, tau, steps, substeps, drag, traj, thr_hist,
+  if (n <= kWaveStates)
+    DPO_LAUNCH(k_simulate<true>, (n + kBlock / 64 - 1) / (kBlock / 64), kBlock, s, a, states, n, tau, steps, substeps,
+               drag, traj, thr_hist, ang_hist);
+  DPO_LAUNCH(k_simulate<false>, blocks_for(n), kBlock, s, a, states, n, tau, steps, substeps, drag, traj, thr_hist,
              ang_hist);
 }
 

@@ -119,18 +119,44 @@ __device__ inline void golden(const QF& qf, float s0, float c0, float half, int 
 }
 
 // Exhaustive pass over the n_ang tabulated angles: first strict minimum.
-template <class QF>
+// kWave: the 64 lanes of a wave search for one state together, lane l taking
+// the entries l, l + 64, ...; the wave then keeps the smallest value with
+// the lowest index among equal values, which is the same first strict
+// minimum (entries whose Q is not below +inf are never taken, and with none
+// taken the index is 0, as in the one-lane pass).  Every lane ends with the
+// result; the caller's lanes must all be active.
+template <bool kWave = false, class QF>
 __device__ inline void scan_table(const QF& qf, const SweepArgs& a, float& bq, int& bk) {
   bq = INFINITY;
   bk = 0;
+  if (!kWave) {
 #pragma unroll 8
-  for (int k = 0; k < a.n_ang; k++) {
+    for (int k = 0; k < a.n_ang; k++) {
+      const float q = qf(a.tab_sin[k], a.tab_cos[k]);
+      if (q < bq) {
+        bq = q;
+        bk = k;
+      }
+    }
+    return;
+  }
+  int k_best = 0x7fffffff;
+  for (int k = (int)(threadIdx.x & 63); k < a.n_ang; k += 64) {
     const float q = qf(a.tab_sin[k], a.tab_cos[k]);
     if (q < bq) {
       bq = q;
-      bk = k;
+      k_best = k;
     }
   }
+  for (int o = 32; o > 0; o >>= 1) {
+    const float q2 = __shfl_xor(bq, o, 64);
+    const int k2 = __shfl_xor(k_best, o, 64);
+    if (q2 < bq || (q2 == bq && k2 < k_best)) {
+      bq = q2;
+      k_best = k2;
+    }
+  }
+  bk = k_best == 0x7fffffff ? 0 : k_best;
 }
 
 // The outcome of the search at one node.
@@ -143,11 +169,11 @@ struct Choice {
 
 // Full search: scan, golden section around the best sample (if n_golden > 0),
 // then thrust iff strictly below the coast value qc.
-template <class QF>
+template <bool kWave = false, class QF>
 __device__ inline void full_search(const QF& qf, const SweepArgs& a, float qc, Choice& ch) {
   float bq;
   int bk;
-  scan_table(qf, a, bq, bk);
+  scan_table<kWave>(qf, a, bq, bk);
   GoldenState g{bq, 0.0f, a.tab_sin[bk], a.tab_cos[bk]};
   if (a.n_golden > 0) golden(qf, a.tab_sin[bk], a.tab_cos[bk], a.half_width, a.n_golden, a.rot_scan, g);
   ch.thr = g.best_q < qc ? 1 : 0;
@@ -158,11 +184,11 @@ __device__ inline void full_search(const QF& qf, const SweepArgs& a, float qc, C
 }
 
 // Tabulated search: first strict minimum over the table, coast on ties.
-template <class QF>
+template <bool kWave = false, class QF>
 __device__ inline void table_search(const QF& qf, const SweepArgs& a, float qc, Choice& ch) {
   float bq;
   int bk;
-  scan_table(qf, a, bq, bk);
+  scan_table<kWave>(qf, a, bq, bk);
   ch.thr = bq < qc ? 1 : 0;
   ch.v = ch.thr ? bq : qc;
   ch.ang = a.tab_ang[bk];

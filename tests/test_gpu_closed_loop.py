@@ -135,6 +135,32 @@ def test_closed_loop_with_drag_parity(dpo, which):
     assert np.any(plain != dragged)
 
 
+@pytest.mark.parametrize("which", ["crown_table", "orbit_scan_golden"])
+def test_wave_and_thread_modes_agree(dpo, which):
+    """Up to 8192 states the feedback and the closed loop give each state a
+    whole wave (its lanes split the table), beyond that one thread: the
+    arithmetic of every evaluation and the order of the minimum are the same,
+    so the first 100 of 8292 states end bit for bit where the same 100 alone
+    do."""
+    if which == "crown_table":
+        p, gold = inputs.crown_problem((8, 6, 6, 8)), "tests/golden/crown8_table72.npz"
+    else:
+        p, gold = dict(inputs.VI12, search=inputs.SCAN_GOLDEN), "tests/golden/vi12_table16.npz"
+    _say("wave and thread modes", which)
+    V = dev(np.load(gold)["V"].astype(np.float32))
+    ctx = dpo.Context(p)
+    starts = inputs.random_states(p, 8192 + 100, seed=124, margin=0.05)
+    big = ctx.simulate(V, starts, tau=p["dt"], steps=40)
+    small = ctx.simulate(V, starts[:100], tau=p["dt"], steps=40)
+    np.testing.assert_array_equal(host(big[0])[:100], host(small[0]))  # final states
+    for b, s in zip(big[1:], small[1:]):  # trajectory, throttles, angles: step-major
+        np.testing.assert_array_equal(host(b)[:, :100], host(s))
+    fb = ctx.feedback(V, starts)
+    fs = ctx.feedback(V, starts[:100])
+    for b, s in zip(fb, fs):
+        np.testing.assert_array_equal(host(b)[:100], host(s))
+
+
 def test_simulate_arguments(dpo):
     ctx = dpo.Context(inputs.VI12)
     V = ctx.init_value()
