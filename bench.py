@@ -171,6 +171,31 @@ def rel_diff(A, B, free):
     return float(d.max()), int((d > 1e-4).sum())
 
 
+# Policy iteration from a 1e-6 stop on to the float32 floor: stop at a
+# relative one-step residual of 3e-7 or on a stall.  The one-step residual
+# understates the distance to the fixed point by the iteration's horizon: on
+# the 24 x 24 x 24 x 16 version of the 96 x 96 x 96 x 64 problem the 1e-6 stop
+# is 2.1e-4 away from the oracle's converged solution, 3e-7 is 1.8e-5 away.
+FLOOR_TOL = 3e-7
+
+
+def to_float32_floor(ctx, V, a, t, eval_sweeps, free):
+    import torch
+
+    from paper_2407_14675_amd import inputs
+
+    Vf, af, tf = V.clone(), a.clone(), t.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, st = ctx.solve_pi(Vf, af, tf, tol_rel=FLOOR_TOL, eval_sweeps=eval_sweeps, max_outer=3000)
+    torch.cuda.synchronize()
+    out = {"extra_seconds": time.perf_counter() - t0, "extra_outer": st["sweeps"], "tol_rel": FLOOR_TOL,
+           "converged": bool(st["converged"]), "stalled": bool(st["stalled"]), "resid_max_rel": st["resid_max_rel"],
+           "V_x0": ctx.value_at(Vf, inputs.X0)}
+    out["max_rel_change_from_1e-6_stop"], out["nodes_changed_over_1e-4"] = rel_diff(V, Vf, free)
+    return out
+
+
 def bench_large(accels=(1e-3,), with_seeded=True):
     """96 x 96 x 96 x 64 problems (dt 0.02, fuel weight 0.1): value iteration
     to 1e-3 then policy iteration to 1e-6 (the reference solution); then, for
@@ -204,6 +229,7 @@ def bench_large(accels=(1e-3,), with_seeded=True):
             "seconds": t2 - t0, "converged": bool(st2["converged"]), "resid_max_rel": st2["resid_max_rel"],
             "V_x0": ctx.value_at(V, inputs.X0),
         }
+        rec["to_float32_floor"] = to_float32_floor(ctx, V, a, t, 20, free)
         log(f"bench: large a={accel}: {rec}")
         # plain policy iteration from V0 (same stop rule), compared with the reference
         Vp = ctx.init_value()
@@ -589,6 +615,7 @@ def main():
             "tol_rel": 1e-6,
             "V_x0": ctx.value_at(Vc1, inputs.X0),
         }
+        converge["to_float32_floor"] = to_float32_floor(ctx, Vc1, ac, tc, E, ctx.kind() == 0)
         log(f"bench: converge {converge}")
 
     variants = None

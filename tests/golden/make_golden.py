@@ -13,6 +13,12 @@ vi12_table16_heun.npz   the same problem with the Heun (second-order
 vi12_walk16.npz   the Euler problem with the table searched by the walk from
               the previous sweep's angles (full table on the first sweep),
               same stop rule.
+large24_a1e-3.npz   the 96 x 96 x 96 x 64 problem's physics (dt = 0.02,
+              l = 1 + 0.1 thr, a = 1e-3, scan 64 + golden 12) on 24 x 24 x 24 x
+              16 nodes: value iteration to a relative change of 1e-3, then
+              modified policy iteration (20 evaluation sweeps) until the
+              greedy step's relative residual is below 1e-9; V and angles
+              stored as float32.
 crown8_table72.npz   the paper's Example 1 problem (crown grid, theta
               periodic, orbital-element cost, discount, Heun foot, 72 angles
               + coast) on 8 x 6 x 6 x 8 nodes, value iteration until the
@@ -70,8 +76,20 @@ def make_crown8():
     print("crown 8x6x6x8 value iteration: sweeps", res["sweeps"])
 
 
+def make_large24():
+    p = inputs.large_problem(accel=1e-3, n=(24, 24, 24, 16))
+    o = Oracle(p)
+    vi = o.solve_vi(tol_abs=0.0, tol_rel=1e-3, max_sweeps=100000)
+    pi = o.solve_pi(V0=vi["V"], tol_abs=0.0, tol_rel=1e-9, eval_sweeps=20, max_outer=100000)
+    assert pi["converged"], pi["resid"]
+    np.savez_compressed(os.path.join(HERE, "large24_a1e-3.npz"), V=pi["V"].astype(np.float32),
+                        angle=pi["angle"].astype(np.float32), thr=pi["thr"], vi_sweeps=np.int64(vi["sweeps"]),
+                        pi_outer=np.int64(pi["outer"]))
+    print("24^3 x 16: VI sweeps", vi["sweeps"], "PI steps", pi["outer"], "V(x0)", o.value_at(pi["V"], inputs.X0))
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["vi12", "vi12_heun", "vi12_walk", "crown8"]
+    which = sys.argv[1:] or ["vi12", "vi12_heun", "vi12_walk", "crown8", "large24"]
     if "vi12" in which:
         make_vi12()
     if "vi12_heun" in which:
@@ -80,3 +98,5 @@ if __name__ == "__main__":
         make_vi12_walk()
     if "crown8" in which:
         make_crown8()
+    if "large24" in which:
+        make_large24()

@@ -132,3 +132,58 @@ def test_greedy_and_eval_sweeps_96x96x96x64(dpo, accel):
     np.testing.assert_array_equal(kind.reshape(-1)[nodes], o.kind.reshape(-1)[nodes])
     n_clear = check_sampled(o, V64, o.shape, nodes, W, tg, ag, E)
     print("  sampled", nodes.size, "non-tie", n_clear, flush=True)
+
+
+def test_downscaled_large_problem_against_the_oracle(dpo):
+    """The 96 x 96 x 96 x 64 problem's physics on 24 x 24 x 24 x 16 nodes,
+    solved with the large problem's schedule (value iteration to 1e-3, then
+    policy iteration to 1e-6) and on to the float32 floor (policy iteration to
+    3e-7), against the oracle's converged solution (stored, written by
+    tests/golden/make_golden.py): values within 1e-4*max(1,|V|) at every free
+    node, and the same controls away from ties.  The 1e-6 stop bounds the
+    one-step residual only; the iteration's slowest mode carries it ~200
+    sweeps, so that stop is ~2e-4 away and is checked against 5e-4."""
+    print("24^3 x 16 against the oracle", flush=True)
+    p = inputs.large_problem(accel=1e-3, n=(24, 24, 24, 16))
+    gold = np.load("tests/golden/large24_a1e-3.npz")
+    ref = gold["V"].astype(np.float64)
+    ctx = dpo.Context(p)
+    V = ctx.init_value()
+    ang, thr = ctx.empty_policy()
+    ctx.solve_vi(V, ang, thr, tol_rel=1e-3, max_sweeps=20000, check_every=16)
+    rc, st = ctx.solve_pi(V, ang, thr, tol_rel=1e-6, eval_sweeps=20, max_outer=3000)
+    assert rc == dpo.DPO_OK
+    o = Oracle(p)
+    free = o.kind == KIND_FREE
+    err = np.abs(host(V) - ref) / np.maximum(1.0, np.abs(ref))
+    print("  1e-6 stop: PI steps", st["sweeps"], "max relative difference", float(err[free].max()), flush=True)
+    assert err[free].max() <= 5e-4
+    rc, st = ctx.solve_pi(V, ang, thr, tol_rel=3e-7, eval_sweeps=20, max_outer=3000)
+    assert st["converged"] or st["stalled"]
+    Vg = host(V)
+    err = np.abs(Vg - ref) / np.maximum(1.0, np.abs(ref))
+    print("  3e-7 stop: PI steps", st["sweeps"], "max relative difference", float(err[free].max()), flush=True)
+    assert err[free].max() <= 1e-4
+    Vo, ao, to, margin = o.bellman_sweep(ref)
+    clear = free & (margin >= 1e-4 * np.maximum(1.0, np.abs(ref)))
+    tg, ag = host(thr), host(ang)
+    agree = (tg[clear] == to[clear]).mean()
+    print("  non-tie nodes", int(clear.sum()), "same throttle", float(agree), flush=True)
+    assert agree >= 0.999
+    # Near its minimum Q changes with the angle by far less than a float32
+    # ulp of V over ~0.03 rad, so the angle itself is not unique in float32:
+    # the device's control must attain the oracle's minimum instead, up to
+    # the search tolerance and twice the largest difference between the two
+    # value functions at the corners its feet can touch (the device chose its
+    # control on its own V).
+    from scipy.ndimage import maximum_filter
+    nodes = np.flatnonzero(free.reshape(-1))
+    q_dev = o.q_many(ref, nodes, tg.reshape(-1)[nodes], ag.reshape(-1)[nodes].astype(np.float64))
+    vo = Vo.reshape(-1)[nodes]
+
+    def box(a):
+        return maximum_filter(a, size=7, mode="nearest").reshape(-1)[nodes]
+
+    tol = 1e-5 * np.maximum(1.0, np.abs(vo)) + 1e-6 * box(np.abs(ref)) + 2.0 * box(np.abs(Vg - ref))
+    assert np.all(q_dev - vo <= tol), float(np.max((q_dev - vo) / tol))
+    assert ctx.value_at(V, inputs.X0) == pytest.approx(o.value_at(ref, inputs.X0), rel=1e-4)
