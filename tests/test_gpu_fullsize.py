@@ -187,3 +187,34 @@ def test_downscaled_large_problem_against_the_oracle(dpo):
     tol = 1e-5 * np.maximum(1.0, np.abs(vo)) + 1e-6 * box(np.abs(ref)) + 2.0 * box(np.abs(Vg - ref))
     assert np.all(q_dev - vo <= tol), float(np.max((q_dev - vo) / tol))
     assert ctx.value_at(V, inputs.X0) == pytest.approx(o.value_at(ref, inputs.X0), rel=1e-4)
+
+
+def test_residual_reduction_in_two_stages(dpo):
+    """A sweep over the unmasked 48^4 grid leaves ~20,000 workgroup partials,
+    which the residual reduction folds in two stages: the FP64 maximum of the
+    float32 differences is exact in any order, so the returned maxima equal
+    the oracle's recomputation from the same arrays bit for bit, and the sum
+    agrees to FP64 rounding."""
+    p = inputs.PI48
+    print("residual in two stages, 48^4", flush=True)
+    ctx = dpo.Context(p)
+    V32 = inputs.random_value(p, seed=51, low=0.0, high=30.0).astype(np.float32)
+    Vin = torch.as_tensor(V32).cuda()
+    Vout = torch.empty_like(Vin)
+    ang, thr = ctx.empty_policy()
+    resid = torch.zeros(5, dtype=torch.float64, device="cuda")
+    ctx.bellman_sweep(Vin, Vout, ang, thr, resid)
+    o = Oracle(p)
+
+    def check(before, after, r):
+        want = o.residual(host(before).astype(np.float64), host(after).astype(np.float64))
+        got = host(r)
+        assert got[0] == want["max_rel"] and got[2] == want["max_abs"]
+        assert got[1] == pytest.approx(want["sum_abs"], rel=1e-12)
+        assert got[3] == 0
+
+    check(Vin, Vout, resid)
+    E = torch.empty_like(Vin)
+    r2 = torch.zeros(5, dtype=torch.float64, device="cuda")
+    ctx.policy_eval_sweep(Vout, E, ang, thr, r2)
+    check(Vout, E, r2)
