@@ -196,6 +196,52 @@ def to_float32_floor(ctx, V, a, t, eval_sweeps, free):
     return out
 
 
+def sweep_times(ctx, V, reps=5):
+    """Event-timed average of one greedy sweep and one evaluation sweep (the
+    descriptors of that greedy sweep) from the value V, in ms."""
+    import torch
+
+    W = torch.empty_like(V)
+    ang, thr = ctx.empty_policy()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ctx.bellman_sweep(V, W, ang, thr)
+    ev0.record(stream)
+    for _ in range(reps):
+        ctx.bellman_sweep(V, W, ang, thr)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    greedy_ms = ev0.elapsed_time(ev1) / reps
+    ctx.policy_eval_sweep_last(V, W)
+    ev0.record(stream)
+    for _ in range(reps):
+        ctx.policy_eval_sweep_last(V, W)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return greedy_ms, ev0.elapsed_time(ev1) / reps
+
+
+def one_gpu_share(p, full_greedy_ms, full_eval_ms, gpus=8):
+    """The kernels on one GPU's share of the m-sharded grid at its real shape:
+    the top 64/gpus mass planes plus the ghost plane below them (the plane a
+    neighbour would send), after 200 value-iteration sweeps on the slab."""
+    from paper_2407_14675_amd import dpo
+
+    n = p["n"]
+    planes = n[3] // gpus
+    h_m = (p["hi"][3] - p["lo"][3]) / (n[3] - 1)
+    first = n[3] - planes - 1
+    q = dict(p, n=(n[0], n[1], n[2], planes + 1), lo=tuple(p["lo"][:3]) + (p["lo"][3] + first * h_m,),
+             name=p["name"] + f"_slab{planes}+1")
+    ctx = dpo.Context(q)
+    V = ctx.init_value()
+    a, t = ctx.empty_policy()
+    ctx.solve_vi(V, a, t, tol_rel=0.0, max_sweeps=200, check_every=200)
+    g, e = sweep_times(ctx, V)
+    return {"gpus": gpus, "grid": list(q["n"]), "nodes": ctx.N, "greedy_ms": g, "eval_ms": e,
+            "full_grid_greedy_ms_over_gpus": full_greedy_ms / gpus, "full_grid_eval_ms_over_gpus": full_eval_ms / gpus}
+
+
 def bench_large(accels=(1e-3,), with_seeded=True):
     """96 x 96 x 96 x 64 problems (dt 0.02, fuel weight 0.1): value iteration
     to 1e-3 then policy iteration to 1e-6 (the reference solution); then, for
@@ -230,6 +276,10 @@ def bench_large(accels=(1e-3,), with_seeded=True):
             "V_x0": ctx.value_at(V, inputs.X0),
         }
         rec["to_float32_floor"] = to_float32_floor(ctx, V, a, t, 20, free)
+        if accel == accels[0]:
+            g, e = sweep_times(ctx, V)
+            rec["sweep_ms"] = {"greedy": g, "eval": e}
+            rec["one_gpu_share"] = one_gpu_share(p, g, e)
         log(f"bench: large a={accel}: {rec}")
         # plain policy iteration from V0 (same stop rule), compared with the reference
         Vp = ctx.init_value()
