@@ -512,7 +512,7 @@ __global__ __launch_bounds__(kBlock) void k_feedback(SweepArgs a, const double* 
   const int c = kWave ? (int)(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) : (int)(blockIdx.x * kBlock + threadIdx.x);
   if (c >= n) return;  // wave-uniform in the wave mode
   double y[4];
-  for (int k = 0; k < 4; k++) y[k] = states[4 * c + k];
+  for (int k = 0; k < 4; k++) y[k] = states[4 * (size_t)c + k];
   Choice ch;
   feedback_at<kWave>(a, y, tau, ch);
   if (kWave && (threadIdx.x & 63) != 0) return;
@@ -572,7 +572,7 @@ __global__ __launch_bounds__(kBlock) void k_simulate(SweepArgs a, double* __rest
   if (c >= n) return;  // wave-uniform in the wave mode
   const bool lead = !kWave || (threadIdx.x & 63) == 0;
   double y[4];
-  for (int k = 0; k < 4; k++) y[k] = states[4 * c + k];
+  for (int k = 0; k < 4; k++) y[k] = states[4 * (size_t)c + k];
   if (traj && lead)
     for (int k = 0; k < 4; k++) traj[4 * (size_t)c + k] = y[k];
   const double h = tau / (double)substeps;
@@ -590,7 +590,7 @@ __global__ __launch_bounds__(kBlock) void k_simulate(SweepArgs a, double* __rest
       for (int k = 0; k < 4; k++) traj[4 * (at + (size_t)n) + k] = y[k];
   }
   if (lead)
-    for (int k = 0; k < 4; k++) states[4 * c + k] = y[k];
+    for (int k = 0; k < 4; k++) states[4 * (size_t)c + k] = y[k];
 }
 
 // Reachability seed: FP64 Q1 value of the coarse V at every fine node.
@@ -658,7 +658,7 @@ __global__ __launch_bounds__(kBlock) void k_probe_interp(const float* __restrict
   int i[4];
   float off[4];
   for (int k = 0; k < 4; k++) {
-    const float sk = s[4 * c + k];
+    const float sk = s[4 * (size_t)c + k];
     float fl = floorf(sk);
     fl = fminf(fmaxf(fl, 0.0f), (float)(G.n[k] - 1));
     i[k] = (int)fl;
@@ -689,7 +689,7 @@ __global__ __launch_bounds__(kBlock) void k_probe_q(SweepArgs a, const int* __re
     float off[4];
     if (heun) foot_off<true>(T, H, th, sn, cs, off);
     else foot_off<false>(T, H, th, sn, cs, off);
-    for (int k = 0; k < 4; k++) off_out[4 * c + k] = off[k];
+    for (int k = 0; k < 4; k++) off_out[4 * (size_t)c + k] = off[k];
   }
 }
 

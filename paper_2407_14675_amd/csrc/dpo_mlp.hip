@@ -154,9 +154,9 @@ __global__ __launch_bounds__(256) void k_mlp_forward(MlpArgs a) {
 #pragma unroll
       for (int i = 0; i < 4; i++)
         if (i == r) {
-          a.y[3 * s + 0] = y[i][0];
-          a.y[3 * s + 1] = y[i][1];
-          a.y[3 * s + 2] = y[i][2];
+          a.y[3 * (size_t)s + 0] = y[i][0];
+          a.y[3 * (size_t)s + 1] = y[i][1];
+          a.y[3 * (size_t)s + 2] = y[i][2];
         }
     }
   }

@@ -218,3 +218,40 @@ def test_residual_reduction_in_two_stages(dpo):
     r2 = torch.zeros(5, dtype=torch.float64, device="cuda")
     ctx.policy_eval_sweep(Vout, E, ang, thr, r2)
     check(Vout, E, r2)
+
+
+def test_largest_grid(dpo):
+    """The largest grid the library takes: 256 x 256 x 255 x 64 nodes
+    (1,069,547,520, just under the 2^30 limit; 4.3 GB per value buffer), one
+    greedy sweep (scan 64 + golden 12, descriptors written) and one
+    evaluation sweep from a random value field, checked against the oracle
+    at 1000 sampled free nodes and 1000 more among the last 2^20 node
+    indices, where 32-bit index arithmetic would overflow first."""
+    n = (256, 256, 255, 64)
+    p = inputs.with_grid(inputs.PI48, n)
+    print("largest grid", n, flush=True)
+    ctx = dpo.Context(p)
+    N = ctx.N
+    assert N == 256 * 256 * 255 * 64
+    g = torch.Generator(device="cuda").manual_seed(71)
+    V = torch.rand((n[3], n[2], n[1], n[0]), generator=g, device="cuda") * 30.0
+    W = V.clone()
+    E = V.clone()
+    ang, thr = ctx.empty_policy()
+    ctx.bellman_sweep(V, W, ang, thr)
+    ctx.policy_eval_sweep_last(V, E)
+    kind = host(ctx.kind()).reshape(-1)
+    rng = np.random.default_rng(72)
+    picks = []
+    for lo in (0, N - (1 << 20)):
+        cand = np.unique(rng.integers(lo, N, size=20000))
+        cand = cand[kind[cand] == KIND_FREE]
+        picks.append(rng.choice(cand, size=1000, replace=False))
+    nodes = np.sort(np.concatenate(picks)).astype(np.int64)
+    o = Oracle(p)
+    np.testing.assert_array_equal(kind[nodes], o.kind.reshape(-1)[nodes])
+    V64 = host(V).astype(np.float64)
+    n_clear = check_sampled(o, V64, o.shape, nodes, host(W), host(thr), host(ang), host(E))
+    print("  sampled", nodes.size, "non-tie", n_clear, "largest index", int(nodes[-1]), flush=True)
+    del V, W, E, ang, thr
+    torch.cuda.empty_cache()
