@@ -43,8 +43,8 @@ VALU_PEAK_TFLOPS = 157.3
 GREEDY_BYTES_PER_NODE = 27
 # the evaluation-sweep kernel that runs for each descriptor form (bytes per
 # free node, the per-node form: 18 + 2 per fixed node)
-EVAL_KERNEL_BY_BYTES = {24: "k_policy_eval_desc<0>", 22: "k_policy_eval_d16<false, 0>",
-                        18: "k_policy_eval_d16<true, 0>"}
+EVAL_KERNEL_BY_BYTES = {24: "k_policy_eval_desc<0>", 22: "k_policy_eval_d16<false, 0, 1>",
+                        18: "k_policy_eval_d16<true, 0, 1>"}
 # Gather bytes of one evaluation done naively: 16 float32 corners.
 GATHER_BYTES_PER_EVAL = 64
 

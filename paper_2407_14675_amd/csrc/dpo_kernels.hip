@@ -307,17 +307,20 @@ __global__ __launch_bounds__(kBlock) void k_policy_eval_desc(SweepArgs a) {
 // free node with the free list (coordinates 4, code 2, weights 8), 10 bytes
 // per node without it (kDense: every node is visited in order, fixed ones
 // carry kDescSkip and are left alone, and the node index is the thread's).
-template <bool kDense, int kNt>
+// kNpt nodes per thread: 2 when the data streams from HBM (more loads in
+// flight per wave), 1 when it is cache-resident (twice the workgroups, a
+// smaller last partial round on the CUs).
+template <bool kDense, int kNt, int kNpt>
 __global__ __launch_bounds__(kBlock) void k_policy_eval_d16(SweepArgs a) {
   typedef float nt_f2 __attribute__((ext_vector_type(2)));
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int t0 = tile * (kDescNpt * kBlock) + threadIdx.x;
+  const int t0 = tile * (kNpt * kBlock) + threadIdx.x;
   const int count = kDense ? a.G.n[0] * a.G.n[1] * a.G.n[2] * a.G.n[3] : a.n_free;
-  uint32_t packed[kDescNpt];
-  uint16_t code[kDescNpt];
-  float2 w[kDescNpt];
+  uint32_t packed[kNpt];
+  uint16_t code[kNpt];
+  float2 w[kNpt];
 #pragma unroll
-  for (int k = 0; k < kDescNpt; k++) {
+  for (int k = 0; k < kNpt; k++) {
     const int t = t0 + k * kBlock;
     if (t < count) {
       if (kNt & 1) {
@@ -333,7 +336,7 @@ __global__ __launch_bounds__(kBlock) void k_policy_eval_d16(SweepArgs a) {
     }
   }
 #pragma unroll
-  for (int k = 0; k < kDescNpt; k++) {
+  for (int k = 0; k < kNpt; k++) {
     const int t = t0 + k * kBlock;
     if (t >= count) continue;
     if (kDense && code[k] == kDescSkip) continue;
@@ -814,11 +817,11 @@ hipError_t launch_policy_eval_desc(const SweepArgs& a, bool streamed, hipStream_
 hipError_t launch_policy_eval_desc16(const SweepArgs& a, int format, bool streamed, hipStream_t s) {
   if (format == 2) {
     const long long N = (long long)a.G.n[0] * a.G.n[1] * a.G.n[2] * a.G.n[3];
-    if (streamed) DPO_LAUNCH((k_policy_eval_d16<true, 3>), blocks_for(N, kDescNpt * kBlock), kBlock, s, a);
-    DPO_LAUNCH((k_policy_eval_d16<true, 0>), blocks_for(N, kDescNpt * kBlock), kBlock, s, a);
+    if (streamed) DPO_LAUNCH((k_policy_eval_d16<true, 3, 2>), blocks_for(N, 2 * kBlock), kBlock, s, a);
+    DPO_LAUNCH((k_policy_eval_d16<true, 0, 1>), blocks_for(N, kBlock), kBlock, s, a);
   }
-  if (streamed) DPO_LAUNCH((k_policy_eval_d16<false, 3>), blocks_for(a.n_free, kDescNpt * kBlock), kBlock, s, a);
-  DPO_LAUNCH((k_policy_eval_d16<false, 0>), blocks_for(a.n_free, kDescNpt * kBlock), kBlock, s, a);
+  if (streamed) DPO_LAUNCH((k_policy_eval_d16<false, 3, 2>), blocks_for(a.n_free, 2 * kBlock), kBlock, s, a);
+  DPO_LAUNCH((k_policy_eval_d16<false, 0, 1>), blocks_for(a.n_free, kBlock), kBlock, s, a);
 }
 
 hipError_t launch_resid_final(const double* partial, int nblocks, double* stage, double* out, hipStream_t s) {
