@@ -255,3 +255,38 @@ def test_largest_grid(dpo):
     print("  sampled", nodes.size, "non-tie", n_clear, "largest index", int(nodes[-1]), flush=True)
     del V, W, E, ang, thr
     torch.cuda.empty_cache()
+
+
+def test_converged_96x96x96x64_is_a_fixed_point_of_the_oracle_operator(dpo):
+    """The full-size solve has no oracle solution (about eight days on one
+    core), so its converged value is checked a posteriori: value iteration
+    to 1e-3, policy iteration to 1e-6 and on to the float32 floor (3e-7 or a
+    stall), then one FP64 Bellman application of the oracle at 100,000
+    sampled free nodes (half where V < 0.98 M) must move the device's value
+    by no more than one evaluation's tolerance (1e-5*max(1,|V|) plus the
+    float32 rounding of the corners), and the device's throttle must be the
+    oracle's at the non-tie nodes."""
+    p = inputs.large_problem(accel=1e-3)
+    print("96^3 x 64 converged, a posteriori", flush=True)
+    ctx = dpo.Context(p)
+    V = ctx.init_value()
+    ang, thr = ctx.empty_policy()
+    ctx.solve_vi(V, ang, thr, tol_rel=1e-3, max_sweeps=20000, check_every=16)
+    rc, st = ctx.solve_pi(V, ang, thr, tol_rel=1e-6, eval_sweeps=20, max_outer=3000)
+    assert rc == dpo.DPO_OK
+    rc, st = ctx.solve_pi(V, ang, thr, tol_rel=3e-7, eval_sweeps=20, max_outer=3000)
+    assert st["converged"] or st["stalled"]
+    kind = host(ctx.kind())
+    V64 = host(V).astype(np.float64)
+    nodes = sample_free(kind, 100000, seed=97, V=V64, below=inputs.MASK_THRESHOLD_FRAC * p["M"])
+    o = Oracle(p)
+    Vo, ao, to, margin = o.bellman_nodes(V64, nodes)
+    v = V64.reshape(-1)[nodes]
+    rel = np.abs(Vo - v) / np.maximum(1.0, np.abs(v))
+    clear = margin >= 1e-4 * np.maximum(1.0, np.abs(Vo))
+    agree = float((host(thr).reshape(-1)[nodes][clear] == to[clear]).mean())
+    print(f"  FP64 one-step residual at {nodes.size} nodes: max {rel.max():.2e}, 99.9 % {np.quantile(rel, 0.999):.2e};"
+          f" non-tie {int(clear.sum())}, same throttle {agree}", flush=True)
+    tol = 1e-5 * np.maximum(1.0, np.abs(v)) + 1e-6 * corner_max(V64, o.shape, nodes)
+    assert np.all(np.abs(Vo - v) <= tol), float(np.max(np.abs(Vo - v) / tol))
+    assert agree >= 0.999
