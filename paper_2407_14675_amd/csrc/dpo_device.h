@@ -208,6 +208,40 @@ __device__ inline float cell_value(const float* __restrict__ p, const Grid& G, c
   return lerp(e0, e1, t[3]);
 }
 
+// The 16 corners of the cell a node's last evaluation read, kept in
+// registers: the feet of one node's controls mostly share a cell (on the
+// crown problem a step moves a foot by less than a tenth of a cell), so a
+// search reloads the corners only when the cell changes.  key: offset of the
+// cell's lowest corner in V (-1 = empty); the lerps are cell_value's, in the
+// same order, so the value is the same bit for bit.
+struct CornerCache {
+  int key;
+  CornerPair v[8];
+};
+
+__device__ inline float cell_value_cached(const float* __restrict__ V, const Grid& G, int key, const float t[4], int s3,
+                                          CornerCache& cc) {
+  if (key != cc.key) {
+    const int s1 = G.st[1], s2 = G.st[2];
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+      const int o = ((e & 1) ? s1 : 0) + ((e & 2) ? s2 : 0) + ((e & 4) ? s3 : 0);
+      cc.v[e] = *reinterpret_cast<const CornerPair*>(V + key + o);
+    }
+    cc.key = key;
+  }
+  float c[8];
+#pragma unroll
+  for (int e = 0; e < 8; e++) c[e] = lerp(cc.v[e].lo, cc.v[e].hi, t[0]);
+  const float d0 = lerp(c[0], c[1], t[1]);
+  const float d1 = lerp(c[2], c[3], t[1]);
+  const float d2 = lerp(c[4], c[5], t[1]);
+  const float d3 = lerp(c[6], c[7], t[1]);
+  const float e0 = lerp(d0, d1, t[2]);
+  const float e1 = lerp(d2, d3, t[2]);
+  return lerp(e0, e1, t[3]);
+}
+
 // Q1 interpolation of V at s = i + off (paper Section 3: multilinear I[V],
 // M outside the closed box).
 template <bool kSnap = false>
@@ -319,6 +353,23 @@ __device__ inline float q_step(const float* __restrict__ V, const Grid& G, const
   float off[4];
   foot_off<kHeun>(T, H, thr, sn, cs, off);
   return fmaf(P.gamma, interp_off<kSnap>(V, G, T.i, off, P.M), (thr ? P.q_thr : P.q_coast) + qx);
+}
+
+// q_step through a node's corner cache (the cell's corners are loaded only
+// when the foot leaves the cell of the previous evaluation).
+template <bool kHeun>
+__device__ inline float q_step_cached(const float* __restrict__ V, const Grid& G, const Phys& P, const NodeTerms& T,
+                                      const HeunTerms& H, int thr, float sn, float cs, float qx, CornerCache& cc) {
+  float off[4];
+  foot_off<kHeun>(T, H, thr, sn, cs, off);
+  int base[4];
+  float t[4];
+  float I = P.M;
+  if (foot_cell(G, T.i, off, base, t)) {
+    const int s3 = (G.periodic3 && base[3] == G.n[3] - 1) ? -base[3] * G.st[3] : G.st[3];
+    I = cell_value_cached(V, G, base[0] + base[1] * G.st[1] + base[2] * G.st[2] + base[3] * G.st[3], t, s3, cc);
+  }
+  return fmaf(P.gamma, I, (thr ? P.q_thr : P.q_coast) + qx);
 }
 
 // The crown problem's orbital-element running cost at a physical state x =

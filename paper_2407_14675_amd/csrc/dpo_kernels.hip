@@ -138,9 +138,10 @@ __device__ inline void node_heun(const SweepArgs& a, const int i[4], HeunTerms& 
   heun_terms(a.G, a.P, x, a.P.dt, H);
 }
 
-// ---- direct path: every evaluation gathers its 16 corners from V.
-// Used for any problem and for the Heun foot; the fast path below covers
-// the orbit workloads with the Euler foot.
+// ---- direct path: every evaluation forms its foot and cell; the 16 corners
+// come from V when the cell differs from the previous evaluation's (a
+// per-node corner cache).  Used for any problem and for the Heun foot; the
+// fast path below covers the orbit workloads with the Euler foot.
 template <int kMode, bool kHeun>
 __global__ __launch_bounds__(kBlock) void k_sweep_direct(SweepArgs a) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -154,8 +155,10 @@ __global__ __launch_bounds__(kBlock) void k_sweep_direct(SweepArgs a) {
     if (kHeun) node_heun(a, T.i, H);
     const float* __restrict__ V = a.V_in;
     const float qx = a.qnode ? a.qnode[j] : 0.0f;
-    auto qf = [&](float sn, float cs) { return q_step<kHeun>(V, a.G, a.P, T, H, 1, sn, cs, qx); };
-    const float qc = q_step<kHeun>(V, a.G, a.P, T, H, 0, 0.0f, 1.0f, qx);
+    CornerCache cc;
+    cc.key = -1;
+    auto qf = [&](float sn, float cs) { return q_step_cached<kHeun>(V, a.G, a.P, T, H, 1, sn, cs, qx, cc); };
+    const float qc = q_step_cached<kHeun>(V, a.G, a.P, T, H, 0, 0.0f, 1.0f, qx, cc);
     const float vin = V[j];
     Choice ch;
     if (kMode == 0) table_search(qf, a, qc, ch);
