@@ -683,6 +683,10 @@ def main():
         }
         converge["to_float32_floor"] = to_float32_floor(ctx, Vc1.clone(), ac.clone(), tc.clone(), E,
                                                          ctx.kind() == 0)
+        # the time at which the solve meets 1e-4 against the oracle's converged
+        # solution (tests/test_gpu_converged48.py: the 1e-6 stop is 1.05e-4 away
+        # at its worst sampled node, the floor 9.1e-6)
+        converge["seconds_to_float32_floor"] = converge["seconds"] + converge["to_float32_floor"]["extra_seconds"]
         log(f"bench: converge {converge}")
 
     variants = None

@@ -19,6 +19,13 @@ large24_a1e-3.npz   the 96 x 96 x 96 x 64 problem's physics (dt = 0.02,
               modified policy iteration (20 evaluation sweeps) until the
               greedy step's relative residual is below 1e-9; V and angles
               stored as float32.
+pi48_masked.npz   the benchmark's 48^4 workload (scan 64 + golden 12, reduced
+              grid): mask from the oracle's 12^4 value iteration (as above) at
+              0.98 M dilated by one cell, then modified policy iteration (20
+              evaluation sweeps) from V0 until the greedy step's relative
+              residual is below 1e-9; stored: the mask, and V, throttle and
+              angle at 100,000 free active nodes drawn without replacement
+              (seed 48), V(x0).
 crown8_table72.npz   the paper's Example 1 problem (crown grid, theta
               periodic, orbital-element cost, discount, Heun foot, 72 angles
               + coast) on 8 x 6 x 6 x 8 nodes, value iteration until the
@@ -88,8 +95,28 @@ def make_large24():
     print("24^3 x 16: VI sweeps", vi["sweeps"], "PI steps", pi["outer"], "V(x0)", o.value_at(pi["V"], inputs.X0))
 
 
+def make_pi48():
+    from oracle.core import KIND_FREE, mask_from_coarse
+
+    c = Oracle(inputs.VI12)
+    vi = c.solve_vi(tol_abs=inputs.VI12_TOL_ABS, max_sweeps=100000)
+    assert vi["converged"], vi
+    p = inputs.PI48
+    mask = mask_from_coarse(inputs.VI12, vi["V"], p, inputs.MASK_DILATE, thresh=inputs.MASK_THRESHOLD_FRAC * p["M"])
+    o = Oracle(p, mask=mask)
+    pi = o.solve_pi(tol_abs=0.0, tol_rel=1e-9, eval_sweeps=inputs.EVAL_SWEEPS, max_outer=100000)
+    assert pi["converged"], pi["resid"]
+    free = np.flatnonzero((o.kind == KIND_FREE).reshape(-1))
+    nodes = np.sort(np.random.default_rng(48).choice(free, size=100000, replace=False)).astype(np.int64)
+    np.savez_compressed(os.path.join(HERE, "pi48_masked.npz"), mask=mask, nodes=nodes,
+                        V=pi["V"].reshape(-1)[nodes], angle=pi["angle"].reshape(-1)[nodes].astype(np.float32),
+                        thr=pi["thr"].reshape(-1)[nodes], V_x0=np.float64(o.value_at(pi["V"], inputs.X0)),
+                        pi_outer=np.int64(pi["outer"]), free_nodes=np.int64(free.size))
+    print("48^4 masked: free active nodes", free.size, "PI steps", pi["outer"], "V(x0)", o.value_at(pi["V"], inputs.X0))
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["vi12", "vi12_heun", "vi12_walk", "crown8", "large24"]
+    which = sys.argv[1:] or ["vi12", "vi12_heun", "vi12_walk", "crown8", "large24", "pi48"]
     if "vi12" in which:
         make_vi12()
     if "vi12_heun" in which:
@@ -100,3 +127,5 @@ if __name__ == "__main__":
         make_crown8()
     if "large24" in which:
         make_large24()
+    if "pi48" in which:
+        make_pi48()
