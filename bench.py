@@ -301,6 +301,29 @@ def bench_large(accels=(1e-3,), with_seeded=True):
         rec["pi_from_v0"]["max_rel_diff_vs_reference"], rec["pi_from_v0"]["nodes_over_1e-4"] = rel_diff(Vp, V, free)
         rec["pi_from_v0"]["to_float32_floor"] = to_float32_floor(ctx, Vp, ap, tp, 20, free, ref=V)
         del Vp, ap, tp
+        if accel == accels[0]:
+            # walk-seeded: the seeds are the previous greedy step's own angles
+            # (the paper's warm start applied to the continuous search)
+            ctx.set_search(inputs.SEEDED)
+            Vw = ctx.init_value()
+            aw, tw = ctx.empty_policy()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, stw = ctx.solve_pi(Vw, aw, tw, tol_rel=1e-6, eval_sweeps=20, max_outer=3000, seed=aw)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            rec["walk_seeded"] = {"seconds": sec, "outer": stw["sweeps"], "verify_steps": stw["verify_steps"],
+                                  "evals": stw["evals"], "converged": bool(stw["converged"]),
+                                  "speedup_vs_plain_pi": rec["pi_from_v0"]["seconds"] / sec,
+                                  "eval_ratio_vs_plain_pi": rec["pi_from_v0"]["evals"] / max(1, stw["evals"])}
+            rec["walk_seeded"]["max_rel_diff_vs_reference"], rec["walk_seeded"]["nodes_over_1e-4"] = rel_diff(Vw, V, free)
+            ctx.set_search(inputs.SCAN_GOLDEN)
+            rec["walk_seeded"]["to_float32_floor"] = fl = to_float32_floor(ctx, Vw, aw, tw, 20, free, ref=V)
+            plain = rec["pi_from_v0"]
+            rec["walk_seeded"]["speedup_vs_plain_pi_to_floor"] = (
+                (plain["seconds"] + plain["to_float32_floor"]["extra_seconds"]) / (sec + fl["extra_seconds"]))
+            log(f"bench: large a={accel} walk-seeded {rec['walk_seeded']}")
+            del Vw, aw, tw
         if with_seeded:
             if net is None:
                 nodes = ctx.feasible_nodes(V, inputs.MLP_FEASIBLE_FRAC * p["M"])
