@@ -481,7 +481,9 @@ int dpo_mlp_grad(dpo_mlp* m, const float* x, const float* tgt, int64_t n, float*
  * (host int32[n] of indices in [0, n), checked; NULL = 0..n-1), batch b taking
  * positions [b*batch, min(n, (b+1)*batch)).  loss_hist (device
  * float[ceil(n/batch)], nullable) receives each batch's mean loss before its
- * step.  1 <= batch <= 65536. */
+ * step.  1 <= batch <= 65536.  Asynchronous on stream: perm is copied into
+ * the context before the call returns (the caller may reuse it at once), and
+ * the call waits only for the previous call's copy of its order. */
 int dpo_mlp_train(dpo_mlp* m, const float* x, const float* tgt, int64_t n, const int32_t* perm, int32_t batch,
                   float* loss_hist, void* stream);
 

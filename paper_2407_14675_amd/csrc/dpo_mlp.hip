@@ -517,6 +517,8 @@ struct dpo_mlp {
   int partial_tiles = 0;
   int* perm = nullptr;
   int64_t perm_cap = 0;
+  int* perm_host = nullptr;           // pinned staging of the epoch's order (host copy of perm)
+  hipEvent_t perm_copied = nullptr;   // the staging buffer's last upload has completed
   int max_blocks = 512;
   double lr = 1e-3, b1 = 0.9, b2 = 0.999, eps = 1e-8;
   int64_t step = 0;
@@ -555,11 +557,21 @@ int ensure_partial(dpo_mlp* m, int tiles) {
 }
 
 int ensure_perm(dpo_mlp* m, int64_t n) {
+  if (!m->perm_copied && hipEventCreateWithFlags(&m->perm_copied, hipEventDisableTiming) != hipSuccess) {
+    m->perm_copied = nullptr;
+    return mfail(m, DPO_EHIP, "permutation event");
+  }
   if (n <= m->perm_cap) return DPO_OK;
+  // the buffers may still be in use by steps and an upload queued by the last call
+  if (hipDeviceSynchronize() != hipSuccess) return mfail(m, DPO_EHIP, "permutation buffer");
   if (m->perm) (void)hipFree(m->perm);
+  if (m->perm_host) (void)hipHostFree(m->perm_host);
   m->perm = nullptr;
+  m->perm_host = nullptr;
   m->perm_cap = 0;
-  if (hipMalloc(&m->perm, (size_t)n * sizeof(int)) != hipSuccess) return mfail(m, DPO_ENOMEM, "permutation buffer");
+  if (hipMalloc(&m->perm, (size_t)n * sizeof(int)) != hipSuccess ||
+      hipHostMalloc(&m->perm_host, (size_t)n * sizeof(int), hipHostMallocDefault) != hipSuccess)
+    return mfail(m, DPO_ENOMEM, "permutation buffer");
   m->perm_cap = n;
   return DPO_OK;
 }
@@ -646,6 +658,11 @@ void dpo_mlp_destroy(dpo_mlp* m) {
   (void)hipFree(m->w2t);
   (void)hipFree(m->partial);
   (void)hipFree(m->perm);
+  if (m->perm_copied) {
+    (void)hipEventSynchronize(m->perm_copied);
+    (void)hipEventDestroy(m->perm_copied);
+  }
+  if (m->perm_host) (void)hipHostFree(m->perm_host);
   delete m;
 }
 
@@ -736,7 +753,15 @@ int dpo_mlp_train(dpo_mlp* m, const float* x, const float* tgt, int64_t n, const
       if (perm[t] < 0 || perm[t] >= n) return mfail(m, DPO_EINVAL, "perm entries must lie in [0, n)");
     rc = ensure_perm(m, n);
     if (rc != DPO_OK) return rc;
-    MLP_HIP(m, hipMemcpyAsync(m->perm, perm, (size_t)n * sizeof(int), hipMemcpyHostToDevice, MS(stream)));
+    // Stage the order in pinned memory so that the upload is asynchronous and
+    // the caller may prepare the next epoch's order while this one trains.
+    // The previous call's upload must have left the staging buffer first; it
+    // runs after that call's steps in stream order, into a device buffer those
+    // steps no longer read.
+    MLP_HIP(m, hipEventSynchronize(m->perm_copied));
+    std::memcpy(m->perm_host, perm, (size_t)n * sizeof(int));
+    MLP_HIP(m, hipMemcpyAsync(m->perm, m->perm_host, (size_t)n * sizeof(int), hipMemcpyHostToDevice, MS(stream)));
+    MLP_HIP(m, hipEventRecord(m->perm_copied, MS(stream)));
     dperm = m->perm;
   }
   for (int64_t b = 0; b < steps; b++) {
@@ -756,8 +781,6 @@ int dpo_mlp_train(dpo_mlp* m, const float* x, const float* tgt, int64_t n, const
     r.c2 = (float)(1.0 / (1.0 - std::pow(m->b2, (double)m->step)));
     MLP_HIP(m, launch_mlp_reduce(r, MS(stream)));
   }
-  // the host permutation buffer is reused by the next call
-  if (perm) MLP_HIP(m, hipStreamSynchronize(MS(stream)));
   return DPO_OK;
 }
 
