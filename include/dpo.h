@@ -294,14 +294,14 @@ int dpo_solve_vi(dpo_ctx* ctx, float* V, float* pol_angle, uint8_t* pol_thr, dou
  * Returns DPO_ENOCONV after max_outer greedy steps, or when 32 full-search
  * greedy steps in a row bring no new lowest residual (stats->stalled). */
 /* Exact policy evaluation (eq:p_eval solved as the sparse linear system
- * (I - exp(-lambda dt) P) v = b of Section 3, by restarted GMRES(32), the
+ * (I - exp(-lambda dt) P) v = b of Section 3, by restarted GMRES(16), the
  * solver the paper names): V (device, N) holds the fixed nodes' values and,
  * at free nodes, the initial guess on entry and the solution on exit; the
  * frozen policy is pol_angle / pol_thr.  The operator is applied matrix-free
  * by the frozen-policy sweep without its affine part; vectors are float32,
  * dot products FP64 in a fixed order.  Stops when the node-wise relative
  * residual max_j |b - A v|_j / max(1, |v_j|) <= tol_rel (checked between
- * restart cycles; a cycle ends after 32 steps or once its 2-norm residual
+ * restart cycles; a cycle ends after 16 steps or once its 2-norm residual
  * has fallen 100-fold) or after max_iter operator applications
  * (DPO_ENOCONV, V holds the last iterate).  *matvecs and
  * *resid_rel (host, nullable): operator applications and the final

@@ -513,7 +513,7 @@ int sweep_eval_desc(dpo_ctx* c, const float* Vin, float* Vout, hipStream_t s) {
 // max_j |b - A v|_j / max(1, |v_j|), checked between cycles; a cycle ends
 // after m steps or once its 2-norm residual has fallen by kCycleDrop.
 
-constexpr int kGmresRestart = 32;
+constexpr int kGmresRestart = 16;
 constexpr double kCycleDrop = 1e-2;
 constexpr double kExactEvalTol = 5e-7;  // node-wise residual of the evaluations inside policy iteration
 
