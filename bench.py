@@ -794,6 +794,9 @@ def main():
             "naive_gather_bytes_per_eval": GATHER_BYTES_PER_EVAL,
             "naive_gather_frac": value * GATHER_BYTES_PER_EVAL / 1e9 / HBM_PEAK_GBS,
         },
+        "setup": {"seconds": setup_s,
+                  "what": "12^4 value iteration for the mask, mask and dilation, context creation "
+                          "(classification, compaction, tables); not in the timed steps"},
         "time_to_converge": converge,
         "paper_variants": variants,
         "paper_example1": example1,
