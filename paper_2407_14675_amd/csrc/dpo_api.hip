@@ -540,6 +540,14 @@ int host_dots(dpo_ctx* c, const float* basis, int k, const float* w, double* h, 
   return DPO_OK;
 }
 
+// w -= basis coef (k terms) and *ww = |w|^2 of the result, read back (synchronises s)
+int axpys_norm(dpo_ctx* c, float* w, const float* basis, int k, const double* coef, double* ww, hipStream_t s) {
+  HIP_TRY(c, launch_axpys(w, basis, k, (size_t)c->N, coef, (int)c->N, s, c->kpart, c->kdots));
+  HIP_TRY(c, hipMemcpyAsync(ww, c->kdots, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  return DPO_OK;
+}
+
 int gmres_eval(dpo_ctx* c, float* V, const float* ang, const uint8_t* thr, double tol, int max_iter, int64_t* matvecs,
                double* rel_out, hipStream_t s) {
   const int m = kGmresRestart;
@@ -600,15 +608,13 @@ int gmres_eval(dpo_ctx* c, float* V, const float* ang, const uint8_t* thr, doubl
       if ((rc = host_dots(c, basis, k + 2, w, h1.data(), s)) != DPO_OK) return rc;
       const double before = std::sqrt(std::max(h1[k + 1], 0.0));
       HIP_TRY(c, hipMemcpyAsync(c->kcoef, h1.data(), sizeof(double) * (k + 1), hipMemcpyHostToDevice, s));
-      HIP_TRY(c, launch_axpys(w, basis, k + 1, ld, c->kcoef, N, s));
       double ww = 0;
-      if ((rc = host_dots(c, w, 1, w, &ww, s)) != DPO_OK) return rc;
+      if ((rc = axpys_norm(c, w, basis, k + 1, c->kcoef, &ww, s)) != DPO_OK) return rc;
       std::fill(h2.begin(), h2.end(), 0.0);
       if (std::sqrt(ww) < 0.7071067811865476 * before) {
         if ((rc = host_dots(c, basis, k + 1, w, h2.data(), s)) != DPO_OK) return rc;
         HIP_TRY(c, hipMemcpyAsync(c->kcoef, h2.data(), sizeof(double) * (k + 1), hipMemcpyHostToDevice, s));
-        HIP_TRY(c, launch_axpys(w, basis, k + 1, ld, c->kcoef, N, s));
-        if ((rc = host_dots(c, w, 1, w, &ww, s)) != DPO_OK) return rc;
+        if ((rc = axpys_norm(c, w, basis, k + 1, c->kcoef, &ww, s)) != DPO_OK) return rc;
       }
       const double hn = std::sqrt(ww);
       for (int i = 0; i <= k; i++) H[(size_t)i * m + k] = h1[i] + h2[i];

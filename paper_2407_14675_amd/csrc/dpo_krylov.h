@@ -23,8 +23,10 @@ hipError_t launch_dots(const float* basis, int k, size_t ld, const float* w, int
                        hipStream_t s);
 // out[0] = max_j |r_j| / max(1, |x_j|) (partial: kStreamBlocks doubles)
 hipError_t launch_relmax(const float* r, const float* x, int N, double* partial, double* out, hipStream_t s);
-// w -= sum_i coef[i] basis_i, i < k <= kMaxBasis
-hipError_t launch_axpys(float* w, const float* basis, int k, size_t ld, const double* coef, int N, hipStream_t s);
+// w -= sum_i coef[i] basis_i, i < k <= kMaxBasis; with nrm_out (device, one
+// double; partial: kStreamBlocks * kDotGroup doubles) also |w|^2 of the result
+hipError_t launch_axpys(float* w, const float* basis, int k, size_t ld, const double* coef, int N, hipStream_t s,
+                       double* partial = nullptr, double* nrm_out = nullptr);
 // dst = s * src
 hipError_t launch_scale(const float* src, double s, float* dst, int N, hipStream_t st);
 // dst[j] = src[j] at the free nodes j

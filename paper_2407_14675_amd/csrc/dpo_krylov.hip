@@ -140,16 +140,32 @@ __global__ __launch_bounds__(kBlock) void k_dots_final(const double* __restrict_
   if (threadIdx.x == 0) out[i] = red[0];
 }
 
-// w -= sum_i coef[i] * basis_i  (k <= kMaxBasis terms, FP64 sum per element)
+// w -= sum_i coef[i] * basis_i  (k <= kMaxBasis terms, FP64 sum per element);
+// with nrm_partial, also the FP64 sum of squares of the new w per workgroup
+// (nrm_partial[blockIdx.x * kDotGroup], the layout k_dots_final reads).
 __global__ __launch_bounds__(kBlock) void k_axpys(float* __restrict__ w, const float* __restrict__ basis, int k,
-                                                  size_t ld, const double* __restrict__ coef, int N) {
+                                                  size_t ld, const double* __restrict__ coef, int N,
+                                                  double* __restrict__ nrm_partial) {
   __shared__ double c[kMaxBasis];
+  __shared__ double red[kBlock / 64];
   for (int i = threadIdx.x; i < k; i += kBlock) c[i] = coef[i];
   __syncthreads();
+  double acc = 0.0;
   for (int j = blockIdx.x * kBlock + threadIdx.x; j < N; j += gridDim.x * kBlock) {
     double s = 0.0;
     for (int i = 0; i < k; i++) s += c[i] * (double)basis[(size_t)i * ld + j];
-    w[j] = (float)((double)w[j] - s);
+    const float nw = (float)((double)w[j] - s);
+    w[j] = nw;
+    acc += (double)nw * (double)nw;
+  }
+  if (!nrm_partial) return;  // uniform over the workgroup
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < kBlock / 64; q++) t += red[q];
+    nrm_partial[(size_t)blockIdx.x * kDotGroup] = t;
   }
 }
 
@@ -222,8 +238,13 @@ hipError_t launch_relmax(const float* r, const float* x, int N, double* partial,
   return hipGetLastError();
 }
 
-hipError_t launch_axpys(float* w, const float* basis, int k, size_t ld, const double* coef, int N, hipStream_t s) {
-  hipLaunchKernelGGL(k_axpys, dim3(stream_blocks(N)), dim3(kBlock), 0, s, w, basis, k, ld, coef, N);
+hipError_t launch_axpys(float* w, const float* basis, int k, size_t ld, const double* coef, int N, hipStream_t s,
+                       double* partial, double* nrm_out) {
+  const int nb = stream_blocks(N);
+  hipLaunchKernelGGL(k_axpys, dim3(nb), dim3(kBlock), 0, s, w, basis, k, ld, coef, N, nrm_out ? partial : nullptr);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !nrm_out) return e;
+  hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(kBlock), 0, s, partial, nb, nrm_out);
   return hipGetLastError();
 }
 
