@@ -261,7 +261,13 @@ int dpo_policy_eval_sweep_last(dpo_ctx* ctx, const float* V_in, float* V_out, vo
  * sweeps, or until it has not decreased for 64 checks (stalled).  Returns
  * DPO_ENOCONV after max_sweeps.  V, pol_angle, pol_thr: device, N entries.
  * TABLE_WALK: the first sweep searches the full table, every later sweep
- * walks from the previous sweep's angles. */
+ * walks from the previous sweep's angles.
+ * Accuracy: tol_rel bounds the one-step change, not the distance to the
+ * fixed point, which is larger by the number of sweeps over which the
+ * slowest mode of the iteration carries a change (on the undiscounted orbit
+ * workloads a 1e-6 stop lies 1e-4 to 3e-3 from the fixed point).  Carry a
+ * solve on with dpo_solve_pi to 3e-7, which float32 meets or stalls at, for
+ * a value within ~2e-5 of the fixed point. */
 int dpo_solve_vi(dpo_ctx* ctx, float* V, float* pol_angle, uint8_t* pol_thr, double tol_rel,
                  int64_t max_sweeps, int32_t check_every, dpo_stats* stats, void* stream);
 
@@ -292,7 +298,10 @@ int dpo_solve_vi(dpo_ctx* ctx, float* V, float* pol_angle, uint8_t* pol_thr, dou
  * stats->eval_sweeps counts the operator applications.  Needs lambda > 0
  * and the TABLE or SCAN_GOLDEN search; no seed_angle.
  * Returns DPO_ENOCONV after max_outer greedy steps, or when 32 full-search
- * greedy steps in a row bring no new lowest residual (stats->stalled). */
+ * greedy steps in a row bring no new lowest residual (stats->stalled).
+ * Accuracy as for dpo_solve_vi.  A seeded solve carried on to a tighter
+ * tolerance starts with seeded steps again, which drift towards the local
+ * search's own fixed point: carry it on without seed_angle. */
 /* Exact policy evaluation (eq:p_eval solved as the sparse linear system
  * (I - exp(-lambda dt) P) v = b of Section 3, by restarted GMRES(16), the
  * solver the paper names): V (device, N) holds the fixed nodes' values and,
