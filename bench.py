@@ -284,6 +284,7 @@ def bench_large(accels=(1e-3,), with_seeded=True):
         }
         # the reference from here on is the float32-floor solution
         rec["to_float32_floor"] = to_float32_floor(ctx, V, a, t, 20, free)
+        rec["seconds_to_float32_floor"] = rec["seconds"] + rec["to_float32_floor"]["extra_seconds"]
         if accel == accels[0]:
             g, e = sweep_times(ctx, V)
             rec["sweep_ms"] = {"greedy": g, "eval": e}
