@@ -87,6 +87,50 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measure_ceilings(reps=10):
+    """HBM and VALU ceilings measured on this GPU with the library's own probe
+    kernels: a 16-byte streaming copy and read of 1 GiB buffers (far above the
+    256 MiB last-level cache) and a plain FP32 FMA loop (eight independent
+    chains per lane, no packed instructions) over 8192 workgroups of 256."""
+    import torch
+
+    from paper_2407_14675_amd import dpo
+
+    n = 1 << 28  # floats: 1 GiB
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    sink = torch.zeros(1, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()
+        ev0.record(stream)
+        for _ in range(reps):
+            fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) * 1e-3 / reps
+
+    t_copy = timed(lambda: dpo.probe_copy(src, dst))
+    t_read = timed(lambda: dpo.probe_read(src, sink))
+    del src, dst
+    blocks, iters = 8192, 4096
+    t_fma = timed(lambda: dpo.probe_fma(blocks, iters, sink))
+    fmas = blocks * 256 * iters * 8
+    wave_instr = blocks * 4 * iters * 8
+    return {
+        "hbm_copy_GBs": 8.0 * n / t_copy / 1e9,
+        "hbm_read_GBs": 4.0 * n / t_read / 1e9,
+        "hbm_peak_GBs": HBM_PEAK_GBS,
+        "fp32_fma_tflops": 2.0 * fmas / t_fma / 1e12,
+        "valu_wave_instr_per_s": wave_instr / t_fma,
+        "fp32_vector_peak_tflops_packed": VALU_PEAK_TFLOPS,
+        "what": "1 GiB float4 copy (read + write bytes) and read; FP32 FMA loop, 8 chains per lane, "
+                "8192 x 256 threads x 4096 iterations, plain v_fma_f32",
+    }
+
+
 def cpu_baseline(problem, seconds=12.0, seed=17):
     """The FP64 oracle on a bounded random sample of 48^4 nodes: one greedy
     step (coast + 64 scan + 14 golden) and 20 frozen-policy evaluations per

@@ -384,6 +384,21 @@ int dpo_probe_q(dpo_ctx* ctx, const float* V, const int32_t* nodes, const uint8_
 int dpo_probe_foot(dpo_ctx* ctx, const int32_t* nodes, const uint8_t* thr, const float* angle,
                    int64_t n, float* off_out, void* stream);
 
+/* Machine ceilings, the measured denominators of the sweeps' rooflines (the
+ * published peaks are reported beside them).  Asynchronous on stream; the
+ * caller times them with events.
+ * dpo_probe_copy: dst[0..n) = src[0..n) with 16-byte loads and stores (both
+ *   device, 16-byte aligned, n a positive multiple of 4): 8n bytes of HBM
+ *   traffic when n is far above the last-level cache.
+ * dpo_probe_read: reads src[0..n) (the same constraints); sink (device
+ *   float[1]) is written only for data that holds -1e38.
+ * dpo_probe_fma: blocks x 256 threads, each issuing iters x 8 dependent-free
+ *   FP32 fused multiply-adds (plain v_fma_f32, no packed form): 16 * 256 *
+ *   blocks * iters flops; sink as above. */
+int dpo_probe_copy(const float* src, float* dst, int64_t n, void* stream);
+int dpo_probe_read(const float* src, int64_t n, float* sink, void* stream);
+int dpo_probe_fma(int32_t blocks, int32_t iters, float* sink, void* stream);
+
 /* ------------------------------------------------------------ batched solve */
 
 /* Many transfer problems solved together by value iteration (paper Section 3):
@@ -493,6 +508,9 @@ int dpo_mlp_grad(dpo_mlp* m, const float* x, const float* tgt, int64_t n, float*
  * step.  1 <= batch <= 65536.  Asynchronous on stream: perm is copied into
  * the context before the call returns (the caller may reuse it at once), and
  * the call waits only for the previous call's copy of its order. */
+/* Ordering: the asynchronous network calls (forward, grad, train, propose)
+ * may be issued on different streams; each makes its stream wait, on the
+ * device, for the work the previous such call queued on the same network. */
 int dpo_mlp_train(dpo_mlp* m, const float* x, const float* tgt, int64_t n, const int32_t* perm, int32_t batch,
                   float* loss_hist, void* stream);
 

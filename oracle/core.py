@@ -117,7 +117,7 @@ def load(precision="f64"):
     lib.or_solve_pi.argtypes = [P, vp, S, vp, vp, vp, C.c_double, C.c_double, C.c_int32, i64,
                                 vp, vp]
     lib.or_solve_pi.restype = i64
-    lib.or_feedback.argtypes = [P, S, vp, vp, i64, C.c_double, vp, vp, vp]
+    lib.or_feedback.argtypes = [P, S, vp, vp, i64, C.c_double, vp, vp, vp, vp]
     lib.or_brute_thrust_min.argtypes = [P, vp, i64, i64, vp]
     lib.or_brute_thrust_min.restype = real
     lib.or_mask_from_coarse.argtypes = [P, vp, P, C.c_double, vp, vp]
@@ -312,7 +312,9 @@ class Oracle:
                     eval_sweeps=int(ev[0]),
                     resid=dict(max_rel=res[0], sum_abs=res[1], max_abs=res[2]))
 
-    def feedback(self, V, states, tau=None, search=None):
+    def feedback(self, V, states, tau=None, search=None, with_margin=False):
+        """eq:feed at arbitrary states: angle, throttle and Q of the chosen
+        control per state, and with with_margin the search's tie margin."""
         Vin = self._arr(V)
         ss = self.ss if search is None else search_struct(search)
         st = np.ascontiguousarray(np.asarray(states, dtype=np.float64).reshape(-1, 4))
@@ -321,8 +323,11 @@ class Oracle:
         thr = np.empty(cnt, dtype=np.uint8)
         q = np.empty(cnt, dtype=self.dtype)
         tau = self.problem["dt"] if tau is None else tau
+        margin = np.empty(cnt, dtype=self.dtype)
         self.lib.or_feedback(C.byref(self.ps), C.byref(ss), _ptr(Vin), _ptr(st), cnt,
-                             float(tau), _ptr(ang), _ptr(thr), _ptr(q))
+                             float(tau), _ptr(ang), _ptr(thr), _ptr(q), _ptr(margin))
+        if with_margin:
+            return ang, thr, q, margin
         return ang, thr, q
 
     def q_state(self, V, y, thr, u, tau=None):

@@ -901,9 +901,11 @@ int64_t or_solve_pi(const or_problem *p, const uint8_t *kind, const or_search *s
 
 /* ------------------------------------------------------------- feedback */
 /* Approximate optimal feedback eq:feed at arbitrary states y (count x 4),
- * with time step tau and the same search as the solver. */
+ * with time step tau and the same search as the solver.  margin_out (may be
+ * NULL) receives the search's tie margin, as the sweeps report it per node. */
 void or_feedback(const or_problem *p, const or_search *sr, const real *V, const double *states,
-                 int64_t count, double tau, real *angle_out, uint8_t *thr_out, real *q_out) {
+                 int64_t count, double tau, real *angle_out, uint8_t *thr_out, real *q_out,
+                 real *margin_out) {
   for (int64_t c = 0; c < count; c++) {
     real y[4];
     for (int k = 0; k < 4; k++) y[k] = (real)states[4 * c + k];
@@ -912,6 +914,7 @@ void or_feedback(const or_problem *p, const or_search *sr, const real *V, const 
     angle_out[c] = ch.angle;
     thr_out[c] = (uint8_t)ch.thr;
     if (q_out) q_out[c] = ch.q;
+    if (margin_out) margin_out[c] = ch.margin;
   }
 }
 

@@ -1335,6 +1335,33 @@ int dpo_probe_foot(dpo_ctx* c, const int32_t* nodes, const uint8_t* thr, const f
   return DPO_OK;
 }
 
+/* ---------------------------------------------------------------- machine ceilings */
+
+int dpo_probe_copy(const float* src, float* dst, int64_t n, void* stream) {
+  if (!src || !dst) return fail(nullptr, DPO_EINVAL, "dpo_probe_copy: NULL argument");
+  if (n < 4 || n % 4 != 0) return fail(nullptr, DPO_EINVAL, "dpo_probe_copy: n must be a positive multiple of 4");
+  if (n / 4 > (int64_t)0x7fffffff * 1024) return fail(nullptr, DPO_EINVAL, "dpo_probe_copy: n too large");
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15u)
+    return fail(nullptr, DPO_EINVAL, "dpo_probe_copy: buffers must be 16-byte aligned");
+  HIP_TRY(nullptr, launch_ceil_copy(src, dst, n, S(stream)));
+  return DPO_OK;
+}
+
+int dpo_probe_read(const float* src, int64_t n, float* sink, void* stream) {
+  if (!src || !sink) return fail(nullptr, DPO_EINVAL, "dpo_probe_read: NULL argument");
+  if (n < 4 || n % 4 != 0) return fail(nullptr, DPO_EINVAL, "dpo_probe_read: n must be a positive multiple of 4");
+  if (n / 4 > (int64_t)0x7fffffff * 1024) return fail(nullptr, DPO_EINVAL, "dpo_probe_read: n too large");
+  if (reinterpret_cast<uintptr_t>(src) & 15u) return fail(nullptr, DPO_EINVAL, "dpo_probe_read: src must be 16-byte aligned");
+  HIP_TRY(nullptr, launch_ceil_read(src, n, sink, S(stream)));
+  return DPO_OK;
+}
+
+int dpo_probe_fma(int32_t blocks, int32_t iters, float* sink, void* stream) {
+  if (!sink) return fail(nullptr, DPO_EINVAL, "dpo_probe_fma: NULL argument");
+  if (blocks < 1 || iters < 1) return fail(nullptr, DPO_EINVAL, "dpo_probe_fma: blocks and iters must be >= 1");
+  HIP_TRY(nullptr, launch_ceil_fma(blocks, iters, sink, S(stream)));
+  return DPO_OK;
+}
 
 /* ------------------------------------------------- training pairs for the network */
 

@@ -160,4 +160,11 @@ hipError_t launch_probe_interp(const float* V, const Grid& G, float M, const flo
 hipError_t launch_probe_q(const SweepArgs& a, const int* nodes, const uint8_t* thr, const float* ang,
                           int n, float* q_out, float* off_out, hipStream_t s);
 
+// Machine ceilings (dpo_ceiling.hip): a float4 streaming copy and read of n
+// floats (n a multiple of 4, 16-byte aligned) and a plain FP32 FMA loop of
+// blocks x 256 threads, each issuing iters x 8 FMAs.
+hipError_t launch_ceil_copy(const float* src, float* dst, int64_t n, hipStream_t s);
+hipError_t launch_ceil_read(const float* src, int64_t n, float* sink, hipStream_t s);
+hipError_t launch_ceil_fma(int blocks, int iters, float* sink, hipStream_t s);
+
 }  // namespace dpo

@@ -235,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void k_policy_eval(SweepArgs a) {
     if (kHeun) node_heun(a, T.i, H);
     const int thr = a.pol_thr_in[j] ? 1 : 0;
     float sn = 0.0f, cs = 1.0f;
-    if (thr) __sincosf(a.pol_ang_in[j], &sn, &cs);
+    if (thr) policy_sincos(a, a.pol_ang_in[j], sn, cs);
     const float v = q_step<kHeun>(a.V_in, a.G, a.P, T, H, thr, sn, cs, a.qnode ? a.qnode[j] : 0.0f);
     a.V_out[j] = v;
     if (kResid) node_residual(a.V_in[j], v, rel, sum, mabs, bad);

@@ -29,7 +29,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_hom(SweepArgs a, const float* _
   }
   const int thr = a.pol_thr_in[j] ? 1 : 0;
   float sn = 0.0f, cs = 1.0f;
-  if (thr) __sincosf(a.pol_ang_in[j], &sn, &cs);
+  if (thr) policy_sincos(a, a.pol_ang_in[j], sn, cs);
   float off[4];
   foot_off<kHeun>(T, H, thr, sn, cs, off);
   int base[4];

@@ -519,6 +519,7 @@ struct dpo_mlp {
   int64_t perm_cap = 0;
   int* perm_host = nullptr;           // pinned staging of the epoch's order (host copy of perm)
   hipEvent_t perm_copied = nullptr;   // the staging buffer's last upload has completed
+  hipEvent_t work_done = nullptr;     // the network's last queued work (any stream) has completed
   int max_blocks = 512;
   double lr = 1e-3, b1 = 0.9, b2 = 0.999, eps = 1e-8;
   int64_t step = 0;
@@ -614,6 +615,13 @@ MlpArgs mlp_args(dpo_mlp* m, const float* x, const float* tgt, const int* perm, 
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
+// Work on the network's buffers (parameters, Adam state, gradient rows, the
+// device copy of the order) is ordered across streams: each asynchronous call
+// first makes its stream wait for the previous call's last queued work, and
+// records its own at the end.  Calls on one stream are ordered anyway.
+hipError_t after_previous(dpo_mlp* m, hipStream_t s) { return hipStreamWaitEvent(s, m->work_done, 0); }
+hipError_t mark_done(dpo_mlp* m, hipStream_t s) { return hipEventRecord(m->work_done, s); }
+
 }  // namespace
 
 extern "C" {
@@ -631,6 +639,11 @@ int dpo_mlp_create(const float* params, dpo_mlp** out) {
   if (!ok) {
     dpo_mlp_destroy(m);
     return mfail(nullptr, DPO_ENOMEM, "network parameter buffers");
+  }
+  if (hipEventCreateWithFlags(&m->work_done, hipEventDisableTiming) != hipSuccess) {
+    m->work_done = nullptr;
+    dpo_mlp_destroy(m);
+    return mfail(nullptr, DPO_EHIP, "network event");
   }
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) == hipSuccess &&
@@ -661,6 +674,10 @@ void dpo_mlp_destroy(dpo_mlp* m) {
   if (m->perm_copied) {
     (void)hipEventSynchronize(m->perm_copied);
     (void)hipEventDestroy(m->perm_copied);
+  }
+  if (m->work_done) {
+    (void)hipEventSynchronize(m->work_done);
+    (void)hipEventDestroy(m->work_done);
   }
   if (m->perm_host) (void)hipHostFree(m->perm_host);
   delete m;
@@ -717,7 +734,9 @@ int dpo_mlp_forward(dpo_mlp* m, const float* x, int64_t n, float* y, void* strea
   if (n == 0) return DPO_OK;
   MlpArgs a = mlp_args(m, x, nullptr, nullptr, (int)n);
   a.y = y;
+  MLP_HIP(m, after_previous(m, MS(stream)));
   MLP_HIP(m, launch_mlp_forward(a, MS(stream)));
+  MLP_HIP(m, mark_done(m, MS(stream)));
   return DPO_OK;
 }
 
@@ -730,11 +749,13 @@ int dpo_mlp_grad(dpo_mlp* m, const float* x, const float* tgt, int64_t n, float*
   if (rc != DPO_OK) return rc;
   MlpArgs a = mlp_args(m, x, tgt, nullptr, (int)n);
   a.partial = m->partial;
+  MLP_HIP(m, after_previous(m, MS(stream)));
   MLP_HIP(m, launch_mlp_grad(a, MS(stream)));
   ReduceArgs r = reduce_args(m, tiles, (int)n, loss ? loss : m->loss, 0);
   MLP_HIP(m, launch_mlp_reduce(r, MS(stream)));
   if (grad)
     MLP_HIP(m, hipMemcpyAsync(grad, m->grad, (size_t)kNParam * sizeof(float), hipMemcpyDeviceToDevice, MS(stream)));
+  MLP_HIP(m, mark_done(m, MS(stream)));
   return DPO_OK;
 }
 
@@ -755,14 +776,17 @@ int dpo_mlp_train(dpo_mlp* m, const float* x, const float* tgt, int64_t n, const
     if (rc != DPO_OK) return rc;
     // Stage the order in pinned memory so that the upload is asynchronous and
     // the caller may prepare the next epoch's order while this one trains.
-    // The previous call's upload must have left the staging buffer first; it
-    // runs after that call's steps in stream order, into a device buffer those
-    // steps no longer read.
+    // The previous call's upload must have left the staging buffer first.  The
+    // new upload waits for the previous call's steps (on whatever stream they
+    // were queued), which read the device copy it overwrites.
     MLP_HIP(m, hipEventSynchronize(m->perm_copied));
     std::memcpy(m->perm_host, perm, (size_t)n * sizeof(int));
+    MLP_HIP(m, after_previous(m, MS(stream)));
     MLP_HIP(m, hipMemcpyAsync(m->perm, m->perm_host, (size_t)n * sizeof(int), hipMemcpyHostToDevice, MS(stream)));
     MLP_HIP(m, hipEventRecord(m->perm_copied, MS(stream)));
     dperm = m->perm;
+  } else {
+    MLP_HIP(m, after_previous(m, MS(stream)));
   }
   for (int64_t b = 0; b < steps; b++) {
     const int64_t lo = b * batch;
@@ -781,6 +805,7 @@ int dpo_mlp_train(dpo_mlp* m, const float* x, const float* tgt, int64_t n, const
     r.c2 = (float)(1.0 / (1.0 - std::pow(m->b2, (double)m->step)));
     MLP_HIP(m, launch_mlp_reduce(r, MS(stream)));
   }
+  MLP_HIP(m, mark_done(m, MS(stream)));
   return DPO_OK;
 }
 
@@ -788,8 +813,10 @@ int dpo_mlp_propose(dpo_mlp* m, const dpo_ctx* ctx, float* seed_angle, void* str
   if (!m || !ctx || !seed_angle) return mfail(m, DPO_EINVAL, "NULL argument");
   const CtxView c = ctx_view(ctx);
   if (c.n_free == 0) return DPO_OK;
+  MLP_HIP(m, after_previous(m, MS(stream)));
   MLP_HIP(m, launch_mlp_propose(m->theta, m->w2, c.G, c.free_node, (int)c.n_free, seed_angle, m->max_blocks,
                                 MS(stream)));
+  MLP_HIP(m, mark_done(m, MS(stream)));
   return DPO_OK;
 }
 

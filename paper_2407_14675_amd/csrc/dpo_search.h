@@ -224,6 +224,22 @@ __device__ inline int table_index(float u, int K) {
   return (k >= 0 && k < K) ? k : 0;
 }
 
+// sin/cos of a stored policy angle, as the greedy step formed them: an angle
+// that is one of the tabulated controls (or scan samples) takes the table's
+// values, which the search evaluated it with; any other angle (golden-section
+// and seeded points, formed there by rotation recurrences) takes sincosf.
+__device__ inline void policy_sincos(const SweepArgs& a, float u, float& sn, float& cs) {
+  if (a.n_ang > 0) {
+    const int k = table_index(u, a.n_ang);
+    if (a.tab_ang[k] == u) {
+      sn = a.tab_sin[k];
+      cs = a.tab_cos[k];
+      return;
+    }
+  }
+  sincosf(u, &sn, &cs);
+}
+
 // Walk over the tabulated angles from the previous optimum (paper Section 3,
 // "Efficient computation of the minimum"): start at the table angle nearest
 // to u_prev, look at both cyclic neighbours, move to the lower one if it is
@@ -309,7 +325,7 @@ __device__ inline void keep_incumbent(const QF& qf, const SweepArgs& a, int j, f
   const float u0 = a.pol_ang_in[j];
   float s0 = 0.0f, c0 = 1.0f, q0 = qc;
   if (thr0) {
-    sincosf(u0, &s0, &c0);
+    policy_sincos(a, u0, s0, c0);
     q0 = qf(s0, c0);
   }
   if (q0 <= ch.v) {

@@ -124,6 +124,9 @@ def load():
         "dpo_mlp_propose": [vp, vp, vp, vp],
         "dpo_feasible_nodes": [vp, vp, dbl, vp, C.POINTER(i64), vp],
         "dpo_gather_pairs": [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp],
+        "dpo_probe_copy": [vp, vp, i64, vp],
+        "dpo_probe_read": [vp, i64, vp, vp],
+        "dpo_probe_fma": [i32, i32, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -586,3 +589,25 @@ class Mlp:
             seed = torch.zeros(ctx.shape, dtype=torch.float32, device=self.device)
         self._check(self.lib.dpo_mlp_propose(self.h, ctx.h, _p(seed), _stream()))
         return seed
+
+
+def _check_global(rc):
+    if rc != DPO_OK:
+        raise DpoError(rc, load().dpo_last_error(None).decode())
+    return rc
+
+
+def probe_copy(src, dst):
+    """dst = src with the library's 16-byte streaming copy (float32 device
+    tensors of equal size, a multiple of 4)."""
+    return _check_global(load().dpo_probe_copy(_p(src), _p(dst), src.numel(), _stream()))
+
+
+def probe_read(src, sink):
+    """Stream src (float32 device tensor) through 16-byte loads."""
+    return _check_global(load().dpo_probe_read(_p(src), src.numel(), _p(sink), _stream()))
+
+
+def probe_fma(blocks, iters, sink):
+    """blocks x 256 threads x iters x 8 plain FP32 fused multiply-adds."""
+    return _check_global(load().dpo_probe_fma(int(blocks), int(iters), _p(sink), _stream()))

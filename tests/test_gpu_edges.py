@@ -113,3 +113,22 @@ def test_network_empty_and_single_batches(dpo):
     xs, ts = inputs.mlp_random_samples(5, seed=9)
     hist = net.train_epoch(torch.from_numpy(xs).cuda(), torch.from_numpy(ts).cuda(), batch=4096)
     assert hist.numel() == 1 and np.isfinite(host(hist)).all() and net.steps() == 1
+
+
+def test_ceiling_probes(dpo):
+    """The machine-ceiling probes: the copy copies, the read and the FMA loop
+    run, and bad sizes are refused."""
+    print("ceiling probes", flush=True)
+    src = torch.arange(1 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.zeros_like(src)
+    sink = torch.zeros(1, dtype=torch.float32, device="cuda")
+    dpo.probe_copy(src, dst)
+    dpo.probe_read(src, sink)
+    dpo.probe_fma(8, 16, sink)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
+    assert float(sink[0]) == 0.0
+    with pytest.raises(dpo.DpoError):
+        dpo.probe_copy(src[:6], dst[:6])
+    with pytest.raises(dpo.DpoError):
+        dpo.probe_fma(0, 16, sink)

@@ -108,11 +108,26 @@ def test_training_lowers_loss_and_is_deterministic(dpo):
         for e, order in enumerate(inputs.mlp_epoch_orders(n, epochs=6)):
             hist.append(host(net.train_epoch(dev(x), dev(t), perm=order, batch=1024)))
         runs.append((np.concatenate(hist), net.params()))
+    # a third run issues its epochs alternately on two streams with no host
+    # synchronisation in between: the network orders its own work across
+    # streams, so the result is the same bit for bit
+    xd, td = dev(x), dev(t)
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    net = dpo.Mlp(inputs.mlp_params32(seed=4))
+    torch.cuda.synchronize()
+    hist = []
+    for e, order in enumerate(inputs.mlp_epoch_orders(n, epochs=6)):
+        with torch.cuda.stream(streams[e % 2]):
+            hist.append(net.train_epoch(xd, td, perm=order, batch=1024))
+    torch.cuda.synchronize()
+    runs.append((np.concatenate([h.cpu().numpy() for h in hist]), net.params()))
     first, last = runs[0][0][:4].mean(), runs[0][0][-4:].mean()
     print("  loss", first, "->", last, flush=True)
     assert last < 0.5 * first
-    np.testing.assert_array_equal(runs[0][0], runs[1][0])
-    np.testing.assert_array_equal(runs[0][1], runs[1][1])
+    for r in runs[1:]:
+        np.testing.assert_array_equal(runs[0][0], r[0])
+        np.testing.assert_array_equal(runs[0][1], r[1])
 
 
 def test_bad_arguments_raise(dpo):

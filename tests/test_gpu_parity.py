@@ -18,6 +18,7 @@ import numpy as np
 import pytest
 import torch
 
+from feedback_parity import check_feedback
 from oracle.core import KIND_FREE, Oracle, mask_from_coarse
 from paper_2407_14675_amd import inputs
 
@@ -485,15 +486,30 @@ def test_value_at_and_feedback_parity(dpo):
     ctx = dpo.Context(p)
     Vd = dev(gold["V"])
     V32 = gold["V"].astype(np.float32).astype(np.float64)
-    states = inputs.random_states(p, 500, seed=41)
+    # most states of this coarse grid are ties (Q is dominated by the exit
+    # value there): 4000 states leave ~60 clear of ties
+    states = inputs.random_states(p, 4000, seed=41)
     for x in states[:50]:
         assert ctx.value_at(Vd, x) == pytest.approx(o.value_at(V32, x), rel=1e-12, abs=1e-9)
     ang, thr, q = ctx.feedback(Vd, states)
-    ao, to, qo = o.feedback(V32, states)
-    assert np.max(rel_err(host(q), qo)) < 1e-5
-    qo_margin = []
-    agree = (host(thr) == to)
-    assert agree.mean() >= 0.98
+    n, n_clear, n_thr = check_feedback(o, V32, states, host(ang), host(thr), host(q), n_table=p["search"]["n_angles"],
+                                       min_clear=40)
+    _say("  states", n, "clear of ties", n_clear, "thrust compared", n_thr)
+
+
+def test_feedback_parity_scan_golden(dpo):
+    """eq:feed with the continuous search (scan 64 + golden 12) at random
+    states of the 10^4 policy-iteration problem, on its converged value."""
+    p = inputs.with_grid(inputs.PI48, (10, 10, 10, 10))
+    _say("feedback scan-golden")
+    o = Oracle(p)
+    ref = o.solve_pi(tol_abs=1e-8, eval_sweeps=20)
+    V32 = ref["V"].astype(np.float32).astype(np.float64)
+    ctx = dpo.Context(p)
+    states = inputs.random_states(p, 500, seed=43)
+    ang, thr, q = ctx.feedback(dev(V32), states)
+    n, n_clear, n_thr = check_feedback(o, V32, states, host(ang), host(thr), host(q), min_clear=100)
+    _say("  states", n, "clear of ties", n_clear, "thrust compared", n_thr)
 
 
 # ----------------------------------------------------------- a1 mask
@@ -658,9 +674,30 @@ def test_descriptor_formats(dpo, case):
     vg = host(W).reshape(-1)[nodes].astype(np.float64)
     assert np.all(np.abs(ve - vg) <= 1e-5 * np.maximum(1.0, np.abs(vg)) + 1e-6 * corner)
     np.testing.assert_array_equal(host(E)[~free], V[~free])
-    if case != "flat_code":
-        # and the oracle's (with 35-cell feet, float32 and FP64 feet straddle
-        # the domain faces differently, so the flat-code case stops above)
-        q = o.q_many(V.astype(np.float64), nodes, host(thr).reshape(-1)[nodes],
-                     host(ang).reshape(-1)[nodes].astype(np.float64))
-        assert np.all(np.abs(ve - q) <= 1e-5 * np.maximum(1.0, np.abs(q)) + 1e-6 * corner)
+    # and the oracle's Q of the same control
+    tg = host(thr).reshape(-1)[nodes]
+    ag = host(ang).reshape(-1)[nodes].astype(np.float64)
+    q = o.q_many(V.astype(np.float64), nodes, tg, ag)
+    ok = np.abs(ve - q) <= 1e-5 * np.maximum(1.0, np.abs(q)) + 1e-6 * corner
+    if case == "flat_code":
+        # Feet 35 cells away: the float32 foot is ~1e-5 cell from the FP64 one,
+        # so where the oracle's foot lies that close to a domain face the two
+        # can fall on different sides of the jump to M (a quarter of the nodes
+        # here: the best angle often puts the foot just inside a face).
+        # Compared exactly at every node whose FP64 foot is farther than 1e-3
+        # cell from every face; at the others the value must be the oracle's Q
+        # within ANGLE_ROUND of the device's angle.
+        n = p["n"]
+        h = [(p["hi"][k] - p["lo"][k]) / (n[k] - 1) for k in range(4)]
+        near = np.zeros(nodes.size, dtype=bool)
+        for c, j in enumerate(nodes):
+            z = o.step(o.node_coords(int(j)), int(tg[c]), float(ag[c]))
+            s = [(z[k] - p["lo"][k]) / h[k] for k in range(4)]
+            near[c] = any(min(abs(s[k]), abs(s[k] - (n[k] - 1))) < 1e-3 for k in range(4))
+        _say("  flat codes: nodes compared with the oracle", int((~near).sum()), "of", nodes.size)
+        assert (~near).sum() >= 0.6 * nodes.size
+        tol = 1e-5 * np.maximum(1.0, np.abs(q)) + 1e-6 * corner
+        for du in (-ANGLE_ROUND, ANGLE_ROUND):
+            qd = o.q_many(V.astype(np.float64), nodes, tg, ag + du)
+            ok |= near & (np.abs(ve - qd) <= tol)
+    assert np.all(ok)

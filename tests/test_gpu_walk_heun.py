@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 import torch
 
+from feedback_parity import check_feedback
 from oracle.core import KIND_FREE, Oracle
 from paper_2407_14675_amd import inputs
 
@@ -226,6 +227,19 @@ def test_heun_sweep_parity(dpo, search):
     # the Euler sweep of the same V differs beyond the tolerance at most nodes
     Ve, _, _, _ = Oracle(base).bellman_sweep(V32.astype(np.float64))
     assert (np.abs(Ve - Vo) > tol)[free].mean() > 0.5
+    # the frozen-policy sweep of the greedy policy (eq:p_eval after eq:p_impr)
+    # applies the greedy step's own operator: where the controls are table
+    # entries the same sin/cos, foot and lerps, equal up to the compiler's
+    # different contraction of the same expressions in the two kernels (a few
+    # ulps); golden-section angles get sincosf where the search rotated,
+    # within one evaluation
+    E = Vin.clone()
+    ctx.policy_eval_sweep(Vin, E, ang, thr)
+    Eg = host(E).astype(np.float64)
+    if search == "table":
+        assert np.all(np.abs(Eg - Vg)[free] <= 1e-6 * np.maximum(1.0, np.abs(Vg))[free])
+    else:
+        assert np.all(np.abs(Eg - Vg)[free] <= tol[free])
 
 
 def test_heun_policy_eval_and_pi(dpo):
@@ -265,13 +279,11 @@ def test_heun_feedback_parity(dpo):
     o = Oracle(p)
     ctx = dpo.Context(p)
     V32 = gold["V"].astype(np.float32)
-    states = inputs.random_states(p, 500, seed=89)
+    states = inputs.random_states(p, 4000, seed=89)  # ~57 of them clear of ties
     ang, thr, q = ctx.feedback(dev(V32), states)
-    ao, to, qo = o.feedback(V32.astype(np.float64), states)
-    # one float32 Q: 1e-5*max(1,|Q|) plus the lerps' rounding at the corners' magnitude (up to max|V|)
-    tol = 1e-5 * np.maximum(1.0, np.abs(qo)) + 1e-6 * np.abs(V32).max()
-    assert np.all(np.abs(host(q) - qo) <= tol), np.max(np.abs(host(q) - qo) / tol)
-    assert (host(thr) == to).mean() >= 0.98
+    n, n_clear, n_thr = check_feedback(o, V32.astype(np.float64), states, host(ang), host(thr), host(q),
+                                       n_table=p["search"]["n_angles"], min_clear=40)
+    _say("  states", n, "clear of ties", n_clear, "thrust compared", n_thr)
 
 
 def test_heun_and_walk_refused_where_they_do_not_apply(dpo):

@@ -133,3 +133,60 @@ def test_discounted_operator_is_a_monotone_contraction():
     assert np.all(TW >= TV - 1e-9)
     gamma = math.exp(-p["lam"] * p["dt"])
     assert np.max(np.abs(TW - TV)) <= gamma * np.max(np.abs(W - V)) * (1 + 1e-12)
+
+
+def test_velocity_faces_clamp_and_circular_faces_exit():
+    """The crown problem's state constraint (Section 3, the polar grid): the
+    exit value M applies on the two circular faces rho = rho_min, rho_max
+    only; a foot beyond a velocity face (v_rho or v_theta) is put onto that
+    face.  Checked on the whole Q of every node of a small grid for several
+    controls, with everything recomputed here: the Euler foot of the polar
+    system in physical units, mapped to grid coordinates and clamped by hand,
+    and a value field whose Q1 interpolant is known in closed form (a
+    periodic blend along theta times an affine function of the other three
+    grid coordinates).  Zero element weights make the running cost vanish, so
+    Q = exp(-lambda dt) * I[V](foot)."""
+    p = dict(small((9, 6, 5, 8), integrator="euler"), el_beta=0.0, el_gamma=0.0, w_fuel=0.0)
+    # a thrust strong enough to carry feet across both velocity faces
+    p["accel"] = 4e-3
+    o = Oracle(p)
+    n = p["n"]
+    lo, hi = p["lo"], p["hi"]
+    h = [(hi[k] - lo[k]) / (n[k] - 1) for k in range(3)] + [2 * math.pi / n[3]]
+    rng = np.random.default_rng(98)
+    g = rng.uniform(1, 10, size=n[3])
+    c = rng.uniform(-1, 1, size=3)
+    i0, i1, i2 = np.arange(n[0]), np.arange(n[1]), np.arange(n[2])
+    aff = 1.0 + 0.1 * (c[0] * i0[None, None, :] + c[1] * i1[None, :, None] + c[2] * i2[:, None, None])
+    V = g[:, None, None, None] * aff[None]
+    gamma = math.exp(-p["lam"] * p["dt"])
+
+    def expected(x, thr, u):
+        r, vr, vt, th = x
+        acc = p["accel"] if thr else 0.0
+        b = [vr, vt * vt / r - MU / (r * r) + acc * math.sin(u), -vr * vt / r + acc * math.cos(u), vt / r]
+        s = [(x[k] + p["dt"] * b[k] - lo[k]) / h[k] for k in range(4)]
+        if s[0] < 0 or s[0] > n[0] - 1:
+            return gamma * p["M"], "rho"  # I = M outside, discounted like any foot value
+        face = None
+        for k in (1, 2):
+            if s[k] < 0 or s[k] > n[k] - 1:
+                face = "v"
+                s[k] = min(max(s[k], 0.0), n[k] - 1.0)
+        w = s[3] % n[3]
+        b3 = int(math.floor(w))
+        t3 = w - b3
+        gb = (1 - t3) * g[b3] + t3 * g[(b3 + 1) % n[3]]
+        return gamma * gb * (1.0 + 0.1 * (c[0] * s[0] + c[1] * s[1] + c[2] * s[2])), face
+
+    seen = {"rho": 0, "v": 0, None: 0}
+    for j in range(o.N):
+        x = o.node_coords(j)
+        for thr, u in ((0, 0.0), (1, math.pi / 2), (1, -math.pi / 2), (1, 0.0), (1, math.pi),
+                       (1, rng.uniform(-math.pi, math.pi))):
+            want, why = expected(x, thr, u)
+            seen[why] += 1
+            got = o.q(V, j, thr, u)
+            assert got == pytest.approx(want, rel=1e-12, abs=1e-12), (j, thr, u, why)
+    # the grid and controls reach every case: interior feet, velocity faces, circular faces
+    assert min(seen.values()) > 20, seen
