@@ -253,6 +253,21 @@ int dpo_policy_eval_sweep(dpo_ctx* ctx, const float* V_in, float* V_out, const f
  * Euler step). */
 int dpo_policy_eval_sweep_last(dpo_ctx* ctx, const float* V_in, float* V_out, void* stream);
 
+/* dpo_policy_eval_sweep for callers that cannot allocate device memory (code
+ * under stream or graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same results, bit for bit, but the
+ * residual's per-workgroup partials and its two-stage reduction use a
+ * static device array of 10,496,000 bytes that each GPU holds from the first
+ * call on it until the process ends; the call itself allocates nothing (the
+ * context was allocated by dpo_create beforehand).  At most 67,108,864 free
+ * nodes (DPO_EINVAL beyond).  All calls on one GPU share that array: calls
+ * that overlap in time on one GPU (different streams, or host threads) race
+ * on it and must be serialised by the caller; consecutive calls on one
+ * stream are safe.  With no free node, resid (if given) is written by a
+ * kernel, not a memset. */
+int dpo_policy_eval_sweep_static(dpo_ctx* ctx, const float* V_in, float* V_out, const float* pol_angle,
+                                 const uint8_t* pol_thr, double* resid, void* stream);
+
 /* --------------------------------------------------------------- solvers */
 
 /* Value iteration (paper Section 3, "Policy Iteration", first display):

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1842,6 +1843,79 @@ int dpo_batch_solve_sequential(dpo_batch* b, float* const* V, float* const* pol_
   }
   if (seconds) *seconds = now_s() - t0;
   return code;
+}
+
+}  // extern "C"
+
+/* ------------------------------------------- frozen-policy sweep without allocation
+ * For callers that cannot allocate device memory (code under graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the per-workgroup FP64
+ * residual partials of the frozen-policy sweep and the first stage of their
+ * reduction live in a file-scope device array instead of the context's
+ * buffer.  Each device holds its own copy of the array for the life of the
+ * process; host code reaches it only through the address hipGetSymbolAddress
+ * returns on that device, taken once per device on the entry point's first
+ * call there. */
+namespace {
+
+constexpr int kStaticMaxBlocks = 262144;  // workgroups of one sweep: up to 67,108,864 free nodes
+constexpr size_t kStaticScratch = (size_t)kPartial * (kStaticMaxBlocks + kResidStage);
+
+__device__ __align__(256) double scratch[kStaticScratch];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch` (nullptr and a message on error).
+double* static_scratch(dpo_ctx* c) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    fail(c, DPO_EHIP, "no current device for the static scratch");
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      hip_fail(c, e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+int dpo_policy_eval_sweep_static(dpo_ctx* c, const float* V_in, float* V_out, const float* pol_angle,
+                                 const uint8_t* pol_thr, double* resid, void* stream) {
+  if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
+  if (!V_in || !V_out || !pol_angle || !pol_thr) return fail(c, DPO_EINVAL, "null array argument");
+  if (V_in == V_out) return fail(c, DPO_EINVAL, "V_in and V_out must differ (Jacobi sweep)");
+  const int nb = blocks_for(c->n_free, kBlock);
+  if (nb > kStaticMaxBlocks)
+    return fail(c, DPO_EINVAL, "dpo_policy_eval_sweep_static: more than 67,108,864 free nodes "
+                               "(the static scratch holds 262,144 workgroup partials)");
+  double* ptr = static_scratch(c);
+  if (!ptr) return DPO_EHIP;
+  hipStream_t s = S(stream);
+  SweepArgs a = base_args(c);
+  a.V_in = V_in;
+  a.V_out = V_out;
+  a.pol_ang_in = pol_angle;
+  a.pol_thr_in = pol_thr;
+  a.partial = ptr;
+  if (c->n_free > 0) HIP_TRY(c, launch_policy_eval(a, resid != nullptr, s));
+  // every workgroup writes its partial before the reduction reads it, so the
+  // array needs no clearing; with no free node the reduction of zero
+  // partials writes the zeros (a kernel, not a memset)
+  if (resid)
+    HIP_TRY(c, launch_resid_final(ptr, c->n_free > 0 ? nb : 0, ptr + (size_t)kPartial * kStaticMaxBlocks, resid, s));
+  return DPO_OK;
 }
 
 }  // extern "C"

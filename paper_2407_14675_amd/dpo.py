@@ -91,6 +91,7 @@ def load():
         "dpo_bellman_sweep_seeded": [vp, vp, vp, vp, vp, vp, vp, vp],
         "dpo_policy_eval_sweep": [vp, vp, vp, vp, vp, vp, vp],
         "dpo_policy_eval_sweep_last": [vp, vp, vp, vp],
+        "dpo_policy_eval_sweep_static": [vp, vp, vp, vp, vp, vp, vp],
         "dpo_solve_vi": [vp, vp, vp, vp, dbl, i64, i32, C.POINTER(Stats), vp],
         "dpo_solve_pi": [vp, vp, vp, vp, dbl, i32, i64, vp, C.POINTER(Stats), vp],
         "dpo_policy_evaluate": [vp, vp, vp, vp, dbl, i32, C.POINTER(i64), C.POINTER(dbl), vp],
@@ -282,6 +283,12 @@ class Context:
     def policy_eval_sweep(self, V_in, V_out, pol_ang, pol_thr, resid=None):
         return self._check(self.lib.dpo_policy_eval_sweep(self.h, _p(V_in), _p(V_out), _p(pol_ang), _p(pol_thr),
                                                            _p(resid), _stream()))
+
+    def policy_eval_sweep_static(self, V_in, V_out, pol_ang, pol_thr, resid=None):
+        """policy_eval_sweep with its scratch in the library's static device
+        array: the call allocates nothing."""
+        return self._check(self.lib.dpo_policy_eval_sweep_static(self.h, _p(V_in), _p(V_out), _p(pol_ang),
+                                                                  _p(pol_thr), _p(resid), _stream()))
 
     def policy_eval_sweep_last(self, V_in, V_out):
         """Frozen-policy sweep for the policy of the last Bellman sweep."""
