@@ -243,6 +243,22 @@ int dpo_bellman_sweep_seeded(dpo_ctx* ctx, const float* V_in, float* V_out, floa
 int dpo_policy_eval_sweep(dpo_ctx* ctx, const float* V_in, float* V_out, const float* pol_angle,
                           const uint8_t* pol_thr, double* resid, void* stream);
 
+/* Kernels of the frozen-policy sweeps: 0 automatic, 1 corner gathers from
+ * global memory (one node per thread over the free list, or per node from
+ * the greedy step's foot descriptors), 2 every node of the grid, workgroups
+ * walking columns of nodes through the mass planes with the value bricks
+ * their feet reach staged in LDS (orbit model, Euler foot, a thrust step
+ * below one mass cell; DPO_EINVAL otherwise).  Automatic takes 2 for the
+ * descriptor sweeps of policy iteration (and dpo_policy_eval_sweep_last)
+ * where the descriptors are stored per node, and 1 for the sweeps that take
+ * the policy arrays (dpo_policy_eval_sweep and its static form), where
+ * recomputing the foot makes the brick kernel arithmetic-bound; 2 forces
+ * the bricks for both.  Each pair of kernels gives the same values bit for
+ * bit.  dpo_eval_path returns the kernel policy iteration's evaluation
+ * sweeps use (1 or 2). */
+int dpo_set_eval_path(dpo_ctx* ctx, int32_t path);
+int dpo_eval_path(const dpo_ctx* ctx);
+
 /* Frozen-policy sweep for the policy chosen by the most recent
  * dpo_bellman_sweep / dpo_bellman_sweep_seeded on this context: the sweep
  * stores, per free node, the cell and cell coordinates of its chosen

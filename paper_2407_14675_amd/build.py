@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdpo.so")
-SOURCES = ["dpo_kernels.hip", "dpo_batch.hip", "dpo_mlp.hip", "dpo_krylov.hip", "dpo_ceiling.hip", "dpo_api.hip"]
+SOURCES = ["dpo_kernels.hip", "dpo_batch.hip", "dpo_mlp.hip", "dpo_krylov.hip", "dpo_ceiling.hip", "dpo_brick.hip", "dpo_api.hip"]
 HEADERS = ["dpo_device.h", "dpo_kernels.h", "dpo_search.h", "dpo_mlp.h", "dpo_krylov.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -39,6 +39,11 @@ struct dpo_ctx {
   float gm = 0;                   // thrust displacement along m
   bool fast_ok = false;           // the factorised thrust kernel applies
   int path = 0;                   // 0 auto, 1 direct, 2 fast
+  BrickPlan brick{};              // frozen-policy sweep with LDS value bricks (dense grids)
+  bool brick_ok = false;          // the plan applies to this problem
+  int4* brick_halo = nullptr;     // its per-tile halo table
+  double brick_over = 0;          // brick floats loaded per node, per plane
+  int eval_path = 0;              // 0 auto, 1 free-list / descriptor kernels, 2 LDS bricks
   int block = kBlock;             // workgroup size of the factorised sweeps
   int last_blocks = 0;            // workgroups of the last kernel that wrote residual partials
   float* tab = nullptr;  // [3][n_ang]: sin, cos, angle
@@ -254,6 +259,130 @@ SweepArgs base_args(const dpo_ctx* c) {
 
 bool use_fast(const dpo_ctx* c);
 
+// The LDS-brick evaluation sweeps are planned for the orbit model with the
+// Euler foot, a thrust step of less than one mass cell, and bricks of the
+// feet's reach that fit half of a CU's LDS.  The descriptor-driven form
+// (policy iteration) is the automatic choice wherever the descriptors are
+// stored per node (at least half of the nodes free); the form that recomputes
+// the foot from the control arrays only on request (eval path 2): the foot's
+// FP64 node terms and sin/cos make it arithmetic-bound, and the free-list
+// kernel is faster there.
+bool use_brick_desc(const dpo_ctx* c) { return c->brick_ok && c->eval_path != 1 && c->desc_format == 2; }
+bool use_brick_policy(const dpo_ctx* c) { return c->brick_ok && c->eval_path == 2; }
+
+// Halo of one brick tile: the signed reach of its nodes' feet along v_r and
+// v_t (in cells, over every r node and every control, from the FP64 node
+// terms the sweeps round, widened by 1e-3 cell), as rows below and above
+// the tile.  At least one row below: a foot clamped to the last cell (n - 2)
+// of a node on the last row reads the row below it.
+struct TileHalo {
+  int r0, r1, t0, t1;
+};
+
+TileHalo tile_halo(const dpo_ctx* c, int A, int tr, int C, int tt) {
+  const dpo_grid& g = c->grid;
+  const dpo_problem& p = c->prob;
+  const int a1 = std::min(A + tr, g.n[1]) - 1, c1 = std::min(C + tt, g.n[2]) - 1;
+  const double vr_a = g.lo[1] + A * c->G.h[1], vr_b = g.lo[1] + a1 * c->G.h[1];
+  const double vt_a = g.lo[2] + C * c->G.h[2], vt_b = g.lo[2] + c1 * c->G.h[2];
+  const double q_a = vt_a * vt_a, q_b = vt_b * vt_b;
+  const double vt2_max = std::max(q_a, q_b), vt2_min = (vt_a <= 0 && vt_b >= 0) ? 0.0 : std::min(q_a, q_b);
+  double lo1 = INFINITY, hi1 = -INFINITY, lo2 = INFINITY, hi2 = -INFINITY;
+  for (int i = 0; i < g.n[0]; i++) {
+    const double ri = 1.0 / (g.lo[0] + i * c->G.h[0]);
+    for (double vt2 : {vt2_min, vt2_max}) {
+      const double d = c->c1 * (vt2 * ri - p.mu * ri * ri);
+      lo1 = std::min(lo1, d);
+      hi1 = std::max(hi1, d);
+    }
+    for (double vr : {vr_a, vr_b})
+      for (double vt : {vt_a, vt_b}) {
+        const double d = -c->c2 * vr * vt * ri;
+        lo2 = std::min(lo2, d);
+        hi2 = std::max(hi2, d);
+      }
+  }
+  const double acc = p.accel / g.lo[3];
+  const double g1 = std::fabs(p.dt * acc * c->G.inv_h[1]) + 1e-3, g2 = std::fabs(p.dt * acc * c->G.inv_h[2]) + 1e-3;
+  TileHalo h;
+  h.r0 = std::max(1, -(int)std::floor(lo1 - g1));
+  h.r1 = std::max(0, (int)std::floor(hi1 + g1) + 1);
+  h.t0 = std::max(1, -(int)std::floor(lo2 - g2));
+  h.t1 = std::max(0, (int)std::floor(hi2 + g2) + 1);
+  return h;
+}
+
+// The brick tile (tr v_r rows by tt v_t rows, every r) with the least LDS
+// traffic per node whose largest brick fits half of a CU's LDS (two
+// workgroups per CU), and its per-tile halo table on the device.
+void plan_brick(dpo_ctx* c) {
+  c->brick_ok = false;
+  const dpo_grid& g = c->grid;
+  const dpo_problem& p = c->prob;
+  if (p.model != DPO_MODEL_ORBIT || p.integrator != DPO_STEP_EULER) return;
+  if (!(c->gm > -1.0f && c->gm <= 0.0f) || !(g.lo[0] > 0) || !(g.lo[3] > 0)) return;
+  // reach over the whole grid: a sanity bound on the halo sizes
+  const TileHalo all = tile_halo(c, 0, g.n[1], 0, g.n[2]);
+  if (all.r0 + all.r1 > 64 || all.t0 + all.t1 > 64) return;
+  const int n0 = g.n[0];
+  const size_t lds_cap = 80 * 1024;
+  double best = INFINITY;
+  BrickPlan B{};
+  std::vector<int4> best_halo;
+  for (int tr : {32, 16, 8, 4, 2, 1})
+    for (int tt : {16, 8, 4, 2, 1}) {
+      if (tr > g.n[1] || tt > g.n[2]) continue;
+      if (n0 * tr * tt > kBrickBlock * kBrickNodes) continue;
+      const int n_at = (g.n[1] + tr - 1) / tr, n_ct = (g.n[2] + tt - 1) / tt;
+      std::vector<int4> halo((size_t)n_at * n_ct);
+      size_t slot = 0;
+      double rows = 0;
+      for (int ct = 0; ct < n_ct; ct++)
+        for (int at = 0; at < n_at; at++) {
+          const TileHalo h = tile_halo(c, at * tr, tr, ct * tt, tt);
+          halo[(size_t)at + (size_t)n_at * ct] = make_int4(h.r0, h.r1, h.t0, h.t1);
+          const size_t br = tr + h.r0 + h.r1, bt = tt + h.t0 + h.t1;
+          slot = std::max(slot, br * bt * n0);
+          rows += (double)br * bt;
+        }
+      if (2 * slot * sizeof(float) > lds_cap) continue;
+      const size_t loads = (n0 % 4 == 0) ? slot / 4 : slot;
+      if (loads > (size_t)kBrickBlock * ((n0 % 4 == 0) ? kBrickMaxPf : 4 * kBrickMaxPf)) continue;
+      const double over = rows / ((double)n_at * n_ct * tr * tt);
+      if (over < best - 1e-9) {
+        best = over;
+        B.tr = tr;
+        B.tt = tt;
+        B.n_at = n_at;
+        B.n_ct = n_ct;
+        B.slot = (int)slot;
+        best_halo.swap(halo);
+      }
+    }
+  if (!(best < INFINITY)) return;
+  B.planes = 4;
+  B.n_mc = (g.n[3] + B.planes - 1) / B.planes;
+  if ((int64_t)B.n_at * B.n_ct * B.n_mc > 0x7fffffff) return;
+  if (prepare_eval_brick(B) != hipSuccess) return;
+  int4* d = nullptr;
+  if (hipMalloc(&d, sizeof(int4) * best_halo.size()) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  if (hipMemcpy(d, best_halo.data(), sizeof(int4) * best_halo.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(d);
+    return;
+  }
+  B.halo = d;
+  c->brick_halo = d;
+  c->brick = B;
+  c->brick_over = best;
+  c->brick_ok = true;
+}
+
+int brick_blocks(const dpo_ctx* c) { return c->brick.n_at * c->brick.n_ct * c->brick.n_mc; }
+
 // Final FP64 reduction of the last node kernel's partials into `out`.
 int finish_resid(dpo_ctx* c, double* out, hipStream_t s) {
   if (!out) return DPO_OK;
@@ -402,7 +531,9 @@ int sweep_full(dpo_ctx* c, const float* Vin, float* Vout, float* ang, uint8_t* t
     a.pol_ang_in = ang;
     a.pol_thr_in = thr;
   }
+  // descriptors describe the policy of the last sweep that wrote them
   if (desc && desc_ok(c)) set_desc_out(c, a);
+  else c->desc_valid = false;
   if (a.n_free == 0) return DPO_OK;
   int mode = c->search.mode == DPO_SEARCH_SCAN_GOLDEN ? 1 : 0;
   if (c->search.mode == DPO_SEARCH_TABLE_WALK && walk_from) {
@@ -431,6 +562,7 @@ int sweep_seeded(dpo_ctx* c, const float* Vin, float* Vout, float* ang, uint8_t*
   }
   a.seed = seed;
   if (desc && desc_ok(c)) set_desc_out(c, a);
+  else c->desc_valid = false;
   if (a.n_free == 0) return DPO_OK;
   if (!use_fast(c)) {
     hipError_t e = launch_sweep_direct(a, 2, s);
@@ -469,6 +601,14 @@ int sweep_eval(dpo_ctx* c, const float* Vin, float* Vout, const float* ang, cons
   a.pol_ang_in = ang;
   a.pol_thr_in = thr;
   if (a.n_free == 0) return DPO_OK;
+  if (use_brick_policy(c)) {
+    // streamed per sweep: angle, throttle and kind, and two value arrays
+    const bool streamed = 14.0 * (double)c->N > kLastLevelCacheBytes;
+    hipError_t e = launch_eval_brick(a, c->brick, c->kind, want_resid, streamed, s);
+    if (want_resid) c->last_blocks = brick_blocks(c);
+    if (e != hipSuccess) return hip_fail(c, e, "policy eval (brick) launch");
+    return DPO_OK;
+  }
   hipError_t e = launch_policy_eval(a, want_resid, s);
   if (want_resid) c->last_blocks = blocks_for(c->n_free, kBlock);
   if (e != hipSuccess) return hip_fail(c, e, "policy eval launch");
@@ -496,6 +636,12 @@ int sweep_eval_desc(dpo_ctx* c, const float* Vin, float* Vout, hipStream_t s) {
   // streamed per sweep: the per-node stream and two value arrays
   const double bytes = (double)eval_stream_bytes(c) + 8.0 * (double)c->N;
   const bool streamed = bytes > kLastLevelCacheBytes;
+  if (use_brick_desc(c)) {
+    a.desc_dense = 1;
+    hipError_t e = launch_eval_brick_desc(a, c->brick, streamed, s);
+    if (e != hipSuccess) return hip_fail(c, e, "policy eval (descriptor brick) launch");
+    return DPO_OK;
+  }
   hipError_t e = c->desc_format == 0 ? launch_policy_eval_desc(a, streamed, s)
                                      : launch_policy_eval_desc16(a, c->desc_format, streamed, s);
   if (e != hipSuccess) return hip_fail(c, e, "policy eval (descriptor) launch");
@@ -755,6 +901,7 @@ int dpo_create(const dpo_grid* grid, const dpo_problem* prob, const dpo_search* 
     // the factorised thrust kernel needs every thrust foot of a node within two
     // cells per moving axis and within one m cell
     c->fast_ok = gmax < 0.45 && gm > -1.0 && gm <= 0.0 && prob->integrator == DPO_STEP_EULER && !crown;
+    plan_brick(c);
     hipError_t e1 = hipMemcpy(c->rinv, rinv.data(), sizeof(double) * rinv.size(), hipMemcpyHostToDevice);
     hipError_t e2 = hipMemcpy(c->gtab, gt.data(), sizeof(float) * gt.size(), hipMemcpyHostToDevice);
     if (e1 != hipSuccess || e2 != hipSuccess) {
@@ -797,6 +944,7 @@ int dpo_create(const dpo_grid* grid, const dpo_problem* prob, const dpo_search* 
 void dpo_destroy(dpo_ctx* c) {
   if (!c) return;
   if (c->kind) hipFree(c->kind);
+  if (c->brick_halo) hipFree(c->brick_halo);
   if (c->free_node) hipFree(c->free_node);
   if (c->rinv) hipFree(c->rinv);
   if (c->gtab) hipFree(c->gtab);
@@ -922,6 +1070,25 @@ int dpo_policy_eval_sweep(dpo_ctx* c, const float* V_in, float* V_out, const flo
   int rc = sweep_eval(c, V_in, V_out, pol_angle, pol_thr, resid != nullptr, S(stream));
   if (rc != DPO_OK) return rc;
   return finish_resid(c, resid, S(stream));
+}
+
+int dpo_set_eval_path(dpo_ctx* c, int32_t path) {
+  if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
+  if (path < 0 || path > 2) return fail(c, DPO_EINVAL, "eval path must be 0 (auto), 1 (free list) or 2 (bricks)");
+  if (path == 2 && !c->brick_ok)
+    return fail(c, DPO_EINVAL, "the LDS-brick evaluation sweep needs the orbit model, the Euler foot and a "
+                               "thrust step of less than one mass cell");
+  c->eval_path = path;
+  return DPO_OK;
+}
+
+int dpo_eval_path(const dpo_ctx* c) {
+  if (!c) return -1;
+  if (desc_ok(c)) {
+    const int format = c->desc_format >= 0 ? c->desc_format : desc_format_for(c);
+    return c->brick_ok && c->eval_path != 1 && format == 2 ? 2 : 1;
+  }
+  return use_brick_policy(c) ? 2 : 1;
 }
 
 int dpo_policy_eval_sweep_last(dpo_ctx* c, const float* V_in, float* V_out, void* stream) {
@@ -1103,7 +1270,10 @@ int dpo_solve_pi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, doubl
   if (!seeded && c->search.mode == DPO_SEARCH_SEEDED) return fail(c, DPO_EINVAL, "SEEDED mode needs seed_angle");
   int rc = ensure_work(c);
   if (rc != DPO_OK) return rc;
-  if (desc_ok(c) && (rc = ensure_desc(c)) != DPO_OK) return rc;
+  // the evaluation sweeps read the greedy step's foot descriptors where the
+  // Euler foot applies, else the policy arrays
+  const bool desc = desc_ok(c);
+  if (desc && (rc = ensure_desc(c)) != DPO_OK) return rc;
   if ((rc = ensure_pi_buffers(c)) != DPO_OK) return rc;
   hipStream_t s = S(stream);
   const bool walk = c->search.mode == DPO_SEARCH_TABLE_WALK;
@@ -1134,8 +1304,8 @@ int dpo_solve_pi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, doubl
     float* G = cur == buf[0] ? buf[1] : buf[0];
     // greedy step: policy improvement together with T V
     const bool use_seed = seeded && it > 0 && !verify;
-    if (use_seed) rc = sweep_seeded(c, cur, G, pol_angle, pol_thr, seed_angle, s, true, true);
-    else rc = sweep_full(c, cur, G, pol_angle, pol_thr, s, true, it > 0, true, walk && it > 0 ? pol_angle : nullptr, true);
+    if (use_seed) rc = sweep_seeded(c, cur, G, pol_angle, pol_thr, seed_angle, s, desc, true);
+    else rc = sweep_full(c, cur, G, pol_angle, pol_thr, s, desc, it > 0, true, walk && it > 0 ? pol_angle : nullptr, true);
     if (rc != DPO_OK) return rc;
     it++;
     if ((rc = finish_resid(c, c->resid, s)) != DPO_OK) return rc;
@@ -1150,7 +1320,7 @@ int dpo_solve_pi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, doubl
           dst = b;
           break;
         }
-      rc = desc_ok(c) ? sweep_eval_desc(c, src, dst, s) : sweep_eval(c, src, dst, pol_angle, pol_thr, false, s);
+      rc = desc ? sweep_eval_desc(c, src, dst, s) : sweep_eval(c, src, dst, pol_angle, pol_thr, false, s);
       if (rc != DPO_OK) return rc;
       src = dst;
     }
@@ -1896,8 +2066,9 @@ int dpo_policy_eval_sweep_static(dpo_ctx* c, const float* V_in, float* V_out, co
   if (!c) return fail(nullptr, DPO_EINVAL, "ctx is NULL");
   if (!V_in || !V_out || !pol_angle || !pol_thr) return fail(c, DPO_EINVAL, "null array argument");
   if (V_in == V_out) return fail(c, DPO_EINVAL, "V_in and V_out must differ (Jacobi sweep)");
-  const int nb = blocks_for(c->n_free, kBlock);
-  if (nb > kStaticMaxBlocks)
+  const bool brick = use_brick_policy(c);
+  const int nb = brick ? brick_blocks(c) : blocks_for(c->n_free, kBlock);
+  if (blocks_for(c->n_free, kBlock) > kStaticMaxBlocks || nb > kStaticMaxBlocks)
     return fail(c, DPO_EINVAL, "dpo_policy_eval_sweep_static: more than 67,108,864 free nodes "
                                "(the static scratch holds 262,144 workgroup partials)");
   double* ptr = static_scratch(c);
@@ -1909,7 +2080,10 @@ int dpo_policy_eval_sweep_static(dpo_ctx* c, const float* V_in, float* V_out, co
   a.pol_ang_in = pol_angle;
   a.pol_thr_in = pol_thr;
   a.partial = ptr;
-  if (c->n_free > 0) HIP_TRY(c, launch_policy_eval(a, resid != nullptr, s));
+  if (c->n_free > 0) {
+    if (brick) HIP_TRY(c, launch_eval_brick(a, c->brick, c->kind, resid != nullptr, false, s));
+    else HIP_TRY(c, launch_policy_eval(a, resid != nullptr, s));
+  }
   // every workgroup writes its partial before the reduction reads it, so the
   // array needs no clearing; with no free node the reduction of zero
   // partials writes the zeros (a kernel, not a memset)

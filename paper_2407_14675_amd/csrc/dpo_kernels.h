@@ -160,6 +160,30 @@ hipError_t launch_probe_interp(const float* V, const Grid& G, float M, const flo
 hipError_t launch_probe_q(const SweepArgs& a, const int* nodes, const uint8_t* thr, const float* ang,
                           int n, float* q_out, float* off_out, hipStream_t s);
 
+// Frozen-policy sweep over a dense grid with value bricks in LDS
+// (dpo_brick.hip).  A workgroup of kBrickBlock threads owns every r of a
+// tile of tr v_r rows and tt v_t rows and walks `planes` mass planes upwards;
+// its LDS holds two planes of the brick its feet can reach: the tile plus,
+// per tile, halo.x rows below and halo.y above along v_r, halo.z below and
+// halo.w above along v_t (the reach of the feet of that tile's nodes).
+constexpr int kBrickBlock = 512;
+constexpr int kBrickMaxPf = 4;  // 16-byte loads per thread for one plane's brick, at most
+constexpr int kBrickNodes = 6;  // nodes of one plane of a tile per thread, at most
+constexpr int kBrickMaxRows = 32;  // v_r rows of a tile, at most
+struct BrickPlan {
+  int tr, tt, planes;
+  int n_at, n_ct, n_mc;  // tiles along v_r, v_t, mass chunks (workgroups = their product)
+  int slot;              // floats of one plane slot: the largest brick's rows times n0
+  const int4* halo;      // device, n_at * n_ct entries (tile at + n_at * ct)
+};
+size_t brick_lds_bytes(const BrickPlan& B);
+hipError_t launch_eval_brick(const SweepArgs& a, const BrickPlan& B, const uint8_t* kind, bool want_resid,
+                             bool streamed, hipStream_t s);
+// the same sweep driven by the dense per-node foot descriptors of the
+// greedy step (SweepArgs::desc16_in / desc_w_in, desc_dense)
+hipError_t launch_eval_brick_desc(const SweepArgs& a, const BrickPlan& B, bool streamed, hipStream_t s);
+hipError_t prepare_eval_brick(const BrickPlan& B);
+
 // Machine ceilings (dpo_ceiling.hip): a float4 streaming copy and read of n
 // floats (n a multiple of 4, 16-byte aligned) and a plain FP32 FMA loop of
 // blocks x 256 threads, each issuing iters x 8 FMAs.

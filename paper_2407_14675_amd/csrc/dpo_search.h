@@ -26,9 +26,9 @@ __device__ inline float drift_r(const SweepArgs& a, int i1) {
   return (float)(a.c0 * vr);
 }
 
-__device__ inline int node_terms_tab(const SweepArgs& a, uint32_t packed, NodeTerms& T) {
+// Node terms of the node whose grid coordinates are already in T.i.
+__device__ inline void node_terms_at(const SweepArgs& a, NodeTerms& T) {
 #pragma clang fp contract(off)
-  const int j = unpack_node(a.G, packed, T.i);
   T.drift[3] = 0.0f;
   if (a.P.model != 1) {
     const double ri = a.rinv[T.i[0]];
@@ -45,6 +45,11 @@ __device__ inline int node_terms_tab(const SweepArgs& a, uint32_t packed, NodeTe
   T.g1 = a.g1tab[T.i[3]];
   T.g2 = a.g2tab[T.i[3]];
   T.gm = a.gm;
+}
+
+__device__ inline int node_terms_tab(const SweepArgs& a, uint32_t packed, NodeTerms& T) {
+  const int j = unpack_node(a.G, packed, T.i);
+  node_terms_at(a, T);
   return j;
 }
 

@@ -92,6 +92,8 @@ def load():
         "dpo_policy_eval_sweep": [vp, vp, vp, vp, vp, vp, vp],
         "dpo_policy_eval_sweep_last": [vp, vp, vp, vp],
         "dpo_policy_eval_sweep_static": [vp, vp, vp, vp, vp, vp, vp],
+        "dpo_set_eval_path": [vp, i32],
+        "dpo_eval_path": [vp],
         "dpo_solve_vi": [vp, vp, vp, vp, dbl, i64, i32, C.POINTER(Stats), vp],
         "dpo_solve_pi": [vp, vp, vp, vp, dbl, i32, i64, vp, C.POINTER(Stats), vp],
         "dpo_policy_evaluate": [vp, vp, vp, vp, dbl, i32, C.POINTER(i64), C.POINTER(dbl), vp],
@@ -240,6 +242,14 @@ class Context:
     def set_kernel_path(self, path):
         """0 automatic, 1 direct 16-corner gathers, 2 factorised thrust kernel."""
         self._check(self.lib.dpo_set_kernel_path(self.h, int(path)))
+
+    def set_eval_path(self, path):
+        """Kernel of the policy-array evaluation sweeps: 0 automatic, 1 free
+        list (descriptors inside policy iteration), 2 LDS value bricks."""
+        self._check(self.lib.dpo_set_eval_path(self.h, int(path)))
+
+    def eval_path(self):
+        return self.lib.dpo_eval_path(self.h)
 
     def kernel_path(self):
         rc = self.lib.dpo_kernel_path(self.h)
