@@ -1,20 +1,24 @@
 """Benchmark of the semi-Lagrangian Bellman hot path on one MI355X.
 
-Workload: modified policy iteration on the 48^4 planar orbit-transfer grid
-(5,308,416 nodes) restricted to the reachability-masked active set; greedy
-step = coast + scan of 64 thrust angles + golden section (12 steps, 14
-evaluations); 20 frozen-policy sweeps per policy update; float32 value and
-policy, FP64 residual.  One step = one outer iteration of policy iteration
-(greedy sweep + residual reduction and read-back + 20 evaluation sweeps),
-run by the library's own solver loop.
+Workload (the largest single-GPU configuration): the 96 x 96 x 96 x 64
+planar orbit-transfer grid (56,623,104 nodes, 226.5 MB per float32 value
+array), thrust acceleration 1e-3, dt = 0.02, running cost 1 + 0.1*thrust,
+scan of 64 thrust angles + golden section (12 steps, 14 evaluations) + coast
+per greedy step, 20 frozen-policy evaluation sweeps per policy update;
+float32 values and policy, FP64 residual.  One step = one outer iteration of
+modified policy iteration (greedy sweep, residual reduction and read-back,
+20 evaluation sweeps), run by the library's own solver loop, from the state
+value iteration to a relative residual of 1e-3 leaves (the schedule's first
+phase, set-up).
 
-The mask comes from a 12^4 pre-solve on the device (value iteration, 16
-angles + coast): a 48^4 node is active where the coarse value interpolated at
-the node is below 0.98*M, dilated by one cell per axis.
-
-Prints one JSON line with the node-control evaluations per second, the
-roofline of the dominant kernel (the evaluation sweep, HBM-bound), the time to a converged
-value function, and the CPU oracle timed on a bounded sample.
+Prints one JSON line: node-control evaluations per second of the timed
+steps; the roofline of the dominant kernel (the evaluation sweep); the time
+to a converged value function (value iteration to 1e-3, policy iteration to
+1e-6, then on to the float32 floor, the accuracy that meets 1e-4 against the
+oracle); network-seeded and walk-seeded against plain policy iteration on the
+held-out thrust level; the CPU oracle timed on a bounded sample of the same
+workload; and, as further keys, the 48^4 reduced-grid workload, the batched
+solve, the paper's Example 1 and its variants.
 """
 import argparse
 import json
@@ -26,32 +30,31 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published peaks.  FP32 vector: 256 CUs x 2.4 GHz x 256 flops per
-# clock = 157.3 TFLOP/s, i.e. one wave64 FP32 instruction per SIMD every two
-# clocks (1.23e12 wave instructions/s over the chip); the sweep kernels use no
-# packed FP32 instructions.
+# MI355X published peaks.  HBM3E 8 TB/s.  FP32 vector 157.3 TFLOP/s is the
+# packed rate (256 CUs x 2.4 GHz x 256 flops per clock); the sweeps issue
+# ordinary (unpacked) VALU instructions, one wave64 instruction per SIMD every
+# four clocks: 256 x 4 x 2.4e9 / 4 = 6.14e11 wave instructions/s, 78.6
+# TFLOP/s of FMA.  bench measures both ceilings on the device beside them.
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TFLOPS = 157.3
+VALU_UNPACKED_WAVE_INSTR_PER_S = 256 * 4 * 2.4e9 / 4
 
-# Algorithmic HBM bytes of one frozen-policy evaluation sweep: reported by
-# the library (dpo_eval_sweep_bytes): per free node the value written (4),
-# its share of the value array read once (4) and the foot descriptor stream
-# (packed coordinates 4 + 16-bit cell code 2 + weights in v_r and v_t 8 on
-# the 48^4 masked grid).
+# Algorithmic HBM bytes of one frozen-policy evaluation per node: the value
+# read (4), the value written (4), the stored control (4) and the node's
+# index (4).  The descriptor form the library streams instead of the control
+# and the index is 10 bytes (16-bit cell code + the two cell coordinates).
+EVAL_ALGO_BYTES_PER_NODE = 16
 # Greedy sweep: packed coordinates (4) + value read (4) + value, angle and
 # throttle written (4 + 4 + 1) + the compact foot descriptor written (2 + 8).
 GREEDY_BYTES_PER_NODE = 27
-# the evaluation-sweep kernel that runs for each descriptor form (bytes per
-# free node, the per-node form: 18 + 2 per fixed node)
-EVAL_KERNEL_BY_BYTES = {24: "k_policy_eval_desc<0>", 22: "k_policy_eval_d16<false, 0, 1>",
-                        18: "k_policy_eval_d16<true, 0, 1>"}
+EVALS_PER_GREEDY_NODE = 1 + 64 + 2 + 12
 # Gather bytes of one evaluation done naively: 16 float32 corners.
 GATHER_BYTES_PER_EVAL = 64
 
 # HBM traffic of the evaluation sweep measured with rocprofv3 counters, with
 # the hash of the kernel sources it was measured on.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_policy_eval_desc_pi_48x4_masked_traffic.json")
-KERNEL_SOURCES = ["dpo_kernels.hip", "dpo_device.h", "dpo_kernels.h", "dpo_search.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_eval_brick_desc_96x96x96x64_traffic.json")
+KERNEL_SOURCES = ["dpo_brick.hip", "dpo_kernels.hip", "dpo_device.h", "dpo_kernels.h", "dpo_search.h"]
 
 
 def kernel_source_hash():
@@ -131,19 +134,18 @@ def measure_ceilings(reps=10):
     }
 
 
-def cpu_baseline(problem, seconds=12.0, seed=17):
-    """The FP64 oracle on a bounded random sample of 48^4 nodes: one greedy
-    step (coast + 64 scan + 14 golden) and 20 frozen-policy evaluations per
-    sampled node, on one host thread."""
+def cpu_baseline(problem, V, seconds=12.0, seed=17):
+    """The FP64 oracle on a bounded random sample of the workload's nodes: one
+    greedy step (coast + 64 scan + 14 golden) and 20 frozen-policy evaluations
+    per sampled node, at the value the timed steps start from, on one host
+    thread."""
     import numpy as np
 
     from oracle.core import Oracle
-    from paper_2407_14675_amd import inputs
 
     o = Oracle(problem)
-    V = inputs.random_value(problem, seed=seed, low=0.0, high=30.0)
     rng = np.random.default_rng(seed)
-    evals_per_node = 1 + 64 + 14 + 20
+    evals_per_node = EVALS_PER_GREEDY_NODE + 20
     done_nodes = 0
     t0 = time.perf_counter()
     chunk = 2000
@@ -154,13 +156,14 @@ def cpu_baseline(problem, seconds=12.0, seed=17):
             o.q_many(V, nodes, thr, ang)
         done_nodes += chunk
     dt = time.perf_counter() - t0
+    shape = "x".join(str(k) for k in problem["n"])
     return {
         "value": done_nodes * evals_per_node / dt,
         "unit": "node-control evals/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"{done_nodes} random 48^4 nodes x (1 coast + 64 scan + 14 golden + 20 policy evals), "
-                  f"FP64, single thread, {dt:.1f} s",
+        "sample": f"{done_nodes} random nodes of the {shape} grid x (1 coast + 64 scan + 14 golden + 20 policy "
+                  f"evals), at the value the timed steps start from, FP64, single thread, {dt:.1f} s",
     }
 
 
@@ -292,139 +295,153 @@ def one_gpu_share(p, full_greedy_ms, full_eval_ms, gpus=8):
             "full_grid_greedy_ms_over_gpus": full_greedy_ms / gpus, "full_grid_eval_ms_over_gpus": full_eval_ms / gpus}
 
 
-def bench_large(accels=(1e-3,), with_seeded=True):
-    """96 x 96 x 96 x 64 problems (dt 0.02, fuel weight 0.1): value iteration
-    to 1e-3, policy iteration to 1e-6 and on to the float32 floor (the
-    reference solution); then, for the first thrust level, plain policy
-    iteration from V0 against policy iteration seeded by the control-proposal
-    network trained on the reference solution (2M pairs, 20 epochs), each
-    timed to 1e-6 and on to the floor and compared with the reference."""
+def solve_to_floor(ctx, V, a, t, schedule, seed=None, free=None, ref=None):
+    """A timed solve from the value in V: `schedule` = "vi_pi" (value
+    iteration to 1e-3, then policy iteration to 1e-6: the workload's
+    schedule) or "pi" (policy iteration from V); with seed, the first policy
+    iteration runs seeded (the context's search must be SEEDED and is reset
+    to the full search after it).  Then policy iteration on with the full
+    search to the float32 floor (3e-7 or a stall).  Returns the record with
+    the times of both stops and, with ref, the distance from it."""
+    import torch
+
+    from paper_2407_14675_amd import inputs
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vi = None
+    if schedule == "vi_pi":
+        rc, vi = ctx.solve_vi(V, a, t, tol_rel=1e-3, max_sweeps=20000, check_every=16)
+        torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rc, st = ctx.solve_pi(V, a, t, tol_rel=1e-6, eval_sweeps=inputs.EVAL_SWEEPS, max_outer=3000, seed=seed)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    rec = {"vi_sweeps": vi["sweeps"] if vi else 0, "vi_seconds": t1 - t0, "pi_outer": st["sweeps"],
+           "pi_eval_sweeps": st["eval_sweeps"], "pi_seconds": t2 - t1, "seconds_to_1e-6": t2 - t0,
+           "evals": (vi["evals"] if vi else 0) + st["evals"], "converged": bool(st["converged"]),
+           "resid_max_rel": st["resid_max_rel"]}
+    if seed is not None:
+        rec["verify_steps"] = st["verify_steps"]
+        rec["fallback_nodes"] = st["fallback_nodes"]
+        ctx.set_search(inputs.SCAN_GOLDEN)
+    if ref is not None and free is not None:
+        rec["max_rel_diff_vs_reference_at_1e-6"], _ = rel_diff(V, ref, free)
+    fl = to_float32_floor(ctx, V, a, t, inputs.EVAL_SWEEPS, free, ref=ref)
+    rec["to_float32_floor"] = fl
+    rec["seconds_to_float32_floor"] = rec["seconds_to_1e-6"] + fl["extra_seconds"]
+    rec["V_x0"] = ctx.value_at(V, inputs.X0)
+    return rec
+
+
+def train_network(ctx, V, a, t):
+    """The control-proposal network trained on a converged solution: 2M
+    (state, control) pairs from the free nodes with V < 0.98 M, 20 epochs of
+    Adam in batches of 4096, on the device.  Returns the network and the
+    record (seconds include drawing the pairs)."""
     import torch
 
     from paper_2407_14675_amd import dpo, inputs
 
-    out = {"grid": [96, 96, 96, 64], "problems": []}
-    net = None
-    for accel in accels:
-        p = inputs.large_problem(accel=accel)
-        ctx = dpo.Context(p)
-        free = ctx.kind() == 0
-        V = ctx.init_value()
-        a, t = ctx.empty_policy()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rc1, st1 = ctx.solve_vi(V, a, t, tol_rel=1e-3, max_sweeps=20000, check_every=16)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        rc2, st2 = ctx.solve_pi(V, a, t, tol_rel=1e-6, eval_sweeps=20, max_outer=3000)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        rec = {
-            "accel": accel, "nodes": ctx.N, "free_nodes": ctx.n_free,
-            "vi_sweeps": st1["sweeps"], "vi_seconds": t1 - t0,
-            "pi_outer": st2["sweeps"], "pi_eval_sweeps": st2["eval_sweeps"], "pi_seconds": t2 - t1,
-            "seconds": t2 - t0, "converged": bool(st2["converged"]), "resid_max_rel": st2["resid_max_rel"],
-            "V_x0": ctx.value_at(V, inputs.X0),
-        }
-        # the reference from here on is the float32-floor solution
-        rec["to_float32_floor"] = to_float32_floor(ctx, V, a, t, 20, free)
-        rec["seconds_to_float32_floor"] = rec["seconds"] + rec["to_float32_floor"]["extra_seconds"]
-        if accel == accels[0]:
-            g, e = sweep_times(ctx, V)
-            rec["sweep_ms"] = {"greedy": g, "eval": e}
-            rec["one_gpu_share"] = one_gpu_share(p, g, e)
-        log(f"bench: large a={accel}: {rec}")
-        # plain policy iteration from V0 (same stop rule), compared with the reference
-        Vp = ctx.init_value()
-        ap, tp = ctx.empty_policy()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rc, stp = ctx.solve_pi(Vp, ap, tp, tol_rel=1e-6, eval_sweeps=20, max_outer=3000)
-        torch.cuda.synchronize()
-        rec["pi_from_v0"] = {"seconds": time.perf_counter() - t0, "outer": stp["sweeps"], "evals": stp["evals"],
-                             "converged": bool(stp["converged"])}
-        rec["pi_from_v0"]["max_rel_diff_vs_reference"], rec["pi_from_v0"]["nodes_over_1e-4"] = rel_diff(Vp, V, free)
-        rec["pi_from_v0"]["to_float32_floor"] = to_float32_floor(ctx, Vp, ap, tp, 20, free, ref=V)
-        del Vp, ap, tp
-        if accel == accels[0]:
-            # walk-seeded: the seeds are the previous greedy step's own angles
-            # (the paper's warm start applied to the continuous search)
-            ctx.set_search(inputs.SEEDED)
-            Vw = ctx.init_value()
-            aw, tw = ctx.empty_policy()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            rc, stw = ctx.solve_pi(Vw, aw, tw, tol_rel=1e-6, eval_sweeps=20, max_outer=3000, seed=aw)
-            torch.cuda.synchronize()
-            sec = time.perf_counter() - t0
-            rec["walk_seeded"] = {"seconds": sec, "outer": stw["sweeps"], "verify_steps": stw["verify_steps"],
-                                  "evals": stw["evals"], "converged": bool(stw["converged"]),
-                                  "speedup_vs_plain_pi": rec["pi_from_v0"]["seconds"] / sec,
-                                  "eval_ratio_vs_plain_pi": rec["pi_from_v0"]["evals"] / max(1, stw["evals"])}
-            rec["walk_seeded"]["max_rel_diff_vs_reference"], rec["walk_seeded"]["nodes_over_1e-4"] = rel_diff(Vw, V, free)
-            ctx.set_search(inputs.SCAN_GOLDEN)
-            rec["walk_seeded"]["to_float32_floor"] = fl = to_float32_floor(ctx, Vw, aw, tw, 20, free, ref=V)
-            plain = rec["pi_from_v0"]
-            rec["walk_seeded"]["speedup_vs_plain_pi_to_floor"] = (
-                (plain["seconds"] + plain["to_float32_floor"]["extra_seconds"]) / (sec + fl["extra_seconds"]))
-            log(f"bench: large a={accel} walk-seeded {rec['walk_seeded']}")
-            del Vw, aw, tw
-        if with_seeded:
-            if net is None:
-                nodes = ctx.feasible_nodes(V, inputs.MLP_FEASIBLE_FRAC * p["M"])
-                sel = inputs.mlp_pair_selection(nodes.numel())
-                x, tgt = ctx.gather_pairs(nodes, sel, a, t)
-                net = dpo.Mlp(inputs.mlp_params32())
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                for order in inputs.mlp_epoch_orders(x.shape[0]):
-                    hist = net.train_epoch(x, tgt, perm=order, batch=inputs.MLP_BATCH)
-                torch.cuda.synchronize()
-                train_s = time.perf_counter() - t0
-                samples = x.shape[0] * inputs.MLP_EPOCHS
-                rec["mlp_training"] = {
-                    "pairs": int(x.shape[0]), "feasible_nodes": int(nodes.numel()), "epochs": inputs.MLP_EPOCHS,
-                    "batch": inputs.MLP_BATCH, "seconds": train_s, "final_loss": float(hist.mean()),
-                    "tflops": samples * MLP_FLOPS_PER_SAMPLE / train_s / 1e12,
-                    "mfma_bf16_peak_tflops": 2500.0,
-                }
-                del x, tgt, nodes
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            seed = net.propose(ctx)
-            torch.cuda.synchronize()
-            prop_s = time.perf_counter() - t0
-            ctx.set_search(inputs.SEEDED)
-            Vs = ctx.init_value()
-            as_, ts = ctx.empty_policy()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            rc, sts = ctx.solve_pi(Vs, as_, ts, tol_rel=1e-6, eval_sweeps=20, max_outer=3000, seed=seed)
-            torch.cuda.synchronize()
-            sec = time.perf_counter() - t0
-            greedy_nodes = ctx.n_free * max(1, sts["sweeps"] - 1 - sts["verify_steps"])
-            rec["nn_seeded"] = {
-                "seconds": sec, "propose_seconds": prop_s, "outer": sts["sweeps"], "verify_steps": sts["verify_steps"],
-                "evals": sts["evals"], "fallback_fraction": sts["fallback_nodes"] / greedy_nodes,
-                "converged": bool(sts["converged"]),
-                "speedup_vs_plain_pi": rec["pi_from_v0"]["seconds"] / sec,
-                "eval_ratio_vs_plain_pi": rec["pi_from_v0"]["evals"] / max(1, sts["evals"]),
-                "held_out": accel != accels[0],
-            }
-            rec["nn_seeded"]["max_rel_diff_vs_reference"], rec["nn_seeded"]["nodes_over_1e-4"] = rel_diff(Vs, V, free)
-            # on to the floor with the full search: a seeded phase would drift
-            # towards the local search's own fixed point, which a full step has
-            # already rejected at 1e-6
-            ctx.set_search(inputs.SCAN_GOLDEN)
-            rec["nn_seeded"]["to_float32_floor"] = fl = to_float32_floor(ctx, Vs, as_, ts, 20, free, ref=V)
-            plain = rec["pi_from_v0"]
-            rec["nn_seeded"]["speedup_vs_plain_pi_to_floor"] = (
-                (plain["seconds"] + plain["to_float32_floor"]["extra_seconds"]) / (sec + fl["extra_seconds"]))
-            del Vs, as_, ts, seed
-            log(f"bench: large a={accel} seeded {rec['nn_seeded']}")
-        out["problems"].append(rec)
-        del V, a, t, free
-        ctx.close()
+    p = ctx.problem
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nodes = ctx.feasible_nodes(V, inputs.MLP_FEASIBLE_FRAC * p["M"])
+    sel = inputs.mlp_pair_selection(nodes.numel())
+    x, tgt = ctx.gather_pairs(nodes, sel, a, t)
+    net = dpo.Mlp(inputs.mlp_params32())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hist = None
+    for order in inputs.mlp_epoch_orders(x.shape[0]):
+        hist = net.train_epoch(x, tgt, perm=order, batch=inputs.MLP_BATCH)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    samples = x.shape[0] * inputs.MLP_EPOCHS
+    rec = {"pairs": int(x.shape[0]), "feasible_nodes": int(nodes.numel()), "epochs": inputs.MLP_EPOCHS,
+           "batch": inputs.MLP_BATCH, "seconds": t2 - t0, "pair_seconds": t1 - t0, "train_seconds": t2 - t1,
+           "final_loss": float(hist.mean()), "tflops": samples * MLP_FLOPS_PER_SAMPLE / (t2 - t1) / 1e12,
+           "mfma_bf16_peak_tflops": 2500.0}
+    del x, tgt, nodes
+    return net, rec
+
+
+def bench_converge_and_learned(with_walk=True):
+    """96 x 96 x 96 x 64, thrust 1e-3: the workload's schedule from V0 to
+    1e-6 and on to the float32 floor (the reference), and plain policy
+    iteration from V0 (to 1e-6 and the floor) against it; walk-seeded policy
+    iteration (seeds = the previous greedy angles); the network trained on
+    the reference; then the held-out thrust 5e-4: plain policy iteration
+    from V0 against network-seeded policy iteration (proposal, seeded phase,
+    full-search certification) to the floor, the seeded time counted with
+    and without the training."""
+    import torch
+
+    from paper_2407_14675_amd import dpo, inputs
+
+    out = {"grid": [96, 96, 96, 64]}
+    p = inputs.large_problem(accel=1e-3)
+    ctx = dpo.Context(p)
+    free = ctx.kind() == 0
+    V = ctx.init_value()
+    a, t = ctx.empty_policy()
+    ref = solve_to_floor(ctx, V, a, t, "vi_pi", free=free)
+    out["reference_a1e-3"] = ref
+    log(f"bench: 96^3 x 64 reference {ref}")
+    Vp = ctx.init_value()
+    ap, tp = ctx.empty_policy()
+    out["plain_pi_a1e-3"] = plain = solve_to_floor(ctx, Vp, ap, tp, "pi", free=free, ref=V)
+    log(f"bench: plain PI a=1e-3 {plain}")
+    del Vp, ap, tp
+    if with_walk:
+        ctx.set_search(inputs.SEEDED)
+        Vw = ctx.init_value()
+        aw, tw = ctx.empty_policy()
+        walk = solve_to_floor(ctx, Vw, aw, tw, "pi", seed=aw, free=free, ref=V)
+        walk["speedup_vs_plain_pi_to_floor"] = plain["seconds_to_float32_floor"] / walk["seconds_to_float32_floor"]
+        walk["speedup_vs_plain_pi_to_1e-6"] = plain["seconds_to_1e-6"] / walk["seconds_to_1e-6"]
+        walk["eval_ratio_vs_plain_pi"] = plain["evals"] / max(1, walk["evals"])
+        out["walk_seeded_pi_a1e-3"] = walk
+        log(f"bench: walk-seeded PI a=1e-3 {walk}")
+        del Vw, aw, tw
+    net, out["mlp_training"] = train_network(ctx, V, a, t)
+    log(f"bench: network {out['mlp_training']}")
+    del V, a, t, free
+    ctx.close()
+    torch.cuda.empty_cache()
+
+    # held-out thrust level
+    q = inputs.large_problem(accel=5e-4)
+    cq = dpo.Context(q)
+    free = cq.kind() == 0
+    Vq = cq.init_value()
+    aq, tq = cq.empty_policy()
+    out["plain_pi_a5e-4"] = plain = solve_to_floor(cq, Vq, aq, tq, "pi", free=free)
+    log(f"bench: plain PI a=5e-4 {plain}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seed = net.propose(cq)
+    torch.cuda.synchronize()
+    prop_s = time.perf_counter() - t0
+    cq.set_search(inputs.SEEDED)
+    Vs = cq.init_value()
+    as_, ts = cq.empty_policy()
+    seeded = solve_to_floor(cq, Vs, as_, ts, "pi", seed=seed, free=free, ref=Vq)
+    greedy_nodes = cq.n_free * max(1, seeded["pi_outer"] - 1 - seeded["verify_steps"])
+    seeded["fallback_fraction"] = seeded["fallback_nodes"] / greedy_nodes
+    seeded["propose_seconds"] = prop_s
+    seeded["held_out"] = True
+    with_prop = seeded["seconds_to_float32_floor"] + prop_s
+    seeded["speedup_vs_plain_pi_to_floor"] = plain["seconds_to_float32_floor"] / with_prop
+    seeded["speedup_vs_plain_pi_to_floor_incl_training"] = (
+        plain["seconds_to_float32_floor"] / (with_prop + out["mlp_training"]["seconds"]))
+    seeded["speedup_vs_plain_pi_to_1e-6"] = plain["seconds_to_1e-6"] / (seeded["seconds_to_1e-6"] + prop_s)
+    seeded["eval_ratio_vs_plain_pi"] = plain["evals"] / max(1, seeded["evals"])
+    out["nn_seeded_pi_a5e-4"] = seeded
+    log(f"bench: network-seeded PI a=5e-4 {seeded}")
+    del Vs, as_, ts, seed, Vq, aq, tq, free
+    cq.close()
+    torch.cuda.empty_cache()
     return out
 
 
@@ -627,45 +644,32 @@ def orbit_raise(p, V, x_start, horizon_s=5e5, batch=4096, cpu=True):
     return out
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-converge", action="store_true", help="skip the time-to-converge run")
-    ap.add_argument("--path", type=int, default=0, help="sweep kernel path: 0 auto, 1 direct, 2 factorised")
-    ap.add_argument("--no-batched", action="store_true", help="skip the batched 16-problem measurement")
-    ap.add_argument("--no-large", action="store_true",
-                    help="skip the 96^3 x 64 solves and the network-seeded comparison")
-    ap.add_argument("--no-variants", action="store_true", help="skip the table-walk and Heun-foot solves")
-    ap.add_argument("--no-example1", action="store_true", help="skip the paper's Example 1 solves")
-    ap.add_argument("--held-out", action="store_true",
-                    help="also solve the 96^3 x 64 problem with thrust 5e-4 using the network trained at 1e-3")
-    ap.add_argument("--calib-copy", action="store_true",
-                    help="first run one plain 512 MiB device copy (reference for HBM byte counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); sharding the grid along the mass "
-              f"axis over several GPUs is not implemented.", file=sys.stderr)
-        sys.exit(2)
+def kernel_launch_ms(ctx, fn, stream, reps=20):
+    """Average duration of one launch of fn (event-timed over reps
+    back-to-back launches on the library's stream, after one untimed)."""
+    import torch
 
-    import numpy as np
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    ev0.record(stream)
+    for _ in range(reps):
+        fn()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / reps
+
+
+def bench_reduced_grid(steps, warmup, with_variants=True):
+    """The 48^4 grid restricted to the reachability-masked active set (mask
+    from a 12^4 pre-solve: the coarse value interpolated at a fine node below
+    0.98*M, dilated by one cell per axis): timed policy-iteration steps, the
+    time to a converged value (1e-6, then the float32 floor), and the paper's
+    variants on the same grid.  At this size the working set sits in the
+    last-level cache, so its sweeps are cache- and latency-bound, not HBM-bound."""
     import torch
 
     from paper_2407_14675_amd import dpo, inputs
 
-    torch.cuda.set_device(0)
-    dev = torch.device("cuda:0")
-    if args.calib_copy:
-        src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    log("bench: setup")
-
-    # ---- reduced grid from the 12^4 pre-solve (setup, not timed)
     t_setup = time.perf_counter()
     c0 = dpo.Context(inputs.VI12)
     Vc = c0.init_value()
@@ -674,20 +678,92 @@ def main():
     p1 = inputs.PI48
     mask = c0.mask_from_coarse(Vc, p1, inputs.MASK_THRESHOLD_FRAC * p1["M"], inputs.MASK_DILATE)
     ctx = dpo.Context(p1, mask=mask)
-    ctx.set_kernel_path(args.path)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
-    n_free = ctx.n_free
-    log(f"bench: active free nodes {n_free} of {ctx.N} ({n_free / ctx.N:.3f}), setup {setup_s:.2f}s")
-
+    E = inputs.EVAL_SWEEPS
     V = ctx.init_value()
     ang, thr = ctx.empty_policy()
-    E = inputs.EVAL_SWEEPS
+    if warmup > 0:
+        ctx.solve_pi(V, ang, thr, tol_rel=0.0, eval_sweeps=E, max_outer=warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, st = ctx.solve_pi(V, ang, thr, tol_rel=0.0, eval_sweeps=E, max_outer=steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    W = V.clone()
+    greedy_ms = kernel_launch_ms(ctx, lambda: ctx.bellman_sweep(V, W, ang, thr), stream)
+    eval_ms = kernel_launch_ms(ctx, lambda: ctx.policy_eval_sweep_last(V, W), stream)
+    n_free = ctx.n_free
+    out = {"grid": list(p1["n"]), "active_free_nodes": int(n_free), "active_fraction": n_free / ctx.N,
+           "setup_seconds": setup_s, "steps": st["sweeps"], "ms_per_step": elapsed * 1e3 / max(1, st["sweeps"]),
+           "evals_per_s": st["evals"] / elapsed, "greedy_ms": greedy_ms, "eval_ms": eval_ms,
+           "eval_bound": "last-level cache / latency (the working set fits the 256 MiB cache)",
+           "eval_sweep_bytes": ctx.eval_sweep_bytes()}
+    Vc1 = ctx.init_value()
+    ac, tc = ctx.empty_policy()
+    out["time_to_converge"] = conv = solve_to_floor(ctx, Vc1, ac, tc, "pi", free=ctx.kind() == 0)
+    log(f"bench: 48^4 {out}")
+    if with_variants:
+        log("bench: paper variants (table walk, Heun foot)")
+        out["paper_variants"] = bench_variants(mask, Vc1)
+    del Vc1, ac, tc, V, W
+    ctx.close()
+    return out
 
-    # ---- warmup
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baselines")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="only the timed steps and the kernel timings of the headline workload")
+    ap.add_argument("--no-converge", action="store_true",
+                    help="skip the 96^3 x 64 solves to convergence and the seeded comparisons")
+    ap.add_argument("--no-reduced", action="store_true", help="skip the 48^4 reduced-grid workload")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched 16-problem measurement")
+    ap.add_argument("--no-example1", action="store_true", help="skip the paper's Example 1 solves")
+    ap.add_argument("--no-ceilings", action="store_true", help="skip the HBM and VALU ceiling probes")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run one 1 GiB copy with the library's probe (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); sharding the grid along the mass "
+              f"axis over several GPUs is not implemented.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2407_14675_amd import dpo, inputs
+
+    torch.cuda.set_device(0)
+    if args.calib_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dpo.probe_copy(src, dst)
+        torch.cuda.synchronize()
+        del src, dst
+    log("bench: setup")
+
+    # ---- headline workload: 96 x 96 x 96 x 64, thrust 1e-3
+    t_setup = time.perf_counter()
+    p = inputs.large_problem(accel=1e-3)
+    ctx = dpo.Context(p)
+    n_free = ctx.n_free
+    V = ctx.init_value()
+    ang, thr = ctx.empty_policy()
+    rc, st_vi = ctx.solve_vi(V, ang, thr, tol_rel=1e-3, max_sweeps=20000, check_every=16)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_setup
+    eval_path = ctx.eval_path()
+    log(f"bench: set-up {setup_s:.2f} s (value iteration to 1e-3: {st_vi['sweeps']} sweeps), eval path {eval_path}")
+    E = inputs.EVAL_SWEEPS
     if args.warmup > 0:
         ctx.solve_pi(V, ang, thr, tol_rel=0.0, eval_sweeps=E, max_outer=args.warmup)
     torch.cuda.synchronize()
+    V_start = V.clone()
 
     # ---- timed region: K outer iterations of modified policy iteration
     torch.cuda.synchronize()
@@ -695,157 +771,138 @@ def main():
     rc, st = ctx.solve_pi(V, ang, thr, tol_rel=0.0, eval_sweeps=E, max_outer=args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    evals = st["evals"]
-    value = evals / elapsed
-    log(f"bench: {args.steps} steps in {elapsed:.4f}s, {value:.3e} evals/s")
+    steps_done = st["sweeps"]
+    value = st["evals"] / elapsed
+    log(f"bench: {steps_done} steps in {elapsed:.4f}s, {value:.3e} evals/s")
 
     # ---- kernel timings by HIP events on the stream the library launches on
-    # (torch's current stream).  The evaluation sweep takes E of every E + 1
-    # sweeps of a step and dominates the step time; the greedy sweep is the
-    # arithmetic-bound one.
+    # (torch's current stream): the greedy sweep of the current value, then
+    # the evaluation sweep of its policy (the kernel policy iteration runs)
     stream = torch.cuda.current_stream()
     W = V.clone()
-    reps = 20
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ctx.bellman_sweep(V, W, ang, thr)
-    ev0.record(stream)
-    for _ in range(reps):
-        ctx.bellman_sweep(V, W, ang, thr)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    greedy_ms = ev0.elapsed_time(ev1) / reps
-    evals_per_greedy = n_free * (1 + 64 + 2 + 12)
-    greedy_evals_s = evals_per_greedy / (greedy_ms * 1e-3)
-    # evaluation sweep of policy iteration (descriptors of the greedy sweep above)
-    ctx.policy_eval_sweep_last(V, W)
-    ev0.record(stream)
-    for _ in range(reps):
-        ctx.policy_eval_sweep_last(V, W)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    eval_ms = ev0.elapsed_time(ev1) / reps
-    log(f"bench: greedy sweep {greedy_ms:.4f} ms ({greedy_evals_s:.3e} evals/s), eval sweep {eval_ms:.4f} ms")
-    eval_bytes = ctx.eval_sweep_bytes()
-    eval_gbs = eval_bytes / (eval_ms * 1e-3) / 1e9
+    greedy_ms = kernel_launch_ms(ctx, lambda: ctx.bellman_sweep(V, W, ang, thr), stream)
+    eval_ms = kernel_launch_ms(ctx, lambda: ctx.policy_eval_sweep_last(V, W), stream)
+    eval_algo_bytes = EVAL_ALGO_BYTES_PER_NODE * n_free
+    eval_gbs = eval_algo_bytes / (eval_ms * 1e-3) / 1e9
+    stream_bytes = ctx.eval_sweep_bytes()
+    greedy_evals = n_free * EVALS_PER_GREEDY_NODE
+    log(f"bench: greedy sweep {greedy_ms:.4f} ms, eval sweep {eval_ms:.4f} ms ({eval_gbs:.0f} GB/s algorithmic)")
     traffic = measured_traffic()
-    step_bytes = GREEDY_BYTES_PER_NODE * n_free + E * eval_bytes
-    step_gbs = step_bytes / (elapsed / args.steps) / 1e9
+    step_ms = elapsed * 1e3 / max(1, steps_done)
 
-    # ---- time to a converged value function from V0 (separate run)
-    converge = None
-    if not args.no_converge:
-        Vc1 = ctx.init_value()
-        ac, tc = ctx.empty_policy()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        rc2, st2 = ctx.solve_pi(Vc1, ac, tc, tol_rel=1e-6, eval_sweeps=E, max_outer=3000)
-        torch.cuda.synchronize()
-        converge = {
-            "seconds": time.perf_counter() - t1,
-            "outer_iterations": st2["sweeps"],
-            "eval_sweeps": st2["eval_sweeps"],
-            "converged": bool(st2["converged"]),
-            "resid_max_rel": st2["resid_max_rel"],
-            "tol_rel": 1e-6,
-            "V_x0": ctx.value_at(Vc1, inputs.X0),
-        }
-        converge["to_float32_floor"] = to_float32_floor(ctx, Vc1.clone(), ac.clone(), tc.clone(), E,
-                                                         ctx.kind() == 0)
-        # the time at which the solve meets 1e-4 against the oracle's converged
-        # solution (tests/test_gpu_converged48.py: the 1e-6 stop is 1.05e-4 away
-        # at its worst sampled node, the floor 9.1e-6)
-        converge["seconds_to_float32_floor"] = converge["seconds"] + converge["to_float32_floor"]["extra_seconds"]
-        log(f"bench: converge {converge}")
-
-    variants = None
-    if not args.no_variants and converge is not None:
-        log("bench: paper variants (table walk, Heun foot)")
-        variants = bench_variants(mask, Vc1)
-
-    example1 = None
-    if not args.no_example1:
-        log("bench: the paper's Example 1 (crown grid)")
-        example1 = bench_example1(with_cpu=not args.no_cpu)
-
-    large = None
-    if not args.no_large:
-        log("bench: 96^3 x 64 solves")
-        large = bench_large(accels=(1e-3, 5e-4) if args.held_out else (1e-3,))
-
-    batched = None
-    if not args.no_batched:
-        log("bench: batched 16-problem solve")
-        batched = bench_batched()
-        log(f"bench: batched {batched}")
-        # the same draws on grids a quarter of the side (6..16): sweeps of a
-        # few microseconds, where launches and stop checks weigh
-        batched["small_grids"] = bench_batched(side_scale=0.25)
-        log(f"bench: batched small {batched['small_grids']}")
+    one_share = None
+    if not args.only_headline:
+        one_share = one_gpu_share(p, greedy_ms, eval_ms)
+        log(f"bench: one GPU's share {one_share}")
 
     cpu = None
     if not args.no_cpu:
         log("bench: cpu baseline")
-        cpu = cpu_baseline(p1)
+        cpu = cpu_baseline(p, V_start.cpu().numpy().astype("float64"))
         log(f"bench: cpu {cpu}")
+    del V_start, W
+    ctx.close()
+    torch.cuda.empty_cache()
+
+    ceilings = None
+    if not args.no_ceilings and not args.only_headline:
+        ceilings = measure_ceilings()
+        log(f"bench: ceilings {ceilings}")
+
+    converge = None
+    if not args.no_converge and not args.only_headline:
+        log("bench: 96^3 x 64 solves to convergence, walk- and network-seeded")
+        converge = bench_converge_and_learned()
+
+    reduced = None
+    if not args.no_reduced and not args.only_headline:
+        log("bench: 48^4 reduced grid")
+        reduced = bench_reduced_grid(args.steps, args.warmup)
+
+    example1 = None
+    if not args.no_example1 and not args.only_headline:
+        log("bench: the paper's Example 1 (crown grid)")
+        example1 = bench_example1(with_cpu=not args.no_cpu)
+
+    batched = None
+    if not args.no_batched and not args.only_headline:
+        log("bench: batched 16-problem solve")
+        batched = bench_batched()
+        log(f"bench: batched {batched}")
+        batched["small_grids"] = bench_batched(side_scale=0.25)
+        log(f"bench: batched small {batched['small_grids']}")
+
+    ttc = None
+    if converge is not None:
+        ref = converge["reference_a1e-3"]
+        ttc = {"seconds_to_1e-4": ref["seconds_to_float32_floor"], "seconds_to_1e-6_stop": ref["seconds_to_1e-6"],
+               "what": "value iteration to 1e-3, policy iteration to 1e-6, then on to the float32 floor "
+                       "(3e-7 or a stall): the stop at which the value meets 1e-4 against the oracle",
+               "nn_seeded_vs_plain_held_out_to_1e-4": converge["nn_seeded_pi_a5e-4"]["speedup_vs_plain_pi_to_floor"],
+               "nn_seeded_vs_plain_held_out_to_1e-4_incl_training":
+                   converge["nn_seeded_pi_a5e-4"]["speedup_vs_plain_pi_to_floor_incl_training"]}
 
     out = {
-        "metric": "node-control Bellman evals/s (modified PI step: greedy scan64+golden12+coast, 20 policy sweeps)",
+        "metric": "node-control Bellman evals/s (modified PI step on 96^3 x 64: greedy scan64+golden12+coast, "
+                  "20 policy sweeps) + time-to-converged V at 1e-4 rel; NN-seeded vs plain",
         "value": value,
         "unit": "evals/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps_done,
         "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps,
+        "ms_per_step": step_ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "policy iteration, 48^4 grid, reachability-masked active set, scan 64 + golden 12, "
-                        "20 evaluation sweeps per update",
-            "grid": list(p1["n"]),
-            "active_free_nodes": int(n_free),
-            "active_fraction": n_free / ctx.N,
+            "workload": "policy iteration, 96 x 96 x 96 x 64 grid (56.6M nodes), thrust 1e-3, dt 0.02, "
+                        "cost 1 + 0.1*thrust, scan 64 + golden 12 + coast, 20 evaluation sweeps per update, "
+                        "from the value after value iteration to 1e-3",
+            "grid": list(p["n"]),
+            "free_nodes": int(n_free),
             "eval_sweeps": E,
+            "steps_requested": args.steps,
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": EVAL_KERNEL_BY_BYTES.get(round(eval_bytes / n_free), "k_policy_eval_d16"),
+            "kernel": "k_eval_brick_desc<true, true>" if eval_path == 2 else "k_policy_eval_d16<true, 3, 2>",
             "achieved": eval_gbs,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": eval_gbs / HBM_PEAK_GBS,
             "traffic": traffic,
-            "algorithmic_bytes": eval_bytes,
-            "bytes_per_node": eval_bytes / n_free,
+            "algorithmic_bytes": eval_algo_bytes,
+            "algorithmic_bytes_per_node": EVAL_ALGO_BYTES_PER_NODE,
+            "stream_bytes_per_launch": stream_bytes,
             "nodes_per_launch": int(n_free),
             "avg_launch_ms": eval_ms,
             "launches_per_step": E,
+            "share_of_step": E * eval_ms / step_ms,
         },
         "greedy_sweep": {
-            "kernel": "k_sweep_fast<1>" if ctx.kernel_path() == 2 else "k_sweep_direct<1>",
+            "kernel": "k_sweep_fast<1>",
             "bound": "alu",
             "avg_launch_ms": greedy_ms,
-            "evals_per_launch": evals_per_greedy,
-            "evals_per_s": greedy_evals_s,
+            "evals_per_launch": greedy_evals,
+            "evals_per_s": greedy_evals / (greedy_ms * 1e-3),
             "hbm_bytes_per_node": GREEDY_BYTES_PER_NODE,
             "hbm_frac": GREEDY_BYTES_PER_NODE * n_free / (greedy_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         },
         "gather_roofline": {
-            "step_algorithmic_bytes": step_bytes,
-            "step_achieved_GBs": step_gbs,
-            "step_frac": step_gbs / HBM_PEAK_GBS,
             "naive_gather_bytes_per_eval": GATHER_BYTES_PER_EVAL,
             "naive_gather_frac": value * GATHER_BYTES_PER_EVAL / 1e9 / HBM_PEAK_GBS,
         },
-        "setup": {"seconds": setup_s,
-                  "what": "12^4 value iteration for the mask, mask and dilation, context creation "
-                          "(classification, compaction, tables); not in the timed steps"},
-        "time_to_converge": converge,
-        "paper_variants": variants,
+        "setup": {"seconds": setup_s, "vi_sweeps": st_vi["sweeps"],
+                  "what": "context creation and value iteration to 1e-3 (the schedule's first phase), "
+                          "not in the timed steps"},
+        "time_to_converge": ttc,
+        "converge_and_learned_96x96x96x64": converge,
+        "one_gpu_share": one_share,
+        "ceilings": ceilings,
+        "reduced_grid_48x4": reduced,
         "paper_example1": example1,
-        "large_96x96x96x64": large,
         "batched": batched,
         "cpu_baseline": cpu,
         "host": {"nproc": os.cpu_count(), "cpu": platform.processor()},
