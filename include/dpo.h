@@ -153,6 +153,12 @@ typedef struct {
   double seconds;         /* wall time from the first launch to the stop decision */
   int32_t stalled;        /* 1 if stopped because the residual stopped decreasing */
   int32_t converged;      /* 1 if the stop rule was met */
+  /* modified policy iteration (dpo_solve_pi with eval_sweeps >= 0; 0 elsewhere):
+   * device time of the greedy sweeps and of the counted evaluation sweeps,
+   * from HIP events recorded on the solver's stream around each step's greedy
+   * sweep and around its run of evaluation sweeps */
+  double greedy_seconds;
+  double eval_seconds;
 } dpo_stats;
 
 typedef struct dpo_ctx dpo_ctx;
@@ -334,14 +340,14 @@ int dpo_solve_vi(dpo_ctx* ctx, float* V, float* pol_angle, uint8_t* pol_thr, dou
  * tolerance starts with seeded steps again, which drift towards the local
  * search's own fixed point: carry it on without seed_angle. */
 /* Exact policy evaluation (eq:p_eval solved as the sparse linear system
- * (I - exp(-lambda dt) P) v = b of Section 3, by restarted GMRES(16), the
+ * (I - exp(-lambda dt) P) v = b of Section 3, by restarted GMRES(8), the
  * solver the paper names): V (device, N) holds the fixed nodes' values and,
  * at free nodes, the initial guess on entry and the solution on exit; the
  * frozen policy is pol_angle / pol_thr.  The operator is applied matrix-free
  * by the frozen-policy sweep without its affine part; vectors are float32,
  * dot products FP64 in a fixed order.  Stops when the node-wise relative
  * residual max_j |b - A v|_j / max(1, |v_j|) <= tol_rel (checked between
- * restart cycles; a cycle ends after 16 steps or once its 2-norm residual
+ * restart cycles; a cycle ends after 8 steps or once its 2-norm residual
  * has fallen 100-fold) or after max_iter operator applications
  * (DPO_ENOCONV, V holds the last iterate).  *matvecs and
  * *resid_rel (host, nullable): operator applications and the final

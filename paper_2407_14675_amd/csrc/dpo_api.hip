@@ -59,6 +59,7 @@ struct dpo_ctx {
   int* fb_list = nullptr;         // seeded sweeps: nodes whose full search is deferred to a second pass
   int* fb_count = nullptr;
   hipEvent_t resid_ready = nullptr;
+  hipEvent_t step_ev[2][4] = {};  // policy iteration: greedy start/end, evaluation start/end, two steps deep
   int* desc_code = nullptr;  // foot descriptors of the greedy step's controls (policy iteration)
   uint16_t* desc16 = nullptr;  // compact codes (desc_format 1 and 2)
   int desc_format = -1;        // 0 flat 32-bit codes, 1 compact by free node, 2 compact by node
@@ -70,6 +71,9 @@ struct dpo_ctx {
   double* kpart = nullptr;   // dot-product partials
   double* kdots = nullptr;   // dot products (kMaxBasis)
   double* kcoef = nullptr;   // update coefficients (kMaxBasis)
+  double* karn = nullptr;    // device Arnoldi state (see gmres_eval)
+  double* karn_host = nullptr;  // pinned: each step's (|g_(k+1)|, h_(k+1)k)
+  hipEvent_t karn_ev[2] = {nullptr, nullptr};
   int kry_m = 0;
   unsigned long long* eval_acc = nullptr;  // table walk: per-workgroup thrust-evaluation counts
   unsigned long long* eval_sum = nullptr;
@@ -360,7 +364,23 @@ void plan_brick(dpo_ctx* c) {
       }
     }
   if (!(best < INFINITY)) return;
-  B.planes = 4;
+  // mass planes per workgroup: 4 (each plane's brick loaded once per 5/4
+  // planes) while that leaves at least 8 workgroups per CU, else fewer, so
+  // that thin grids (one GPU's slab of a sharded grid) still fill the chip
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1) {
+    (void)hipGetLastError();
+    cus = 256;
+  }
+  const int64_t columns = (int64_t)B.n_at * B.n_ct;
+  B.planes = 1;
+  for (int P : {4, 2}) {
+    if (columns * ((g.n[3] + P - 1) / P) >= (int64_t)(P == 4 ? 8 : 4) * cus) {
+      B.planes = P;
+      break;
+    }
+  }
   B.n_mc = (g.n[3] + B.planes - 1) / B.planes;
   if ((int64_t)B.n_at * B.n_ct * B.n_mc > 0x7fffffff) return;
   if (prepare_eval_brick(B) != hipSuccess) return;
@@ -409,6 +429,12 @@ int ensure_pi_buffers(dpo_ctx* c) {
     return fail(c, DPO_ENOMEM, "pinned residual buffer alloc");
   if (!c->resid_ready && hipEventCreateWithFlags(&c->resid_ready, hipEventDisableTiming) != hipSuccess)
     return fail(c, DPO_EHIP, "residual event create");
+  for (auto& row : c->step_ev)
+    for (auto& e : row)
+      if (!e && hipEventCreate(&e) != hipSuccess) {
+        e = nullptr;
+        return fail(c, DPO_EHIP, "step timing event create");
+      }
   return DPO_OK;
 }
 
@@ -653,16 +679,26 @@ int sweep_eval_desc(dpo_ctx* c, const float* Vin, float* Vout, hipStream_t s) {
 // GMRES is the solver the paper names).  b is the frozen-policy sweep of V
 // with its free entries zeroed (running cost plus the fixed corners and M);
 // the operator is the sweep without that affine part.  Classical
-// Gram-Schmidt with one reorthogonalisation; Hessenberg and Givens rotations
-// on the host in FP64; the second pass only where the first lost more than a
-// factor 1/sqrt(2) of the vector's norm (the criterion of Daniel, Gragg,
-// Kaufman and Stewart).  Stop measure: the node-wise relative residual
-// max_j |b - A v|_j / max(1, |v_j|), checked between cycles; a cycle ends
-// after m steps or once its 2-norm residual has fallen by kCycleDrop.
+// Gram-Schmidt in two passes every step (for I - gamma P the first pass
+// loses more than a factor 1/sqrt(2) of the norm nearly every step, the
+// criterion of Daniel, Gragg, Kaufman and Stewart for a second one); the
+// coefficients, the Hessenberg matrix and its Givens rotations stay on the
+// device in FP64, so a step needs no host synchronisation; the triangular
+// solve of a cycle runs on the host.  Stop measure: the node-wise relative
+// residual max_j |b - A v|_j / max(1, |v_j|), checked between cycles; a cycle
+// ends after m steps or once its 2-norm residual has fallen by kCycleDrop
+// (read one step late, so at most one step more).
 
-constexpr int kGmresRestart = 16;
+constexpr int kGmresRestart = 8;
 constexpr double kCycleDrop = 1e-2;
 constexpr double kExactEvalTol = 5e-7;  // node-wise residual of the evaluations inside policy iteration
+
+// Device Arnoldi state of gmres_eval: the two Gram-Schmidt passes' dot
+// products, the new vector's squared norm, the Hessenberg matrix, the Givens
+// rotations, the rotated right-hand side, 1/h_(k+1)k and the step's status.
+constexpr int kArnD1 = 0, kArnD2 = kMaxBasis, kArnNrm = 2 * kMaxBasis, kArnH = 2 * kMaxBasis + 1;
+constexpr int kArnCs = kArnH + (kMaxBasis + 1) * kMaxBasis, kArnSn = kArnCs + kMaxBasis, kArnG = kArnSn + kMaxBasis;
+constexpr int kArnInv = kArnG + kMaxBasis + 1, kArnStat = kArnInv + 1, kArnDoubles = kArnStat + 2;
 
 int ensure_krylov(dpo_ctx* c, int m) {
   const size_t N = (size_t)c->N;
@@ -676,6 +712,14 @@ int ensure_krylov(dpo_ctx* c, int m) {
     return fail(c, DPO_ENOMEM, "Krylov partials alloc");
   if (!c->kdots && hipMalloc(&c->kdots, sizeof(double) * kMaxBasis) != hipSuccess) return fail(c, DPO_ENOMEM, "alloc");
   if (!c->kcoef && hipMalloc(&c->kcoef, sizeof(double) * kMaxBasis) != hipSuccess) return fail(c, DPO_ENOMEM, "alloc");
+  if (!c->karn && hipMalloc(&c->karn, sizeof(double) * kArnDoubles) != hipSuccess) return fail(c, DPO_ENOMEM, "alloc");
+  if (!c->karn_host && hipHostMalloc(&c->karn_host, sizeof(double) * 2 * kMaxBasis, hipHostMallocDefault) != hipSuccess)
+    return fail(c, DPO_ENOMEM, "pinned Arnoldi status alloc");
+  for (auto& e : c->karn_ev)
+    if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      e = nullptr;
+      return fail(c, DPO_EHIP, "Arnoldi event create");
+    }
   return DPO_OK;
 }
 
@@ -683,14 +727,6 @@ int ensure_krylov(dpo_ctx* c, int m) {
 int host_dots(dpo_ctx* c, const float* basis, int k, const float* w, double* h, hipStream_t s) {
   HIP_TRY(c, launch_dots(basis, k, (size_t)c->N, w, (int)c->N, c->kpart, c->kdots, s));
   HIP_TRY(c, hipMemcpyAsync(h, c->kdots, sizeof(double) * k, hipMemcpyDeviceToHost, s));
-  HIP_TRY(c, hipStreamSynchronize(s));
-  return DPO_OK;
-}
-
-// w -= basis coef (k terms) and *ww = |w|^2 of the result, read back (synchronises s)
-int axpys_norm(dpo_ctx* c, float* w, const float* basis, int k, const double* coef, double* ww, hipStream_t s) {
-  HIP_TRY(c, launch_axpys(w, basis, k, (size_t)c->N, coef, (int)c->N, s, c->kpart, c->kdots));
-  HIP_TRY(c, hipMemcpyAsync(ww, c->kdots, sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
   return DPO_OK;
 }
@@ -724,7 +760,8 @@ int gmres_eval(dpo_ctx* c, float* V, const float* ang, const uint8_t* thr, doubl
   // x: the current V at free nodes, zero elsewhere
   HIP_TRY(c, hipMemsetAsync(X, 0, sizeof(float) * ld, s));
   HIP_TRY(c, launch_free_copy(a, V, X, s));
-  std::vector<double> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), y(m), h1(m + 2), h2(m + 1);
+  std::vector<double> H((size_t)(m + 1) * m), g(m + 1), y(m);
+  double* arn = c->karn;
   double rel = 0;
   int it = 0;
   while (true) {
@@ -739,52 +776,42 @@ int gmres_eval(dpo_ctx* c, float* V, const float* ang, const uint8_t* thr, doubl
     const double beta = std::sqrt(rr);
     if (!(rel > tol) || !(beta > 0) || it >= max_iter) break;
     HIP_TRY(c, launch_scale(basis, 1.0 / beta, basis, N, s));
-    std::fill(H.begin(), H.end(), 0.0);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
+    HIP_TRY(c, hipMemcpyAsync(arn + kArnG, g.data(), sizeof(double) * (m + 1), hipMemcpyHostToDevice, s));
+    // Arnoldi steps with no host synchronisation: classical Gram-Schmidt in
+    // two passes (the coefficients stay on the device), the Hessenberg column
+    // and its Givens rotation in one small kernel; the host reads each step's
+    // status one step late, so the device always has the next step queued.
     int k = 0;
-    while (k < m && it < max_iter) {
+    bool stop = false;
+    while (k < m && it < max_iter && !stop) {
       float* vk = basis + (size_t)k * ld;
       float* w = basis + (size_t)(k + 1) * ld;
       HIP_TRY(c, launch_eval_hom(a, vk, Y, s));
       mv++;
       it++;
       HIP_TRY(c, launch_sub(vk, Y, w, N, s));
-      // classical Gram-Schmidt against v_0..v_k; w is basis row k+1, so the
-      // same pass also gives |w|^2 (h1[k+1])
-      if ((rc = host_dots(c, basis, k + 2, w, h1.data(), s)) != DPO_OK) return rc;
-      const double before = std::sqrt(std::max(h1[k + 1], 0.0));
-      HIP_TRY(c, hipMemcpyAsync(c->kcoef, h1.data(), sizeof(double) * (k + 1), hipMemcpyHostToDevice, s));
-      double ww = 0;
-      if ((rc = axpys_norm(c, w, basis, k + 1, c->kcoef, &ww, s)) != DPO_OK) return rc;
-      std::fill(h2.begin(), h2.end(), 0.0);
-      if (std::sqrt(ww) < 0.7071067811865476 * before) {
-        if ((rc = host_dots(c, basis, k + 1, w, h2.data(), s)) != DPO_OK) return rc;
-        HIP_TRY(c, hipMemcpyAsync(c->kcoef, h2.data(), sizeof(double) * (k + 1), hipMemcpyHostToDevice, s));
-        if ((rc = axpys_norm(c, w, basis, k + 1, c->kcoef, &ww, s)) != DPO_OK) return rc;
-      }
-      const double hn = std::sqrt(ww);
-      for (int i = 0; i <= k; i++) H[(size_t)i * m + k] = h1[i] + h2[i];
-      H[(size_t)(k + 1) * m + k] = hn;
-      // previous rotations, then a new one that zeroes H[k+1][k]
-      for (int i = 0; i < k; i++) {
-        const double t0 = H[(size_t)i * m + k], t1 = H[(size_t)(i + 1) * m + k];
-        H[(size_t)i * m + k] = cs[i] * t0 + sn[i] * t1;
-        H[(size_t)(i + 1) * m + k] = -sn[i] * t0 + cs[i] * t1;
-      }
-      const double d0 = H[(size_t)k * m + k], d1 = H[(size_t)(k + 1) * m + k];
-      const double den = std::hypot(d0, d1);
-      cs[k] = den > 0 ? d0 / den : 1.0;
-      sn[k] = den > 0 ? d1 / den : 0.0;
-      H[(size_t)k * m + k] = den;
-      H[(size_t)(k + 1) * m + k] = 0.0;
-      g[k + 1] = -sn[k] * g[k];
-      g[k] = cs[k] * g[k];
+      HIP_TRY(c, launch_dots(basis, k + 1, ld, w, N, c->kpart, arn + kArnD1, s));
+      HIP_TRY(c, launch_axpys_dots(w, basis, k + 1, ld, arn + kArnD1, N, c->kpart, arn + kArnD2, s));
+      HIP_TRY(c, launch_axpys(w, basis, k + 1, ld, arn + kArnD2, N, s, c->kpart, arn + kArnNrm));
+      HIP_TRY(c, launch_arnoldi_col(k, m, arn + kArnD1, arn + kArnD2, arn + kArnNrm, arn + kArnH, arn + kArnCs,
+                                    arn + kArnSn, arn + kArnG, arn + kArnInv, arn + kArnStat, s));
+      HIP_TRY(c, launch_scale_dev(w, arn + kArnInv, w, N, s));
+      HIP_TRY(c, hipMemcpyAsync(c->karn_host + 2 * k, arn + kArnStat, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(c, hipEventRecord(c->karn_ev[k & 1], s));
       k++;
-      if (hn > 0) HIP_TRY(c, launch_scale(w, 1.0 / hn, w, N, s));
-      if (!(std::fabs(g[k]) > kCycleDrop * beta) || !(hn > 0)) break;
+      // the previous step's stop test (this step is already queued behind it)
+      if (k >= 2) {
+        HIP_TRY(c, hipEventSynchronize(c->karn_ev[k & 1]));
+        const double* st = c->karn_host + 2 * (k - 2);
+        if (!(st[0] > kCycleDrop * beta) || !(st[1] > 0)) stop = true;
+      }
     }
-    // x += V_k y with H y = g (upper triangular k x k)
+    // x += V_k y with H y = g over the k columns the device formed
+    HIP_TRY(c, hipMemcpyAsync(H.data(), arn + kArnH, sizeof(double) * (size_t)(m + 1) * m, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipMemcpyAsync(g.data(), arn + kArnG, sizeof(double) * (m + 1), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
     for (int i = k - 1; i >= 0; i--) {
       double t = g[i];
       for (int q = i + 1; q < k; q++) t -= H[(size_t)i * m + q] * y[q];
@@ -958,6 +985,9 @@ void dpo_destroy(dpo_ctx* c) {
   if (c->fb_count) hipFree(c->fb_count);
   if (c->resid_host) hipHostFree(c->resid_host);
   if (c->resid_ready) hipEventDestroy(c->resid_ready);
+  for (auto& row : c->step_ev)
+    for (auto& e : row)
+      if (e) hipEventDestroy(e);
   if (c->desc_code) hipFree(c->desc_code);
   if (c->desc16) hipFree(c->desc16);
   if (c->desc_w) hipFree(c->desc_w);
@@ -968,6 +998,10 @@ void dpo_destroy(dpo_ctx* c) {
   if (c->kpart) hipFree(c->kpart);
   if (c->kdots) hipFree(c->kdots);
   if (c->kcoef) hipFree(c->kcoef);
+  if (c->karn) hipFree(c->karn);
+  if (c->karn_host) hipHostFree(c->karn_host);
+  for (auto& e : c->karn_ev)
+    if (e) hipEventDestroy(e);
   if (c->eval_sum) hipFree(c->eval_sum);
   delete c;
 }
@@ -1300,19 +1334,32 @@ int dpo_solve_pi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, doubl
   bool verify = false;
   double seeded_best = INFINITY, full_best = INFINITY;
   int seeded_stall = 0, full_stall = 0;
+  // device time of the greedy sweeps and of the counted evaluation sweeps:
+  // events around each, read one step later (by then the stream has passed them)
+  double greedy_ms = 0, eval_ms = 0;
+  auto span_ms = [&](hipEvent_t a, hipEvent_t b) {
+    float ms = 0;
+    return hipEventElapsedTime(&ms, a, b) == hipSuccess ? (double)ms : 0.0;
+  };
+  bool pending = false, pending_eval = false;  // the previous step's events, not yet read
+  int prev = 0;
   while (it < max_outer) {
     float* G = cur == buf[0] ? buf[1] : buf[0];
+    hipEvent_t* ev = c->step_ev[it & 1];
     // greedy step: policy improvement together with T V
     const bool use_seed = seeded && it > 0 && !verify;
+    HIP_TRY(c, hipEventRecord(ev[0], s));
     if (use_seed) rc = sweep_seeded(c, cur, G, pol_angle, pol_thr, seed_angle, s, desc, true);
     else rc = sweep_full(c, cur, G, pol_angle, pol_thr, s, desc, it > 0, true, walk && it > 0 ? pol_angle : nullptr, true);
     if (rc != DPO_OK) return rc;
+    HIP_TRY(c, hipEventRecord(ev[1], s));
     it++;
     if ((rc = finish_resid(c, c->resid, s)) != DPO_OK) return rc;
     HIP_TRY(c, hipMemcpyAsync(c->resid_host, c->resid, sizeof(double) * kPartial, hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipEventRecord(c->resid_ready, s));
     // evaluation sweeps of this step, queued ahead of the stop decision
     float* src = G;
+    HIP_TRY(c, hipEventRecord(ev[2], s));
     for (int e = 0; e < eval_sweeps; e++) {
       float* dst = nullptr;
       for (float* b : buf)
@@ -1324,7 +1371,15 @@ int dpo_solve_pi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, doubl
       if (rc != DPO_OK) return rc;
       src = dst;
     }
+    HIP_TRY(c, hipEventRecord(ev[3], s));
     HIP_TRY(c, hipEventSynchronize(c->resid_ready));
+    if (pending) {
+      greedy_ms += span_ms(c->step_ev[prev][0], c->step_ev[prev][1]);
+      if (pending_eval) eval_ms += span_ms(c->step_ev[prev][2], c->step_ev[prev][3]);
+    }
+    pending = true;
+    pending_eval = false;
+    prev = (int)((it - 1) & 1);
     std::memcpy(h, c->resid_host, sizeof(h));
     cur = G;  // T V, the result if this step stops the solve
     if (use_seed) {
@@ -1372,9 +1427,16 @@ int dpo_solve_pi(dpo_ctx* c, float* V, float* pol_angle, uint8_t* pol_thr, doubl
     cur = src;
     local.eval_sweeps += eval_sweeps;
     evals += (int64_t)eval_sweeps * c->n_free;
+    pending_eval = eval_sweeps > 0;
   }
   if (cur != V) HIP_TRY(c, hipMemcpyAsync(V, cur, sizeof(float) * (size_t)c->N, hipMemcpyDeviceToDevice, s));
   HIP_TRY(c, hipStreamSynchronize(s));
+  if (pending) {
+    greedy_ms += span_ms(c->step_ev[prev][0], c->step_ev[prev][1]);
+    if (pending_eval) eval_ms += span_ms(c->step_ev[prev][2], c->step_ev[prev][3]);
+  }
+  local.greedy_seconds = 1e-3 * greedy_ms;
+  local.eval_seconds = 1e-3 * eval_ms;
   if (walk) {
     int64_t w = 0;
     if ((rc = walk_counts_read(c, s, &w)) != DPO_OK) return rc;

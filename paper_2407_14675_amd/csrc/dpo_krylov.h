@@ -28,8 +28,15 @@ hipError_t launch_relmax(const float* r, const float* x, int N, double* partial,
 hipError_t launch_axpys(float* w, const float* basis, int k, size_t ld, const double* coef, int N, hipStream_t s,
                        double* partial = nullptr, double* nrm_out = nullptr);
 // dst = s * src
+// w -= basis coef (k terms), then out[0..k) = <basis_i, new w>; one pass for k <= kDotGroup
+hipError_t launch_axpys_dots(float* w, const float* basis, int k, size_t ld, const double* coef, int N,
+                             double* partial, double* out, hipStream_t s);
 hipError_t launch_scale(const float* src, double s, float* dst, int N, hipStream_t st);
 // dst[j] = src[j] at the free nodes j
+hipError_t launch_scale_dev(const float* src, const double* sc, float* dst, int N, hipStream_t s);
+// column k of the Arnoldi process and its Givens rotation, on the device (see k_arnoldi_col)
+hipError_t launch_arnoldi_col(int k, int m, const double* d1, const double* d2, const double* nrm2, double* H,
+                              double* cs, double* sn, double* g, double* inv_hn, double* status, hipStream_t s);
 hipError_t launch_free_copy(const SweepArgs& a, const float* src, float* dst, hipStream_t s);
 // dst[j] = 0 at the free nodes j
 hipError_t launch_free_zero(const SweepArgs& a, float* dst, hipStream_t s);

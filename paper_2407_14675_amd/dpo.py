@@ -58,7 +58,8 @@ class Stats(C.Structure):
     _fields_ = [("sweeps", C.c_int64), ("eval_sweeps", C.c_int64), ("evals", C.c_int64),
                 ("fallback_nodes", C.c_int64), ("verify_steps", C.c_int64), ("resid_max_rel", C.c_double),
                 ("resid_sum_abs", C.c_double), ("resid_max_abs", C.c_double), ("seconds", C.c_double),
-                ("stalled", C.c_int32), ("converged", C.c_int32)]
+                ("stalled", C.c_int32), ("converged", C.c_int32), ("greedy_seconds", C.c_double),
+                ("eval_seconds", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

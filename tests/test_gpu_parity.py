@@ -426,6 +426,8 @@ def test_pi_edge_cases(dpo):
     a3, t3 = ctx.empty_policy()
     rc, st = ctx.solve_pi(V3, a3, t3, tol_rel=0.0, eval_sweeps=5, max_outer=3)
     assert rc == dpo.DPO_ENOCONV and st["sweeps"] == 3 and st["eval_sweeps"] == 15
+    # the device times of the greedy and evaluation sweeps, within the wall time
+    assert 0 < st["greedy_seconds"] < st["seconds"] and 0 < st["eval_seconds"] < st["seconds"]
     v3 = host(V3)
     assert np.isfinite(v3).all() and np.all(v3 <= host(ctx.init_value()) + 3 * 6 * p["dt"])
 
