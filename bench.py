@@ -550,6 +550,15 @@ def bench_example1(with_cpu=True):
                     "hardware": "MacBook Air laptop, Mex-compiled Matlab (paper Section 4)"}
     out["orbit_raise"] = orbit_raise(p, Vt, x_start, cpu=with_cpu)
     log(f"bench: example 1 orbit raise {out['orbit_raise']}")
+    # the second reading of the fuel weight's units: alpha per second of
+    # thrust (u_bar read as the on/off throttle), solved and flown the same way
+    q = inputs.crown_problem(fuel_reading="throttle")
+    Vq, rec = run(q, "pi")
+    rec["fuel_weight_per_thrust_second"] = q["w_fuel"]
+    rec["orbit_raise"] = orbit_raise(q, Vq, x_start, cpu=False)
+    rec["reading"] = "alpha * u_bar with u_bar = 1 while the thruster fires (2.04e-8 per second of thrust)"
+    out["fuel_per_thrust_second"] = rec
+    log(f"bench: example 1, fuel weight per second of thrust {rec}")
     return out
 
 
@@ -726,9 +735,22 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 16-problem measurement")
     ap.add_argument("--no-example1", action="store_true", help="skip the paper's Example 1 solves")
     ap.add_argument("--no-ceilings", action="store_true", help="skip the HBM and VALU ceiling probes")
+    ap.add_argument("--sections", default="all",
+                    help="comma list of the sections after the headline: converge, reduced, example1, batched, "
+                         "ceilings, share (default all)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one 1 GiB copy with the library's probe (reference for HBM byte counters)")
     args = ap.parse_args()
+    known = {"converge", "reduced", "example1", "batched", "ceilings", "share"}
+    sections = known if args.sections == "all" else set(args.sections.split(","))
+    if not sections <= known:
+        ap.error(f"unknown sections {sorted(sections - known)}")
+    if args.only_headline:
+        sections = set()
+    for flag, name in ((args.no_converge, "converge"), (args.no_reduced, "reduced"), (args.no_example1, "example1"),
+                       (args.no_batched, "batched"), (args.no_ceilings, "ceilings")):
+        if flag:
+            sections.discard(name)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); sharding the grid along the mass "
               f"axis over several GPUs is not implemented.", file=sys.stderr)
@@ -789,7 +811,7 @@ def main():
     step_ms = elapsed * 1e3 / max(1, steps_done)
 
     one_share = None
-    if not args.only_headline:
+    if "share" in sections:
         one_share = one_gpu_share(p, greedy_ms, eval_ms)
         log(f"bench: one GPU's share {one_share}")
 
@@ -803,27 +825,27 @@ def main():
     torch.cuda.empty_cache()
 
     ceilings = None
-    if not args.no_ceilings and not args.only_headline:
+    if "ceilings" in sections:
         ceilings = measure_ceilings()
         log(f"bench: ceilings {ceilings}")
 
     converge = None
-    if not args.no_converge and not args.only_headline:
+    if "converge" in sections:
         log("bench: 96^3 x 64 solves to convergence, walk- and network-seeded")
         converge = bench_converge_and_learned()
 
     reduced = None
-    if not args.no_reduced and not args.only_headline:
+    if "reduced" in sections:
         log("bench: 48^4 reduced grid")
         reduced = bench_reduced_grid(args.steps, args.warmup)
 
     example1 = None
-    if not args.no_example1 and not args.only_headline:
+    if "example1" in sections:
         log("bench: the paper's Example 1 (crown grid)")
         example1 = bench_example1(with_cpu=not args.no_cpu)
 
     batched = None
-    if not args.no_batched and not args.only_headline:
+    if "batched" in sections:
         log("bench: batched 16-problem solve")
         batched = bench_batched()
         log(f"bench: batched {batched}")

@@ -149,7 +149,15 @@ EX1_ACCEL = 5e-7
 EX1_ALPHA = 2.04e-8
 
 
-def crown_problem(n=(110, 30, 30, 30), *, integrator="heun", n_angles=72, M=1e6, name="example1_crown"):
+def crown_problem(n=(110, 30, 30, 30), *, integrator="heun", n_angles=72, M=1e6, name="example1_crown",
+                  fuel_reading="accel"):
+    """The paper's Example 1.  fuel_reading: how the fuel term alpha*u_bar of
+    the running cost is read, the units of the weights not being stated:
+    "accel" takes u_bar as the thrust acceleration in km/s^2 (alpha*u_bar =
+    1.02e-14 per second of thrust), "throttle" takes u_bar as 1 while the
+    thruster fires (alpha = 2.04e-8 per second of thrust)."""
+    if fuel_reading not in ("accel", "throttle"):
+        raise ValueError(fuel_reading)
     return dict(
         name=name,
         model="crown",
@@ -162,7 +170,7 @@ def crown_problem(n=(110, 30, 30, 30), *, integrator="heun", n_angles=72, M=1e6,
         dt=10.0,
         lam=1e-3,
         w_time=0.0,
-        w_fuel=EX1_ALPHA * EX1_ACCEL,
+        w_fuel=EX1_ALPHA * (EX1_ACCEL if fuel_reading == "accel" else 1.0),
         M=float(M),
         speed=0.0,
         tgt_c=(0.0, 0.0, 0.0, 0.0),

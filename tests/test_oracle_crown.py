@@ -58,6 +58,14 @@ def test_running_cost_vanishes_on_the_target_orbit():
         x = [r, math.sqrt(MU / pp) * e * math.sin(nu), math.sqrt(MU / pp) * (1 + e * math.cos(nu)), w + nu]
         assert o.running_cost(x, 0) == pytest.approx(0.0, abs=1e-12)
         assert o.running_cost(x, 1) == pytest.approx(p["w_fuel"], rel=1e-9, abs=1e-20)
+    # the two readings of the fuel weight's units: alpha times the thrust
+    # acceleration (5e-7 km/s^2), or alpha per second of thrust
+    q = small(fuel_reading="throttle")
+    assert p["w_fuel"] == pytest.approx(2.04e-8 * 5e-7, rel=1e-12)
+    assert q["w_fuel"] == pytest.approx(2.04e-8, rel=1e-12)
+    assert Oracle(q).running_cost(x, 1) - Oracle(q).running_cost(x, 0) == pytest.approx(2.04e-8, rel=1e-9)
+    with pytest.raises(ValueError):
+        small(fuel_reading="kg")
     # a circular orbit 22 km below: cost beta*22^2 + gamma*e_bar^2
     r = 6978.0
     want = p["el_beta"] * (r - a) ** 2 + p["el_gamma"] * e * e
