@@ -561,7 +561,9 @@ int sweep_full(dpo_ctx* c, const float* Vin, float* Vout, float* ang, uint8_t* t
   if (desc && desc_ok(c)) set_desc_out(c, a);
   else c->desc_valid = false;
   if (a.n_free == 0) return DPO_OK;
-  int mode = c->search.mode == DPO_SEARCH_SCAN_GOLDEN ? 1 : 0;
+  // a SEEDED context's full steps (the first step of a seeded solve and the
+  // steps that certify it) take its scan + golden parameters
+  int mode = (c->search.mode == DPO_SEARCH_SCAN_GOLDEN || c->search.mode == DPO_SEARCH_SEEDED) ? 1 : 0;
   if (c->search.mode == DPO_SEARCH_TABLE_WALK && walk_from) {
     mode = 3;
     a.walk_from = walk_from;

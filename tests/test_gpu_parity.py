@@ -638,6 +638,54 @@ def test_walk_seeded_pi_matches_plain(dpo, small_pi_ref):
     assert rel_err(host(V), ref["V"])[free].max() <= 1e-4
 
 
+@pytest.mark.parametrize("path", [1, 2])
+def test_seeded_pi_is_certified_by_the_full_search(dpo, small_pi_ref, path):
+    """A seeded solve stops only on a full-search greedy step, which runs the
+    scan + golden search of the context's SEEDED parameters (here a coarse
+    8-angle scan, so that the scan alone is far from the golden-refined
+    minimum): at its result no node's scan + golden value lies below its
+    value by more than the stop tolerance, as at the result of an unseeded
+    solve.  The seeds are fixed random angles, so the local searches settle
+    in wrong basins that only the full search can leave."""
+    p, o, ref = small_pi_ref
+    _say("seeded PI certified by scan + golden, path", path)
+    sr = dict(inputs.SEEDED, n_scan=8)
+    tol = 1e-6
+    ctx = dpo.Context(p)
+    ctx.set_kernel_path(path)
+    ctx.set_search(sr)
+    V = ctx.init_value()
+    ang, thr = ctx.empty_policy()
+    seed = dev(np.random.default_rng(32).uniform(-math.pi, math.pi, o.shape).astype(np.float32))
+    # the solve's first greedy step is a full step with no incumbent yet: from
+    # V0 it is one scan + golden sweep, bit for bit
+    sg = dict(mode="scan_golden", n_scan=8, n_golden=12)
+    V1 = ctx.init_value()
+    a1, t1 = ctx.empty_policy()
+    rc, _ = ctx.solve_pi(V1, a1, t1, tol_rel=0.0, eval_sweeps=0, max_outer=1, seed=seed)
+    assert rc == dpo.DPO_ENOCONV
+    ctx.set_search(sg)
+    V0 = ctx.init_value()
+    G = V0.clone()
+    a0, t0 = ctx.empty_policy()
+    ctx.bellman_sweep(V0, G, a0, t0)
+    np.testing.assert_array_equal(host(V1), host(G))
+    np.testing.assert_array_equal(host(t1), host(t0))
+    np.testing.assert_array_equal(host(a1), host(a0))
+    ctx.set_search(sr)
+    rc, st = ctx.solve_pi(V, ang, thr, tol_rel=tol, eval_sweeps=20, max_outer=5000, seed=seed)
+    assert rc == dpo.DPO_OK and st["verify_steps"] >= 1
+    ctx.set_search(sg)
+    W = V.clone()
+    a2, t2 = ctx.empty_policy()
+    ctx.bellman_sweep(V, W, a2, t2)
+    free = o.kind == KIND_FREE
+    Vh, Wh = host(V).astype(np.float64), host(W).astype(np.float64)
+    gain = ((Vh - Wh) / np.maximum(1.0, np.abs(Vh)))[free]
+    _say("  outer", st["sweeps"], "full-search steps", st["verify_steps"], "largest full-search gain", gain.max())
+    assert gain.max() <= 2 * tol, gain.max()
+
+
 # ----------------------------------------------- foot-descriptor formats
 @pytest.mark.parametrize("case", ["per_node", "per_free_node", "flat_code"])
 def test_descriptor_formats(dpo, case):
