@@ -264,11 +264,14 @@ def mlp_params32(seed=4):
 # Learned control proposal: training pairs come from the converged solution
 # at nodes whose value is not the exit penalty (V < 0.98 M, the mask's
 # threshold; on these grids the numerical diffusion of the penalty leaves
-# almost no value below M/2), sampled without replacement, seed 4; batch
-# 4096, 20 epochs, each epoch in its own random order.
+# almost no value below M/2), sampled without replacement in random order,
+# seed 4; batch 16384 (one 64-sample tile per CU), 10 epochs, Adam with step
+# size 2e-3, each epoch in its own random order of batch-sized windows of the
+# shuffled pairs.
 MLP_PAIRS = 2_000_000
-MLP_BATCH = 4096
-MLP_EPOCHS = 20
+MLP_BATCH = 16384
+MLP_EPOCHS = 10
+MLP_LR = 2e-3
 MLP_SEED = 4
 MLP_FEASIBLE_FRAC = 0.98
 
@@ -279,16 +282,32 @@ SEEDED = dict(mode="seeded", n_scan=64, n_golden=12, n_local=8, local_half_width
 
 
 def mlp_pair_selection(n_feasible, n_pairs=MLP_PAIRS, seed=MLP_SEED):
-    """Indices of the training pairs among the feasible nodes (int32)."""
+    """Indices of the training pairs among the feasible nodes, in random
+    order (int32)."""
     rng = np.random.default_rng(seed)
     k = min(int(n_pairs), int(n_feasible))
-    return np.sort(rng.choice(int(n_feasible), size=k, replace=False)).astype(np.int32)
+    return rng.choice(int(n_feasible), size=k, replace=False).astype(np.int32)
 
 
-def mlp_epoch_orders(n, epochs=MLP_EPOCHS, seed=MLP_SEED):
-    """One random permutation of range(n) per epoch (int32)."""
+def mlp_epoch_orders(n, epochs=MLP_EPOCHS, seed=MLP_SEED, batch=MLP_BATCH):
+    """The sample order of each epoch (int32, a permutation of range(n)),
+    drawn lazily: the pairs, already in random order, cut into windows of
+    `batch` consecutive samples starting at a random offset (cyclically), and
+    the windows taken in random order.  Drawing one takes a few milliseconds
+    for 2M pairs (a full random permutation of 2M takes tens), so the next
+    epoch's order is ready while the device trains on the current one."""
     rng = np.random.default_rng(seed + 1000)
-    return [rng.permutation(int(n)).astype(np.int32) for _ in range(epochs)]
+    n = int(n)
+    nb = (n + batch - 1) // batch
+    within = np.arange(batch, dtype=np.int32)
+    for _ in range(epochs):
+        shift = int(rng.integers(n))
+        idx = (rng.permutation(nb).astype(np.int32)[:, None] * np.int32(batch) + within[None, :]).reshape(-1)
+        if n % batch:
+            idx = idx[idx < n]
+        idx += np.int32(shift)
+        np.subtract(idx, np.int32(n), out=idx, where=idx >= n)
+        yield idx
 
 
 def mlp_random_samples(n, seed, thrust_frac=0.6):

@@ -105,7 +105,7 @@ def test_training_lowers_loss_and_is_deterministic(dpo):
     for _ in range(2):
         net = dpo.Mlp(inputs.mlp_params32(seed=4))
         hist = []
-        for e, order in enumerate(inputs.mlp_epoch_orders(n, epochs=6)):
+        for e, order in enumerate(inputs.mlp_epoch_orders(n, epochs=6, batch=1024)):
             hist.append(host(net.train_epoch(dev(x), dev(t), perm=order, batch=1024)))
         runs.append((np.concatenate(hist), net.params()))
     # a third run issues its epochs alternately on two streams with no host
@@ -117,7 +117,7 @@ def test_training_lowers_loss_and_is_deterministic(dpo):
     net = dpo.Mlp(inputs.mlp_params32(seed=4))
     torch.cuda.synchronize()
     hist = []
-    for e, order in enumerate(inputs.mlp_epoch_orders(n, epochs=6)):
+    for e, order in enumerate(inputs.mlp_epoch_orders(n, epochs=6, batch=1024)):
         with torch.cuda.stream(streams[e % 2]):
             hist.append(net.train_epoch(xd, td, perm=order, batch=1024))
     torch.cuda.synchronize()
@@ -211,7 +211,7 @@ def train_on_solution(dpo, ctx, p, V, a, t, epochs=20, batch=4096):
     x, tgt = ctx.gather_pairs(nodes, sel, a, t)
     net = dpo.Mlp(inputs.mlp_params32(seed=inputs.MLP_SEED))
     hist = [host(net.train_epoch(x, tgt, perm=o, batch=batch)).mean()
-            for o in inputs.mlp_epoch_orders(x.shape[0], epochs=epochs)]
+            for o in inputs.mlp_epoch_orders(x.shape[0], epochs=epochs, batch=batch)]
     return net, hist, x.shape[0]
 
 
