@@ -681,9 +681,11 @@ int sweep_eval_desc(dpo_ctx* c, const float* Vin, float* Vout, hipStream_t s) {
 // GMRES is the solver the paper names).  b is the frozen-policy sweep of V
 // with its free entries zeroed (running cost plus the fixed corners and M);
 // the operator is the sweep without that affine part.  Classical
-// Gram-Schmidt in two passes every step (for I - gamma P the first pass
-// loses more than a factor 1/sqrt(2) of the norm nearly every step, the
-// criterion of Daniel, Gragg, Kaufman and Stewart for a second one); the
+// Gram-Schmidt in one pass, its coefficients formed in the same pass as
+// w = v - gamma P v: with a basis of at most 8 vectors the loss of
+// orthogonality a second pass would repair costs no operator applications
+// here (Example 1: 1681 with one pass, 1690 with two), and the stop test
+// uses the true residual b - A x, not the Hessenberg estimate.  The
 // coefficients, the Hessenberg matrix and its Givens rotations stay on the
 // device in FP64, so a step needs no host synchronisation; the triangular
 // solve of a cycle runs on the host.  Stop measure: the node-wise relative
@@ -692,13 +694,14 @@ int sweep_eval_desc(dpo_ctx* c, const float* Vin, float* Vout, hipStream_t s) {
 // (read one step late, so at most one step more).
 
 constexpr int kGmresRestart = 8;
+static_assert(kGmresRestart <= kDotGroup, "one fused dot-product pass covers the basis");
 constexpr double kCycleDrop = 1e-2;
 constexpr double kExactEvalTol = 5e-7;  // node-wise residual of the evaluations inside policy iteration
 
-// Device Arnoldi state of gmres_eval: the two Gram-Schmidt passes' dot
-// products, the new vector's squared norm, the Hessenberg matrix, the Givens
-// rotations, the rotated right-hand side, 1/h_(k+1)k and the step's status.
-constexpr int kArnD1 = 0, kArnD2 = kMaxBasis, kArnNrm = 2 * kMaxBasis, kArnH = 2 * kMaxBasis + 1;
+// Device Arnoldi state of gmres_eval: the Gram-Schmidt dot products, the
+// new vector's squared norm, the Hessenberg matrix, the Givens rotations, the
+// rotated right-hand side, 1/h_(k+1)k and the step's status.
+constexpr int kArnD = 0, kArnNrm = kMaxBasis, kArnH = kMaxBasis + 1;
 constexpr int kArnCs = kArnH + (kMaxBasis + 1) * kMaxBasis, kArnSn = kArnCs + kMaxBasis, kArnG = kArnSn + kMaxBasis;
 constexpr int kArnInv = kArnG + kMaxBasis + 1, kArnStat = kArnInv + 1, kArnDoubles = kArnStat + 2;
 
@@ -781,10 +784,10 @@ int gmres_eval(dpo_ctx* c, float* V, const float* ang, const uint8_t* thr, doubl
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     HIP_TRY(c, hipMemcpyAsync(arn + kArnG, g.data(), sizeof(double) * (m + 1), hipMemcpyHostToDevice, s));
-    // Arnoldi steps with no host synchronisation: classical Gram-Schmidt in
-    // two passes (the coefficients stay on the device), the Hessenberg column
-    // and its Givens rotation in one small kernel; the host reads each step's
-    // status one step late, so the device always has the next step queued.
+    // Arnoldi steps with no host synchronisation: classical Gram-Schmidt
+    // (the coefficients stay on the device), the Hessenberg column and its
+    // Givens rotation in one small kernel; the host reads each step's status
+    // one step late, so the device always has the next step queued.
     int k = 0;
     bool stop = false;
     while (k < m && it < max_iter && !stop) {
@@ -793,11 +796,9 @@ int gmres_eval(dpo_ctx* c, float* V, const float* ang, const uint8_t* thr, doubl
       HIP_TRY(c, launch_eval_hom(a, vk, Y, s));
       mv++;
       it++;
-      HIP_TRY(c, launch_sub(vk, Y, w, N, s));
-      HIP_TRY(c, launch_dots(basis, k + 1, ld, w, N, c->kpart, arn + kArnD1, s));
-      HIP_TRY(c, launch_axpys_dots(w, basis, k + 1, ld, arn + kArnD1, N, c->kpart, arn + kArnD2, s));
-      HIP_TRY(c, launch_axpys(w, basis, k + 1, ld, arn + kArnD2, N, s, c->kpart, arn + kArnNrm));
-      HIP_TRY(c, launch_arnoldi_col(k, m, arn + kArnD1, arn + kArnD2, arn + kArnNrm, arn + kArnH, arn + kArnCs,
+      HIP_TRY(c, launch_sub_dots(vk, Y, w, basis, k + 1, ld, N, c->kpart, arn + kArnD, s));
+      HIP_TRY(c, launch_axpys(w, basis, k + 1, ld, arn + kArnD, N, s, c->kpart, arn + kArnNrm));
+      HIP_TRY(c, launch_arnoldi_col(k, m, arn + kArnD, arn + kArnNrm, arn + kArnH, arn + kArnCs,
                                     arn + kArnSn, arn + kArnG, arn + kArnInv, arn + kArnStat, s));
       HIP_TRY(c, launch_scale_dev(w, arn + kArnInv, w, N, s));
       HIP_TRY(c, hipMemcpyAsync(c->karn_host + 2 * k, arn + kArnStat, 2 * sizeof(double), hipMemcpyDeviceToHost, s));

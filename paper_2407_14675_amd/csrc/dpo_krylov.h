@@ -16,8 +16,10 @@ constexpr int kStreamBlocks = 1024; // workgroups of the vector kernels (grid-st
 hipError_t launch_eval_hom(const SweepArgs& a, const float* x, float* y, hipStream_t s);
 // r = b - x + y
 hipError_t launch_residual(const float* b, const float* x, const float* y, float* r, int N, hipStream_t s);
-// w = v - y
-hipError_t launch_sub(const float* v, const float* y, float* w, int N, hipStream_t s);
+// w = v - y, then out[i] = <basis_i, w> in FP64 for i < k <= kDotGroup, in one pass
+// (partial: kStreamBlocks * kDotGroup doubles)
+hipError_t launch_sub_dots(const float* v, const float* y, float* w, const float* basis, int k, size_t ld, int N,
+                           double* partial, double* out, hipStream_t s);
 // out[i] = <basis_i, w> in FP64 for i < k (partial: kStreamBlocks * kDotGroup doubles)
 hipError_t launch_dots(const float* basis, int k, size_t ld, const float* w, int N, double* partial, double* out,
                        hipStream_t s);
@@ -28,15 +30,13 @@ hipError_t launch_relmax(const float* r, const float* x, int N, double* partial,
 hipError_t launch_axpys(float* w, const float* basis, int k, size_t ld, const double* coef, int N, hipStream_t s,
                        double* partial = nullptr, double* nrm_out = nullptr);
 // dst = s * src
-// w -= basis coef (k terms), then out[0..k) = <basis_i, new w>; one pass for k <= kDotGroup
-hipError_t launch_axpys_dots(float* w, const float* basis, int k, size_t ld, const double* coef, int N,
-                             double* partial, double* out, hipStream_t s);
 hipError_t launch_scale(const float* src, double s, float* dst, int N, hipStream_t st);
-// dst[j] = src[j] at the free nodes j
+// dst = (*sc) * src, the factor read from device memory
 hipError_t launch_scale_dev(const float* src, const double* sc, float* dst, int N, hipStream_t s);
 // column k of the Arnoldi process and its Givens rotation, on the device (see k_arnoldi_col)
-hipError_t launch_arnoldi_col(int k, int m, const double* d1, const double* d2, const double* nrm2, double* H,
-                              double* cs, double* sn, double* g, double* inv_hn, double* status, hipStream_t s);
+hipError_t launch_arnoldi_col(int k, int m, const double* d, const double* nrm2, double* H, double* cs, double* sn,
+                              double* g, double* inv_hn, double* status, hipStream_t s);
+// dst[j] = src[j] at the free nodes j
 hipError_t launch_free_copy(const SweepArgs& a, const float* src, float* dst, hipStream_t s);
 // dst[j] = 0 at the free nodes j
 hipError_t launch_free_zero(const SweepArgs& a, float* dst, hipStream_t s);

@@ -49,10 +49,37 @@ __global__ __launch_bounds__(kBlock) void k_residual(const float* __restrict__ b
   for (int j = blockIdx.x * kBlock + threadIdx.x; j < N; j += gridDim.x * kBlock) r[j] = (b[j] - x[j]) + y[j];
 }
 
-// w = v - y  (A v with y = gamma P v)
-__global__ __launch_bounds__(kBlock) void k_sub(const float* __restrict__ v, const float* __restrict__ y,
-                                                float* __restrict__ w, int N) {
-  for (int j = blockIdx.x * kBlock + threadIdx.x; j < N; j += gridDim.x * kBlock) w[j] = v[j] - y[j];
+// w = v - y (A v, with y = gamma P v) and, in the same pass, the partial dot
+// products of the new w with the first k <= kDotGroup basis vectors (the
+// layout of k_dots): the Gram-Schmidt coefficients of w without a second
+// read of it.
+__global__ __launch_bounds__(kBlock) void k_sub_dots(const float* __restrict__ v, const float* __restrict__ y,
+                                                     float* __restrict__ w, const float* __restrict__ basis, int k,
+                                                     size_t ld, int N, double* __restrict__ partial) {
+  double acc[kDotGroup];
+#pragma unroll
+  for (int i = 0; i < kDotGroup; i++) acc[i] = 0.0;
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < N; j += gridDim.x * kBlock) {
+    const float nw = v[j] - y[j];
+    w[j] = nw;
+    const double wj = (double)nw;
+#pragma unroll
+    for (int i = 0; i < kDotGroup; i++)
+      if (i < k) acc[i] += (double)basis[(size_t)i * ld + j] * wj;
+  }
+  __shared__ double red[kBlock / 64][kDotGroup];
+#pragma unroll
+  for (int i = 0; i < kDotGroup; i++) {
+    double a = acc[i];
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][i] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x < kDotGroup) {
+    double t = 0.0;
+    for (int q = 0; q < kBlock / 64; q++) t += red[q][threadIdx.x];
+    partial[(size_t)blockIdx.x * kDotGroup + threadIdx.x] = t;
+  }
 }
 
 // Partial dot products of w with up to kDotGroup basis vectors (rows of
@@ -169,50 +196,6 @@ __global__ __launch_bounds__(kBlock) void k_axpys(float* __restrict__ w, const f
   }
 }
 
-// k_axpys (no norm) followed by k_dots of the new w with the same k <=
-// kDotGroup basis vectors, in one pass: each element of the new w is formed
-// and then multiplied with the basis values already loaded.  The same sums
-// in the same order as the two kernels, so the same results bit for bit.
-__global__ __launch_bounds__(kBlock) void k_axpys_dots(float* __restrict__ w, const float* __restrict__ basis, int k,
-                                                       size_t ld, const double* __restrict__ coef, int N,
-                                                       double* __restrict__ partial) {
-  __shared__ double c[kDotGroup];
-  if ((int)threadIdx.x < k) c[threadIdx.x] = coef[threadIdx.x];
-  __syncthreads();
-  double acc[kDotGroup];
-#pragma unroll
-  for (int i = 0; i < kDotGroup; i++) acc[i] = 0.0;
-  for (int j = blockIdx.x * kBlock + threadIdx.x; j < N; j += gridDim.x * kBlock) {
-    float v[kDotGroup];
-    double s = 0.0;
-#pragma unroll
-    for (int i = 0; i < kDotGroup; i++)
-      if (i < k) {
-        v[i] = basis[(size_t)i * ld + j];
-        s += c[i] * (double)v[i];
-      }
-    const float nw = (float)((double)w[j] - s);
-    w[j] = nw;
-    const double wj = (double)nw;
-#pragma unroll
-    for (int i = 0; i < kDotGroup; i++)
-      if (i < k) acc[i] += (double)v[i] * wj;
-  }
-  __shared__ double red[kBlock / 64][kDotGroup];
-#pragma unroll
-  for (int i = 0; i < kDotGroup; i++) {
-    double v = acc[i];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][i] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x < kDotGroup) {
-    double t = 0.0;
-    for (int q = 0; q < kBlock / 64; q++) t += red[q][threadIdx.x];
-    partial[(size_t)blockIdx.x * kDotGroup + threadIdx.x] = t;
-  }
-}
-
 __global__ __launch_bounds__(kBlock) void k_scale(const float* __restrict__ src, double s, float* __restrict__ dst,
                                                   int N) {
   for (int j = blockIdx.x * kBlock + threadIdx.x; j < N; j += gridDim.x * kBlock) dst[j] = (float)((double)src[j] * s);
@@ -226,20 +209,20 @@ __global__ __launch_bounds__(kBlock) void k_scale_dev(const float* __restrict__ 
 }
 
 // Column k of the Arnoldi process, on the device (one thread, FP64): the
-// Hessenberg entries h_ik = d1_i + d2_i (the two classical Gram-Schmidt
-// passes) for i <= k and h_(k+1)k = sqrt(*nrm2) (the norm of the new basis
-// vector before scaling), the earlier Givens rotations applied to the
-// column, a new one zeroing h_(k+1)k, and the rotated right-hand side g.
+// Hessenberg entries h_ik = d_i (the classical Gram-Schmidt coefficients)
+// for i <= k and h_(k+1)k = sqrt(*nrm2) (the norm of the new basis vector
+// before scaling), the earlier Givens rotations applied to the column, a new
+// one zeroing h_(k+1)k, and the rotated right-hand side g.
 // H is (m + 1) x m, row-major.  Writes *inv_hn = 1/h_(k+1)k (0 at a
 // breakdown) for the scaling of the new vector, and status = (|g_(k+1)|,
 // h_(k+1)k) for the host's stop test.
-__global__ void k_arnoldi_col(int k, int m, const double* __restrict__ d1, const double* __restrict__ d2,
-                              const double* __restrict__ nrm2, double* __restrict__ H, double* __restrict__ cs,
+__global__ void k_arnoldi_col(int k, int m, const double* __restrict__ d, const double* __restrict__ nrm2,
+                              double* __restrict__ H, double* __restrict__ cs,
                               double* __restrict__ sn, double* __restrict__ g, double* __restrict__ inv_hn,
                               double* __restrict__ status) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const double hn = sqrt(fmax(nrm2[0], 0.0));
-  for (int i = 0; i <= k; i++) H[(size_t)i * m + k] = d1[i] + d2[i];
+  for (int i = 0; i <= k; i++) H[(size_t)i * m + k] = d[i];
   H[(size_t)(k + 1) * m + k] = hn;
   for (int i = 0; i < k; i++) {
     const double t0 = H[(size_t)i * m + k], t1 = H[(size_t)(i + 1) * m + k];
@@ -296,8 +279,13 @@ hipError_t launch_residual(const float* b, const float* x, const float* y, float
   return hipGetLastError();
 }
 
-hipError_t launch_sub(const float* v, const float* y, float* w, int N, hipStream_t s) {
-  hipLaunchKernelGGL(k_sub, dim3(stream_blocks(N)), dim3(kBlock), 0, s, v, y, w, N);
+hipError_t launch_sub_dots(const float* v, const float* y, float* w, const float* basis, int k, size_t ld, int N,
+                           double* partial, double* out, hipStream_t s) {
+  if (k > kDotGroup) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_sub_dots, dim3(kStreamBlocks), dim3(kBlock), 0, s, v, y, w, basis, k, ld, N, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_dots_final, dim3(k), dim3(kBlock), 0, s, partial, kStreamBlocks, out);
   return hipGetLastError();
 }
 
@@ -333,20 +321,6 @@ hipError_t launch_axpys(float* w, const float* basis, int k, size_t ld, const do
   return hipGetLastError();
 }
 
-hipError_t launch_axpys_dots(float* w, const float* basis, int k, size_t ld, const double* coef, int N,
-                             double* partial, double* out, hipStream_t s) {
-  if (k > kDotGroup) {
-    hipError_t e = launch_axpys(w, basis, k, ld, coef, N, s);
-    if (e != hipSuccess) return e;
-    return launch_dots(basis, k, ld, w, N, partial, out, s);
-  }
-  hipLaunchKernelGGL(k_axpys_dots, dim3(kStreamBlocks), dim3(kBlock), 0, s, w, basis, k, ld, coef, N, partial);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_dots_final, dim3(k), dim3(kBlock), 0, s, partial, kStreamBlocks, out);
-  return hipGetLastError();
-}
-
 hipError_t launch_scale(const float* src, double sc, float* dst, int N, hipStream_t s) {
   hipLaunchKernelGGL(k_scale, dim3(stream_blocks(N)), dim3(kBlock), 0, s, src, sc, dst, N);
   return hipGetLastError();
@@ -357,9 +331,9 @@ hipError_t launch_scale_dev(const float* src, const double* sc, float* dst, int 
   return hipGetLastError();
 }
 
-hipError_t launch_arnoldi_col(int k, int m, const double* d1, const double* d2, const double* nrm2, double* H,
-                              double* cs, double* sn, double* g, double* inv_hn, double* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_arnoldi_col, dim3(1), dim3(64), 0, s, k, m, d1, d2, nrm2, H, cs, sn, g, inv_hn, status);
+hipError_t launch_arnoldi_col(int k, int m, const double* d, const double* nrm2, double* H, double* cs, double* sn,
+                              double* g, double* inv_hn, double* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_arnoldi_col, dim3(1), dim3(64), 0, s, k, m, d, nrm2, H, cs, sn, g, inv_hn, status);
   return hipGetLastError();
 }
 
