@@ -54,7 +54,8 @@ GATHER_BYTES_PER_EVAL = 64
 # HBM traffic of the evaluation sweep measured with rocprofv3 counters, with
 # the hash of the kernel sources it was measured on.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_eval_brick_desc_96x96x96x64_traffic.json")
-KERNEL_SOURCES = ["dpo_brick.hip", "dpo_kernels.hip", "dpo_device.h", "dpo_kernels.h", "dpo_search.h"]
+KERNEL_SOURCES = ["dpo_brick.hip", "dpo_kernels.hip", "dpo_device.h", "dpo_kernels.h", "dpo_search.h",
+                  "dpo_api.hip"]  # the last holds the brick plan (tiles, planes per workgroup)
 
 
 def kernel_source_hash():
