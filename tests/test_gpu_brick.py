@@ -148,14 +148,15 @@ def test_descriptor_brick_matches_global_gathers_and_oracle(dpo, case):
     assert np.all(np.abs(ve - q) <= 1e-5 * np.maximum(1.0, np.abs(q)) + 1e-6 * corner)
 
 
-@pytest.mark.parametrize("n_m", [64, 60])
+@pytest.mark.parametrize("n_m", [64, 60, 32, 9])
 def test_brick_full_size_96x96x96x64(dpo, n_m):
-    """The 96^3 x 64 grid (runs of 8 mass planes per workgroup) and 96^3 x 60
-    (seven runs of 8 and a last run of 4), the greedy policy of a partly
-    converged value: each brick sweep equals its global-gather counterpart
-    at every node (descriptor form and policy-array form), and the
-    no-allocation entry point on the brick path equals both policy-array
-    sweeps."""
+    """The 96^3 x 64 grid (runs of 8 mass planes per workgroup), 96^3 x 60
+    (seven runs of 8 and a last run of 4), 96^3 x 32 (runs of 4) and
+    96^3 x 9 (one GPU's slab of an 8-way split: runs of 2 and a last run of
+    1), the greedy policy of a partly converged value: each brick sweep
+    equals its global-gather counterpart at every node (descriptor form and
+    policy-array form), and the no-allocation entry point on the brick path
+    equals both policy-array sweeps."""
     p = inputs.large_problem(accel=1e-3)
     if n_m != 64:
         p = inputs.with_grid(p, (96, 96, 96, n_m))
