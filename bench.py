@@ -48,6 +48,9 @@ EVAL_ALGO_BYTES_PER_NODE = 16
 # throttle written (4 + 4 + 1) + the compact foot descriptor written (2 + 8).
 GREEDY_BYTES_PER_NODE = 27
 EVALS_PER_GREEDY_NODE = 1 + 64 + 2 + 12
+# VALU wave instructions per wave of 64 nodes of the greedy sweep with foot
+# descriptors, from the SQ_INSTS_VALU counter (profiles/k_sweep_fast_seeded_96x96x96x64.md)
+GREEDY_VALU_PER_WAVE = 2198
 # Gather bytes of one evaluation done naively: 16 float32 corners.
 GATHER_BYTES_PER_EVAL = 64
 
@@ -888,6 +891,7 @@ def main():
     eval_gbs = eval_algo_bytes / (eval_ms * 1e-3) / 1e9
     stream_bytes = ctx.eval_sweep_bytes()
     greedy_evals = n_free * EVALS_PER_GREEDY_NODE
+    greedy_valu = GREEDY_VALU_PER_WAVE * ((n_free + 63) // 64) / (greedy_ms * 1e-3)
     log(f"bench: greedy sweep {greedy_ms:.4f} ms, eval sweep {eval_ms:.4f} ms ({eval_gbs:.0f} GB/s algorithmic)")
     # the counter record holds the brick kernel's bytes
     traffic = measured_traffic() if eval_path == 2 else None
@@ -1005,6 +1009,13 @@ def main():
             "evals_per_s": greedy_evals / (greedy_ms * 1e-3),
             "hbm_bytes_per_node": GREEDY_BYTES_PER_NODE,
             "hbm_frac": GREEDY_BYTES_PER_NODE * n_free / (greedy_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "valu_wave_instr_per_wave": GREEDY_VALU_PER_WAVE,
+            "valu_wave_instr_per_s": greedy_valu,
+            "valu_peak_unpacked_wave_instr_per_s": VALU_UNPACKED_WAVE_INSTR_PER_S,
+            "valu_frac_of_unpacked_peak": greedy_valu / VALU_UNPACKED_WAVE_INSTR_PER_S,
+            "valu_frac_of_measured_fma_loop": (greedy_valu / ceilings["valu_wave_instr_per_s"]) if ceilings else None,
+            "valu_note": "issue rate from the counted instructions per wave; above 1 because the sweep's moves, "
+                         "selects and integer operations issue faster than the FP32 FMAs the peak counts",
         },
         "gather_roofline": {
             "naive_gather_bytes_per_eval": GATHER_BYTES_PER_EVAL,
