@@ -50,10 +50,13 @@ def rel_err(a, b):
     return np.abs(a - b) / np.maximum(1.0, np.abs(b))
 
 
-@pytest.mark.parametrize("integrator", ["euler", "heun"])
-def test_exact_evaluation_parity(dpo, integrator):
-    p = inputs.crown_problem((8, 6, 6, 8), integrator=integrator)
-    _say("exact evaluation", integrator)
+@pytest.mark.parametrize("integrator,n", [("euler", (8, 6, 6, 8)), ("heun", (8, 6, 6, 8)),
+                                          ("heun", (16, 10, 10, 12))])
+def test_exact_evaluation_parity(dpo, integrator, n):
+    """Against the oracle's direct sparse solve: 2,304 nodes with either foot,
+    and 19,200 nodes (several GMRES restarts over a basis of 8)."""
+    p = inputs.crown_problem(n, integrator=integrator)
+    _say("exact evaluation", integrator, n)
     o = Oracle(p)
     rng = np.random.default_rng(141)
     ang = rng.uniform(-math.pi, math.pi, size=o.shape).astype(np.float32)
@@ -76,6 +79,33 @@ def test_exact_evaluation_parity(dpo, integrator):
     assert rel64 <= 3e-6
     assert err <= 1.01 * np.max(np.abs(r)) / (1 - gamma)
     assert rel_err(v, want).max() <= 1e-4
+
+
+def test_exact_evaluation_full_size_a_posteriori(dpo):
+    """The paper's Example 1 grid (110 x 30 x 30 x 30, 2.97M unknowns, Heun
+    foot) under a random policy, solved by GMRES to a node-wise relative
+    residual of 1e-6: at 100,000 sampled nodes the oracle's FP64 frozen-policy
+    step (its Q of the node's control at the device's solution) moves the
+    solution by no more than a few times the tolerance, which bounds the
+    error by the residual over 1 - exp(-lambda dt)."""
+    p = inputs.EX1
+    _say("exact evaluation, Example 1 grid")
+    ctx = dpo.Context(p)
+    o = Oracle(p)
+    rng = np.random.default_rng(143)
+    ang = rng.uniform(-math.pi, math.pi, size=o.shape).astype(np.float32)
+    thr = rng.integers(0, 2, size=o.shape).astype(np.uint8)
+    V = ctx.init_value()
+    rc, mv, rel = ctx.policy_evaluate(V, dev(ang), dev(thr, torch.uint8), tol_rel=1e-6, max_iter=5000)
+    _say("  operator applications", mv, "relative residual", rel)
+    assert rc == dpo.DPO_OK and rel <= 1e-6
+    v = host(V).astype(np.float64)
+    nodes = np.sort(rng.choice(o.N, size=100000, replace=False)).astype(np.int64)
+    q = o.q_many(v, nodes, thr.reshape(-1)[nodes], ang.reshape(-1)[nodes].astype(np.float64))
+    vn = v.reshape(-1)[nodes]
+    r = np.abs(q - vn) / np.maximum(1.0, np.abs(vn))
+    _say(f"  FP64 node-wise residual at the sampled nodes: max {r.max():.2e}, 99.9 % {np.quantile(r, 0.999):.2e}")
+    assert r.max() <= 3e-6
 
 
 def test_policy_iteration_with_exact_evaluation(dpo):
