@@ -241,6 +241,28 @@ def test_vi_and_pi_reach_the_same_fixed_point():
     assert pix["outer"] < vi["sweeps"] / 5
 
 
+@pytest.mark.parametrize("lam", [0.0, 0.7])
+def test_pi_with_the_incumbent_rule_reaches_vis_fixed_point_under_the_search(lam):
+    """With the continuous search (scan 64 + golden section) the greedy step
+    is only approximately the argmin, and policy iteration keeps a node's
+    control unless the search finds a strictly smaller Q, so its fixed point
+    is a fixed point of min(search, incumbent).  On the 6^4 orbit problem it
+    is value iteration's under the same search (to 1e-11 relative, undiscounted
+    and discounted, with 20 frozen-policy sweeps per update and with exact
+    evaluation)."""
+    p = inputs.orbit_problem((6, 6, 6, 6), search=inputs.SCAN_GOLDEN, lam=lam)
+    o = Oracle(p)
+    vi = o.solve_vi(tol_abs=1e-11, max_sweeps=200000)
+    runs = [o.solve_pi(tol_abs=1e-11, eval_sweeps=20)]
+    if lam > 0:
+        runs.append(o.solve_pi(tol_abs=1e-11, eval_sweeps=-1))
+    scale = np.maximum(np.abs(vi["V"]), 1.0)
+    assert vi["converged"]
+    for r in runs:
+        assert r["converged"]
+        assert np.max(np.abs(r["V"] - vi["V"]) / scale) < 1e-11
+
+
 # ------------------------------------------------ T5 search vs brute force
 def test_golden_search_matches_brute_force():
     """Scan of 64 + golden refinement reaches the minimum of Q over a
