@@ -232,6 +232,34 @@ class Context:
             raise DpoError(rc, self.lib.dpo_last_error(self.h).decode())
         return rc
 
+    def _arr(self, t, dtype, name, n=None):
+        """A node array (or n elements) of the given dtype, contiguous on the
+        device: checked here, since the library cannot see a tensor's size."""
+        if t is None:
+            return None
+        n = self.N if n is None else n
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous() or t.dtype != dtype \
+                or t.numel() != n:
+            raise DpoError(DPO_EINVAL, f"{name} must be a contiguous device tensor of {n} {dtype} elements")
+        return _p(t)
+
+    def _v(self, t, name="V"):
+        return self._arr(t, torch.float32, name)
+
+    def _ang(self, t, name="pol_ang"):
+        return self._arr(t, torch.float32, name)
+
+    def _thr(self, t, name="pol_thr"):
+        return self._arr(t, torch.uint8, name)
+
+    def _res(self, t):
+        if t is None:
+            return None
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous() or t.dtype != torch.float64 \
+                or t.numel() < 5:
+            raise DpoError(DPO_EINVAL, "resid must be a contiguous device float64 tensor of at least 5 elements")
+        return _p(t)
+
     # ---------------------------------------------------------- buffers
     def empty_value(self):
         return torch.empty(self.shape, dtype=torch.float32, device=self.device)
@@ -279,44 +307,50 @@ class Context:
 
     def init_value(self, V=None):
         V = self.empty_value() if V is None else V
-        self._check(self.lib.dpo_init_value(self.h, _p(V), _stream()))
+        self._check(self.lib.dpo_init_value(self.h, self._v(V), _stream()))
         return V
 
     # ------------------------------------------------------------ sweeps
     def bellman_sweep(self, V_in, V_out, pol_ang=None, pol_thr=None, resid=None):
-        return self._check(self.lib.dpo_bellman_sweep(self.h, _p(V_in), _p(V_out), _p(pol_ang), _p(pol_thr),
-                                                       _p(resid), _stream()))
+        return self._check(self.lib.dpo_bellman_sweep(self.h, self._v(V_in, "V_in"), self._v(V_out, "V_out"),
+                                                       self._ang(pol_ang), self._thr(pol_thr), self._res(resid),
+                                                       _stream()))
 
     def bellman_sweep_seeded(self, V_in, V_out, pol_ang, pol_thr, seed, resid=None):
-        return self._check(self.lib.dpo_bellman_sweep_seeded(self.h, _p(V_in), _p(V_out), _p(pol_ang),
-                                                              _p(pol_thr), _p(seed), _p(resid), _stream()))
+        return self._check(self.lib.dpo_bellman_sweep_seeded(self.h, self._v(V_in, "V_in"), self._v(V_out, "V_out"),
+                                                              self._ang(pol_ang), self._thr(pol_thr),
+                                                              self._ang(seed, "seed"), self._res(resid), _stream()))
 
     def policy_eval_sweep(self, V_in, V_out, pol_ang, pol_thr, resid=None):
-        return self._check(self.lib.dpo_policy_eval_sweep(self.h, _p(V_in), _p(V_out), _p(pol_ang), _p(pol_thr),
-                                                           _p(resid), _stream()))
+        return self._check(self.lib.dpo_policy_eval_sweep(self.h, self._v(V_in, "V_in"), self._v(V_out, "V_out"),
+                                                           self._ang(pol_ang), self._thr(pol_thr), self._res(resid),
+                                                           _stream()))
 
     def policy_eval_sweep_static(self, V_in, V_out, pol_ang, pol_thr, resid=None):
         """policy_eval_sweep with its scratch in the library's static device
         array: the call allocates nothing."""
-        return self._check(self.lib.dpo_policy_eval_sweep_static(self.h, _p(V_in), _p(V_out), _p(pol_ang),
-                                                                  _p(pol_thr), _p(resid), _stream()))
+        return self._check(self.lib.dpo_policy_eval_sweep_static(self.h, self._v(V_in, "V_in"),
+                                                                  self._v(V_out, "V_out"), self._ang(pol_ang),
+                                                                  self._thr(pol_thr), self._res(resid), _stream()))
 
     def policy_eval_sweep_last(self, V_in, V_out):
         """Frozen-policy sweep for the policy of the last Bellman sweep."""
-        return self._check(self.lib.dpo_policy_eval_sweep_last(self.h, _p(V_in), _p(V_out), _stream()))
+        return self._check(self.lib.dpo_policy_eval_sweep_last(self.h, self._v(V_in, "V_in"), self._v(V_out, "V_out"),
+                                                                _stream()))
 
     # ----------------------------------------------------------- solvers
     def solve_vi(self, V, pol_ang, pol_thr, tol_rel=1e-6, max_sweeps=100000, check_every=16):
         st = Stats()
-        rc = self.lib.dpo_solve_vi(self.h, _p(V), _p(pol_ang), _p(pol_thr), float(tol_rel), int(max_sweeps),
+        rc = self.lib.dpo_solve_vi(self.h, self._v(V), self._ang(pol_ang), self._thr(pol_thr), float(tol_rel),
+                                   int(max_sweeps),
                                    int(check_every), C.byref(st), _stream())
         self._check(rc, allow=(DPO_OK, DPO_ENOCONV))
         return rc, st.as_dict()
 
     def solve_pi(self, V, pol_ang, pol_thr, tol_rel=1e-6, eval_sweeps=20, max_outer=100000, seed=None):
         st = Stats()
-        rc = self.lib.dpo_solve_pi(self.h, _p(V), _p(pol_ang), _p(pol_thr), float(tol_rel), int(eval_sweeps),
-                                   int(max_outer), _p(seed), C.byref(st), _stream())
+        rc = self.lib.dpo_solve_pi(self.h, self._v(V), self._ang(pol_ang), self._thr(pol_thr), float(tol_rel),
+                                   int(eval_sweeps), int(max_outer), self._ang(seed, "seed"), C.byref(st), _stream())
         self._check(rc, allow=(DPO_OK, DPO_ENOCONV))
         return rc, st.as_dict()
 
@@ -325,7 +359,8 @@ class Context:
         applications, final relative residual)."""
         mv = C.c_int64()
         rel = C.c_double()
-        rc = self.lib.dpo_policy_evaluate(self.h, _p(V), _p(pol_ang), _p(pol_thr), float(tol_rel), int(max_iter),
+        rc = self.lib.dpo_policy_evaluate(self.h, self._v(V), self._ang(pol_ang), self._thr(pol_thr), float(tol_rel),
+                                          int(max_iter),
                                           C.byref(mv), C.byref(rel), _stream())
         self._check(rc, allow=(DPO_OK, DPO_ENOCONV))
         return rc, mv.value, rel.value
@@ -334,7 +369,7 @@ class Context:
     def value_at(self, V, x):
         xs = (C.c_double * 4)(*[float(v) for v in x])
         out = C.c_double()
-        self._check(self.lib.dpo_value_at(self.h, _p(V), xs, C.byref(out), _stream()))
+        self._check(self.lib.dpo_value_at(self.h, self._v(V), xs, C.byref(out), _stream()))
         return out.value
 
     def feedback(self, V, states, tau=None):
@@ -344,7 +379,7 @@ class Context:
         thr = torch.empty(n, dtype=torch.uint8, device=self.device)
         q = torch.empty(n, dtype=torch.float32, device=self.device)
         tau = self.problem["dt"] if tau is None else tau
-        self._check(self.lib.dpo_extract_feedback(self.h, _p(V), _p(states), n, float(tau), _p(ang), _p(thr),
+        self._check(self.lib.dpo_extract_feedback(self.h, self._v(V), _p(states), n, float(tau), _p(ang), _p(thr),
                                                   _p(q), _stream()))
         return ang, thr, q
 
@@ -362,7 +397,7 @@ class Context:
             thr = torch.empty((steps, n), dtype=torch.uint8, device=self.device)
             ang = torch.empty((steps, n), dtype=torch.float32, device=self.device)
         tau = self.problem["dt"] if tau is None else tau
-        self._check(self.lib.dpo_simulate(self.h, _p(V), _p(st), n, float(tau), int(steps), int(substeps),
+        self._check(self.lib.dpo_simulate(self.h, self._v(V), _p(st), n, float(tau), int(steps), int(substeps),
                                           float(drag), _p(traj), _p(thr), _p(ang), _stream()))
         return st, traj, thr, ang
 
@@ -371,7 +406,7 @@ class Context:
         n = fine_problem["n"]
         mask = torch.empty((n[3], n[2], n[1], n[0]), dtype=torch.uint8, device=self.device)
         dil = (C.c_int32 * 4)(*[int(d) for d in dilate])
-        self._check(self.lib.dpo_mask_from_coarse(self.h, _p(Vc), C.byref(g), float(thresh), dil, _p(mask),
+        self._check(self.lib.dpo_mask_from_coarse(self.h, self._v(Vc, "Vc"), C.byref(g), float(thresh), dil, _p(mask),
                                                   _stream()))
         return mask
 
@@ -380,7 +415,7 @@ class Context:
         """Packed coordinates (int32 view of u32) of the free nodes with V < thresh, in node order."""
         nodes = torch.empty(max(1, self.n_free), dtype=torch.int32, device=self.device)
         n = C.c_int64()
-        self._check(self.lib.dpo_feasible_nodes(self.h, _p(V), float(thresh), _p(nodes), C.byref(n), _stream()))
+        self._check(self.lib.dpo_feasible_nodes(self.h, self._v(V), float(thresh), _p(nodes), C.byref(n), _stream()))
         return nodes[: n.value]
 
     def gather_pairs(self, nodes, sel, pol_ang, pol_thr):
@@ -392,14 +427,14 @@ class Context:
         x = torch.empty((n, 4), dtype=torch.float32, device=self.device)
         tgt = torch.empty((n, 4), dtype=torch.float32, device=self.device)
         self._check(self.lib.dpo_gather_pairs(self.h, _p(nodes), nodes.numel(), sel.ctypes.data_as(C.c_void_p), n,
-                                              _p(pol_ang), _p(pol_thr), _p(x), _p(tgt), _stream()))
+                                              self._ang(pol_ang), self._thr(pol_thr), _p(x), _p(tgt), _stream()))
         return x, tgt
 
     # ------------------------------------------------------------ probes
     def probe_interp(self, V, pts):
         pts = torch.as_tensor(pts, dtype=torch.float32).to(self.device).contiguous().reshape(-1, 4)
         out = torch.empty(pts.shape[0], dtype=torch.float32, device=self.device)
-        self._check(self.lib.dpo_probe_interp(self.h, _p(V), _p(pts), pts.shape[0], _p(out), _stream()))
+        self._check(self.lib.dpo_probe_interp(self.h, self._v(V), _p(pts), pts.shape[0], _p(out), _stream()))
         return out
 
     def probe_q(self, V, nodes, thr, angle):
@@ -408,7 +443,7 @@ class Context:
         angle = torch.as_tensor(angle, dtype=torch.float32).to(self.device).contiguous()
         q = torch.empty(nodes.numel(), dtype=torch.float32, device=self.device)
         torch.cuda.synchronize(self.device)
-        self._check(self.lib.dpo_probe_q(self.h, _p(V), _p(nodes), _p(thr), _p(angle), nodes.numel(), _p(q),
+        self._check(self.lib.dpo_probe_q(self.h, self._v(V), _p(nodes), _p(thr), _p(angle), nodes.numel(), _p(q),
                                          _stream()))
         return q
 
@@ -473,6 +508,21 @@ class Batch:
             raise DpoError(rc, self.lib.dpo_batch_last_error(self.h).decode())
         return rc
 
+    def _arrs(self, ts, dtype, name):
+        """One node array per problem, each of its problem's size."""
+        if ts is None:
+            return None
+        ts = list(ts)
+        if len(ts) != self.n:
+            raise DpoError(DPO_EINVAL, f"{name}: {self.n} arrays expected, got {len(ts)}")
+        for t, shape in zip(ts, self.shapes):
+            n = shape[0] * shape[1] * shape[2] * shape[3]
+            if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous() or t.dtype != dtype \
+                    or t.numel() != n:
+                raise DpoError(DPO_EINVAL, f"{name}: each must be a contiguous device tensor of its problem's "
+                                           f"node count in {dtype}")
+        return _ptr_array(ts)
+
     def init_values(self):
         Vs = [torch.empty(s, dtype=torch.float32, device=self.device) for s in self.shapes]
         self._check(self.lib.dpo_batch_init_value(self.h, _ptr_array(Vs), _stream()))
@@ -485,8 +535,9 @@ class Batch:
     def solve_vi(self, Vs, angs=None, thrs=None, tol_rel=1e-6, max_sweeps=100000, sweeps_per_graph=16, block=256):
         st = (BatchStats * self.n)()
         sec = C.c_double()
-        rc = self.lib.dpo_batch_solve_vi(self.h, _ptr_array(Vs), None if angs is None else _ptr_array(angs),
-                                         None if thrs is None else _ptr_array(thrs), float(tol_rel), int(max_sweeps),
+        rc = self.lib.dpo_batch_solve_vi(self.h, self._arrs(Vs, torch.float32, "Vs"),
+                                         self._arrs(angs, torch.float32, "angs"),
+                                         self._arrs(thrs, torch.uint8, "thrs"), float(tol_rel), int(max_sweeps),
                                          int(sweeps_per_graph), int(block), st, C.byref(sec), _stream())
         self._check(rc, allow=(DPO_OK, DPO_ENOCONV))
         return rc, [s.as_dict() for s in st], sec.value
@@ -494,7 +545,9 @@ class Batch:
     def solve_sequential(self, Vs, angs, thrs, tol_rel=1e-6, max_sweeps=100000, check_every=16):
         st = (BatchStats * self.n)()
         sec = C.c_double()
-        rc = self.lib.dpo_batch_solve_sequential(self.h, _ptr_array(Vs), _ptr_array(angs), _ptr_array(thrs),
+        rc = self.lib.dpo_batch_solve_sequential(self.h, self._arrs(Vs, torch.float32, "Vs"),
+                                                 self._arrs(angs, torch.float32, "angs"),
+                                                 self._arrs(thrs, torch.uint8, "thrs"),
                                                  float(tol_rel), int(max_sweeps), int(check_every), st,
                                                  C.byref(sec), _stream())
         self._check(rc, allow=(DPO_OK, DPO_ENOCONV))
@@ -605,7 +658,7 @@ class Mlp:
         """Seed angles at every free node of ctx (float32, node-shaped; other nodes 0)."""
         if seed is None:
             seed = torch.zeros(ctx.shape, dtype=torch.float32, device=self.device)
-        self._check(self.lib.dpo_mlp_propose(self.h, ctx.h, _p(seed), _stream()))
+        self._check(self.lib.dpo_mlp_propose(self.h, ctx.h, ctx._ang(seed, "seed"), _stream()))
         return seed
 
 

@@ -132,3 +132,43 @@ def test_ceiling_probes(dpo):
         dpo.probe_copy(src[:6], dst[:6])
     with pytest.raises(dpo.DpoError):
         dpo.probe_fma(0, 16, sink)
+
+
+def test_binding_refuses_mis_sized_and_mis_typed_arrays(dpo):
+    """Arrays are checked before any launch: a node array of the wrong size
+    or type (which a kernel would index past its end, or read as other
+    values) is refused, and so is a residual buffer that is too short."""
+    print("binding argument checks", flush=True)
+    p = inputs.with_grid(inputs.PI48, (8, 7, 6, 5))
+    ctx = dpo.Context(p)
+    V = ctx.init_value()
+    W = V.clone()
+    a, t = ctx.empty_policy()
+    bad = [
+        dict(V_in=V[:-1].contiguous() if V.dim() == 1 else V.reshape(-1)[:-1]),
+        dict(V_in=V.double()),
+        dict(V_out=W.reshape(-1)[::2]),
+        dict(pol_ang=a.half()),
+        dict(pol_thr=t.int()),
+        dict(resid=torch.zeros(4, dtype=torch.float64, device="cuda")),
+        dict(resid=torch.zeros(5, dtype=torch.float32, device="cuda")),
+        dict(V_in=V.cpu()),
+    ]
+    for kw in bad:
+        args = dict(V_in=V, V_out=W, pol_ang=a, pol_thr=t, resid=None)
+        args.update(kw)
+        with pytest.raises(dpo.DpoError):
+            ctx.bellman_sweep(args["V_in"], args["V_out"], args["pol_ang"], args["pol_thr"], args["resid"])
+    with pytest.raises(dpo.DpoError):
+        ctx.solve_pi(V.reshape(-1)[:10], a, t, max_outer=1)
+    with pytest.raises(dpo.DpoError):
+        ctx.value_at(V.double(), inputs.X0)
+    # the right arrays in any node-count shape are accepted
+    ctx.bellman_sweep(V.reshape(-1), W.reshape(-1), a.reshape(-1), t.reshape(-1),
+                      torch.zeros(5, dtype=torch.float64, device="cuda"))
+    b = dpo.Batch([inputs.with_grid(inputs.VI12, (6, 6, 6, 6)), inputs.with_grid(inputs.VI12, (7, 6, 6, 6))])
+    Vs = b.init_values()
+    with pytest.raises(dpo.DpoError):
+        b.solve_vi(Vs[:1], max_sweeps=2)
+    with pytest.raises(dpo.DpoError):
+        b.solve_vi([Vs[1], Vs[0]], max_sweeps=2)
