@@ -475,19 +475,26 @@ __device__ inline float fast_setup(const SweepArgs& a, const NodeTerms& T, float
   const float qM = fmaf(a.P.gamma, a.P.M, a.P.q_thr);
   float W[3][3], Wc[3][3];
   if (ok_r) {
-    const float* __restrict__ base = a.V_in + br;
+    const float* __restrict__ base = a.V_in + br + m_lo * G.st[3];
     const int so = (m_hi - m_lo) * G.st[3];
 #pragma unroll
     for (int p = 0; p < 3; p++) {
       const int v = min(max(Rv.b0 + p, 0), G.n[1] - 1);
+      // the row's six corner pairs are loaded before any of them is used,
+      // so that their latencies overlap
+      CornerPair lo[3], hi[3];
 #pragma unroll
       for (int q = 0; q < 3; q++) {
         const int w = min(max(Rt.b0 + q, 0), G.n[2] - 1);
-        const float* pp = base + v * G.st[1] + w * G.st[2] + m_lo * G.st[3];
-        const float lo = lerp_pair(pp, tr);
-        const float hi = lerp_pair(pp + so, tr);
-        W[p][q] = lerp(lo, hi, tm);
-        Wc[p][q] = coast_plane == m_lo ? lo : hi;
+        const float* pp = base + v * G.st[1] + w * G.st[2];
+        lo[q] = *reinterpret_cast<const CornerPair*>(pp);
+        hi[q] = *reinterpret_cast<const CornerPair*>(pp + so);
+      }
+#pragma unroll
+      for (int q = 0; q < 3; q++) {
+        const float l = lerp(lo[q].lo, lo[q].hi, tr), h = lerp(hi[q].lo, hi[q].hi, tr);
+        W[p][q] = lerp(l, h, tm);
+        Wc[p][q] = coast_plane == m_lo ? l : h;
       }
     }
   }
