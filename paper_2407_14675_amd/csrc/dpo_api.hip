@@ -1688,8 +1688,9 @@ struct dpo_batch {
   double* rinv_all = nullptr;
   float* g_all = nullptr;
   std::vector<BatchProblem> rec;  // host copy of the records (tile_begin per config)
-  BatchProblem* d_probs = nullptr;
+  BatchProblem* d_probs = nullptr;  // records of the running problems, in run order (n)
   int* d_tile_begin = nullptr;  // over the running problems (n + 1)
+  int* d_tile_run = nullptr;    // running problem of each tile (partial_cap)
   int* d_run = nullptr;         // running problems (n)
   int* d_done = nullptr;        // per problem: 0 running, 1 converged, 2 non-finite
   double* d_partial = nullptr;
@@ -1717,14 +1718,20 @@ int bfail(dpo_batch* b, int code, const std::string& msg) {
 // uploaded too); returns the tile count.
 int batch_tables(dpo_batch* b, int block, const std::vector<int>& run, int* n_tiles) {
   std::vector<int> tb(run.size() + 1, 0);
+  std::vector<BatchProblem> rr(run.size());
   for (size_t k = 0; k < run.size(); k++) {
     b->rec[run[k]].tile_begin = tb[k];
+    rr[k] = b->rec[run[k]];
     tb[k + 1] = tb[k] + blocks_for(b->ctx[run[k]]->n_free, block);
   }
   if (tb[run.size()] > b->partial_cap) return bfail(b, DPO_EINVAL, "batch: too many tiles for the partial buffer");
-  BHIP_TRY(b, hipMemcpyAsync(b->d_probs, b->rec.data(), sizeof(BatchProblem) * b->n, hipMemcpyHostToDevice, b->stream));
+  std::vector<int> tr(std::max(1, tb[run.size()]));
+  for (size_t k = 0; k < run.size(); k++)
+    std::fill(tr.begin() + tb[k], tr.begin() + tb[k + 1], (int)k);
+  BHIP_TRY(b, hipMemcpyAsync(b->d_probs, rr.data(), sizeof(BatchProblem) * rr.size(), hipMemcpyHostToDevice, b->stream));
   BHIP_TRY(b, hipMemcpyAsync(b->d_run, run.data(), sizeof(int) * run.size(), hipMemcpyHostToDevice, b->stream));
   BHIP_TRY(b, hipMemcpyAsync(b->d_tile_begin, tb.data(), sizeof(int) * tb.size(), hipMemcpyHostToDevice, b->stream));
+  BHIP_TRY(b, hipMemcpyAsync(b->d_tile_run, tr.data(), sizeof(int) * tb[run.size()], hipMemcpyHostToDevice, b->stream));
   BHIP_TRY(b, hipStreamSynchronize(b->stream));
   *n_tiles = tb[run.size()];
   return DPO_OK;
@@ -1737,6 +1744,7 @@ BatchArgs batch_args(dpo_batch* b, double tol, int n_run, int n_tiles, bool poli
   a.probs = b->d_probs;
   a.run = b->d_run;
   a.tile_begin = b->d_tile_begin;
+  a.tile_run = b->d_tile_run;
   a.n_run = n_run;
   a.n_tiles = n_tiles;
   a.free_all = b->free_all;
@@ -1895,6 +1903,7 @@ int dpo_batch_create(int32_t n_prob, const dpo_grid* grids, const dpo_problem* p
       hipMalloc(&b->g_all, sizeof(float) * g_off[n_prob]) != hipSuccess ||
       hipMalloc(&b->d_probs, sizeof(BatchProblem) * n_prob) != hipSuccess ||
       hipMalloc(&b->d_tile_begin, sizeof(int) * (n_prob + 1)) != hipSuccess ||
+      hipMalloc(&b->d_tile_run, sizeof(int) * b->partial_cap) != hipSuccess ||
       hipMalloc(&b->d_run, sizeof(int) * n_prob) != hipSuccess ||
       hipMalloc(&b->d_done, sizeof(int) * n_prob) != hipSuccess ||
       hipMalloc(&b->d_partial, sizeof(double) * kPartial * b->partial_cap) != hipSuccess ||
@@ -1942,7 +1951,7 @@ void dpo_batch_destroy(dpo_batch* b) {
   if (b->stream) hipStreamSynchronize(b->stream);
   for (dpo_ctx* c : b->ctx) dpo_destroy(c);
   void* bufs[] = {b->Va, b->Vb, b->ang, b->thr, b->free_all, b->rinv_all, b->g_all,
-                  b->d_probs, b->d_tile_begin, b->d_run, b->d_done, b->d_partial, b->d_resid};
+                  b->d_probs, b->d_tile_begin, b->d_tile_run, b->d_run, b->d_done, b->d_partial, b->d_resid};
   for (void* v : bufs)
     if (v) hipFree(v);
   if (b->stream) hipStreamDestroy(b->stream);

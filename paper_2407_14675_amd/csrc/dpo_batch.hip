@@ -10,14 +10,14 @@ namespace dpo {
 
 // One workgroup per tile of the running problems (numbered problem by
 // problem, XCD-contiguous); the problem's record holds offsets into the
-// concatenated buffers, whose bases are kernel arguments.
+// concatenated buffers, whose bases are kernel arguments.  The tile's problem
+// is one table lookup, so a workgroup's set-up waits on two dependent loads
+// (table entry, then record) whatever the number of running problems.
 template <int kMode>
 __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_batch_sweep(BatchArgs B, int parity, int want_resid) {
   extern __shared__ float4 dyn_lds[];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  int k = 0;
-  while (k + 1 < B.n_run && B.tile_begin[k + 1] <= tile) k++;
-  const BatchProblem& R = B.probs[B.run[k]];
+  const BatchProblem& R = B.probs[B.tile_run[tile]];
   SweepArgs a;
   a.G = R.G;
   a.P = R.P;
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(8))) 
   a.fb_count = nullptr;
   a.walk_from = nullptr;
   a.eval_acc = nullptr;
-  const int t = (tile - B.tile_begin[k]) * blockDim.x + threadIdx.x;
+  const int t = (tile - R.tile_begin) * blockDim.x + threadIdx.x;
   double rel = 0, sum = 0, mabs = 0, bad = 0;
   int fell_back = 0, deferred = 0, evals = 0;
   if (t < a.n_free) fast_node<kMode>(a, t, dyn_lds, rel, sum, mabs, bad, fell_back, deferred, evals);

@@ -95,9 +95,10 @@ struct BatchProblem {
 };
 
 struct BatchArgs {
-  const BatchProblem* probs;
-  const int* run;         // running problems of this graph (n_run entries)
-  const int* tile_begin;  // first tile of each running problem (n_run + 1 entries)
+  const BatchProblem* probs;  // records of the running problems, in run order (n_run entries)
+  const int* run;             // problem number of each running problem (n_run entries)
+  const int* tile_begin;      // first tile of each running problem (n_run + 1 entries)
+  const int* tile_run;        // running problem of each tile (n_tiles entries)
   int n_run;
   int n_tiles;
   const uint32_t* free_all;
