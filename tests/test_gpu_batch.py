@@ -49,6 +49,32 @@ def test_batch_equals_sequential_bit_for_bit(dpo):
         np.testing.assert_array_equal(host(t1[p]), host(t2[p]))
 
 
+def test_many_problems_stop_as_the_sequential_solves_do(dpo):
+    """40 problems of 4..10 nodes per axis: the running set shrinks many
+    times (each time the per-tile problem table is rebuilt), and with the
+    stop test on the same sweeps (every 8) every problem stops on the same
+    sweep as its sequential solve, with the same values bit for bit."""
+    print("40 problems", flush=True)
+    rng = np.random.default_rng(11)
+    sides = [int(x) for x in rng.integers(4, 11, size=40)]
+    probs = small_batch(sides)
+    b = dpo.Batch(probs)
+    V1 = b.init_values()
+    a1, t1 = b.empty_policies()
+    rc, st1, _ = b.solve_vi(V1, a1, t1, tol_rel=1e-6, max_sweeps=20000, sweeps_per_graph=8, block=64)
+    assert rc == dpo.DPO_OK and all(s["converged"] for s in st1)
+    V2 = b.init_values()
+    a2, t2 = b.empty_policies()
+    rc2, st2, _ = b.solve_sequential(V2, a2, t2, tol_rel=1e-6, max_sweeps=20000, check_every=8)
+    assert rc2 == dpo.DPO_OK
+    counts = [s["sweeps"] for s in st1]
+    assert counts == [s["sweeps"] for s in st2]
+    assert len(set(counts)) > 10  # the running set really shrinks step by step
+    for p in range(len(probs)):
+        np.testing.assert_array_equal(host(V1[p]), host(V2[p]))
+        np.testing.assert_array_equal(host(a1[p]), host(a2[p]))
+
+
 def test_batch_converges_to_oracle(dpo):
     print("batch vs oracle", flush=True)
     probs = small_batch([6, 8, 7])
