@@ -41,16 +41,16 @@ VALU_UNPACKED_WAVE_INSTR_PER_S = 256 * 4 * 2.4e9 / 4
 
 # Algorithmic HBM bytes of one frozen-policy evaluation per node: the value
 # read (4), the value written (4), the stored control (4) and the node's
-# index (4).  The descriptor form the library streams instead of the control
-# and the index is 10 bytes (16-bit cell code + the two cell coordinates).
+# index (4).  The descriptor the library streams instead of the control and
+# the index is 8 bytes (cell code + the two cell coordinates, packed).
 EVAL_ALGO_BYTES_PER_NODE = 16
 # Greedy sweep: packed coordinates (4) + value read (4) + value, angle and
-# throttle written (4 + 4 + 1) + the compact foot descriptor written (2 + 8).
-GREEDY_BYTES_PER_NODE = 27
+# throttle written (4 + 4 + 1) + the packed foot descriptor written (8).
+GREEDY_BYTES_PER_NODE = 25
 EVALS_PER_GREEDY_NODE = 1 + 64 + 2 + 12
 # VALU wave instructions per wave of 64 nodes of the greedy sweep with foot
 # descriptors, from the SQ_INSTS_VALU counter (profiles/k_sweep_fast_seeded_96x96x96x64.md)
-GREEDY_VALU_PER_WAVE = 2198
+GREEDY_VALU_PER_WAVE = 2208
 # Gather bytes of one evaluation done naively: 16 float32 corners.
 GATHER_BYTES_PER_EVAL = 64
 

@@ -204,9 +204,10 @@ int dpo_kernel_path(const dpo_ctx* ctx);
  * (4 + 4), plus the per-node stream of the foot descriptors: 16 bytes per free
  * node (packed coordinates, 32-bit cell code, two cell coordinates); 14 with
  * the compact 16-bit code, used when every foot stays within 31 cells of its
- * node along v_r and v_t; or, when at least half of the nodes are free, 10
- * per free node and 2 per fixed node (codes stored per node, no coordinate
- * list). */
+ * node along v_r and v_t; or, when at least half of the nodes are free, 8
+ * per node, free or fixed (one packed descriptor per node: the compact code
+ * and the two cell coordinates rounded to multiples of 2^-24 of a cell, no
+ * coordinate list). */
 int dpo_eval_sweep_bytes(const dpo_ctx* ctx, int64_t* bytes);
 
 /* Replace the search settings (same rules as in dpo_create). */

@@ -61,9 +61,10 @@ struct dpo_ctx {
   hipEvent_t resid_ready = nullptr;
   hipEvent_t step_ev[2][4] = {};  // policy iteration: greedy start/end, evaluation start/end, two steps deep
   int* desc_code = nullptr;  // foot descriptors of the greedy step's controls (policy iteration)
-  uint16_t* desc16 = nullptr;  // compact codes (desc_format 1 and 2)
-  int desc_format = -1;        // 0 flat 32-bit codes, 1 compact by free node, 2 compact by node
-  float2* desc_w = nullptr;
+  uint16_t* desc16 = nullptr;  // compact codes (desc_format 1)
+  int desc_format = -1;        // 0 flat 32-bit codes, 1 compact by free node, 2 packed by node
+  float2* desc_w = nullptr;    // cell coordinates (desc_format 0 and 1)
+  uint2* desc_pk = nullptr;    // packed descriptors, one per node (desc_format 2)
   bool desc_valid = false;    // a sweep has written them
   float* qnode = nullptr;                  // crown problem: dt * running cost per node
   float* kry = nullptr;      // exact policy evaluation: Krylov basis, (kry_m + 1) x N
@@ -479,23 +480,30 @@ int ensure_desc(dpo_ctx* c) {
   if (c->desc_format >= 0) return DPO_OK;
   const int format = desc_format_for(c);
   const size_t n = (size_t)std::max<int64_t>(1, format == 2 ? c->N : c->n_free);
-  bool ok = hipMalloc(&c->desc_w, sizeof(float2) * n) == hipSuccess;
-  if (format == 0) ok = ok && hipMalloc(&c->desc_code, sizeof(int) * n) == hipSuccess;
-  else ok = ok && hipMalloc(&c->desc16, sizeof(uint16_t) * n) == hipSuccess;
-  // dense form: every code starts as kDescSkip; greedy sweeps overwrite the free nodes'
-  if (ok && format == 2) ok = hipMemset(c->desc16, 0xff, sizeof(uint16_t) * n) == hipSuccess;
+  bool ok = true;
+  if (format == 2) {
+    // every descriptor starts as the skip code (all bits set); greedy sweeps
+    // overwrite the free nodes'
+    ok = hipMalloc(&c->desc_pk, sizeof(uint2) * n) == hipSuccess &&
+         hipMemset(c->desc_pk, 0xff, sizeof(uint2) * n) == hipSuccess;
+  } else {
+    ok = hipMalloc(&c->desc_w, sizeof(float2) * n) == hipSuccess;
+    if (format == 0) ok = ok && hipMalloc(&c->desc_code, sizeof(int) * n) == hipSuccess;
+    else ok = ok && hipMalloc(&c->desc16, sizeof(uint16_t) * n) == hipSuccess;
+  }
   if (!ok) return fail(c, DPO_ENOMEM, "descriptor alloc");
   c->desc_format = format;
   return DPO_OK;
 }
 
 void set_desc_out(dpo_ctx* c, SweepArgs& a) {
-  a.desc_w = c->desc_w;
-  if (c->desc_format == 0) {
-    a.desc_code = c->desc_code;
+  if (c->desc_format == 2) {
+    a.desc_pk = c->desc_pk;
+    a.desc_dense = 1;
   } else {
-    a.desc16 = c->desc16;
-    a.desc_dense = c->desc_format == 2;
+    a.desc_w = c->desc_w;
+    if (c->desc_format == 0) a.desc_code = c->desc_code;
+    else a.desc16 = c->desc16;
   }
   c->desc_valid = true;
 }
@@ -652,7 +660,7 @@ int64_t eval_stream_bytes(const dpo_ctx* c) {
   const int format = c->desc_format >= 0 ? c->desc_format : desc_format_for(c);
   if (format == 0) return 16 * c->n_free;
   if (format == 1) return 14 * c->n_free;
-  return 10 * c->n_free + 2 * (c->N - c->n_free);
+  return 8 * c->N;
 }
 
 // Frozen-policy sweep driven by the descriptors of the last greedy sweep.
@@ -663,6 +671,7 @@ int sweep_eval_desc(dpo_ctx* c, const float* Vin, float* Vout, hipStream_t s) {
   a.desc_code_in = c->desc_code;
   a.desc16_in = c->desc16;
   a.desc_w_in = c->desc_w;
+  a.desc_pk_in = c->desc_pk;
   if (a.n_free == 0) return DPO_OK;
   // streamed per sweep: the per-node stream and two value arrays
   const double bytes = (double)eval_stream_bytes(c) + 8.0 * (double)c->N;
@@ -997,6 +1006,7 @@ void dpo_destroy(dpo_ctx* c) {
   if (c->desc_code) hipFree(c->desc_code);
   if (c->desc16) hipFree(c->desc16);
   if (c->desc_w) hipFree(c->desc_w);
+  if (c->desc_pk) hipFree(c->desc_pk);
   if (c->eval_acc) hipFree(c->eval_acc);
   if (c->qnode) hipFree(c->qnode);
   if (c->kry) hipFree(c->kry);

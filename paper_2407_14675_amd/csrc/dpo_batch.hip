@@ -43,6 +43,8 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(8))) 
   a.rot_scan = B.rot_scan;
   a.desc_code = nullptr;
   a.desc16 = nullptr;
+  a.desc_pk = nullptr;
+  a.desc_pk_in = nullptr;
   a.desc_dense = 0;
   a.seed = nullptr;
   a.pol_ang_in = nullptr;

@@ -218,14 +218,14 @@ __global__ __launch_bounds__(kBrickBlock) __attribute__((amdgpu_waves_per_eu(4))
 }
 
 // The same column walk driven by the foot descriptors of the greedy step
-// (per-node 16-bit codes and cell coordinates along v_r and v_t, the dense
-// form): per node one code and one weight pair are streamed instead of the
+// (the packed per-node form: cell offsets and cell coordinates along v_r and
+// v_t in eight bytes): per node one descriptor is streamed instead of the
 // control, and the corners come from the brick.  Everything about a node
 // that does not change from one mass plane to the next -- its offset in the
 // plane, its brick row, its r cell and weight (r' = v_r does not depend on
 // the control) -- is formed once per tile; the m cell and weight depend only
-// on the plane and the throttle.  The next plane's codes and weights are
-// loaded together with its brick, while the current plane is computed.
+// on the plane and the throttle.  The next plane's descriptors are loaded
+// together with its brick, while the current plane is computed.
 // Same values, bit for bit, as the descriptor sweep that gathers from global
 // memory (k_policy_eval_d16): the same cells, weights and lerps.
 template <bool kVec, bool kNt>
@@ -234,7 +234,6 @@ __global__ __launch_bounds__(kBrickBlock) __attribute__((amdgpu_waves_per_eu(4))
   extern __shared__ float4 lds4[];
   float* lds = reinterpret_cast<float*>(lds4);
   typedef float native4 __attribute__((ext_vector_type(4)));
-  typedef float native2 __attribute__((ext_vector_type(2)));
   typedef typename std::conditional<kVec, native4, float>::type Chunk;
   constexpr int kW = kVec ? 4 : 1;
   constexpr int kPf = kVec ? kBrickMaxPf : 4 * kBrickMaxPf;
@@ -327,24 +326,21 @@ __global__ __launch_bounds__(kBrickBlock) __attribute__((amdgpu_waves_per_eu(4))
     return (r & 255) + (((r >> 8) & 255) + r_lo) * st1 + (((r >> 16) & 255) + t_lo) * st2;
   };
 
-  // the stream of one plane: codes and weights of this thread's nodes
+  // the stream of one plane: the packed descriptors of this thread's nodes
   // (unconditional loads; a missing node's code is replaced by the skip code)
+  typedef unsigned native_u2 __attribute__((ext_vector_type(2)));
   struct Stream {
-    uint16_t c[kN];
-    native2 w[kN];
+    uint2 d[kN];
   };
   auto stream = [&](int q, Stream& S) {
     const size_t po = (size_t)q * st3;
 #pragma unroll
     for (int k = 0; k < kN; k++) {
       const size_t j = po + node_of(k);
-      if (kNt) {
-        S.c[k] = __builtin_nontemporal_load(a.desc16_in + j);
-        S.w[k] = __builtin_nontemporal_load(reinterpret_cast<const native2*>(a.desc_w_in) + j);
-      } else {
-        S.c[k] = a.desc16_in[j];
-        S.w[k] = reinterpret_cast<const native2*>(a.desc_w_in)[j];
-      }
+      native_u2 v;
+      if (kNt) v = __builtin_nontemporal_load(reinterpret_cast<const native_u2*>(a.desc_pk_in) + j);
+      else v = reinterpret_cast<const native_u2*>(a.desc_pk_in)[j];
+      S.d[k] = make_uint2(v.x, v.y);
     }
   };
 
@@ -368,8 +364,9 @@ __global__ __launch_bounds__(kBrickBlock) __attribute__((amdgpu_waves_per_eu(4))
       // keep the packed node words packed: unpacking them once per tile
       // (loop-invariant hoisting) would take more registers than there are
       asm volatile("" : "+v"(rc[k]));
-      const uint16_t c = S.c[k];
-      if (rc[k] == -1 || c == kDescSkip) continue;
+      const uint32_t c = desc_pk_code(S.d[k]);
+      if (rc[k] == -1 || c == kDescPkSkip) continue;
+      const float w1 = desc_pk_w1(S.d[k]), w2 = desc_pk_w2(S.d[k]);
       const bool thr = (c & kDescThr) != 0;
       float I = a.P.M;
       if (!(c & kDescOut)) {
@@ -379,16 +376,15 @@ __global__ __launch_bounds__(kBrickBlock) __attribute__((amdgpu_waves_per_eu(4))
         const float t3 = thr ? tth : tc;
         if ((unsigned)y <= (unsigned)(bt - 2) && (unsigned)x <= (unsigned)(br - 2)) {
           const int o = y * ls2 + x * n0 + b0;
-          const float e0 = plane_value((thr ? lt0 : lc0) + o, ls1, ls2, t0[k], S.w[k].x, S.w[k].y);
+          const float e0 = plane_value((thr ? lt0 : lc0) + o, ls1, ls2, t0[k], w1, w2);
           // lerp(e0, e1, 0) is e0 for any finite e1: a coast foot on plane p
           // reads only that plane
-          const float e1 =
-              t3 != 0.0f ? plane_value((thr ? lt1 : lc1) + o, ls1, ls2, t0[k], S.w[k].x, S.w[k].y) : e0;
+          const float e1 = t3 != 0.0f ? plane_value((thr ? lt1 : lc1) + o, ls1, ls2, t0[k], w1, w2) : e0;
           I = lerp(e0, e1, t3);
         } else {
           // beyond the brick (the host's reach bound makes this unreachable)
           const int b3 = thr ? bth : bc;
-          const float t[4] = {t0[k], S.w[k].x, S.w[k].y, t3};
+          const float t[4] = {t0[k], w1, w2, t3};
           const int b1 = x + r_lo, b2 = y + t_lo;
           I = cell_value(a.V_in + (b0 + b1 * st1 + b2 * st2 + b3 * st3), a.G, t, st3);
         }

@@ -62,6 +62,12 @@ struct SweepArgs {
   // sweep then runs over every node and skips the code kDescSkip).
   uint16_t* desc16;
   const uint16_t* desc16_in;
+  // Packed form, stored per node (desc_dense): the 14 low bits of the compact
+  // code (kDescPkSkip for a node that is not free), then the two cell
+  // coordinates as 25-bit fixed-point numbers in units of 2^-24 of a cell
+  // (see desc_pack).
+  uint2* desc_pk;
+  const uint2* desc_pk_in;
   int desc_dense;
   int mode;         // search mode (feedback)
   double w_time, w_fuel, lambda;
@@ -72,6 +78,22 @@ inline int blocks_for(long long n, int per = kBlock) { return (int)((n + per - 1
 constexpr uint16_t kDescOut = 1u << 12;
 constexpr uint16_t kDescThr = 1u << 13;
 constexpr uint16_t kDescSkip = 0xffffu;  // not a free node (dense form)
+constexpr uint32_t kDescPkSkip = 0x3fffu;  // not a free node (packed form; no code of a free node has it)
+
+// Packed descriptor of one node: code (14 bits), then the cell coordinates w1
+// and w2 in [0, 1] rounded to the nearest multiple of 2^-24 (25 bits each:
+// exact for coordinates in [0.5, 1], within 2^-25 of a cell below that, which
+// is half a float32 unit at 0.25-0.5).  Eight bytes per node instead of ten.
+__device__ inline uint2 desc_pack(uint32_t code, float w1, float w2) {
+  const uint32_t q1 = (uint32_t)rintf(fminf(fmaxf(w1, 0.0f), 1.0f) * 16777216.0f);
+  const uint32_t q2 = (uint32_t)rintf(fminf(fmaxf(w2, 0.0f), 1.0f) * 16777216.0f);
+  return make_uint2(code | (q1 << 14), (q1 >> 18) | (q2 << 7));
+}
+__device__ inline uint32_t desc_pk_code(uint2 d) { return d.x & kDescPkSkip; }
+__device__ inline float desc_pk_w1(uint2 d) {
+  return (float)(__builtin_amdgcn_alignbit(d.y, d.x, 14) & 0x1ffffffu) * 5.9604644775390625e-8f;
+}
+__device__ inline float desc_pk_w2(uint2 d) { return (float)(d.y >> 7) * 5.9604644775390625e-8f; }
 // Feedback and closed loop: up to this many states one wave per state (the
 // lanes split the table), beyond it one thread per state.
 constexpr int kWaveStates = 8192;

@@ -169,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_direct(SweepArgs a) {
     a.V_out[j] = ch.v;
     if (a.pol_ang) a.pol_ang[j] = ch.ang;
     if (a.pol_thr) a.pol_thr[j] = (uint8_t)ch.thr;
-    if (!kHeun && (a.desc_code || a.desc16)) write_desc(a, t, j, T, ch);
+    if (!kHeun && (a.desc_code || a.desc16 || a.desc_pk)) write_desc(a, t, j, T, ch);
     node_residual(vin, ch.v, rel, sum, mabs, bad);
   }
   if (kMode == 3 && a.eval_acc) block_add_count(evals, a.eval_acc);
@@ -306,33 +306,41 @@ __global__ __launch_bounds__(kBlock) void k_policy_eval_desc(SweepArgs a) {
   }
 }
 
-// The same sweep from compact descriptors (SweepArgs::desc16): 14 bytes per
-// free node with the free list (coordinates 4, code 2, weights 8), 10 bytes
-// per node without it (kDense: every node is visited in order, fixed ones
-// carry kDescSkip and are left alone, and the node index is the thread's).
+// The same sweep from compact descriptors: 14 bytes per free node with the
+// free list (SweepArgs::desc16: coordinates 4, code 2, weights 8), 8 bytes
+// per node without it (kDense, SweepArgs::desc_pk: every node is visited in
+// order, fixed ones carry kDescPkSkip and are left alone, and the node index
+// is the thread's).
 // kNpt nodes per thread: 2 when the data streams from HBM (more loads in
 // flight per wave), 1 when it is cache-resident (twice the workgroups, a
 // smaller last partial round on the CUs).
 template <bool kDense, int kNt, int kNpt>
 __global__ __launch_bounds__(kBlock) void k_policy_eval_d16(SweepArgs a) {
   typedef float nt_f2 __attribute__((ext_vector_type(2)));
+  typedef unsigned nt_u2 __attribute__((ext_vector_type(2)));
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int t0 = tile * (kNpt * kBlock) + threadIdx.x;
   const int count = kDense ? a.G.n[0] * a.G.n[1] * a.G.n[2] * a.G.n[3] : a.n_free;
   uint32_t packed[kNpt];
-  uint16_t code[kNpt];
+  uint32_t code[kNpt];
   float2 w[kNpt];
 #pragma unroll
   for (int k = 0; k < kNpt; k++) {
     const int t = t0 + k * kBlock;
     if (t < count) {
-      if (kNt & 1) {
-        if (!kDense) packed[k] = __builtin_nontemporal_load(a.free_node + t);
+      if (kDense) {
+        const nt_u2 v = (kNt & 1) ? __builtin_nontemporal_load(reinterpret_cast<const nt_u2*>(a.desc_pk_in) + t)
+                                  : reinterpret_cast<const nt_u2*>(a.desc_pk_in)[t];
+        const uint2 d = make_uint2(v.x, v.y);
+        code[k] = desc_pk_code(d);
+        w[k] = make_float2(desc_pk_w1(d), desc_pk_w2(d));
+      } else if (kNt & 1) {
+        packed[k] = __builtin_nontemporal_load(a.free_node + t);
         code[k] = __builtin_nontemporal_load(a.desc16_in + t);
         const nt_f2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f2*>(a.desc_w_in) + t);
         w[k] = make_float2(v.x, v.y);
       } else {
-        if (!kDense) packed[k] = a.free_node[t];
+        packed[k] = a.free_node[t];
         code[k] = a.desc16_in[t];
         w[k] = a.desc_w_in[t];
       }
@@ -342,7 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_policy_eval_d16(SweepArgs a) {
   for (int k = 0; k < kNpt; k++) {
     const int t = t0 + k * kBlock;
     if (t >= count) continue;
-    if (kDense && code[k] == kDescSkip) continue;
+    if (kDense && code[k] == kDescPkSkip) continue;
     int i[4];
     int j;
     if (kDense) {

@@ -353,6 +353,13 @@ __device__ inline void write_desc(const SweepArgs& a, int t, int j, const NodeTe
   float w[4];
   const bool inside = foot_cell(a.G, T.i, off, base, w);
   const float2 wv = inside ? make_float2(w[1], w[2]) : make_float2(0.0f, 0.0f);
+  if (a.desc_pk) {
+    uint32_t code = ch.thr ? kDescThr : 0;
+    if (inside) code |= (uint32_t)((base[1] - T.i[1] + 32) | ((base[2] - T.i[2] + 32) << 6));
+    else code |= kDescOut;
+    a.desc_pk[j] = desc_pack(code, wv.x, wv.y);
+    return;
+  }
   if (a.desc16) {
     const int k = a.desc_dense ? j : t;
     uint16_t code = ch.thr ? kDescThr : 0;
@@ -574,7 +581,7 @@ __device__ inline void fast_node(const SweepArgs& a, int t, float4* lds, double&
   a.V_out[j] = ch.v;
   if (a.pol_ang) a.pol_ang[j] = ch.ang;
   if (a.pol_thr) a.pol_thr[j] = (uint8_t)ch.thr;
-  if (a.desc_code || a.desc16) write_desc(a, t, j, T, ch);
+  if (a.desc_code || a.desc16 || a.desc_pk) write_desc(a, t, j, T, ch);
   node_residual(vin, ch.v, rel, sum, mabs, bad);
 }
 

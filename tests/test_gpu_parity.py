@@ -707,7 +707,7 @@ def test_descriptor_formats(dpo, case):
     ctx = dpo.Context(p, mask=None if mask is None else dev(mask, torch.uint8))
     free = o.kind == KIND_FREE
     nf = int(free.sum())
-    want = {"per_node": 18 * nf + 2 * (o.N - nf), "per_free_node": 22 * nf, "flat_code": 24 * nf}[case]
+    want = {"per_node": 16 * nf + 8 * (o.N - nf), "per_free_node": 22 * nf, "flat_code": 24 * nf}[case]
     assert ctx.eval_sweep_bytes() == want
     V = inputs.random_value(p, seed=73, frac_M=0.1).astype(np.float32)
     Vin = dev(V)
