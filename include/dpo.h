@@ -271,6 +271,11 @@ int dpo_eval_path(const dpo_ctx* ctx);
  * stores, per free node, the cell and cell coordinates of its chosen
  * control's foot, so this sweep is one descriptor load, 16 gathers and 15
  * lerps per node (the evaluation sweep of policy iteration, eq:p_eval).
+ * Where the descriptors are stored per node (dpo_eval_sweep_bytes) the two
+ * cell coordinates along v_r and v_t are kept to the nearest multiple of
+ * 2^-24 of a cell, so the sweep reproduces the Bellman sweep's Q of the
+ * chosen control up to 2^-25 of the differences between neighbouring
+ * values (below the rounding of the float32 interpolation itself).
  * Same fixed-node rule as dpo_bellman_sweep; no residual.  DPO_EINVAL if no
  * Bellman sweep has run on ctx, or for the Heun foot (descriptors need the
  * Euler step). */
