@@ -195,3 +195,36 @@ def test_brick_full_size_96x96x96x64(dpo, n_m):
     del outs, S, W, V, ang, thr
     ctx.close()
     torch.cuda.empty_cache()
+
+
+def test_packed_descriptors_reproduce_the_greedy_q(dpo):
+    """On a grid stored per node the descriptors keep the two cell
+    coordinates to 2^-24 of a cell: the evaluation sweep of the greedy
+    policy then reproduces the greedy step's own Q to within float32
+    rounding of the corner values (the coordinates' rounding moves an
+    interpolant by at most 2^-25 of each of the two corner differences it
+    spans, under three units in the last place of the corners here)."""
+    p = inputs.with_grid(inputs.PI48, (11, 10, 9, 8))
+    _say("packed descriptors")
+    ctx = dpo.Context(p)
+    o = Oracle(p)
+    free = o.kind == KIND_FREE
+    nf = int(free.sum())
+    assert ctx.eval_sweep_bytes() == 16 * nf + 8 * (o.N - nf)  # the packed per-node form
+    V = inputs.random_value(p, seed=91, low=0, high=40).astype(np.float32)
+    Vd = dev(V)
+    W = Vd.clone()
+    ang, thr = ctx.empty_policy()
+    ctx.bellman_sweep(Vd, W, ang, thr)
+    for path in (1, 2):
+        ctx.set_eval_path(path)
+        E = Vd.clone()
+        ctx.policy_eval_sweep_last(Vd, E)
+        from scipy.ndimage import maximum_filter
+        corner = maximum_filter(np.abs(V), size=7, mode="nearest")
+        ulp = np.spacing(corner.astype(np.float32)).astype(np.float64)
+        d = np.abs(host(E).astype(np.float64) - host(W).astype(np.float64))
+        _say("  path", path, "largest difference in corner ulps", float((d / ulp)[free].max()))
+        assert np.all(d[free] <= 4 * ulp[free])  # measured: 2
+        np.testing.assert_array_equal(host(E)[~free], V[~free])
+    ctx.set_eval_path(0)
