@@ -369,7 +369,8 @@ void plan_brick(dpo_ctx* c) {
   // planes) while that leaves at least 8 workgroups per CU, else 4, else 2
   // with at least 4 per CU, else 1, so that thin grids (one GPU's slab of a
   // sharded grid) still fill the chip.  At 96^3 x 64 runs of 8 planes take
-  // 0.207 ms per sweep against 0.216 ms with 4 and 0.224 ms with 16 (half
+  // 0.201 ms per sweep against 0.214-0.217 ms with 9 or 10; with 10-byte
+  // descriptors 0.207 ms against 0.216 ms with 4 and 0.224 ms with 16 (half
   // the workgroups: the last round leaves CUs idle).
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
